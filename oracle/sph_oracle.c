@@ -1,0 +1,832 @@
+/*
+ * sph_oracle.c -- TEST INFRASTRUCTURE ONLY (not part of the product path).
+ *
+ * A plain, slow, obviously-correct FP64 CPU reference for the data-parallel
+ * hot path of truncated-Wendland SPH as described in
+ *   Wang, Zhang, Haidn & Hu, "An efficient truncation scheme for Eulerian and
+ *   total Lagrangian SPH methods", arXiv:2405.05155.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code, header, table or
+ * helper with the HIP library: every formula is written out again here from
+ * the paper, in FP64, with per-particle sums taken in ascending neighbour
+ * order.
+ *
+ * Conventions (the readings of the paper this file follows):
+ *  - positions are SoA, pos[a*n + i] for axis a; tensors are row-major
+ *    T[i*d*d + a*d + b];
+ *  - r_ij = r_i - r_j, with the minimum-image rule on periodic axes;
+ *  - grad W_ij is the gradient with respect to r_i,
+ *      grad W_ij = (dW/dr)(|r_ij|) * r_ij / |r_ij|,
+ *    the only sign that makes the relaxation force (Eq. 7), the correction
+ *    matrix (Eq. 9), the Eulerian system (Eq. 19) and the total Lagrangian
+ *    system (Eqs. 31-32) physically consistent.  For coincident particles
+ *    (|r_ij| = 0) the unit vector is undefined and grad W_ij is taken as 0;
+ *  - the neighbour set of i is {j != i : |r_ij|^2 <= rc^2} with |r_ij|^2
+ *    evaluated in FP64 as ((dx*dx + dy*dy) + dz*dz) and rc^2 supplied by the
+ *    caller (Eq. 5: W = 0 only for |r| > kappa h, so r = kappa h is inside).
+ *
+ * Parity pins: every function here is checked by tests/test_oracle_pins.py
+ * against closed forms, printed values (Table 1), brute force or invariants;
+ * see the header comment of each function for what pins it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    int dim;            /* 1, 2 or 3 */
+    int periodic[3];    /* per axis, nonzero = periodic */
+    double lo[3];
+    double hi[3];
+} or_box;
+
+enum { OR_WENDLAND = 0, OR_LAGUERRE_GAUSS = 1 };
+
+/* ------------------------------------------------------------------ */
+/* Kernels                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Wendland C2, Eq. (6), Sec. 2.3.1: W = alpha_d (1 - q/2)^4 (2q + 1),
+ * q = r/h, alpha_1 = 3/(4h), alpha_2 = 7/(4 pi h^2), alpha_3 = 21/(16 pi h^3).
+ * The support test (q <= kappa) is applied by the neighbour set, so this
+ * function evaluates the polynomial for any q in [0, 2]. */
+static double wendland_alpha(int dim, double h)
+{
+    if (dim == 1) return 3.0 / (4.0 * h);
+    if (dim == 2) return 7.0 / (4.0 * M_PI * h * h);
+    return 21.0 / (16.0 * M_PI * h * h * h);
+}
+
+/* Laguerre-Gauss, Eq. (8), Sec. 2.3.2, read as
+ *   W = (a_d / h^d) (1 - q^2 + q^4/6) exp(-q^2),  q <= 2,
+ * with a_1 = 8/(5 sqrt(pi)), a_2 = 3/pi, a_3 = 8/pi^(3/2).  The printed
+ * polynomial (1 - q^2/2 + q^4/6) does not integrate to one with the printed
+ * a_d; the form above does, in 1, 2 and 3 dimensions. */
+static double lg_alpha(int dim, double h)
+{
+    if (dim == 1) return 8.0 / (5.0 * sqrt(M_PI)) / h;
+    if (dim == 2) return 3.0 / M_PI / (h * h);
+    return 8.0 / pow(M_PI, 1.5) / (h * h * h);
+}
+
+double or_kernel_W(int kernel, int dim, double h, double r)
+{
+    double q = r / h;
+    if (kernel == OR_WENDLAND) {
+        double t = 1.0 - 0.5 * q;
+        return wendland_alpha(dim, h) * t * t * t * t * (2.0 * q + 1.0);
+    }
+    return lg_alpha(dim, h) * (1.0 - q * q + q * q * q * q / 6.0) * exp(-q * q);
+}
+
+/* dW/dr obtained by differentiating the expressions above term by term
+ * (product rule, written out, not simplified). */
+double or_kernel_dWdr(int kernel, int dim, double h, double r)
+{
+    double q = r / h;
+    if (kernel == OR_WENDLAND) {
+        double t = 1.0 - 0.5 * q;
+        /* d/dq [t^4 (2q+1)] = 4 t^3 (-1/2) (2q+1) + t^4 * 2 */
+        double dq = 4.0 * t * t * t * (-0.5) * (2.0 * q + 1.0) + t * t * t * t * 2.0;
+        return wendland_alpha(dim, h) * dq / h;
+    }
+    {
+        double poly = 1.0 - q * q + q * q * q * q / 6.0;
+        double dpoly = -2.0 * q + 4.0 * q * q * q / 6.0;
+        double e = exp(-q * q);
+        double dq = dpoly * e + poly * (-2.0 * q) * e;
+        return lg_alpha(dim, h) * dq / h;
+    }
+}
+
+void or_kernel_eval(int kernel, int dim, double h, int64_t m, const double* r,
+                    double* W, double* dWdr)
+{
+    for (int64_t k = 0; k < m; ++k) {
+        if (W) W[k] = or_kernel_W(kernel, dim, h, r[k]);
+        if (dWdr) dWdr[k] = or_kernel_dWdr(kernel, dim, h, r[k]);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Pair geometry                                                       */
+/* ------------------------------------------------------------------ */
+
+/* r_ij = r_i - r_j with the minimum image on periodic axes. */
+static void pair_vec(const or_box* b, int64_t n, const double* pos, int64_t i, int64_t j, double d[3])
+{
+    for (int a = 0; a < 3; ++a) d[a] = 0.0;
+    for (int a = 0; a < b->dim; ++a) {
+        double x = pos[a * n + i] - pos[a * n + j];
+        if (b->periodic[a]) {
+            double L = b->hi[a] - b->lo[a];
+            if (x > 0.5 * L) x -= L;
+            else if (x < -0.5 * L) x += L;
+        }
+        d[a] = x;
+    }
+}
+
+static double dist2(const double d[3]) { return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]; }
+
+/* grad_i W_ij = dW/dr * r_ij / r  (0 when r = 0). Returns r. */
+static double grad_w(int kernel, int dim, double h, const double d[3], double g[3])
+{
+    double r = sqrt(dist2(d));
+    g[0] = g[1] = g[2] = 0.0;
+    if (r > 0.0) {
+        double w1 = or_kernel_dWdr(kernel, dim, h, r);
+        for (int a = 0; a < dim; ++a) g[a] = w1 * d[a] / r;
+    }
+    return r;
+}
+
+/* ------------------------------------------------------------------ */
+/* Neighbour sets                                                      */
+/* ------------------------------------------------------------------ */
+
+/* Brute force over all j for the listed rows (rows == NULL: all n rows).
+ * Fills row_ptr[0..m]; writes col only when col != NULL and nnz <= cap.
+ * Returns nnz. */
+int64_t or_neighbors_brute(const or_box* b, int64_t n, const double* pos, double rc2,
+                           int64_t m, const int64_t* rows,
+                           int64_t* row_ptr, int32_t* col, int64_t cap)
+{
+    int64_t* cnt = (int64_t*)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        int64_t c = 0;
+        double d[3];
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            pair_vec(b, n, pos, i, j, d);
+            if (dist2(d) <= rc2) ++c;
+        }
+        cnt[k] = c;
+    }
+    row_ptr[0] = 0;
+    for (int64_t k = 0; k < m; ++k) row_ptr[k + 1] = row_ptr[k] + cnt[k];
+    free(cnt);
+    int64_t nnz = row_ptr[m];
+    if (col && nnz <= cap) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = 0; k < m; ++k) {
+            int64_t i = rows ? rows[k] : k;
+            int64_t p = row_ptr[k];
+            double d[3];
+            for (int64_t j = 0; j < n; ++j) {
+                if (j == i) continue;
+                pair_vec(b, n, pos, i, j, d);
+                if (dist2(d) <= rc2) col[p++] = (int32_t)j;
+            }
+        }
+    }
+    return nnz;
+}
+
+static int cmp_i32(const void* a, const void* b)
+{
+    int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+    return (x > y) - (x < y);
+}
+
+/* Uniform-grid neighbour search: cells of edge >= rc on every axis, the
+ * 3^dim block of cells around each particle's cell (duplicates removed when
+ * an axis has fewer than three cells), then the same test as the brute
+ * force, then each row sorted ascending.  Pinned against or_neighbors_brute. */
+int64_t or_neighbors_grid(const or_box* b, int64_t n, const double* pos, double rc, double rc2,
+                          int64_t* row_ptr, int32_t* col, int64_t cap)
+{
+    int dim = b->dim;
+    int64_t nc[3] = {1, 1, 1};
+    for (int a = 0; a < dim; ++a) {
+        double L = b->hi[a] - b->lo[a];
+        int64_t c = (int64_t)floor(L / (rc * (1.0 + 1e-9)));
+        nc[a] = c < 1 ? 1 : c;
+    }
+    int64_t ncell = nc[0] * nc[1] * nc[2];
+    int64_t* cell_of = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* cstart = (int64_t*)calloc((size_t)(ncell + 1), sizeof(int64_t));
+    int64_t* members = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t* coord = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t cidx = 0;
+        for (int a = 2; a >= 0; --a) {
+            int64_t c = 0;
+            if (a < dim) {
+                double L = b->hi[a] - b->lo[a];
+                c = (int64_t)floor((pos[a * n + i] - b->lo[a]) / L * (double)nc[a]);
+                if (c < 0) c = 0;
+                if (c > nc[a] - 1) c = nc[a] - 1;
+            }
+            coord[i * 3 + a] = c;
+            cidx = cidx * nc[a] + c;
+        }
+        cell_of[i] = cidx;
+        cstart[cidx + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+    {
+        int64_t* fill = (int64_t*)malloc((size_t)(ncell > 0 ? ncell : 1) * sizeof(int64_t));
+        memcpy(fill, cstart, (size_t)ncell * sizeof(int64_t));
+        for (int64_t i = 0; i < n; ++i) members[fill[cell_of[i]]++] = i;
+        free(fill);
+    }
+
+    int64_t* cnt = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t nnz = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            row_ptr[0] = 0;
+            for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+            nnz = row_ptr[n];
+            if (!col || nnz > cap) break;
+        }
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t cells[27];
+            int ncells = 0;
+            int64_t lim[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) lim[a] = 1;
+            for (int64_t oz = -lim[2]; oz <= lim[2]; ++oz)
+                for (int64_t oy = -lim[1]; oy <= lim[1]; ++oy)
+                    for (int64_t ox = -lim[0]; ox <= lim[0]; ++ox) {
+                        int64_t off[3] = {ox, oy, oz};
+                        int64_t cc[3];
+                        int ok = 1;
+                        for (int a = 0; a < 3; ++a) {
+                            int64_t c = coord[i * 3 + a] + off[a];
+                            if (a < dim && b->periodic[a]) {
+                                c = ((c % nc[a]) + nc[a]) % nc[a];
+                            } else if (c < 0 || c >= nc[a]) {
+                                ok = 0;
+                            }
+                            cc[a] = c;
+                        }
+                        if (!ok) continue;
+                        int64_t cidx = (cc[2] * nc[1] + cc[1]) * nc[0] + cc[0];
+                        int dup = 0;
+                        for (int u = 0; u < ncells; ++u) dup |= (cells[u] == cidx);
+                        if (!dup) cells[ncells++] = cidx;
+                    }
+            int64_t c = 0;
+            int64_t p = pass ? row_ptr[i] : 0;
+            double d[3];
+            for (int u = 0; u < ncells; ++u) {
+                for (int64_t s = cstart[cells[u]]; s < cstart[cells[u] + 1]; ++s) {
+                    int64_t j = members[s];
+                    if (j == i) continue;
+                    pair_vec(b, n, pos, i, j, d);
+                    if (dist2(d) <= rc2) {
+                        if (pass) col[p + c] = (int32_t)j;
+                        ++c;
+                    }
+                }
+            }
+            if (pass) qsort(col + p, (size_t)c, sizeof(int32_t), cmp_i32);
+            else cnt[i] = c;
+        }
+    }
+    free(cnt);
+    free(cell_of);
+    free(cstart);
+    free(members);
+    free(coord);
+    return nnz;
+}
+
+/* ------------------------------------------------------------------ */
+/* Small dense linear algebra (FP64)                                   */
+/* ------------------------------------------------------------------ */
+
+/* Inverse by Gauss-Jordan elimination with partial pivoting. Returns the
+ * determinant (product of pivots with the row-swap sign). */
+static double invert(int d, const double* A, double* Ainv)
+{
+    double a[3][6];
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < 2 * d; ++c)
+            a[r][c] = c < d ? A[r * d + c] : (c - d == r ? 1.0 : 0.0);
+    double det = 1.0;
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < 2 * d; ++k) { double t = a[c][k]; a[c][k] = a[piv][k]; a[piv][k] = t; }
+            det = -det;
+        }
+        double p = a[c][c];
+        det *= p;
+        if (p == 0.0) return 0.0;
+        for (int k = 0; k < 2 * d; ++k) a[c][k] /= p;
+        for (int r = 0; r < d; ++r) {
+            if (r == c) continue;
+            double f = a[r][c];
+            for (int k = 0; k < 2 * d; ++k) a[r][k] -= f * a[c][k];
+        }
+    }
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) Ainv[r * d + c] = a[r][d + c];
+    return det;
+}
+
+static double det_of(int d, const double* A)
+{
+    if (d == 1) return A[0];
+    if (d == 2) return A[0] * A[3] - A[1] * A[2];
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+static void matmul(int d, const double* A, const double* B, double* C)
+{
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < d; ++k) s += A[r * d + k] * B[k * d + c];
+            C[r * d + c] = s;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Kernel summation, correction matrix, corrected gradient             */
+/* ------------------------------------------------------------------ */
+
+/* SPH approximation of f = 1 (Eq. 1 with f = 1; Table 1):
+ *   out_i = sum_{j in N(i) U {i}} W_ij V_j,  self term included.
+ * Pinned by Table 1 (lattice row) and the closed-form normalisation. */
+void or_kernel_sum(const or_box* b, int64_t n, const double* pos, int kernel, double h,
+                   int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                   const double* vol, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double s = 0.0, d[3];
+        int self_done = 0;
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            if (!self_done && j > i) { s += or_kernel_W(kernel, b->dim, h, 0.0) * vol[i]; self_done = 1; }
+            pair_vec(b, n, pos, i, j, d);
+            s += or_kernel_W(kernel, b->dim, h, sqrt(dist2(d))) * vol[j];
+        }
+        if (!self_done) s += or_kernel_W(kernel, b->dim, h, 0.0) * vol[i];
+        out[k] = s;
+    }
+}
+
+/* Kernel-gradient correction matrix, Eq. (9), Sec. 2.3.2:
+ *   M_i = sum_j r_ij (x) grad W_ij V_j,   B_i = -M_i^{-1}.
+ * Inverse by Gauss-Jordan with partial pivoting.  When
+ * |det M_i| < 1e-10 |tr M_i / d|^d the matrix is taken as degenerate and
+ * B_i = I is used (the paper gives no rule; this one is a reading).
+ * Writes B[k*d*d ...] and returns the number of degenerate rows.
+ * Pinned: B_i = I/m on lattices, linear-field exactness of the corrected
+ * gradient on jittered sets. */
+int64_t or_correction_B(const or_box* b, int64_t n, const double* pos, int kernel, double h,
+                        int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                        const double* vol, double* B)
+{
+    int dim = b->dim;
+    int64_t ndeg = 0;
+#pragma omp parallel for schedule(static) reduction(+ : ndeg)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double M[9] = {0}, d[3], g[3];
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            pair_vec(b, n, pos, i, j, d);
+            grad_w(kernel, dim, h, d, g);
+            for (int r = 0; r < dim; ++r)
+                for (int c = 0; c < dim; ++c) M[r * dim + c] += d[r] * g[c] * vol[j];
+        }
+        double tr = 0.0;
+        for (int r = 0; r < dim; ++r) tr += M[r * dim + r];
+        double scale = pow(fabs(tr / dim), dim);
+        double Minv[9];
+        double det = det_of(dim, M);
+        double* Bi = B + k * dim * dim;
+        if (!(fabs(det) >= 1e-10 * scale) || scale == 0.0) {
+            for (int r = 0; r < dim; ++r)
+                for (int c = 0; c < dim; ++c) Bi[r * dim + c] = (r == c) ? 1.0 : 0.0;
+            ndeg += 1;
+            continue;
+        }
+        invert(dim, M, Minv);
+        for (int r = 0; r < dim * dim; ++r) Bi[r] = -Minv[r];
+    }
+    return ndeg;
+}
+
+/* Corrected field gradient (Eq. 1 in its difference form, with the
+ * correction of Eq. 9):
+ *   grad f_i = B_i sum_j (f_j - f_i) grad W_ij V_j,     out[a*m + k].
+ * Pinned: exact for linear fields on any non-degenerate set. */
+void or_gradient(const or_box* b, int64_t n, const double* pos, int kernel, double h,
+                 int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                 const double* vol, const double* B, const double* f, double* out)
+{
+    int dim = b->dim;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double s[3] = {0, 0, 0}, d[3], g[3];
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            pair_vec(b, n, pos, i, j, d);
+            grad_w(kernel, dim, h, d, g);
+            for (int a = 0; a < dim; ++a) s[a] += (f[j] - f[i]) * g[a] * vol[j];
+        }
+        const double* Bi = B + i * dim * dim;
+        for (int a = 0; a < dim; ++a) {
+            double t = 0.0;
+            for (int c = 0; c < dim; ++c) t += Bi[a * dim + c] * s[c];
+            out[a * m + k] = t;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Eulerian weakly-compressible SPH with the linearised Riemann solver */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double c;       /* artificial sound speed */
+    double rho0;    /* EOS reference density: p = c^2 (rho - rho0), Eq. (18) */
+    double eta;     /* limiter coefficient of Eq. (27) (15 in the paper) */
+    double mu;      /* dynamic viscosity of the added viscous term (0: inviscid) */
+    double dt;      /* time step of the Heun integrator */
+} or_euler_params;
+
+/* Right-hand side of Eq. (19) for the mass and momentum rows, per unit
+ * volume:
+ *   d rho_i/dt      = -2 sum_j w_j (rho v)* . gradW'_ij
+ *   d (rho v)_i/dt  = -2 sum_j w_j [ (rho v (x) v)* + p* I ] . gradW'_ij
+ *                     + 2 mu sum_j w_j (v_i - v_j) (dW/dr)_ij / r_ij
+ * with gradW'_ij = (B_i + B_j)/2 gradW_ij (Eq. 28), the Riemann problem
+ * posed along n = r_ji / r (left state i, right state j), the linearised
+ * solver with its dissipation limiter (Eqs. 26-27), the interface velocity
+ *   v* = u* n + ((v_l + v_r)/2 - (u_l + u_r)/2 n)
+ * (the tangential part as in the HLLC state of Eq. 22) and the interface
+ * density from the EOS, rho* = rho0 + p* / c^2.  The viscous term is not in
+ * the paper (its examples state Re only); it is the standard SPH Laplacian.
+ * Optional abs-sum scales (sum_j |term_ij| per output component) are
+ * returned for the tolerance of the parity tests.
+ * Pinned: pairwise conservation, the central-flux special case, uniform
+ * state -> zero, and a hand-evaluated single pair. */
+void or_euler_rhs(const or_box* b, int64_t n, const double* pos, double h,
+                  int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                  const double* vol, const double* B, const or_euler_params* prm,
+                  const double* rho, const double* mom,
+                  double* drho, double* dmom, double* scale_rho, double* scale_mom)
+{
+    int dim = b->dim;
+    double c = prm->c, c2 = c * c;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double sr = 0.0, sm[3] = {0, 0, 0}, ar = 0.0, am[3] = {0, 0, 0};
+        double vi[3] = {0, 0, 0};
+        for (int a = 0; a < dim; ++a) vi[a] = mom[a * n + i] / rho[i];
+        double pi_ = c2 * (rho[i] - prm->rho0);
+        const double* Bi = B + i * dim * dim;
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            double d[3], g[3];
+            pair_vec(b, n, pos, i, j, d);
+            double r = grad_w(OR_WENDLAND, dim, h, d, g);
+            if (r == 0.0) continue;
+            const double* Bj = B + j * dim * dim;
+            double gc[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a)
+                for (int q = 0; q < dim; ++q) gc[a] += 0.5 * (Bi[a * dim + q] + Bj[a * dim + q]) * g[q];
+            double nrm[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) nrm[a] = -d[a] / r;
+            double vj[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) vj[a] = mom[a * n + j] / rho[j];
+            double pj = c2 * (rho[j] - prm->rho0);
+            double ul = 0.0, ur = 0.0;
+            for (int a = 0; a < dim; ++a) { ul += vi[a] * nrm[a]; ur += vj[a] * nrm[a]; }
+            double rhobar = 0.5 * (rho[i] + rho[j]);
+            double cbar = c;
+            double beta = prm->eta * fmax((ul - ur) / cbar, 0.0);
+            if (beta > 1.0) beta = 1.0;
+            double ustar = 0.5 * (ul + ur) + 0.5 * beta * beta * (pi_ - pj) / (rhobar * cbar);
+            double pstar = 0.5 * (pi_ + pj) + 0.5 * beta * rhobar * cbar * (ul - ur);
+            double vstar[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a)
+                vstar[a] = ustar * nrm[a] + (0.5 * (vi[a] + vj[a]) - 0.5 * (ul + ur) * nrm[a]);
+            double rhostar = prm->rho0 + pstar / c2;
+            double vg = 0.0;
+            for (int a = 0; a < dim; ++a) vg += vstar[a] * gc[a];
+            double tr = -2.0 * vol[j] * rhostar * vg;
+            sr += tr;
+            ar += fabs(tr);
+            double w1 = or_kernel_dWdr(OR_WENDLAND, dim, h, r);
+            for (int a = 0; a < dim; ++a) {
+                double tm = -2.0 * vol[j] * (rhostar * vstar[a] * vg + pstar * gc[a]);
+                double tv = 2.0 * prm->mu * vol[j] * (vi[a] - vj[a]) * w1 / r;
+                sm[a] += tm + tv;
+                am[a] += fabs(tm) + fabs(tv);
+            }
+        }
+        drho[k] = sr;
+        for (int a = 0; a < dim; ++a) dmom[a * m + k] = sm[a];
+        if (scale_rho) scale_rho[k] = ar;
+        if (scale_mom)
+            for (int a = 0; a < dim; ++a) scale_mom[a * m + k] = am[a];
+    }
+}
+
+/* Heun (two-stage, strong-stability-preserving) integration with fixed dt:
+ *   U* = U + dt R(U);   U <- (U + U* + dt R(U*)) / 2.
+ * The paper names no integrator; this is the reading used for the
+ * time-stepping parity.  rho, mom updated in place (full n). */
+void or_euler_heun(const or_box* b, int64_t n, const double* pos, double h,
+                   const int64_t* row_ptr, const int32_t* col,
+                   const double* vol, const double* B, const or_euler_params* prm,
+                   double* rho, double* mom, int64_t nsteps)
+{
+    int dim = b->dim;
+    double* r1 = (double*)malloc((size_t)n * sizeof(double));
+    double* m1 = (double*)malloc((size_t)n * dim * sizeof(double));
+    double* dr = (double*)malloc((size_t)n * sizeof(double));
+    double* dm = (double*)malloc((size_t)n * dim * sizeof(double));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        or_euler_rhs(b, n, pos, h, n, NULL, row_ptr, col, vol, B, prm, rho, mom, dr, dm, NULL, NULL);
+        for (int64_t i = 0; i < n; ++i) r1[i] = rho[i] + prm->dt * dr[i];
+        for (int64_t i = 0; i < n * dim; ++i) m1[i] = mom[i] + prm->dt * dm[i];
+        or_euler_rhs(b, n, pos, h, n, NULL, row_ptr, col, vol, B, prm, r1, m1, dr, dm, NULL, NULL);
+        for (int64_t i = 0; i < n; ++i) rho[i] = 0.5 * (rho[i] + r1[i] + prm->dt * dr[i]);
+        for (int64_t i = 0; i < n * dim; ++i) mom[i] = 0.5 * (mom[i] + m1[i] + prm->dt * dm[i]);
+    }
+    free(r1); free(m1); free(dr); free(dm);
+}
+
+/* ------------------------------------------------------------------ */
+/* Total Lagrangian SPH                                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double rho0;     /* reference density */
+    double E;        /* Young's modulus */
+    double nu;       /* Poisson ratio */
+    double dt;       /* time step */
+    int model;       /* 0: compressible neo-Hookean, 1: St. Venant-Kirchhoff (Eq. 30) */
+} or_tlsph_params;
+
+/* First Piola-Kirchhoff stress P = F S.
+ *  model 1 (Eq. 30): E = (F^T F - I)/2,  S = lambda tr(E) I + 2 G E.
+ *  model 0 (compressible neo-Hookean, the law the plate workload names):
+ *          S = G (I - C^{-1}) + lambda ln(J) C^{-1},  C = F^T F, J = det F.
+ *  lambda = E nu / ((1+nu)(1-2nu)), G = E / (2 (1+nu)). */
+void or_tlsph_stress(int dim, const or_tlsph_params* prm, const double* F, double* P)
+{
+    double lam = prm->E * prm->nu / ((1.0 + prm->nu) * (1.0 - 2.0 * prm->nu));
+    double G = prm->E / (2.0 * (1.0 + prm->nu));
+    double Ft[9], C[9], S[9];
+    for (int r = 0; r < dim; ++r)
+        for (int c = 0; c < dim; ++c) Ft[r * dim + c] = F[c * dim + r];
+    matmul(dim, Ft, F, C);
+    if (prm->model == 1) {
+        double Eg[9], tr = 0.0;
+        for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) Eg[r * dim + c] = 0.5 * (C[r * dim + c] - (r == c ? 1.0 : 0.0));
+        for (int r = 0; r < dim; ++r) tr += Eg[r * dim + r];
+        for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) S[r * dim + c] = (r == c ? lam * tr : 0.0) + 2.0 * G * Eg[r * dim + c];
+    } else {
+        double Ci[9];
+        invert(dim, C, Ci);
+        double J = det_of(dim, F);
+        double lnJ = log(J);
+        for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c)
+                S[r * dim + c] = G * ((r == c ? 1.0 : 0.0) - Ci[r * dim + c]) + lam * lnJ * Ci[r * dim + c];
+    }
+    matmul(dim, F, S, P);
+}
+
+/* Eqs. (31)-(32), Sec. 3.2:
+ *   dF_i/dt = [ sum_j V0_j (v_j - v_i) (x) grad0 W_ij ] B0_i
+ *   rho0 a_i = sum_j (P_i B0_i^T + P_j B0_j^T) grad0 W_ij V0_j
+ * (the dot in Eq. 32 is an outer product; this is the form that is exact
+ * for linear velocity fields).  Geometry (pos0, neighbours, B0) is the
+ * reference configuration.  acc of rows with fixed[i] != 0 is set to 0.
+ * dFdt[k*d*d], acc[a*m + k].  Pinned: linear exactness, conservation,
+ * F = I -> a = 0. */
+void or_tlsph_rhs(const or_box* b, int64_t n, const double* pos0, double h,
+                  int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                  const double* vol0, const double* B0, const or_tlsph_params* prm,
+                  const double* vel, const double* F, const int32_t* fixed,
+                  double* dFdt, double* acc, double* scale_acc)
+{
+    int dim = b->dim, dd = dim * dim;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double L[9] = {0}, a[3] = {0, 0, 0}, sa[3] = {0, 0, 0};
+        double Pi[9], Ai[9], Bt[9];
+        or_tlsph_stress(dim, prm, F + i * dd, Pi);
+        for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) Bt[r * dim + c] = B0[i * dd + c * dim + r];
+        matmul(dim, Pi, Bt, Ai);
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            double d[3], g[3];
+            pair_vec(b, n, pos0, i, j, d);
+            grad_w(OR_WENDLAND, dim, h, d, g);
+            for (int r = 0; r < dim; ++r)
+                for (int c = 0; c < dim; ++c)
+                    L[r * dim + c] += vol0[j] * (vel[r * n + j] - vel[r * n + i]) * g[c];
+            double Pj[9], Aj[9], Btj[9];
+            or_tlsph_stress(dim, prm, F + j * dd, Pj);
+            for (int r = 0; r < dim; ++r)
+                for (int c = 0; c < dim; ++c) Btj[r * dim + c] = B0[j * dd + c * dim + r];
+            matmul(dim, Pj, Btj, Aj);
+            for (int r = 0; r < dim; ++r) {
+                double t = 0.0, ta = 0.0;
+                for (int c = 0; c < dim; ++c) {
+                    double e = (Ai[r * dim + c] + Aj[r * dim + c]) * g[c] * vol0[j];
+                    t += e;
+                    ta += fabs(e);
+                }
+                a[r] += t;
+                sa[r] += ta;
+            }
+        }
+        matmul(dim, L, B0 + i * dd, dFdt + k * dd);
+        int fx = fixed ? fixed[i] : 0;
+        for (int r = 0; r < dim; ++r) {
+            acc[r * m + k] = fx ? 0.0 : a[r] / prm->rho0;
+            if (scale_acc) scale_acc[r * m + k] = sa[r] / prm->rho0;
+        }
+    }
+}
+
+/* One kick-drift-kick step with fixed dt (the paper gives no integrator):
+ *   v^{1/2} = v + dt/2 a;  x += dt v^{1/2};  F += dt dF/dt(v^{1/2});
+ *   a <- a(F);  v = v^{1/2} + dt/2 a.
+ * Rows with fixed[i] != 0 keep x, v = 0 and F = I; their a is 0.
+ * acc must hold a(F) on entry (from or_tlsph_rhs). All arrays full n. */
+void or_tlsph_step(const or_box* b, int64_t n, const double* pos0, double h,
+                   const int64_t* row_ptr, const int32_t* col,
+                   const double* vol0, const double* B0, const or_tlsph_params* prm,
+                   const int32_t* fixed, double* pos, double* vel, double* F, double* acc,
+                   int64_t nsteps)
+{
+    int dim = b->dim, dd = dim * dim;
+    double* vh = (double*)malloc((size_t)n * dim * sizeof(double));
+    double* dF = (double*)malloc((size_t)n * dd * sizeof(double));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < dim; ++a) {
+                int fx = fixed ? fixed[i] : 0;
+                vh[a * n + i] = fx ? 0.0 : vel[a * n + i] + 0.5 * prm->dt * acc[a * n + i];
+            }
+        for (int64_t i = 0; i < n; ++i) {
+            if (fixed && fixed[i]) continue;
+            for (int a = 0; a < dim; ++a) pos[a * n + i] += prm->dt * vh[a * n + i];
+        }
+        or_tlsph_rhs(b, n, pos0, h, n, NULL, row_ptr, col, vol0, B0, prm, vh, F, fixed, dF, acc, NULL);
+        for (int64_t i = 0; i < n; ++i) {
+            if (fixed && fixed[i]) continue;
+            for (int e = 0; e < dd; ++e) F[i * dd + e] += prm->dt * dF[i * dd + e];
+        }
+        /* a(F_new): the dF output of this call is discarded */
+        or_tlsph_rhs(b, n, pos0, h, n, NULL, row_ptr, col, vol0, B0, prm, vh, F, fixed, dF, acc, NULL);
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < dim; ++a) {
+                int fx = fixed ? fixed[i] : 0;
+                vel[a * n + i] = fx ? 0.0 : vh[a * n + i] + 0.5 * prm->dt * acc[a * n + i];
+            }
+    }
+    free(vh);
+    free(dF);
+}
+
+/* ------------------------------------------------------------------ */
+/* Laguerre-Gauss particle relaxation inside a sphere                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double p0;        /* background pressure of Eq. (7) */
+    double rho;       /* density of Eq. (7) */
+    double h;         /* smoothing length; LG support radius 2h */
+    double center[3]; /* sphere centre */
+    double radius;    /* sphere radius; SDF phi = |r - c| - R */
+} or_relax_params;
+
+/* Exterior kernel-gradient integral for a sphere (a reading: the paper's
+ * relaxation, Eq. 7, has no boundary term; without one the truncated
+ * support at the surface pushes particles out).
+ *   t_i = int_{|r - c| > R} grad_i W(r_i - r) dV = T(rho_i) e_i,
+ * rho_i = |r_i - c|, e_i = (r_i - c)/rho_i.  In spherical coordinates about
+ * r_i only the radial component survives:
+ *   T = pi int_0^{2h} (-dW/ds) s^2 (1 - clamp(u0, -1, 1)^2) ds,
+ *   u0 = (R^2 - rho^2 - s^2) / (2 rho s).
+ * Composite Simpson rule with 2000 panels on [max(0, R - rho), 2h].
+ * Pinned against the half-space limit and a direct 3-D quadrature. */
+double or_relax_tail(const or_relax_params* prm, double rho_c)
+{
+    double h = prm->h, R = prm->radius;
+    if (rho_c <= 0.0) return 0.0;
+    double s0 = R - rho_c;
+    if (s0 < 0.0) s0 = 0.0;
+    double s1 = 2.0 * h;
+    if (s0 >= s1) return 0.0;
+    const int NP = 2000;
+    double hs = (s1 - s0) / NP, acc = 0.0;
+    for (int k = 0; k <= NP; ++k) {
+        double s = s0 + hs * k;
+        double f = 0.0;
+        if (s > 0.0) {
+            double u0 = (R * R - rho_c * rho_c - s * s) / (2.0 * rho_c * s);
+            if (u0 < -1.0) u0 = -1.0;
+            if (u0 > 1.0) u0 = 1.0;
+            f = -or_kernel_dWdr(OR_LAGUERRE_GAUSS, 3, h, s) * s * s * (1.0 - u0 * u0);
+        }
+        double wgt = (k == 0 || k == NP) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        acc += wgt * f;
+    }
+    return M_PI * acc * hs / 3.0;
+}
+
+/* Residual force of the relaxation, Eq. (7) with the LG kernel:
+ *   g_i = sum_j grad W^LG_ij V_j + T(rho_i) e_i
+ * (a_i = -(2 p0 / rho) g_i).  Neighbours at cutoff 2h, 3-D, non-periodic.
+ * g[a*m + k]. */
+void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_params* prm,
+                int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                const double* vol, double* g, double* scale_g)
+{
+    int dim = b->dim;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double s[3] = {0, 0, 0}, sa[3] = {0, 0, 0}, d[3], gw[3];
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            pair_vec(b, n, pos, i, j, d);
+            grad_w(OR_LAGUERRE_GAUSS, dim, prm->h, d, gw);
+            for (int a = 0; a < dim; ++a) { s[a] += gw[a] * vol[j]; sa[a] += fabs(gw[a] * vol[j]); }
+        }
+        double e[3] = {0, 0, 0}, rc = 0.0;
+        for (int a = 0; a < dim; ++a) { e[a] = pos[a * n + i] - prm->center[a]; rc += e[a] * e[a]; }
+        rc = sqrt(rc);
+        double T = or_relax_tail(prm, rc);
+        for (int a = 0; a < dim; ++a) {
+            double t = rc > 0.0 ? T * e[a] / rc : 0.0;
+            g[a * m + k] = s[a] + t;
+            if (scale_g) scale_g[a * m + k] = sa[a] + fabs(t);
+        }
+    }
+}
+
+/* One relaxation iteration on the full set (neighbours passed in):
+ *   g from or_relax_g; a = -(2 p0/rho) g; dt = 0.25 sqrt(h / max|a|);
+ *   r += a dt^2 / 2; particles with phi > 0 are projected back onto the
+ *   surface, r -= phi grad(phi).
+ * Returns the residue R = sqrt(mean_i |h g_i|^2) of the positions on entry.
+ * (Step rule, bounding and residue are readings: the paper gives none.) */
+double or_relax_step(const or_box* b, int64_t n, double* pos, const or_relax_params* prm,
+                     const int64_t* row_ptr, const int32_t* col, const double* vol,
+                     double* g_out)
+{
+    int dim = b->dim;
+    double* g = g_out ? g_out : (double*)malloc((size_t)n * dim * sizeof(double));
+    or_relax_g(b, n, pos, prm, n, NULL, row_ptr, col, vol, g, NULL);
+    double res = 0.0, amax = 0.0, cf = 2.0 * prm->p0 / prm->rho;
+    for (int64_t i = 0; i < n; ++i) {
+        double g2 = 0.0;
+        for (int a = 0; a < dim; ++a) g2 += g[a * n + i] * g[a * n + i];
+        res += prm->h * prm->h * g2;
+        double am = cf * sqrt(g2);
+        if (am > amax) amax = am;
+    }
+    res = sqrt(res / (double)(n > 0 ? n : 1));
+    if (amax > 0.0) {
+        double dt = 0.25 * sqrt(prm->h / amax);
+        for (int64_t i = 0; i < n; ++i) {
+            double e[3] = {0, 0, 0}, rc = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                pos[a * n + i] += 0.5 * (-cf * g[a * n + i]) * dt * dt;
+                e[a] = pos[a * n + i] - prm->center[a];
+                rc += e[a] * e[a];
+            }
+            rc = sqrt(rc);
+            double phi = rc - prm->radius;
+            if (phi > 0.0 && rc > 0.0)
+                for (int a = 0; a < dim; ++a) pos[a * n + i] -= phi * e[a] / rc;
+        }
+    }
+    if (!g_out) free(g);
+    return res;
+}
