@@ -1,0 +1,154 @@
+#!/usr/bin/env python3
+"""Benchmark: particle-neighbour interactions/s of the Eulerian SPH hot path.
+
+Workload: 2-D Taylor-Green vortex, 512 x 512 = 262,144 particles on the
+periodic unit square, h = 1.3 dx, c = 10, Re = 100 (nu = 0.01), Heun (RK2)
+steps with fixed dt.  One step = two evaluations of the corrected
+Riemann-flux RHS over every directed neighbour pair.  The primary line is the
+truncated kernel (cut-off 1.6h); the standard kernel (2h) runs on the same
+state for the speed ratio.
+
+Printed: ONE JSON line (see keys below), with
+  roofline      the dominant kernel (the Heun stage kernel) against HBM,
+  cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-neighbour interactions/s, 1.6h vs 2h; relax time-to-residue, MLP vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def stage_bytes_2d(n: int, nnz: int) -> float:
+    """Algorithmic HBM bytes of one Heun stage launch (2-D), averaged over the
+    two stages: per particle the geometry record (16 B) and B record (8 B),
+    the state record (16 B), the stage-start record (16 B, second stage
+    only), the output record (16 B), the row offset (8 B); per pair the
+    column index (4 B).  Neighbour records are re-reads served by caches and
+    are not counted."""
+    per_particle = 16 + 8 + 16 + 16 + 8 + 0.5 * 16
+    return n * per_particle + 4.0 * nnz
+
+
+def run_gpu(w, kappa, steps, warmup):
+    import torch
+
+    from paper_2405_05155_amd import sph as S
+    f = w.fields
+    ctx = S.Context(2)
+    ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa), torch.as_tensor(w.pos, device="cuda"))
+    ctx.neighbors()
+    vol = torch.as_tensor(w.vol, device="cuda")
+    ctx.correction_B(vol)
+    prm = S.euler_params(c=f["c"], rho0=f["rho0_eos"], rho_ref=f["rho_ref"], eta=f["eta"], mu=f["mu"],
+                         dt=w.meta["dt"])
+    d = torch.as_tensor(f["drho"], device="cuda").clone()
+    m = torch.as_tensor(f["mom"], device="cuda").clone()
+    if warmup > 0:
+        ctx.euler_step(prm, d, m, warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.euler_step(prm, d, m, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nnz = ctx.nnz
+    ctx.close()
+    return {"ms": ms, "nnz": nnz, "ms_per_step": ms / steps, "launches": 2 * steps,
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+
+
+def run_cpu_baseline(w, kappa, budget_s):
+    import numpy as np
+
+    import oracle as O
+    f = w.fields
+    box = O.make_box(2)
+    rc = kappa * w.h
+    rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+    B, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    prm = O.euler_params(c=f["c"], rho0=f["rho0_eos"], eta=f["eta"], mu=f["mu"], dt=w.meta["dt"])
+    rho = f["rho_ref"] + f["drho"].astype(np.float64)
+    mom = f["mom"].astype(np.float64)
+    t0 = time.perf_counter()
+    rho, mom = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, B, prm, rho, mom, 1)
+    t1 = time.perf_counter() - t0
+    steps = max(1, min(200, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    O.euler_heun(box, w.pos, w.h, rp, col, w.vol, B, prm, rho, mom, steps)
+    dt = time.perf_counter() - t0
+    nnz = int(rp[-1])
+    return {"value": 2.0 * nnz * steps / dt, "unit": "interactions/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{steps} Heun steps of the same 512^2 workload at kappa={kappa} (FP64 oracle, "
+                      f"{dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
+    ap.add_argument("--nside", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only: the hot path is single-GPU (see the sharding note in the "
+              "design document); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    w = I.taylor_green_2d(nside=args.nside)
+
+    tw = run_gpu(w, 1.6, args.steps, args.warmup)
+    sw = run_gpu(w, 2.0, args.steps, args.warmup)
+
+    launch_s = tw["ms"] * 1e-3 / tw["launches"]
+    bytes_launch = stage_bytes_2d(w.n, tw["nnz"])
+    achieved = bytes_launch / launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": tw["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": tw["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"taylor_green_2d_{args.nside}x{args.nside}_heun_kappa1.6",
+                   "n_particles": w.n, "h_over_dx": 1.3, "c": 10.0, "nu": 0.01, "dt": w.meta["dt"],
+                   "nnz_1.6h": tw["nnz"], "nnz_2h": sw["nnz"]},
+        "sw_2h": {"value": sw["interactions_per_s"], "ms_per_step": sw["ms_per_step"]},
+        "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_euler<2,stage> (Heun stage, 1.6h)",
+                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = run_cpu_baseline(w, 1.6, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

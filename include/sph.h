@@ -1,0 +1,188 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) truncated-Wendland SPH hot path.
+ *
+ * Method: Wang, Zhang, Haidn & Hu, "An efficient truncation scheme for
+ * Eulerian and total Lagrangian SPH methods" (arXiv:2405.05155).
+ *
+ * General conventions
+ *  - Every array argument is a DEVICE pointer (hipMalloc'd or a PyTorch CUDA
+ *    tensor) owned by the caller, unless its comment says "(host)".
+ *  - Positions and vectors are SoA FP32, x[a*n + i] for axis a.  Tensors are
+ *    row-major FP32 [n][dim][dim].  Indices are always the caller's
+ *    particle order; the library's internal cell order is invisible.
+ *  - A context (sph_ctx) is bound to the device that is current when it is
+ *    created and to one HIP stream; every call enqueues its kernels on that
+ *    stream and returns before they complete, except the calls that return a
+ *    host count (they synchronise the stream).  A context is not
+ *    thread-safe.  It owns only scratch memory (cell table, neighbour list,
+ *    packed per-particle records).
+ *  - Every call returns an int status (SPH_OK = 0).  Arguments are checked
+ *    on the host before anything is enqueued; on error nothing is enqueued
+ *    and sph_last_error() describes the problem.  Asynchronous HIP failures
+ *    surface as SPH_ERR_HIP on a later call.
+ *  - Kernel-gradient sign: grad W_ij is the gradient with respect to r_i,
+ *    dW/dr (r_i - r_j)/|r_i - r_j| (the sign under which Eqs. 7, 9, 19 and
+ *    31-32 of the paper are consistent).
+ *  - Precision: pair arithmetic is FP32 with compensated (Kahan) per-particle
+ *    sums; the correction matrices are inverted in FP64 and the relaxation
+ *    residue is reduced in FP64.
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sph_ctx sph_ctx;
+
+enum {
+    SPH_OK = 0,
+    SPH_ERR_ARG = -1,       /* invalid argument (message says which) */
+    SPH_ERR_CAPACITY = -2,  /* caller buffer too small; the needed size is returned */
+    SPH_ERR_HIP = -3,       /* a HIP runtime call failed */
+    SPH_ERR_STATE = -5      /* call out of order (e.g. no configuration bound) */
+};
+
+enum { SPH_WENDLAND = 0, SPH_LAGUERRE_GAUSS = 1 };
+
+/* Kernels.
+ *  SPH_WENDLAND (Eq. 6, Sec. 2.3.1): W = a_d (1 - q/2)^4 (2q + 1), q = r/h,
+ *    a_2 = 7/(4 pi h^2), a_3 = 21/(16 pi h^3); support r <= kappa h with
+ *    kappa = 2 (standard) or 1.6 (truncated, Sec. 2.3.1), a hard cut with no
+ *    renormalisation.
+ *  SPH_LAGUERRE_GAUSS (Eq. 8, Sec. 2.3.2): W = a_d h^-d (1 - q^2 + q^4/6)
+ *    exp(-q^2), a_2 = 3/pi, a_3 = 8/pi^(3/2), support r <= 2h.  (The
+ *    printed polynomial (1 - q^2/2 + q^4/6) does not normalise with the
+ *    printed a_d; this form does.)
+ */
+typedef struct {
+    int dim;            /* 2 or 3 */
+    int periodic[3];    /* nonzero: periodic axis (minimum image) */
+    double lo[3];       /* box; particles must lie in [lo, hi] (periodic: [lo, hi)) */
+    double hi[3];
+    double h;           /* smoothing length, > 0 */
+    double kappa;       /* cut-off factor: neighbours are j != i with |r_ij| <= kappa h */
+    int kernel;         /* SPH_WENDLAND or SPH_LAGUERRE_GAUSS */
+} sph_domain;
+
+/* Create a context for `dim` = 2 or 3 on the current device, enqueueing on
+ * `hip_stream` (a hipStream_t; NULL = the null stream). */
+int sph_ctx_create(sph_ctx** out, int dim, void* hip_stream);
+void sph_ctx_destroy(sph_ctx* ctx);
+/* Message of the last non-OK return of this context (never NULL). */
+const char* sph_last_error(const sph_ctx* ctx);
+/* Re-bind the context to another stream of the same device. */
+int sph_set_stream(sph_ctx* ctx, void* hip_stream);
+
+/* ---------------------------------------------------------------- neighbours
+ * sph_build_cells: bind a particle configuration.  Bins the n positions
+ * (FP32 SoA [dim][n]) into a uniform grid of cells with edge >= kappa h
+ * (counting sort by cell, members of each cell in ascending index), then
+ * builds the neighbour set N(i) = {j != i : |r_ij|^2 <= (kappa h)^2} of every
+ * particle (the compact support of Eq. 5 with r = kappa h inside), the
+ * squared distance evaluated in FP64 from the FP32 inputs as
+ * ((dx*dx + dy*dy) + dz*dz) with the minimum image on periodic axes and
+ * (kappa h)^2 computed once in FP64 on the host.  Stored as CSR in the
+ * caller's order with each row ascending.  Synchronises once (to size the
+ * list).  Periodic axes need hi - lo >= 3 (kappa h) (1 + 1e-3).
+ * The positions are copied: the caller may reuse `pos` afterwards.
+ * Invalidates the cached correction geometry. */
+int sph_build_cells(sph_ctx* ctx, const sph_domain* dom, int32_t n, const float* pos);
+
+/* Copy the neighbour CSR of the bound configuration: row_ptr int64 [n+1],
+ * col int32 [nnz].  *nnz (host) receives the entry count.  If cap < nnz
+ * nothing is written and SPH_ERR_CAPACITY is returned. */
+int sph_neighbors(sph_ctx* ctx, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
+
+/* ---------------------------------------------------------------- kernel sums
+ * SPH approximation of f = 1 (Eq. 1 with f = 1; the quantity of Table 1):
+ *   out_i = sum_{j in N(i)} W_ij V_j + W(0) V_i      (self term included).
+ * vol FP32 [n], out FP32 [n].  Uses the domain's kernel. */
+int sph_kernel_sum(sph_ctx* ctx, const float* vol, float* out);
+
+/* Kernel-gradient correction matrix (Eq. 9, Sec. 2.3.2):
+ *   M_i = sum_j r_ij (x) grad W_ij V_j   (FP32 Kahan sums),  B_i = -M_i^{-1}
+ * inverted in FP64 (adjugate / determinant).  If |det M_i| <
+ * 1e-10 |tr M_i / dim|^dim the row is degenerate and B_i = I.
+ * B: FP32 [n][dim][dim] (required); B64: FP64 copy (nullable);
+ * n_degenerate (host, nullable): count of degenerate rows (synchronises).
+ * Also caches (position, V_i, B_i) in the context for sph_gradient,
+ * sph_euler_* and sph_tlsph_*. */
+int sph_correction_B(sph_ctx* ctx, const float* vol, float* B, double* B64, int32_t* n_degenerate);
+
+/* Cache caller-supplied volumes and matrices instead (e.g. B = I for the
+ * uncorrected "without B" variants).  B FP32 [n][dim][dim], assumed symmetric
+ * (only the upper triangle is read). */
+int sph_set_correction(sph_ctx* ctx, const float* vol, const float* B);
+
+/* Corrected field gradient (Eq. 1 in difference form with Eq. 9):
+ *   grad_i = B_i sum_j (f_j - f_i) grad W_ij V_j.
+ * f FP32 [n]; grad FP32 [dim][n].  Needs a cached correction. */
+int sph_gradient(sph_ctx* ctx, const float* f, float* grad);
+
+/* ---------------------------------------------------------------- Eulerian SPH
+ * Weakly-compressible Eulerian SPH, Eq. (19) (mass and momentum rows) with
+ * the corrected gradient of Eq. (28), the linearised Riemann solver and its
+ * limiter (Eqs. 26-27) posed along n = (r_j - r_i)/r (left state i), the
+ * interface velocity v* = u* n + ((v_l+v_r)/2 - (u_l+u_r)/2 n) and density
+ * rho* = rho0 + p* / c^2, EOS p = c^2 (rho - rho0) (Eq. 18), plus the viscous
+ * term 2 mu sum_j V_j (v_i - v_j) (dW/dr)/r (Wendland kernel only).
+ * State: drho = rho - rho_ref (FP32 [n]; storing the deviation keeps FP32
+ * resolution for small density changes) and mom = rho v (FP32 [dim][n]). */
+typedef struct {
+    double c;        /* sound speed */
+    double rho0;     /* EOS reference density */
+    double rho_ref;  /* state offset: rho = rho_ref + drho */
+    double eta;      /* limiter coefficient of Eq. (27); the paper uses 15 */
+    double mu;       /* dynamic viscosity (0: inviscid) */
+    double dt;       /* time step for sph_euler_step */
+} sph_euler_params;
+
+/* Rates per unit volume: drho_dt FP32 [n], dmom_dt FP32 [dim][n]. */
+int sph_euler_rhs(sph_ctx* ctx, const sph_euler_params* prm, const float* drho, const float* mom,
+                  float* drho_dt, float* dmom_dt);
+
+/* nsteps Heun steps with fixed dt, in place:
+ *   U* = U + dt R(U);  U <- (U + U* + dt R(U*)) / 2.
+ * The state is packed once into context scratch, advanced there, and
+ * unpacked into drho, mom at the end. */
+int sph_euler_step(sph_ctx* ctx, const sph_euler_params* prm, float* drho, float* mom, int32_t nsteps);
+
+/* ---------------------------------------------------------------- total Lagrangian SPH
+ * Sec. 3.2, with the bound configuration as the reference configuration
+ * (positions, V0, B0 from the cached correction):
+ *   dF_i/dt = [ sum_j V0_j (v_j - v_i) (x) grad0 W_ij ] B0_i          (Eq. 32)
+ *   rho0 a_i = sum_j (P_i B0_i^T + P_j B0_j^T) grad0 W_ij V0_j         (Eq. 31)
+ * P = F S with S from model 0 (compressible neo-Hookean:
+ * S = G (I - C^-1) + lambda ln J C^-1, C = F^T F, J = det F) or model 1
+ * (St. Venant-Kirchhoff, Eq. 30).  lambda = E nu/((1+nu)(1-2nu)),
+ * G = E/(2(1+nu)).  3-D only. */
+typedef struct {
+    double rho0;
+    double E;
+    double nu;
+    double dt;       /* for sph_tlsph_step */
+    int model;       /* 0 neo-Hookean, 1 St. Venant-Kirchhoff */
+} sph_tlsph_params;
+
+/* vel FP32 [3][n], F FP32 [n][3][3], fixed int32 [n] (nullable; rows with
+ * fixed[i] != 0 get acc = 0), dF_dt FP32 [n][3][3], acc FP32 [3][n]. */
+int sph_tlsph_rhs(sph_ctx* ctx, const sph_tlsph_params* prm, const float* vel, const float* F,
+                  const int32_t* fixed, float* dF_dt, float* acc);
+
+/* nsteps kick-drift-kick steps with fixed dt, in place:
+ *   v+ = v + dt/2 a;  x += dt v+;  F += dt dF/dt(v+);  a = a(F);  v = v+ + dt/2 a.
+ * acc must hold a(F) on entry (sph_tlsph_rhs) and holds it on exit.  Rows
+ * with fixed[i] != 0 keep x, v = 0, F and a = 0.  pos FP32 [3][n] (current
+ * positions; the reference positions are the bound configuration). */
+int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fixed, float* pos,
+                   float* vel, float* F, float* acc, int32_t nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_MI355X_H */

@@ -64,6 +64,7 @@ def lib():
         path = _LIB_PATH if os.path.exists(_LIB_PATH) else build()
         L = C.CDLL(path)
         d, i64, i32, vp = C.c_double, C.c_int64, C.c_int, C.c_void_p
+        L.or_num_threads.restype = C.c_int
         L.or_kernel_W.restype = d
         L.or_kernel_W.argtypes = [i32, i32, d, d]
         L.or_kernel_dWdr.restype = d
@@ -72,7 +73,7 @@ def lib():
         L.or_neighbors_brute.restype = i64
         L.or_neighbors_brute.argtypes = [vp, i64, vp, d, i64, vp, vp, vp, i64]
         L.or_neighbors_grid.restype = i64
-        L.or_neighbors_grid.argtypes = [vp, i64, vp, d, d, vp, vp, i64]
+        L.or_neighbors_grid.argtypes = [vp, i64, vp, d, d, i64, vp, vp, vp, i64]
         L.or_kernel_sum.argtypes = [vp, i64, vp, i32, d, i64, vp, vp, vp, vp, vp]
         L.or_correction_B.restype = i64
         L.or_correction_B.argtypes = [vp, i64, vp, i32, d, i64, vp, vp, vp, vp, vp]
@@ -118,6 +119,10 @@ def _rows(rows, n):
     return r, int(r.shape[0])
 
 
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
 # ---------------------------------------------------------------- kernels
 
 def kernel_W(kernel, dim, h, r):
@@ -148,13 +153,15 @@ def neighbors_brute(box, pos, rc2, rows=None):
     return rp, col[:nnz]
 
 
-def neighbors_grid(box, pos, rc, rc2):
+def neighbors_grid(box, pos, rc, rc2, rows=None):
+    """Same set as neighbors_brute, found through a uniform cell grid."""
     pos = _f64(pos)
     n = pos.shape[1]
-    rp = np.zeros(n + 1, dtype=np.int64)
-    nnz = lib().or_neighbors_grid(C.byref(box), n, _p(pos), rc, rc2, _p(rp), None, 0)
+    r, m = _rows(rows, n)
+    rp = np.zeros(m + 1, dtype=np.int64)
+    nnz = lib().or_neighbors_grid(C.byref(box), n, _p(pos), rc, rc2, m, _p(r), _p(rp), None, 0)
     col = np.empty(max(nnz, 1), dtype=np.int32)
-    lib().or_neighbors_grid(C.byref(box), n, _p(pos), rc, rc2, _p(rp), _p(col), nnz)
+    lib().or_neighbors_grid(C.byref(box), n, _p(pos), rc, rc2, m, _p(r), _p(rp), _p(col), nnz)
     return rp, col[:nnz]
 
 

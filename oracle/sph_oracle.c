@@ -30,6 +30,7 @@
  * see the header comment of each function for what pins it.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -46,6 +47,9 @@ typedef struct {
 } or_box;
 
 enum { OR_WENDLAND = 0, OR_LAGUERRE_GAUSS = 1 };
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Kernels                                                             */
@@ -201,7 +205,7 @@ static int cmp_i32(const void* a, const void* b)
  * an axis has fewer than three cells), then the same test as the brute
  * force, then each row sorted ascending.  Pinned against or_neighbors_brute. */
 int64_t or_neighbors_grid(const or_box* b, int64_t n, const double* pos, double rc, double rc2,
-                          int64_t* row_ptr, int32_t* col, int64_t cap)
+                          int64_t m, const int64_t* rows, int64_t* row_ptr, int32_t* col, int64_t cap)
 {
     int dim = b->dim;
     int64_t nc[3] = {1, 1, 1};
@@ -239,17 +243,18 @@ int64_t or_neighbors_grid(const or_box* b, int64_t n, const double* pos, double 
         free(fill);
     }
 
-    int64_t* cnt = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t* cnt = (int64_t*)calloc((size_t)(m > 0 ? m : 1), sizeof(int64_t));
     int64_t nnz = 0;
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1) {
             row_ptr[0] = 0;
-            for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
-            nnz = row_ptr[n];
+            for (int64_t k = 0; k < m; ++k) row_ptr[k + 1] = row_ptr[k] + cnt[k];
+            nnz = row_ptr[m];
             if (!col || nnz > cap) break;
         }
 #pragma omp parallel for schedule(dynamic, 64)
-        for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = 0; k < m; ++k) {
+            int64_t i = rows ? rows[k] : k;
             int64_t cells[27];
             int ncells = 0;
             int64_t lim[3] = {0, 0, 0};
@@ -276,7 +281,7 @@ int64_t or_neighbors_grid(const or_box* b, int64_t n, const double* pos, double 
                         if (!dup) cells[ncells++] = cidx;
                     }
             int64_t c = 0;
-            int64_t p = pass ? row_ptr[i] : 0;
+            int64_t p = pass ? row_ptr[k] : 0;
             double d[3];
             for (int u = 0; u < ncells; ++u) {
                 for (int64_t s = cstart[cells[u]]; s < cstart[cells[u] + 1]; ++s) {
@@ -290,7 +295,7 @@ int64_t or_neighbors_grid(const or_box* b, int64_t n, const double* pos, double 
                 }
             }
             if (pass) qsort(col + p, (size_t)c, sizeof(int32_t), cmp_i32);
-            else cnt[i] = c;
+            else cnt[k] = c;
         }
     }
     free(cnt);

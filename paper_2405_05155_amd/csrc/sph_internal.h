@@ -1,0 +1,175 @@
+// sph_internal.h -- context, scratch buffers and device helpers shared by the
+// HIP translation units of libsph.  Not installed; the public ABI is sph.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/sph.h"
+
+// ------------------------------------------------------------------ host side
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need) {
+        if (need <= bytes && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            if (e != hipSuccess) return e;
+            p = nullptr;
+            bytes = 0;
+        }
+        size_t b = need < 256 ? 256 : need;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-axis geometry passed by value to kernels.
+struct BoxArgs {
+    float lo[3];
+    float L[3];
+    float halfL[3];
+    float inv_cell[3];  // nc / L
+    int nc[3];
+    int periodic[3];
+    double Ld[3];       // FP64 box lengths for the exact neighbour test
+    double halfLd[3];
+};
+
+struct sph_ctx {
+    int dim = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char err[1024] = {0};
+
+    // bound configuration
+    bool bound = false;
+    sph_domain dom{};
+    int32_t n = 0;
+    double rc = 0.0, rc2 = 0.0;
+    BoxArgs box{};
+    int64_t ncell = 0;
+    int64_t nnz = 0;
+
+    DevBuf pos4;        // float4 [n] (x, y, z, 0), caller order
+    DevBuf cell_of;     // int32 [n]
+    DevBuf slot;        // int32 [n]
+    DevBuf cell_start;  // int32 [ncell + 1]
+    DevBuf sorted;      // float4 [n] (x, y, z, bits(index)) in cell order
+    DevBuf cnt;         // int32 [n]
+    DevBuf row_ptr;     // int64 [n + 1]
+    DevBuf col;         // int32 [nnz]
+    DevBuf scan_tmp;    // block sums of the scans
+    DevBuf counter;     // small device counters / reductions
+
+    // cached corrected geometry: (position, V, B upper triangle)
+    bool geo_valid = false;
+    DevBuf geo0;  // float4 [n]: 3-D (x, y, z, V); 2-D (x, y, V, B00)
+    DevBuf geo1;  // float4 [n]: 3-D (B00, B01, B02, B11); 2-D float2 (B01, B11)
+    DevBuf geo2;  // float2 [n]: 3-D (B12, B22)
+
+    // state scratch
+    DevBuf ua, ub;      // float4 [n] packed states
+    DevBuf ta, tb, tc;  // misc per-particle scratch
+};
+
+int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
+
+#define SPH_HIP(ctx, expr)                                                                     \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return sph_fail((ctx), SPH_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+    } while (0)
+
+#define SPH_LAUNCH_CHECK(ctx)                                                                      \
+    do {                                                                                           \
+        hipError_t _e = hipGetLastError();                                                         \
+        if (_e != hipSuccess)                                                                      \
+            return sph_fail((ctx), SPH_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(_e)); \
+    } while (0)
+
+// exclusive scan of int32 counts into int32 or int64 offsets, out[n] = total
+int sph_scan_i32_to_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
+int sph_scan_i32_to_i64(sph_ctx* c, const int32_t* in, int64_t* out, int64_t n);
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+// ------------------------------------------------------------------ device side
+
+// Compensated (Kahan) accumulator.  The running estimate of the sum is
+// s - c (c holds the rounding error of the last addition, with sign).
+struct Kahan {
+    float s, c;
+    __device__ __forceinline__ void init(float v = 0.f) { s = v; c = 0.f; }
+    __device__ __forceinline__ void add(float x) {
+        float y = x - c;
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ float value() const { return s - c; }
+    __device__ __forceinline__ double value64() const { return (double)s - (double)c; }
+};
+
+__device__ __forceinline__ float min_image(float d, float L, float halfL, int periodic) {
+    if (periodic) {
+        if (d > halfL) d -= L;
+        else if (d < -halfL) d += L;
+    }
+    return d;
+}
+
+// Kernel constants (host computes them in FP64 once per call).
+struct KernelConsts {
+    float hinv;      // 1/h
+    float cW;        // W normalisation: Wendland alpha_d; LG a_d / h^d
+    float cF;        // (dW/dr)/r prefactor: Wendland -5 alpha_d / h^2; LG -a_d/(3 h^{d+2})
+    int type;        // SPH_WENDLAND / SPH_LAGUERRE_GAUSS
+};
+
+// Wendland: W = cW (1 - q/2)^4 (2q + 1);  (dW/dr)/r = cF (1 - q/2)^3.
+// LG:       W = cW (1 - q^2 + q^4/6) e^{-q^2};
+//           (dW/dr)/r = cF e^{-q^2} (12 - 8 q^2 + q^4).
+__device__ __forceinline__ float kernel_W(const KernelConsts& k, float q) {
+    if (k.type == SPH_WENDLAND) {
+        float t = 1.f - 0.5f * q;
+        float t2 = t * t;
+        return k.cW * t2 * t2 * (2.f * q + 1.f);
+    }
+    float q2 = q * q;
+    return k.cW * (1.f - q2 + q2 * q2 * (1.f / 6.f)) * __expf(-q2);
+}
+
+__device__ __forceinline__ float kernel_F(const KernelConsts& k, float q) {
+    if (k.type == SPH_WENDLAND) {
+        float t = 1.f - 0.5f * q;
+        return k.cF * t * t * t;
+    }
+    float q2 = q * q;
+    return k.cF * __expf(-q2) * (12.f - 8.f * q2 + q2 * q2);
+}
+
+__device__ __forceinline__ float wendland_F(float q, float cF) {
+    float t = 1.f - 0.5f * q;
+    return cF * t * t * t;
+}
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+KernelConsts make_kernel_consts(int type, int dim, double h);
+BoxArgs make_box_args(const sph_domain& d, double rc);

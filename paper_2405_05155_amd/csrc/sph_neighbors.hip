@@ -1,0 +1,267 @@
+// sph_neighbors.hip -- binding a particle configuration: uniform cell grid
+// (counting sort by cell), and the exact neighbour sets N(i) = {j != i :
+// |r_ij|^2 <= (kappa h)^2} stored as CSR in caller order, rows ascending.
+//
+// Neighbour decision.  The compact support of Eq. (5) keeps r = kappa h.  The
+// squared distance is evaluated in FP64 from the FP32 coordinates with the
+// minimum image on periodic axes, as ((dx*dx + dy*dy) + dz*dz) with
+// explicitly rounded operations (no contraction), and compared with
+// (kappa h)^2 computed once on the host in FP64.  For coordinates that are
+// multiples of a power of two (quantised inputs) every step is exact, so the
+// set is defined independently of the evaluation order.
+#include "sph_internal.h"
+
+namespace {
+
+constexpr int BLK = 256;
+
+__device__ __forceinline__ int cell_coord(float x, float lo, float inv, int nc) {
+    int c = (int)floorf((x - lo) * inv);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+__global__ void k_bin(int32_t n, int dim, const float* __restrict__ pos, BoxArgs b,
+                      float4* __restrict__ pos4, int32_t* __restrict__ cell_of,
+                      int32_t* __restrict__ slot, int32_t* __restrict__ count) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x = pos[i];
+    float y = pos[(int64_t)n + i];
+    float z = dim == 3 ? pos[2 * (int64_t)n + i] : 0.f;
+    pos4[i] = make_float4(x, y, z, 0.f);
+    int cx = cell_coord(x, b.lo[0], b.inv_cell[0], b.nc[0]);
+    int cy = cell_coord(y, b.lo[1], b.inv_cell[1], b.nc[1]);
+    int cz = dim == 3 ? cell_coord(z, b.lo[2], b.inv_cell[2], b.nc[2]) : 0;
+    int32_t key = (cz * b.nc[1] + cy) * b.nc[0] + cx;
+    cell_of[i] = key;
+    slot[i] = atomicAdd(&count[key], 1);
+}
+
+__global__ void k_scatter(int32_t n, const float4* __restrict__ pos4, const int32_t* __restrict__ cell_of,
+                          const int32_t* __restrict__ slot, const int32_t* __restrict__ cell_start,
+                          float4* __restrict__ sorted) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 p = pos4[i];
+    p.w = __int_as_float(i);
+    sorted[cell_start[cell_of[i]] + slot[i]] = p;
+}
+
+// members of each cell in ascending caller index (deterministic order)
+__global__ void k_sort_cells(int64_t ncell, const int32_t* __restrict__ cell_start, float4* __restrict__ sorted) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
+    for (int32_t a = s0 + 1; a < s1; ++a) {
+        float4 v = sorted[a];
+        int32_t key = __float_as_int(v.w);
+        int32_t b2 = a - 1;
+        while (b2 >= s0 && __float_as_int(sorted[b2].w) > key) {
+            sorted[b2 + 1] = sorted[b2];
+            --b2;
+        }
+        sorted[b2 + 1] = v;
+    }
+}
+
+__device__ __forceinline__ double md_image(double d, double L, double halfL, int periodic) {
+    if (periodic) {
+        if (d > halfL) d = __dsub_rn(d, L);
+        else if (d < -halfL) d = __dadd_rn(d, L);
+    }
+    return d;
+}
+
+// Visit every j in the 3^dim block of cells around particle p; call f(j).
+template <int DIM, class F>
+__device__ __forceinline__ void for_each_candidate(const float4& p, const BoxArgs& b,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   const float4* __restrict__ sorted, F&& f) {
+    int cx = cell_coord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
+    int cy = cell_coord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
+    int cz = DIM == 3 ? cell_coord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) : 0;
+    const int zr = DIM == 3 ? 1 : 0;
+    for (int oz = -zr; oz <= zr; ++oz) {
+        int z = cz + oz;
+        if (DIM == 3) {
+            if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
+            else if (z < 0 || z >= b.nc[2]) continue;
+        }
+        for (int oy = -1; oy <= 1; ++oy) {
+            int y = cy + oy;
+            if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
+            else if (y < 0 || y >= b.nc[1]) continue;
+            for (int ox = -1; ox <= 1; ++ox) {
+                int x = cx + ox;
+                if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
+                else if (x < 0 || x >= b.nc[0]) continue;
+                int32_t key = (z * b.nc[1] + y) * b.nc[0] + x;
+                int32_t s1 = cell_start[key + 1];
+                for (int32_t s = cell_start[key]; s < s1; ++s) f(sorted[s]);
+            }
+        }
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ bool is_neighbour(const float4& p, const float4& q, const BoxArgs& b, double rc2) {
+    double dx = md_image(__dsub_rn((double)p.x, (double)q.x), b.Ld[0], b.halfLd[0], b.periodic[0]);
+    double dy = md_image(__dsub_rn((double)p.y, (double)q.y), b.Ld[1], b.halfLd[1], b.periodic[1]);
+    double d2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
+    if (DIM == 3) {
+        double dz = md_image(__dsub_rn((double)p.z, (double)q.z), b.Ld[2], b.halfLd[2], b.periodic[2]);
+        d2 = __dadd_rn(d2, __dmul_rn(dz, dz));
+    } else {
+        d2 = __dadd_rn(d2, 0.0);
+    }
+    return d2 <= rc2;
+}
+
+// One thread per particle in cell order: count neighbours (pass 0) or write
+// them into the row of the caller index, then sort the row (pass 1).
+template <int DIM, int PASS>
+__global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restrict__ cell_start,
+                        const float4* __restrict__ sorted, int32_t* __restrict__ cnt,
+                        const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float4 p = sorted[s];
+    int32_t i = __float_as_int(p.w);
+    int32_t c = 0;
+    int64_t base = PASS ? row_ptr[i] : 0;
+    for_each_candidate<DIM>(p, b, cell_start, sorted, [&](const float4& q) {
+        int32_t j = __float_as_int(q.w);
+        if (j != i && is_neighbour<DIM>(p, q, b, rc2)) {
+            if (PASS) col[base + c] = j;
+            ++c;
+        }
+    });
+    if (!PASS) {
+        cnt[i] = c;
+        return;
+    }
+    // insertion sort of the row (rows are short and arrive cell by cell)
+    int32_t* r = col + base;
+    for (int32_t a = 1; a < c; ++a) {
+        int32_t v = r[a];
+        int32_t k = a - 1;
+        while (k >= 0 && r[k] > v) {
+            r[k + 1] = r[k];
+            --k;
+        }
+        r[k + 1] = v;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
+    if (!c) return SPH_ERR_ARG;
+    c->bound = false;
+    c->geo_valid = false;
+    if (!dom) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom is NULL");
+    if (dom->dim != c->dim) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom->dim %d != context dim %d", dom->dim, c->dim);
+    if (!(dom->h > 0.0) || !(dom->kappa > 0.0))
+        return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: h and kappa must be > 0");
+    if (dom->kernel != SPH_WENDLAND && dom->kernel != SPH_LAGUERRE_GAUSS)
+        return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: unknown kernel %d", dom->kernel);
+    if (n < 0) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: n < 0");
+    if (n > 0 && !pos) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: pos is NULL");
+    double rc = dom->kappa * dom->h;
+    for (int a = 0; a < c->dim; ++a) {
+        double L = dom->hi[a] - dom->lo[a];
+        if (!(L > 0.0)) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: empty box on axis %d", a);
+        if (dom->periodic[a] && L < 3.0 * rc * (1.0 + 1e-3))
+            return sph_fail(c, SPH_ERR_ARG,
+                            "sph_build_cells: periodic axis %d of length %g is shorter than 3 kappa h (1+1e-3) = %g", a,
+                            L, 3.0 * rc * (1.0 + 1e-3));
+    }
+    BoxArgs b = make_box_args(*dom, rc);
+    int64_t ncell = (int64_t)b.nc[0] * b.nc[1] * b.nc[2];
+    if (ncell > (int64_t)1 << 30) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: %lld cells exceed the table limit", (long long)ncell);
+
+    c->dom = *dom;
+    c->n = n;
+    c->rc = rc;
+    c->rc2 = rc * rc;
+    c->box = b;
+    c->ncell = ncell;
+
+    int64_t nn = n > 0 ? n : 1;
+    SPH_HIP(c, c->pos4.ensure(nn * sizeof(float4)));
+    SPH_HIP(c, c->cell_of.ensure(nn * sizeof(int32_t)));
+    SPH_HIP(c, c->slot.ensure(nn * sizeof(int32_t)));
+    SPH_HIP(c, c->sorted.ensure(nn * sizeof(float4)));
+    SPH_HIP(c, c->cnt.ensure((ncell + 1 > nn ? ncell + 1 : nn) * sizeof(int32_t)));
+    SPH_HIP(c, c->cell_start.ensure((ncell + 1) * sizeof(int32_t)));
+    SPH_HIP(c, c->row_ptr.ensure((nn + 1) * sizeof(int64_t)));
+
+    int32_t* count = c->cnt.as<int32_t>();  // reused: per-cell counts here, per-row counts below
+    SPH_HIP(c, hipMemsetAsync(count, 0, (ncell + 1) * sizeof(int32_t), c->stream));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->dim, pos, b,
+                           c->pos4.as<float4>(), c->cell_of.as<int32_t>(), c->slot.as<int32_t>(), count);
+        SPH_LAUNCH_CHECK(c);
+    }
+    int rcode = sph_scan_i32_to_i32(c, count, c->cell_start.as<int32_t>(), ncell);
+    if (rcode) return rcode;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->pos4.as<float4>(),
+                           c->cell_of.as<int32_t>(), c->slot.as<int32_t>(), c->cell_start.as<int32_t>(),
+                           c->sorted.as<float4>());
+        hipLaunchKernelGGL(k_sort_cells, dim3(grid_for(ncell, BLK)), dim3(BLK), 0, c->stream, ncell,
+                           c->cell_start.as<int32_t>(), c->sorted.as<float4>());
+        SPH_LAUNCH_CHECK(c);
+    }
+
+    // neighbour counts -> row offsets -> rows
+    int32_t* rcnt = c->cnt.as<int32_t>();
+    if (n > 0) {
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_neigh<2, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), rcnt, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL((k_neigh<3, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), rcnt, nullptr, nullptr);
+        SPH_LAUNCH_CHECK(c);
+    }
+    rcode = sph_scan_i32_to_i64(c, rcnt, c->row_ptr.as<int64_t>(), n);
+    if (rcode) return rcode;
+    int64_t nnz = 0;
+    SPH_HIP(c, hipMemcpyAsync(&nnz, c->row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    SPH_HIP(c, hipStreamSynchronize(c->stream));
+    c->nnz = nnz;
+    SPH_HIP(c, c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+    if (n > 0 && nnz > 0) {
+        if (c->dim == 2)
+            hipLaunchKernelGGL((k_neigh<2, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr,
+                               c->row_ptr.as<int64_t>(), c->col.as<int32_t>());
+        else
+            hipLaunchKernelGGL((k_neigh<3, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr,
+                               c->row_ptr.as<int64_t>(), c->col.as<int32_t>());
+        SPH_LAUNCH_CHECK(c);
+    }
+    c->bound = true;
+    return SPH_OK;
+}
+
+int sph_neighbors(sph_ctx* c, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_neighbors: no configuration bound (call sph_build_cells)");
+    if (nnz) *nnz = c->nnz;
+    if (!row_ptr) return sph_fail(c, SPH_ERR_ARG, "sph_neighbors: row_ptr is NULL");
+    if (cap < c->nnz) return sph_fail(c, SPH_ERR_CAPACITY, "sph_neighbors: capacity %lld < nnz %lld", (long long)cap, (long long)c->nnz);
+    if (c->nnz > 0 && !col) return sph_fail(c, SPH_ERR_ARG, "sph_neighbors: col is NULL");
+    SPH_HIP(c, hipMemcpyAsync(row_ptr, c->row_ptr.as<int64_t>(), (size_t)(c->n + 1) * sizeof(int64_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+    if (c->nnz > 0)
+        SPH_HIP(c, hipMemcpyAsync(col, c->col.as<int32_t>(), (size_t)c->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                  c->stream));
+    return SPH_OK;
+}
+
+}  // extern "C"

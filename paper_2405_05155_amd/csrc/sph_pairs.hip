@@ -1,0 +1,331 @@
+// sph_pairs.hip -- per-particle neighbour loops on the bound configuration:
+// kernel summation, the correction matrix B_i (Eq. 9) with its FP64
+// inversion, the cached geometry records, and the corrected gradient.
+//
+// Mapping: one thread per particle in caller order, looping over its CSR
+// row; all sums are FP32 with Kahan compensation, gathers of neighbour data
+// are 16-byte records.
+#include "sph_internal.h"
+
+namespace {
+
+constexpr int BLK = 256;
+
+template <int DIM>
+__device__ __forceinline__ void pair_d(const float4& pi, const float4& pj, const BoxArgs& b, float d[3]) {
+    d[0] = min_image(pi.x - pj.x, b.L[0], b.halfL[0], b.periodic[0]);
+    d[1] = min_image(pi.y - pj.y, b.L[1], b.halfL[1], b.periodic[1]);
+    d[2] = DIM == 3 ? min_image(pi.z - pj.z, b.L[2], b.halfL[2], b.periodic[2]) : 0.f;
+}
+
+template <int DIM>
+__global__ void k_kernel_sum(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ pos4,
+                             const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             const float* __restrict__ vol, float* __restrict__ out) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 pi = pos4[i];
+    Kahan s;
+    s.init(kernel_W(kc, 0.f) * vol[i]);
+    int64_t e = row_ptr[i + 1];
+    for (int64_t k = row_ptr[i]; k < e; ++k) {
+        int32_t j = col[k];
+        float d[3];
+        pair_d<DIM>(pi, pos4[j], b, d);
+        float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        float q = sqrtf(r2) * kc.hinv;
+        s.add(kernel_W(kc, q) * vol[j]);
+    }
+    out[i] = s.value();
+}
+
+// FP64 inverse of the symmetric matrix given by its upper triangle
+// (2-D: m00 m01 m11; 3-D: m00 m01 m02 m11 m12 m22) by adjugate / det.
+// Returns false for the degenerate case |det| < 1e-10 |tr/d|^d.
+template <int DIM>
+__device__ __forceinline__ bool inv_sym(const double* m, double* inv) {
+    if (DIM == 2) {
+        double det = m[0] * m[2] - m[1] * m[1];
+        double tr = 0.5 * (m[0] + m[2]);
+        if (!(fabs(det) >= 1e-10 * tr * tr) || tr == 0.0) return false;
+        double id = 1.0 / det;
+        inv[0] = m[2] * id;
+        inv[1] = -m[1] * id;
+        inv[2] = m[0] * id;
+        return true;
+    }
+    double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5];
+    // cofactors of [[a b c][b d e][c e f]]
+    double A = d * f - e * e;
+    double B = c * e - b * f;
+    double C = b * e - c * d;
+    double D = a * f - c * c;
+    double E = b * c - a * e;
+    double F = a * d - b * b;
+    double det = a * A + b * B + c * C;
+    double tr = (a + d + f) / 3.0;
+    if (!(fabs(det) >= 1e-10 * fabs(tr * tr * tr)) || tr == 0.0) return false;
+    double id = 1.0 / det;
+    inv[0] = A * id;
+    inv[1] = B * id;
+    inv[2] = C * id;
+    inv[3] = D * id;
+    inv[4] = E * id;
+    inv[5] = F * id;
+    return true;
+}
+
+template <int DIM>
+__device__ __forceinline__ void store_geo(int32_t i, const float4& p, float V, const float* Bu,
+                                          float4* __restrict__ geo0, float4* __restrict__ geo1,
+                                          float2* __restrict__ geo2) {
+    if (DIM == 2) {
+        geo0[i] = make_float4(p.x, p.y, V, Bu[0]);
+        reinterpret_cast<float2*>(geo1)[i] = make_float2(Bu[1], Bu[2]);
+    } else {
+        geo0[i] = make_float4(p.x, p.y, p.z, V);
+        geo1[i] = make_float4(Bu[0], Bu[1], Bu[2], Bu[3]);
+        geo2[i] = make_float2(Bu[4], Bu[5]);
+    }
+}
+
+template <int DIM>
+__global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ pos4,
+                             const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                             const float* __restrict__ vol, float* __restrict__ Bout, double* __restrict__ B64,
+                             float4* __restrict__ geo0, float4* __restrict__ geo1, float2* __restrict__ geo2,
+                             int32_t* __restrict__ ndeg) {
+    constexpr int NU = DIM == 2 ? 3 : 6;
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 pi = pos4[i];
+    Kahan M[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) M[u].init();
+    int64_t e = row_ptr[i + 1];
+    for (int64_t k = row_ptr[i]; k < e; ++k) {
+        int32_t j = col[k];
+        float d[3];
+        pair_d<DIM>(pi, pos4[j], b, d);
+        float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        float q = sqrtf(r2) * kc.hinv;
+        float w = kernel_F(kc, q) * vol[j];  // grad W = F d;  r (x) grad W V = F V d d^T
+        if (DIM == 2) {
+            M[0].add(w * d[0] * d[0]);
+            M[1].add(w * d[0] * d[1]);
+            M[2].add(w * d[1] * d[1]);
+        } else {
+            M[0].add(w * d[0] * d[0]);
+            M[1].add(w * d[0] * d[1]);
+            M[2].add(w * d[0] * d[2]);
+            M[3].add(w * d[1] * d[1]);
+            M[4].add(w * d[1] * d[2]);
+            M[5].add(w * d[2] * d[2]);
+        }
+    }
+    double m[NU], inv[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) m[u] = M[u].value64();
+    double Bd[NU];
+    if (inv_sym<DIM>(m, inv)) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) Bd[u] = -inv[u];
+    } else {
+        atomicAdd(ndeg, 1);
+        if (DIM == 2) {
+            Bd[0] = 1.0; Bd[1] = 0.0; Bd[2] = 1.0;
+        } else {
+            Bd[0] = 1.0; Bd[1] = 0.0; Bd[2] = 0.0; Bd[3] = 1.0; Bd[4] = 0.0; Bd[5] = 1.0;
+        }
+    }
+    float Bu[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) Bu[u] = (float)Bd[u];
+    // full matrices (upper triangle mirrored)
+    if (DIM == 2) {
+        const int idx[4] = {0, 1, 1, 2};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            Bout[(int64_t)i * 4 + t] = Bu[idx[t]];
+            if (B64) B64[(int64_t)i * 4 + t] = Bd[idx[t]];
+        }
+    } else {
+        const int idx[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            Bout[(int64_t)i * 9 + t] = Bu[idx[t]];
+            if (B64) B64[(int64_t)i * 9 + t] = Bd[idx[t]];
+        }
+    }
+    store_geo<DIM>(i, pi, vol[i], Bu, geo0, geo1, geo2);
+}
+
+template <int DIM>
+__global__ void k_set_geo(int32_t n, const float4* __restrict__ pos4, const float* __restrict__ vol,
+                          const float* __restrict__ B, float4* __restrict__ geo0, float4* __restrict__ geo1,
+                          float2* __restrict__ geo2) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float Bu[6];
+    if (DIM == 2) {
+        const float* m = B + (int64_t)i * 4;
+        Bu[0] = m[0]; Bu[1] = m[1]; Bu[2] = m[3];
+    } else {
+        const float* m = B + (int64_t)i * 9;
+        Bu[0] = m[0]; Bu[1] = m[1]; Bu[2] = m[2]; Bu[3] = m[4]; Bu[4] = m[5]; Bu[5] = m[8];
+    }
+    store_geo<DIM>(i, pos4[i], vol[i], Bu, geo0, geo1, geo2);
+}
+
+// Unpack the upper triangle of B_i from the geometry records.
+template <int DIM>
+__device__ __forceinline__ void load_B(int32_t i, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                                       const float2* __restrict__ geo2, float4& g0, float* Bu) {
+    g0 = geo0[i];
+    if (DIM == 2) {
+        float2 t = reinterpret_cast<const float2*>(geo1)[i];
+        Bu[0] = g0.w; Bu[1] = t.x; Bu[2] = t.y;
+    } else {
+        float4 t = geo1[i];
+        float2 u = geo2[i];
+        Bu[0] = t.x; Bu[1] = t.y; Bu[2] = t.z; Bu[3] = t.w; Bu[4] = u.x; Bu[5] = u.y;
+    }
+}
+
+template <int DIM>
+__global__ void k_gradient(int32_t n, BoxArgs b, float hinv, float cF, const int64_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col, const float4* __restrict__ geo0,
+                           const float4* __restrict__ geo1, const float2* __restrict__ geo2,
+                           const float* __restrict__ f, float* __restrict__ grad) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 gi;
+    float Bu[6];
+    load_B<DIM>(i, geo0, geo1, geo2, gi, Bu);
+    float fi = f[i];
+    Kahan s[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) s[a].init();
+    int64_t e = row_ptr[i + 1];
+    for (int64_t k = row_ptr[i]; k < e; ++k) {
+        int32_t j = col[k];
+        float4 gj = geo0[j];
+        float d[3];
+        pair_d<DIM>(gi, gj, b, d);
+        float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        float q = sqrtf(r2) * hinv;
+        float Vj = DIM == 2 ? gj.z : gj.w;
+        float w = wendland_F(q, cF) * Vj * (f[j] - fi);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) s[a].add(w * d[a]);
+    }
+    float v[3] = {s[0].value(), s[1].value(), DIM == 3 ? s[DIM - 1].value() : 0.f};
+    if (DIM == 2) {
+        grad[i] = Bu[0] * v[0] + Bu[1] * v[1];
+        grad[(int64_t)n + i] = Bu[1] * v[0] + Bu[2] * v[1];
+    } else {
+        grad[i] = Bu[0] * v[0] + Bu[1] * v[1] + Bu[2] * v[2];
+        grad[(int64_t)n + i] = Bu[1] * v[0] + Bu[3] * v[1] + Bu[4] * v[2];
+        grad[2 * (int64_t)n + i] = Bu[2] * v[0] + Bu[4] * v[1] + Bu[5] * v[2];
+    }
+}
+
+int ensure_geo(sph_ctx* c) {
+    int64_t nn = c->n > 0 ? c->n : 1;
+    SPH_HIP(c, c->geo0.ensure(nn * sizeof(float4)));
+    SPH_HIP(c, c->geo1.ensure(nn * sizeof(float4)));
+    SPH_HIP(c, c->geo2.ensure(nn * sizeof(float2)));
+    return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sph_kernel_sum(sph_ctx* c, const float* vol, float* out) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_kernel_sum: no configuration bound");
+    if (c->n > 0 && (!vol || !out)) return sph_fail(c, SPH_ERR_ARG, "sph_kernel_sum: NULL array");
+    if (c->n == 0) return SPH_OK;
+    KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_kernel_sum<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
+                           c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, out);
+    else
+        hipLaunchKernelGGL(k_kernel_sum<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
+                           c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, out);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+int sph_correction_B(sph_ctx* c, const float* vol, float* B, double* B64, int32_t* n_degenerate) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_correction_B: no configuration bound");
+    if (c->n > 0 && (!vol || !B)) return sph_fail(c, SPH_ERR_ARG, "sph_correction_B: NULL array");
+    int r = ensure_geo(c);
+    if (r) return r;
+    SPH_HIP(c, c->counter.ensure(64));
+    int32_t* ndeg = c->counter.as<int32_t>();
+    SPH_HIP(c, hipMemsetAsync(ndeg, 0, sizeof(int32_t), c->stream));
+    if (c->n > 0) {
+        KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
+        if (c->dim == 2)
+            hipLaunchKernelGGL(k_correction<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
+                               c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, B, B64,
+                               c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+        else
+            hipLaunchKernelGGL(k_correction<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
+                               c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, B, B64,
+                               c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+        SPH_LAUNCH_CHECK(c);
+    }
+    if (n_degenerate) {
+        SPH_HIP(c, hipMemcpyAsync(n_degenerate, ndeg, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        SPH_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    c->geo_valid = true;
+    return SPH_OK;
+}
+
+int sph_set_correction(sph_ctx* c, const float* vol, const float* B) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_set_correction: no configuration bound");
+    if (c->n > 0 && (!vol || !B)) return sph_fail(c, SPH_ERR_ARG, "sph_set_correction: NULL array");
+    int r = ensure_geo(c);
+    if (r) return r;
+    if (c->n > 0) {
+        if (c->dim == 2)
+            hipLaunchKernelGGL(k_set_geo<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                               c->pos4.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->geo2.as<float2>());
+        else
+            hipLaunchKernelGGL(k_set_geo<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                               c->pos4.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->geo2.as<float2>());
+        SPH_LAUNCH_CHECK(c);
+    }
+    c->geo_valid = true;
+    return SPH_OK;
+}
+
+int sph_gradient(sph_ctx* c, const float* f, float* grad) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound || !c->geo_valid)
+        return sph_fail(c, SPH_ERR_STATE, "sph_gradient: needs a bound configuration and a cached correction");
+    if (c->dom.kernel != SPH_WENDLAND) return sph_fail(c, SPH_ERR_ARG, "sph_gradient: Wendland kernel only");
+    if (c->n > 0 && (!f || !grad)) return sph_fail(c, SPH_ERR_ARG, "sph_gradient: NULL array");
+    if (c->n == 0) return SPH_OK;
+    KernelConsts kc = make_kernel_consts(SPH_WENDLAND, c->dim, c->dom.h);
+    if (c->dim == 2)
+        hipLaunchKernelGGL(k_gradient<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc.hinv,
+                           kc.cF, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), c->geo0.as<float4>(),
+                           c->geo1.as<float4>(), c->geo2.as<float2>(), f, grad);
+    else
+        hipLaunchKernelGGL(k_gradient<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc.hinv,
+                           kc.cF, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), c->geo0.as<float4>(),
+                           c->geo1.as<float4>(), c->geo2.as<float2>(), f, grad);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+"""Shared test helpers: device set-up, the oracle side of each workload and
+the scaled tolerance.  Imported by tests only."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+
+def scaled_check(gpu, ref, scale, rtol, name):
+    """|gpu - ref| <= rtol * max(|ref|, scale) elementwise, where scale is the
+    absolute-sum scale sum_j |term_ij| of each output (the error bound of a
+    compensated sum of FP32 terms is proportional to it)."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.broadcast_to(np.asarray(scale, dtype=np.float64), ref.shape)
+    err = np.abs(gpu - ref)
+    bound = rtol * np.maximum(np.abs(ref), scale)
+    bad = err > bound
+    worst = float(np.max(err / np.maximum(bound, 1e-300))) if err.size else 0.0
+    assert not bad.any(), f"{name}: {int(bad.sum())}/{bad.size} beyond tolerance, worst err/bound {worst:.3g}"
+    return worst
+
+
+def normwise(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(gpu - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def oracle_box(w):
+    return O.make_box(w.dim, lo=w.lo, hi=w.hi, periodic=w.periodic)
+
+
+def csr_rows_equal(rp_a, col_a, rp_b, col_b, rows=None):
+    """Compare CSR a (full, indexed by particle) with CSR b (indexed by
+    position in `rows`, or full).  Returns the first differing row or None."""
+    rp_a, col_a = np.asarray(rp_a), np.asarray(col_a)
+    rp_b, col_b = np.asarray(rp_b), np.asarray(col_b)
+    it = range(len(rp_b) - 1)
+    for k in it:
+        i = rows[k] if rows is not None else k
+        a = col_a[rp_a[i]:rp_a[i + 1]]
+        b = col_b[rp_b[k]:rp_b[k + 1]]
+        if a.shape != b.shape or not np.array_equal(a, b):
+            return i
+    return None
+
+
+def two_ring_B(box, pos, h, rc, rows):
+    """Oracle B on rows and on all their neighbours (for RHS checks on a
+    sample of rows).  Returns (rp_rows, col_rows, B_full) with B_full zero
+    outside the ring."""
+    rc2 = rc * rc
+    rp, col = O.neighbors_grid(box, pos, rc, rc2, rows=rows)
+    ring = np.unique(np.concatenate([np.asarray(rows, dtype=np.int64), col.astype(np.int64)]))
+    rp2, col2 = O.neighbors_grid(box, pos, rc, rc2, rows=ring)
+    n = pos.shape[1]
+    dim = box.dim
+    return rp, col, ring, rp2, col2
+
+
+def sample_rows(n, k, seed):
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=min(k, n), replace=False)]))
+    return rows.astype(np.int64)

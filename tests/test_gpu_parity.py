@@ -1,0 +1,347 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical seeded inputs.
+
+Neighbour sets must match bit for bit.  FP32 fields must satisfy, per
+element, |gpu - ref| <= 1e-5 max(|ref|, S) with S the absolute-sum scale
+sum_j |term_ij| of that output (the error bound of a compensated sum of
+FP32 terms scales with it, not with the possibly cancelled result); runs
+of many steps are compared normwise (relative L2 <= 1e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2405_05155_amd import inputs as I
+from tests.gpu_helpers import csr_rows_equal, normwise, oracle_box, sample_rows, scaled_check
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_05155_amd import sph
+    sph.lib()
+    return sph
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def gpu_ctx(S, w, kappa, kernel=0):
+    ctx = S.Context(w.dim)
+    dom = S.Domain(dim=w.dim, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=w.periodic, kernel=kernel)
+    ctx.build_cells(dom, dev(w.pos))
+    return ctx
+
+
+# ------------------------------------------------------------------ neighbours
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_neighbours_single_step_bit_exact(S, seed, kappa):
+    w = I.single_step_2d(seed=seed)
+    ctx = gpu_ctx(S, w, kappa)
+    rp, col = ctx.neighbors()
+    rc = kappa * w.h
+    rp_o, col_o = O.neighbors_grid(oracle_box(w), w.pos, rc, rc * rc)
+    assert np.array_equal(host(rp), rp_o)
+    assert np.array_equal(host(col), col_o)
+
+
+def test_neighbours_exact_ties(S):
+    t = I.adversarial_ties_2d(kappa=2.0)
+    ctx = gpu_ctx(S, t, 2.0)
+    rp, col = ctx.neighbors()
+    rc = 2.0 * t.h
+    rp_o, col_o = O.neighbors_brute(oracle_box(t), t.pos, rc * rc)
+    assert np.array_equal(host(rp), rp_o) and np.array_equal(host(col), col_o)
+
+
+@pytest.mark.parametrize("dim,n,periodic", [(3, 1000, True), (3, 1001, False), (2, 777, False), (2, 1, True)])
+def test_neighbours_random_ragged(S, dim, n, periodic):
+    w = I.random_points(n, dim, seed=n, periodic=periodic)
+    for kappa in (2.0, 1.6):
+        if periodic and 3 * kappa * w.h * 1.001 > 1.0:
+            continue
+        ctx = gpu_ctx(S, w, kappa)
+        rp, col = ctx.neighbors()
+        rc = kappa * w.h
+        rp_o, col_o = O.neighbors_brute(oracle_box(w), w.pos, rc * rc)
+        assert np.array_equal(host(rp), rp_o) and np.array_equal(host(col), col_o)
+
+
+def test_neighbours_empty_configuration(S):
+    ctx = S.Context(2)
+    ctx.build_cells(S.Domain(dim=2, h=0.05, kappa=2.0), torch.empty((2, 0), device="cuda"))
+    rp, col = ctx.neighbors()
+    assert host(rp).tolist() == [0] and col.numel() == 0
+
+
+def test_invalid_arguments_raise(S):
+    ctx = S.Context(2)
+    with pytest.raises(S.SphError):
+        ctx.build_cells(S.Domain(dim=2, h=0.3, kappa=2.0), dev(np.zeros((2, 4))))  # box < 3 kappa h
+    # nothing bound: the C layer refuses before enqueueing anything
+    assert S.lib().sph_kernel_sum(ctx._h, None, None) == S.SPH_ERR_STATE
+    assert b"no configuration bound" in S.lib().sph_last_error(ctx._h)
+    with pytest.raises(S.SphError):
+        ctx.build_cells(S.Domain(dim=3, h=0.01, kappa=2.0), dev(np.zeros((2, 4))))  # dim mismatch
+
+
+# ------------------------------------------------------------------ kernel sum, B, gradient
+
+def _c0_oracle(w, kappa):
+    box = oracle_box(w)
+    rc = kappa * w.h
+    rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+    B, nd = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    return box, rp, col, B, nd
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_kernel_sum_and_table1(S, kappa):
+    w = I.single_step_2d(seed=0)
+    ctx = gpu_ctx(S, w, kappa)
+    out = host(ctx.kernel_sum(dev(w.vol)))
+    box, rp, col, _, _ = _c0_oracle(w, kappa)
+    ref = O.kernel_sum(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    scaled_check(out, ref, ref, RTOL, "kernel sum")
+    # Table 1 lattice row on the GPU: L2(f=1) = 0.010 (SW), 0.006 (TW)
+    lat = I.periodic_square_case(32, 2, 1.3, 0.0, None, "lattice")
+    ctx = gpu_ctx(S, lat, kappa)
+    s = host(ctx.kernel_sum(dev(lat.vol))).astype(np.float64)
+    err = np.sqrt(np.mean((s - 1.0) ** 2))
+    assert round(err, 3) == {2.0: 0.010, 1.6: 0.006}[kappa]
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_correction_matrix(S, seed, kappa):
+    w = I.single_step_2d(seed=seed)
+    ctx = gpu_ctx(S, w, kappa)
+    B, B64, nd = ctx.correction_B(dev(w.vol), want_fp64=True)
+    box, rp, col, Bo, ndo = _c0_oracle(w, kappa)
+    assert nd == ndo == 0
+    scale = np.abs(Bo).reshape(w.n, -1).max(axis=1)[:, None, None]
+    scaled_check(host(B), Bo, scale, RTOL, "B fp32")
+    scaled_check(host(B64), Bo, scale, RTOL, "B fp64")
+    assert np.array_equal(host(B), np.transpose(host(B), (0, 2, 1)))
+
+
+def _grad_scale(w, box, rp, col, Bo, f, h):
+    """||B_i||_max * sum_j |f_j - f_i| |dW/dr| V_j (per row, all components)."""
+    pos = w.pos.astype(np.float64)
+    n = w.n
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    d = pos[:, rows] - pos[:, col]
+    d = d - np.round(d)  # periodic unit box
+    r = np.sqrt((d ** 2).sum(0))
+    t = np.abs(f[col] - f[rows]) * np.abs(O.kernel_dWdr(O.WENDLAND, w.dim, h, r)) * w.vol[col]
+    s = np.bincount(rows, weights=t, minlength=n)
+    return s * np.abs(Bo).reshape(n, -1).max(axis=1) * w.dim
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_corrected_gradient(S, kappa):
+    w = I.single_step_2d(seed=1)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    rho = 1.0 + w.fields["drho"].astype(np.float64)
+    fields = {"rho": w.fields["drho"], "ux": w.fields["mom"][0] / rho, "uy": w.fields["mom"][1] / rho,
+              "p": (100.0 * rho)}
+    for name, f in fields.items():
+        f32 = np.asarray(f, dtype=np.float32)
+        g = host(ctx.gradient(dev(f32)))
+        ref = O.gradient(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol, Bo, f32)
+        scale = _grad_scale(w, box, rp, col, Bo, f32.astype(np.float64), w.h)
+        scaled_check(g, ref, scale[None, :], RTOL, f"gradient {name}")
+
+
+# ------------------------------------------------------------------ Eulerian RHS
+
+def _euler_prm(S, w, dt=0.0):
+    f = w.fields
+    return (S.euler_params(c=f["c"], rho0=f["rho0_eos"], rho_ref=f["rho_ref"], eta=f["eta"], mu=f["mu"], dt=dt),
+            O.euler_params(c=f["c"], rho0=f["rho0_eos"], eta=f["eta"], mu=f["mu"], dt=dt))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+@pytest.mark.parametrize("mu", [0.0, 0.01])
+def test_euler_rhs_single_step(S, seed, kappa, mu):
+    w = I.single_step_2d(seed=seed)
+    w.fields["mu"] = mu
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    pg, po = _euler_prm(S, w)
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    rho = w.fields["rho_ref"] + w.fields["drho"].astype(np.float64)
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho, w.fields["mom"])
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_euler_heun_steps_taylor_green(S, kappa):
+    w = I.taylor_green_2d(nside=64, nu=0.01)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    dt = w.meta["dt"]
+    pg, po = _euler_prm(S, w, dt)
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    drho0 = w.fields["drho"].astype(np.float64)
+    mom0 = w.fields["mom"].astype(np.float64)
+    rho0 = 1.0 + drho0
+    # one step: the increment matches to 1e-5 of itself plus the FP32
+    # resolution of the stored state (the increment of one step is only
+    # ~1e3 ulps of the state)
+    d = dev(w.fields["drho"])
+    m = dev(w.fields["mom"])
+    ctx.euler_step(pg, d, m, 1)
+    r1, m1 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0, 1)
+    eps = np.finfo(np.float32).eps
+    _, _, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0)
+    inc_g, inc_o = host(d) - drho0, (r1 - 1.0) - drho0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dr) + 4 * eps * np.abs(r1 - 1.0))
+    inc_g, inc_o = host(m) - mom0, m1 - mom0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(m1))
+    # many steps: normwise 1e-3 on the state
+    ctx.euler_step(pg, d, m, 99)
+    r100, m100 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, r1, m1, 99)
+    assert normwise(host(m), m100) < 1e-3
+    assert normwise(host(d), r100 - 1.0) < 1e-3
+
+
+def test_euler_rhs_full_size_taylor_green_sampled(S):
+    """512^2 Taylor-Green (the timed workload): neighbour rows, B and the RHS
+    on a sample of particles, against the oracle computed on those rows."""
+    w = I.taylor_green_2d(nside=512)
+    box = oracle_box(w)
+    rows = sample_rows(w.n, 48, seed=7)
+    for kappa in (2.0, 1.6):
+        rc = kappa * w.h
+        ctx = gpu_ctx(S, w, kappa)
+        rp, col = ctx.neighbors()
+        rp_g, col_g = host(rp), host(col)
+        rp_o, col_o = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=rows)
+        assert csr_rows_equal(rp_g, col_g, rp_o, col_o, rows) is None
+        B, _, nd = ctx.correction_B(dev(w.vol))
+        assert nd == 0
+        ring = np.unique(np.concatenate([rows, col_o.astype(np.int64)]))
+        rp_r, col_r = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=ring)
+        B_r, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp_r, col_r, w.vol, rows=ring)
+        Bg = host(B)
+        scale = np.abs(B_r).reshape(len(ring), -1).max(axis=1)[:, None, None]
+        scaled_check(Bg[ring], B_r, scale, RTOL, "B sampled")
+        B_full = np.zeros((w.n, 2, 2))
+        B_full[ring] = B_r
+        pg, po = _euler_prm(S, w)
+        dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+        rho = 1.0 + w.fields["drho"].astype(np.float64)
+        r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp_o, col_o, w.vol, B_full, po, rho,
+                                             w.fields["mom"], rows=rows)
+        scaled_check(host(dr)[rows], r_dr, s_dr, RTOL, "drho/dt sampled")
+        scaled_check(host(dm)[:, rows], r_dm, s_dm, RTOL, "dmom/dt sampled")
+
+
+def test_euler_rhs_3d_taylor_green_sampled(S):
+    """3-D Taylor-Green at 96^3 (ragged tail, several thousand blocks)."""
+    w = I.taylor_green_3d(nside=96)
+    box = oracle_box(w)
+    rows = sample_rows(w.n, 24, seed=3)
+    for kappa in (2.0, 1.6):
+        rc = kappa * w.h
+        ctx = gpu_ctx(S, w, kappa)
+        rp, col = ctx.neighbors()
+        rp_o, col_o = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=rows)
+        assert csr_rows_equal(host(rp), host(col), rp_o, col_o, rows) is None
+        ctx.correction_B(dev(w.vol))
+        ring = np.unique(np.concatenate([rows, col_o.astype(np.int64)]))
+        rp_r, col_r = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=ring)
+        B_r, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp_r, col_r, w.vol, rows=ring)
+        B_full = np.zeros((w.n, 3, 3))
+        B_full[ring] = B_r
+        pg, po = _euler_prm(S, w)
+        dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+        rho = 1.0 + w.fields["drho"].astype(np.float64)
+        r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp_o, col_o, w.vol, B_full, po, rho,
+                                             w.fields["mom"], rows=rows)
+        scaled_check(host(dr)[rows], r_dr, s_dr, RTOL, "3d drho/dt")
+        scaled_check(host(dm)[:, rows], r_dm, s_dm, RTOL, "3d dmom/dt")
+
+
+# ------------------------------------------------------------------ total Lagrangian
+
+def _plate(nx=24):
+    return I.cantilever_plate(nx=nx, length=0.2, thick=0.02 * 3, width=0.04)
+
+
+def _tl_setup(S, w, kappa, model):
+    ctx = gpu_ctx(S, w, kappa)
+    _, _, nd = ctx.correction_B(dev(w.vol))
+    box = oracle_box(w)
+    rc = kappa * w.h
+    rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+    Bo, ndo = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    assert nd == ndo
+    f = w.fields
+    pg = S.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=model)
+    po = O.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=model)
+    return ctx, box, rp, col, Bo, pg, po
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+@pytest.mark.parametrize("model", [0, 1])
+def test_tlsph_rhs(S, kappa, model):
+    w = _plate()
+    ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, model)
+    rng = np.random.default_rng(2)
+    F = (np.eye(3)[None] + 0.01 * rng.normal(size=(w.n, 3, 3))).astype(np.float32)
+    vel = w.fields["vel"]
+    fixed = w.fields["fixed"]
+    dF, acc = ctx.tlsph_rhs(pg, dev(vel), dev(F), dev(fixed, torch.int32))
+    r_dF, r_acc, s_acc = O.tlsph_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, vel, F, fixed)
+    scaled_check(host(acc), r_acc, s_acc, RTOL, "acc")
+    # dF/dt scale: ||B_i|| sum_j V_j |v_j - v_i| |dW/dr|
+    pos = w.pos.astype(np.float64)
+    rows = np.repeat(np.arange(w.n), np.diff(rp))
+    d = pos[:, rows] - pos[:, col]
+    r = np.sqrt((d ** 2).sum(0))
+    t = np.abs(vel[:, col] - vel[:, rows]).max(0) * np.abs(O.kernel_dWdr(O.WENDLAND, 3, w.h, r)) * w.vol[col]
+    sc = np.bincount(rows, weights=t, minlength=w.n) * np.abs(Bo).reshape(w.n, -1).max(1) * 3
+    scaled_check(host(dF), r_dF, sc[:, None, None], RTOL, "dF/dt")
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_tlsph_steps(S, kappa):
+    w = _plate()
+    ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, 0)
+    F0 = np.tile(np.eye(3, dtype=np.float32), (w.n, 1, 1))
+    vel0 = w.fields["vel"]
+    fixed = w.fields["fixed"]
+    _, acc0, _ = O.tlsph_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, vel0, F0, fixed)
+    nsteps = 100
+    pos_o, vel_o, F_o, acc_o = O.tlsph_step(box, w.pos, w.h, rp, col, w.vol, Bo, po, fixed, w.pos, vel0, F0,
+                                            acc0, nsteps)
+    pos = dev(w.pos)
+    vel = dev(vel0)
+    F = dev(F0)
+    _, acc = ctx.tlsph_rhs(pg, vel, F, dev(fixed, torch.int32))
+    ctx.tlsph_step(pg, dev(fixed, torch.int32), pos, vel, F, acc, nsteps)
+    assert normwise(host(vel), vel_o) < 1e-3
+    assert normwise(host(F) - np.eye(3), F_o - np.eye(3)) < 1e-3
+    assert normwise(host(pos) - w.pos, pos_o - w.pos) < 1e-3
+    assert np.all(host(vel)[:, fixed.astype(bool)] == 0.0)
