@@ -126,6 +126,26 @@ struct Kahan {
     __device__ __forceinline__ double value64() const { return (double)s - (double)c; }
 };
 
+// Combine the compensated partial sums held by the L lanes of an aligned
+// lane group (xor butterfly; every lane ends with the same value).  Each
+// partial is the pair (hi, lo) = (s, -c); partners merge with TwoSum so the
+// rounding error of adding the high parts is carried in the low part.
+template <int L>
+__device__ __forceinline__ float group_sum(const Kahan& k) {
+    float hi = k.s, lo = -k.c;
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1) {
+        float ohi = __shfl_xor(hi, m, 64);
+        float olo = __shfl_xor(lo, m, 64);
+        float s = hi + ohi;
+        float bp = s - hi;
+        float e = (hi - (s - bp)) + (ohi - bp);
+        lo = (lo + olo) + e;
+        hi = s;
+    }
+    return hi + lo;
+}
+
 __device__ __forceinline__ float min_image(float d, float L, float halfL, int periodic) {
     if (periodic) {
         if (d > halfL) d -= L;

@@ -257,9 +257,11 @@ def test_euler_rhs_full_size_taylor_green_sampled(S):
         scaled_check(host(dm)[:, rows], r_dm, s_dm, RTOL, "dmom/dt sampled")
 
 
-def test_euler_rhs_3d_taylor_green_sampled(S):
-    """3-D Taylor-Green at 96^3 (ragged tail, several thousand blocks)."""
-    w = I.taylor_green_3d(nside=96)
+@pytest.mark.parametrize("nside", [80, 104])
+def test_euler_rhs_3d_taylor_green_sampled(S, nside):
+    """3-D Taylor-Green at 80^3 and 104^3 (the two sizes take different
+    lanes-per-particle mappings: 2 and 1)."""
+    w = I.taylor_green_3d(nside=nside)
     box = oracle_box(w)
     rows = sample_rows(w.n, 24, seed=3)
     for kappa in (2.0, 1.6):
