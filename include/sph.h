@@ -181,6 +181,49 @@ int sph_tlsph_rhs(sph_ctx* ctx, const sph_tlsph_params* prm, const float* vel, c
 int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fixed, float* pos,
                    float* vel, float* F, float* acc, int32_t nsteps);
 
+/* ---------------------------------------------------------------- particle relaxation
+ * Laguerre-Gauss particle relaxation (Eq. 7 with the kernel of Eq. 8, 3-D)
+ * of particles filling the sphere |r - center| < radius.  The residual
+ * force of particle i is
+ *   g_i = sum_{j : |r_ij| <= 2h} grad W^LG_ij V_j + T(rho_i) e_i,
+ * where the second term is the integral of grad W^LG over the exterior of
+ * the sphere within the support (rho_i = |r_i - c|, e_i = (r_i - c)/rho_i;
+ * the paper's relaxation has no boundary term: this one makes a uniform
+ * fill up to the surface force-free).  T is tabulated on the host in FP64
+ * by Gauss-Legendre quadrature (16385 entries over phi in [-2h, 2h], linear
+ * interpolation).  The acceleration is a_i = -(2 p0/rho) g_i (Eq. 7).
+ * One iteration (the paper gives no integrator; this is the damped reading):
+ *   s = min(kappa h^2, h / (32 max_i |g_i|));
+ *   u_i = damping u_i - s g_i,  |u_i| <= max_move h;   r_i += u_i;
+ *   particles outside (phi > 0) are projected onto the surface, u_i = 0.
+ * The residue of a configuration is R = sqrt(mean_i |h g_i|^2), reduced in
+ * FP64 (two-stage, fixed order: deterministic).
+ * The domain supplies h and the box of the cell grid (dom->kernel and
+ * dom->kappa are ignored: the call always uses the LG kernel with cut-off
+ * 2h). */
+typedef struct {
+    double p0;          /* background pressure of Eq. (7) */
+    double rho;         /* density of Eq. (7) */
+    double center[3];   /* sphere centre */
+    double radius;      /* sphere radius */
+    double kappa;       /* step coefficient (0.1) */
+    double damping;     /* carried-displacement factor (0.9) */
+    double max_move;    /* cap on |u_i| per iteration in units of h (0.1) */
+} sph_relax_params;
+
+/* niter iterations in place.  pos FP32 [3][n] (in/out), u FP32 [3][n]
+ * carried displacement (in/out; zero to start), vol FP32 [n].
+ * residue: device FP64 scalar (nullable) receiving the residue of the
+ * configuration at the start of the last iteration.  The cell grid is
+ * rebuilt every iteration.  Synchronises nothing. */
+int sph_relax_step(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n, float* pos,
+                   float* u, const float* vol, double* residue, int32_t niter);
+
+/* Residual force and residue of a configuration without moving it.
+ * g FP32 [3][n] (nullable), residue device FP64 scalar (nullable). */
+int sph_relax_residue(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n,
+                      const float* pos, const float* vol, float* g, double* residue);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,8 @@ class TlsphParams(C.Structure):
 
 class RelaxParams(C.Structure):
     _fields_ = [("p0", C.c_double), ("rho", C.c_double), ("h", C.c_double),
-                ("center", C.c_double * 3), ("radius", C.c_double)]
+                ("center", C.c_double * 3), ("radius", C.c_double),
+                ("kappa", C.c_double), ("mu", C.c_double), ("max_move", C.c_double)]
 
 
 _lib = None
@@ -87,7 +88,7 @@ def lib():
         L.or_relax_tail.argtypes = [vp, d]
         L.or_relax_g.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.or_relax_step.restype = d
-        L.or_relax_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+        L.or_relax_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -261,9 +262,10 @@ def tlsph_step(box, pos0, h, row_ptr, col, vol0, B0, prm, fixed, pos, vel, F, ac
     return pos, vel, F, acc
 
 
-def relax_params(h, center, radius, p0=1.0, rho=1.0) -> RelaxParams:
+def relax_params(h, center, radius, p0=1.0, rho=1.0, kappa=0.1, mu=0.9, max_move=0.1) -> RelaxParams:
     p = RelaxParams()
     p.p0, p.rho, p.h, p.radius = p0, rho, h, radius
+    p.kappa, p.mu, p.max_move = kappa, mu, max_move
     for a in range(3):
         p.center[a] = center[a]
     return p
@@ -283,10 +285,25 @@ def relax_g(box, pos, prm, row_ptr, col, vol, rows=None):
     return g, s
 
 
-def relax_step(box, pos, prm, row_ptr, col, vol):
-    """One iteration; returns (new positions, residue of the input positions, g)."""
-    pos, vol = _f64(pos).copy(), _f64(vol)
+def relax_step(box, pos, u, prm, row_ptr, col, vol):
+    """One iteration; returns (new positions, new carried displacement,
+    residue of the input positions, g of the input positions)."""
+    pos, u, vol = _f64(pos).copy(), _f64(u).copy(), _f64(vol)
     g = np.empty_like(pos)
-    res = lib().or_relax_step(C.byref(box), pos.shape[1], _p(pos), C.byref(prm), _p(row_ptr), _p(col),
+    res = lib().or_relax_step(C.byref(box), pos.shape[1], _p(pos), _p(u), C.byref(prm), _p(row_ptr), _p(col),
                               _p(vol), _p(g))
-    return pos, res, g
+    return pos, u, res, g
+
+
+def relax_run(box, pos, prm, vol, iters, u=None):
+    """iters iterations with a fresh neighbour search each; returns
+    (positions, u, residues per iteration)."""
+    pos = _f64(pos).copy()
+    u = np.zeros_like(pos) if u is None else _f64(u).copy()
+    rc = 2.0 * prm.h
+    res = []
+    for _ in range(iters):
+        rp, col = neighbors_grid(box, pos, rc, rc * rc)
+        pos, u, r, _ = relax_step(box, pos, u, prm, rp, col, vol)
+        res.append(r)
+    return pos, u, np.array(res)

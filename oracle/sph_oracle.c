@@ -727,6 +727,9 @@ typedef struct {
     double h;         /* smoothing length; LG support radius 2h */
     double center[3]; /* sphere centre */
     double radius;    /* sphere radius; SDF phi = |r - c| - R */
+    double kappa;     /* step: displacement per unit acceleration, in h^2 rho / (2 p0) units */
+    double mu;        /* damping factor of the carried displacement (0: none carried) */
+    double max_move;  /* cap on |u_i| per iteration, in units of h */
 } or_relax_params;
 
 /* Exterior kernel-gradient integral for a sphere (a reading: the paper's
@@ -735,33 +738,37 @@ typedef struct {
  *   t_i = int_{|r - c| > R} grad_i W(r_i - r) dV = T(rho_i) e_i,
  * rho_i = |r_i - c|, e_i = (r_i - c)/rho_i.  In spherical coordinates about
  * r_i only the radial component survives:
- *   T = pi int_0^{2h} (-dW/ds) s^2 (1 - clamp(u0, -1, 1)^2) ds,
- *   u0 = (R^2 - rho^2 - s^2) / (2 rho s).
- * Composite Simpson rule with 2000 panels on [max(0, R - rho), 2h].
+ *   T = pi int_{s0}^{2h} (-dW/ds) s^2 (1 - clamp(u0, -1, 1)^2) ds,
+ *   u0 = (R^2 - rho^2 - s^2) / (2 rho s),  s0 = |R - rho|
+ * (the integrand vanishes for s < s0).  Composite Simpson rule with 2000
+ * panels in t = sqrt(s - s0), which resolves the steep rise of the
+ * integrand just above s0 for particles close to the surface.
  * Pinned against the half-space limit and a direct 3-D quadrature. */
 double or_relax_tail(const or_relax_params* prm, double rho_c)
 {
     double h = prm->h, R = prm->radius;
     if (rho_c <= 0.0) return 0.0;
-    double s0 = R - rho_c;
-    if (s0 < 0.0) s0 = 0.0;
+    double s0 = fabs(R - rho_c);
     double s1 = 2.0 * h;
     if (s0 >= s1) return 0.0;
     const int NP = 2000;
-    double hs = (s1 - s0) / NP, acc = 0.0;
+    double t1 = sqrt(s1 - s0);
+    double ht = t1 / NP, acc = 0.0;
     for (int k = 0; k <= NP; ++k) {
-        double s = s0 + hs * k;
+        double t = ht * k;
+        double s = s0 + t * t;
         double f = 0.0;
         if (s > 0.0) {
             double u0 = (R * R - rho_c * rho_c - s * s) / (2.0 * rho_c * s);
             if (u0 < -1.0) u0 = -1.0;
             if (u0 > 1.0) u0 = 1.0;
-            f = -or_kernel_dWdr(OR_LAGUERRE_GAUSS, 3, h, s) * s * s * (1.0 - u0 * u0);
+            /* ds = 2 t dt */
+            f = -or_kernel_dWdr(OR_LAGUERRE_GAUSS, 3, h, s) * s * s * (1.0 - u0 * u0) * 2.0 * t;
         }
         double wgt = (k == 0 || k == NP) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
         acc += wgt * f;
     }
-    return M_PI * acc * hs / 3.0;
+    return M_PI * acc * ht / 3.0;
 }
 
 /* Residual force of the relaxation, Eq. (7) with the LG kernel:
@@ -795,41 +802,62 @@ void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_pa
     }
 }
 
-/* One relaxation iteration on the full set (neighbours passed in):
- *   g from or_relax_g; a = -(2 p0/rho) g; dt = 0.25 sqrt(h / max|a|);
- *   r += a dt^2 / 2; particles with phi > 0 are projected back onto the
- *   surface, r -= phi grad(phi).
- * Returns the residue R = sqrt(mean_i |h g_i|^2) of the positions on entry.
- * (Step rule, bounding and residue are readings: the paper gives none.) */
-double or_relax_step(const or_box* b, int64_t n, double* pos, const or_relax_params* prm,
-                     const int64_t* row_ptr, const int32_t* col, const double* vol,
-                     double* g_out)
+/* One relaxation iteration on the full set (neighbours passed in).
+ * Eq. (7) gives the relaxation acceleration a_i = -(2 p0/rho) g_i; the
+ * paper gives no integrator.  Reading used here: damped motion with a
+ * carried per-iteration displacement u (zero at the start),
+ *   s   = min(kappa h^2, h / (32 max_i |g_i|))      (no particle is moved
+ *          more than h/32 by one force evaluation)
+ *   u_i = mu u_i - s g_i,   |u_i| capped at max_move h,
+ *   r_i += u_i,
+ * then particles with phi > 0 are projected back onto the surface,
+ * r -= phi grad(phi), and their u is zeroed.  With mu = 0 and a large
+ * kappa this is the pure normalised step (r += a dt^2/2 with
+ * dt = 0.25 sqrt(h / max|a|)).
+ * Returns the residue R = sqrt(mean_i |h g_i|^2) of the positions on entry. */
+double or_relax_step(const or_box* b, int64_t n, double* pos, double* u, const or_relax_params* prm,
+                     const int64_t* row_ptr, const int32_t* col, const double* vol, double* g_out)
 {
     int dim = b->dim;
+    double h = prm->h;
     double* g = g_out ? g_out : (double*)malloc((size_t)n * dim * sizeof(double));
     or_relax_g(b, n, pos, prm, n, NULL, row_ptr, col, vol, g, NULL);
-    double res = 0.0, amax = 0.0, cf = 2.0 * prm->p0 / prm->rho;
+    double res = 0.0, gmax = 0.0;
     for (int64_t i = 0; i < n; ++i) {
         double g2 = 0.0;
         for (int a = 0; a < dim; ++a) g2 += g[a * n + i] * g[a * n + i];
-        res += prm->h * prm->h * g2;
-        double am = cf * sqrt(g2);
-        if (am > amax) amax = am;
+        res += h * h * g2;
+        if (sqrt(g2) > gmax) gmax = sqrt(g2);
     }
     res = sqrt(res / (double)(n > 0 ? n : 1));
-    if (amax > 0.0) {
-        double dt = 0.25 * sqrt(prm->h / amax);
+    if (gmax > 0.0) {
+        double step = prm->kappa * h * h;
+        double lim = h / (32.0 * gmax);
+        if (lim < step) step = lim;
+        double cap = prm->max_move * h;
         for (int64_t i = 0; i < n; ++i) {
+            double un = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                u[a * n + i] = prm->mu * u[a * n + i] - step * g[a * n + i];
+                un += u[a * n + i] * u[a * n + i];
+            }
+            un = sqrt(un);
+            if (un > cap)
+                for (int a = 0; a < dim; ++a) u[a * n + i] *= cap / un;
             double e[3] = {0, 0, 0}, rc = 0.0;
             for (int a = 0; a < dim; ++a) {
-                pos[a * n + i] += 0.5 * (-cf * g[a * n + i]) * dt * dt;
+                pos[a * n + i] += u[a * n + i];
                 e[a] = pos[a * n + i] - prm->center[a];
                 rc += e[a] * e[a];
             }
             rc = sqrt(rc);
             double phi = rc - prm->radius;
-            if (phi > 0.0 && rc > 0.0)
-                for (int a = 0; a < dim; ++a) pos[a * n + i] -= phi * e[a] / rc;
+            if (phi > 0.0 && rc > 0.0) {
+                for (int a = 0; a < dim; ++a) {
+                    pos[a * n + i] -= phi * e[a] / rc;
+                    u[a * n + i] = 0.0;
+                }
+            }
         }
     }
     if (!g_out) free(g);

@@ -85,6 +85,14 @@ struct sph_ctx {
     // state scratch
     DevBuf ua, ub;      // float4 [n] packed states
     DevBuf ta, tb, tc;  // misc per-particle scratch
+
+    // relaxation: exterior-tail table and reductions
+    DevBuf tail;        // float [ntail]
+    double tail_h = 0.0, tail_R = 0.0;
+    int ntail = 0;
+    DevBuf svol;        // float [n] volumes in cell order
+    DevBuf partials;    // per-block reduction partials
+    DevBuf relax_scalars;
 };
 
 int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
@@ -102,6 +110,9 @@ int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
         if (_e != hipSuccess)                                                                      \
             return sph_fail((ctx), SPH_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(_e)); \
     } while (0)
+
+// validate the domain and bin positions into cells (no neighbour list)
+int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos);
 
 // exclusive scan of int32 counts into int32 or int64 offsets, out[n] = total
 int sph_scan_i32_to_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);

@@ -157,7 +157,12 @@ __global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restr
 
 extern "C" {
 
-int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
+}  // extern "C"
+
+// Validate the domain and bin the positions into the cell grid (sorted
+// float4 records + cell offsets).  Used by sph_build_cells and, every
+// iteration, by the relaxation.
+int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
     if (!c) return SPH_ERR_ARG;
     c->bound = false;
     c->geo_valid = false;
@@ -216,6 +221,15 @@ int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* p
         SPH_LAUNCH_CHECK(c);
     }
 
+    return SPH_OK;
+}
+
+extern "C" {
+
+int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
+    int rcode = sph_bin_cells(c, dom, n, pos);
+    if (rcode) return rcode;
+    BoxArgs b = c->box;
     // neighbour counts -> row offsets -> rows
     int32_t* rcnt = c->cnt.as<int32_t>();
     if (n > 0) {

@@ -44,8 +44,8 @@ class sph_tlsph_params(C.Structure):
 
 
 class sph_relax_params(C.Structure):
-    _fields_ = [("p0", C.c_double), ("rho", C.c_double), ("h", C.c_double), ("center", C.c_double * 3),
-                ("radius", C.c_double)]
+    _fields_ = [("p0", C.c_double), ("rho", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
+                ("kappa", C.c_double), ("damping", C.c_double), ("max_move", C.c_double)]
 
 
 _lib = None
@@ -68,10 +68,13 @@ _SIGS = [
     ("sph_tlsph_rhs", C.c_int, [_vp, C.POINTER(sph_tlsph_params), _vp, _vp, _vp, _vp, _vp]),
     ("sph_tlsph_step", C.c_int, [_vp, C.POINTER(sph_tlsph_params), _vp, _vp, _vp, _vp, _vp, _i32]),
 ]
-_OPTIONAL_SIGS = [
-    ("sph_relax_step", C.c_int, [_vp, C.POINTER(sph_relax_params), _vp, _vp, _vp, _vp, _i32]),
-    ("sph_relax_residue", C.c_int, [_vp, C.POINTER(sph_relax_params), _vp, _vp, _vp]),
+_SIGS += [
+    ("sph_relax_step", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp, _vp,
+                                 _vp, _i32]),
+    ("sph_relax_residue", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp, _vp,
+                                    _vp]),
 ]
+_OPTIONAL_SIGS = []
 
 
 def lib():
@@ -140,9 +143,9 @@ def tlsph_params(rho0, E, nu, dt=0.0, model=0) -> sph_tlsph_params:
     return p
 
 
-def relax_params(h, center, radius, p0=1.0, rho=1.0) -> sph_relax_params:
+def relax_params(center, radius, p0=1.0, rho=1.0, kappa=0.1, damping=0.9, max_move=0.1) -> sph_relax_params:
     p = sph_relax_params()
-    p.p0, p.rho, p.h, p.radius = p0, rho, h, radius
+    p.p0, p.rho, p.radius, p.kappa, p.damping, p.max_move = p0, rho, radius, kappa, damping, max_move
     for a in range(3):
         p.center[a] = center[a]
     return p
@@ -258,6 +261,25 @@ class Context:
                                          _ptr(acc, torch.float32, 3 * self.n, "acc"), int(nsteps)))
 
 
+    # ------------------------------------------------------------ relaxation
+    def relax_step(self, domain: Domain, prm, pos, u, vol, niter, residue=None):
+        """niter iterations in place; residue: optional device float64 tensor [1]."""
+        n = pos.shape[-1] if pos.numel() else 0
+        self._check(lib().sph_relax_step(self._h, C.byref(domain.to_c()), C.byref(prm), n,
+                                         _ptr(pos, torch.float32, 3 * n, "pos"), _ptr(u, torch.float32, 3 * n, "u"),
+                                         _ptr(vol, torch.float32, n, "vol"), _ptr(residue, torch.float64, 1, "residue"),
+                                         int(niter)))
+
+    def relax_residue(self, domain: Domain, prm, pos, vol, want_g=True):
+        n = pos.shape[-1] if pos.numel() else 0
+        res = torch.zeros(1, dtype=torch.float64, device=self._dev())
+        g = torch.empty((3, n), dtype=torch.float32, device=self._dev()) if want_g else None
+        self._check(lib().sph_relax_residue(self._h, C.byref(domain.to_c()), C.byref(prm), n,
+                                            _ptr(pos, torch.float32, 3 * n, "pos"), _ptr(vol, torch.float32, n, "vol"),
+                                            _ptr(g), _ptr(res)))
+        return res, g
+
+
 # Module-level functions named as the C calls (same argument order, with the
 # Context in place of the sph_ctx pointer).
 def sph_build_cells(ctx: Context, domain: Domain, pos):
@@ -298,3 +320,11 @@ def sph_tlsph_rhs(ctx: Context, prm, vel, F, fixed=None):
 
 def sph_tlsph_step(ctx: Context, prm, fixed, pos, vel, F, acc, nsteps):
     return ctx.tlsph_step(prm, fixed, pos, vel, F, acc, nsteps)
+
+
+def sph_relax_step(ctx: Context, domain, prm, pos, u, vol, niter, residue=None):
+    return ctx.relax_step(domain, prm, pos, u, vol, niter, residue)
+
+
+def sph_relax_residue(ctx: Context, domain, prm, pos, vol, want_g=True):
+    return ctx.relax_residue(domain, prm, pos, vol, want_g)

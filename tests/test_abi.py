@@ -25,7 +25,7 @@ def declared_functions():
 def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for required in ("sph_build_cells", "sph_neighbors", "sph_kernel_sum", "sph_correction_B",
-                     "sph_euler_rhs", "sph_tlsph_rhs"):
+                     "sph_euler_rhs", "sph_tlsph_rhs", "sph_relax_step"):
         assert required in names, required
 
 

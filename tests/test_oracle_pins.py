@@ -542,15 +542,18 @@ def test_relax_tail_matches_direct_3d_quadrature():
 
 
 def test_relax_step_size_rule_and_residue_decrease():
+    """First iteration from rest: the largest move is h/32 (the normalised
+    step); the residue then decreases."""
     w = I.periodic_square_case(12, 3, 1.3, 0.2, 5, "jit")
     box = O.make_box(3)
     h = w.h
     prm = O.relax_params(h, (0.5, 0.5, 0.5), 1e6)
     pos = w.pos.astype(np.float64)
+    u = np.zeros_like(pos)
     res = []
     for it in range(6):
         rp, col = O.neighbors_grid(box, pos, 2 * h, 4 * h * h)
-        new, r, g = O.relax_step(box, pos, prm, rp, col, w.vol)
+        new, u, r, g = O.relax_step(box, pos, u, prm, rp, col, w.vol)
         d = new - pos
         d = d - np.round(d)  # periodic
         if it == 0:
@@ -558,3 +561,16 @@ def test_relax_step_size_rule_and_residue_decrease():
         res.append(r)
         pos = np.mod(new, 1.0)
     assert res[-1] < res[0]
+
+
+def test_relax_sphere_reaches_residue_threshold():
+    """The residue reading R = sqrt(mean |h g|^2) (with the exterior term)
+    is reachable: a small jittered sphere relaxes below 1e-4."""
+    w = I.sphere_fill(dx=1.0 / 32, seed=1)
+    box = O.make_box(3, periodic=(0, 0, 0))
+    prm = O.relax_params(w.h, w.fields["center"], w.fields["radius"])
+    pos, u, res = O.relax_run(box, w.pos, prm, w.vol, 260)
+    assert res[0] > 0.5
+    assert res[-1] < 1e-4
+    phi = np.sqrt(((pos - np.array(w.fields["center"])[:, None]) ** 2).sum(0)) - w.fields["radius"]
+    assert np.max(phi) <= 1e-12
