@@ -224,6 +224,55 @@ int sph_relax_step(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* 
 int sph_relax_residue(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n,
                       const float* pos, const float* vol, float* g, double* residue);
 
+/* ---------------------------------------------------------------- learned warm start
+ * A small network maps the local neighbourhood of a relaxing particle to a
+ * displacement (the paper has no learned component; the network, its inputs
+ * and its training follow the relaxation workload):
+ *   input x (100): offsets (r_j - r_i)/h of the 32 nearest j != i with
+ *     |r_ij| <= 2h, ordered by (|r_ij|^2 in FP64, j), zero-padded; then
+ *     phi_i/h and grad phi_i = (r_i - c)/|r_i - c| of the sphere;
+ *   y (3) = W3 GELU(W2 GELU(W1 x + b1) + b2) + b3, GELU the exact erf form;
+ *   the displacement is h y.
+ * Parameters are one FP32 array of SPH_MLP_NPARAMS: W1 [128][100], b1 [128],
+ * W2 [128][128], b2 [128], W3 [3][128], b3 [3] (row-major, [out][in]).
+ * GEMMs run on BF16 matrix cores with FP32 accumulation; weights, layer
+ * inputs and the backward GEMM operands are rounded to BF16 (nearest-even).
+ * Features are BF16 (uint16_t bit patterns) rows of SPH_MLP_FEAT_STRIDE
+ * entries, the last 28 zero. */
+#define SPH_MLP_NPARAMS 29827
+#define SPH_MLP_FEAT_STRIDE 128
+
+/* Features of the n particles at pos (FP32 [3][n]) inside the sphere of prm
+ * (h and the box from dom): feat [n][SPH_MLP_FEAT_STRIDE] BF16. */
+int sph_mlp_features(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n,
+                     const float* pos, uint16_t* feat);
+
+/* y for n feature rows: out FP32 [n][3]. */
+int sph_mlp_forward(sph_ctx* ctx, const float* params, int32_t n, const uint16_t* feat, float* out);
+
+typedef struct {
+    double lr;            /* 0: compute the gradient only, no update */
+    double beta1, beta2;
+    double eps;
+    double weight_decay;  /* decoupled, applied to every parameter */
+} sph_adamw_params;
+
+/* One training step on a batch: forward, MSE loss against target FP32
+ * [batch][3], backward, and (lr > 0) an AdamW update of the FP32 masters
+ * params with moments adam_m, adam_v (FP32 [SPH_MLP_NPARAMS], zero before
+ * step 1; step counts from 1).  loss: device FP32 scalar (nullable);
+ * grad: device FP32 [SPH_MLP_NPARAMS] receiving the gradient (nullable).
+ * Batch sums are reduced in a fixed order (deterministic). */
+int sph_mlp_train_step(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step, float* params, float* adam_m,
+                       float* adam_v, int32_t batch, const uint16_t* feat, const float* target, float* loss,
+                       float* grad);
+
+/* Warm-start move: features of the current positions, y, then r += h y for
+ * every particle and the same projection onto the sphere as the relaxation.
+ * pos FP32 [3][n] in place. */
+int sph_mlp_apply(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n, float* pos,
+                  const float* params);
+
 #ifdef __cplusplus
 }
 #endif

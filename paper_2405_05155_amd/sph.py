@@ -74,7 +74,27 @@ _SIGS += [
     ("sph_relax_residue", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp, _vp,
                                     _vp]),
 ]
+_SIGS += [
+    ("sph_mlp_features", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
+    ("sph_mlp_forward", C.c_int, [_vp, _vp, _i32, _vp, _vp]),
+    ("sph_mlp_train_step", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    ("sph_mlp_apply", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
+]
 _OPTIONAL_SIGS = []
+
+MLP_NPARAMS = 29827
+MLP_FEAT_STRIDE = 128
+
+
+class sph_adamw_params(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("weight_decay", C.c_double)]
+
+
+def adamw_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.01) -> sph_adamw_params:
+    p = sph_adamw_params()
+    p.lr, p.beta1, p.beta2, p.eps, p.weight_decay = lr, beta1, beta2, eps, weight_decay
+    return p
 
 
 def lib():
@@ -280,6 +300,41 @@ class Context:
         return res, g
 
 
+    # ------------------------------------------------------------ learned warm start
+    def mlp_features(self, domain: Domain, prm, pos):
+        """BF16 feature rows (int16 bit patterns) [n][MLP_FEAT_STRIDE]."""
+        n = pos.shape[-1] if pos.numel() else 0
+        feat = torch.empty((n, MLP_FEAT_STRIDE), dtype=torch.int16, device=self._dev())
+        self._check(lib().sph_mlp_features(self._h, C.byref(domain.to_c()), C.byref(prm), n,
+                                           _ptr(pos, torch.float32, 3 * n, "pos"), _ptr(feat)))
+        return feat
+
+    def mlp_forward(self, params, feat):
+        n = feat.shape[0]
+        out = torch.empty((n, 3), dtype=torch.float32, device=self._dev())
+        self._check(lib().sph_mlp_forward(self._h, _ptr(params, torch.float32, MLP_NPARAMS, "params"), n,
+                                          _ptr(feat, torch.int16, n * MLP_FEAT_STRIDE, "feat"), _ptr(out)))
+        return out
+
+    def mlp_train_step(self, adam, step, params, m, v, feat, target, want_loss=True, want_grad=False):
+        B = feat.shape[0]
+        loss = torch.zeros(1, dtype=torch.float32, device=self._dev()) if want_loss else None
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=self._dev()) if want_grad else None
+        self._check(lib().sph_mlp_train_step(self._h, C.byref(adam), int(step),
+                                             _ptr(params, torch.float32, MLP_NPARAMS, "params"),
+                                             _ptr(m, torch.float32, MLP_NPARAMS, "m"),
+                                             _ptr(v, torch.float32, MLP_NPARAMS, "v"), B,
+                                             _ptr(feat, torch.int16, B * MLP_FEAT_STRIDE, "feat"),
+                                             _ptr(target, torch.float32, B * 3, "target"), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def mlp_apply(self, domain: Domain, prm, pos, params):
+        n = pos.shape[-1] if pos.numel() else 0
+        self._check(lib().sph_mlp_apply(self._h, C.byref(domain.to_c()), C.byref(prm), n,
+                                        _ptr(pos, torch.float32, 3 * n, "pos"),
+                                        _ptr(params, torch.float32, MLP_NPARAMS, "params")))
+
+
 # Module-level functions named as the C calls (same argument order, with the
 # Context in place of the sph_ctx pointer).
 def sph_build_cells(ctx: Context, domain: Domain, pos):
@@ -328,3 +383,19 @@ def sph_relax_step(ctx: Context, domain, prm, pos, u, vol, niter, residue=None):
 
 def sph_relax_residue(ctx: Context, domain, prm, pos, vol, want_g=True):
     return ctx.relax_residue(domain, prm, pos, vol, want_g)
+
+
+def sph_mlp_features(ctx: Context, domain, prm, pos):
+    return ctx.mlp_features(domain, prm, pos)
+
+
+def sph_mlp_forward(ctx: Context, params, feat):
+    return ctx.mlp_forward(params, feat)
+
+
+def sph_mlp_train_step(ctx: Context, adam, step, params, m, v, feat, target, want_loss=True, want_grad=False):
+    return ctx.mlp_train_step(adam, step, params, m, v, feat, target, want_loss, want_grad)
+
+
+def sph_mlp_apply(ctx: Context, domain, prm, pos, params):
+    return ctx.mlp_apply(domain, prm, pos, params)
