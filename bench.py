@@ -95,6 +95,55 @@ def run_cpu_baseline(w, kappa, budget_s):
                       f"{dt:.1f} s)"}
 
 
+def run_relax(epochs, nside=260):
+    """Relaxation time-to-residue (R < 1e-4), plain vs learned warm start, on
+    the sphere of radius 0.3 (dx = 1/nside; 1,987,776 particles at 260).
+    The network is trained (not timed) on the plain trajectory of seed 1:
+    snapshots every 20 iterations up to 180, targets (r_final - r_k)/h,
+    batch 65,536, AdamW lr 1e-3; the timed runs use seed 2."""
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    from paper_2405_05155_amd import warmstart as WS
+    ctx = S.Context(3)
+    w1 = I.sphere_fill(dx=1.0 / nside, seed=1)
+    run1, final, snaps = WS.relax_plain(ctx, w1, snapshot_every=20, snapshot_until=180)
+    feat, targ = WS.training_set(ctx, w1, snaps, final)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, losses = WS.train(ctx, feat, targ, epochs=epochs, init=init_params(0))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    var = float(targ.pow(2).mean())
+    nsamp = int(feat.shape[0])
+    del feat, targ, snaps
+    w2 = I.sphere_fill(dx=1.0 / nside, seed=2)
+    WS.relax_plain(ctx, w2, max_iter=20)          # warm the code paths
+    plain, _, _ = WS.relax_plain(ctx, w2)
+    warm, _ = WS.relax_warm(ctx, w2, params)
+    return {"metric": "relax time-to-residue (R < 1e-4), MLP warm start vs plain", "n_particles": w2.n,
+            "plain_s": plain.seconds, "plain_iters": plain.iterations, "mlp_s": warm.seconds,
+            "mlp_iters": warm.iterations, "ratio_mlp_over_plain": warm.seconds / plain.seconds,
+            "mlp_moves_accepted": warm.accepted, "mlp_moves_tried": warm.attempted,
+            "train_s": train_s, "train_samples": nsamp, "train_epochs": epochs,
+            "train_loss_first_last": [losses[0], losses[-1]], "target_mean_square": var,
+            "train_trajectory_iters": run1.iterations}
+
+
+def init_params(seed):
+    """Seeded initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) (PyTorch's
+    linear-layer default), drawn on the host and passed in."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    shapes = [(128, 100, 100), (128, 0, 100), (128, 128, 128), (128, 0, 128), (3, 128, 128), (3, 0, 128)]
+    parts = []
+    for rows, cols, fan_in in shapes:
+        b = 1.0 / fan_in ** 0.5
+        parts.append(rng.uniform(-b, b, size=(rows, cols) if cols else (rows,)).reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,10 +152,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--nside", type=int, default=512)
+    ap.add_argument("--no-relax", action="store_true", help="skip the relaxation time-to-residue part")
+    ap.add_argument("--relax-epochs", type=int, default=50)
+    ap.add_argument("--relax-nside", type=int, default=260)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only: the hot path is single-GPU (see the sharding note in the "
-              "design document); run with --gpus 1", file=sys.stderr)
+        print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -145,6 +196,8 @@ def main():
                      "kernel": "k_euler<2,stage> (Heun stage, 1.6h)",
                      "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch},
     }
+    if not args.no_relax:
+        out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(w, 1.6, args.cpu_budget)
     print(json.dumps(out), flush=True)
