@@ -70,6 +70,70 @@ def run_gpu(w, kappa, steps, warmup):
             "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
 
 
+def run_euler_3d(nside, kappa, steps, warmup):
+    """3-D Taylor-Green in the periodic unit cube (nside^3 particles)."""
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    w = I.taylor_green_3d(nside=nside)
+    f = w.fields
+    ctx = S.Context(3)
+    ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa), torch.as_tensor(w.pos, device="cuda"))
+    ctx.neighbors()
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    prm = S.euler_params(c=f["c"], rho0=f["rho0_eos"], rho_ref=f["rho_ref"], eta=f["eta"], mu=f["mu"],
+                         dt=w.meta["dt"])
+    d = torch.as_tensor(f["drho"], device="cuda").clone()
+    m = torch.as_tensor(f["mom"], device="cuda").clone()
+    ctx.euler_step(prm, d, m, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.euler_step(prm, d, m, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nnz = ctx.nnz
+    ctx.close()
+    return {"n_particles": w.n, "nnz": nnz, "ms_per_step": ms / steps,
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+
+
+def run_plate(kappa, steps, warmup, nx=430):
+    """TLSPH cantilever plate 0.2 x 0.02 x 0.04 at dx = 0.2/nx (plus four
+    clamp layers), neo-Hookean, kick-drift-kick steps."""
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    w = I.cantilever_plate(nx=nx)
+    f = w.fields
+    ctx = S.Context(3)
+    ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=(0, 0, 0)),
+                    torch.as_tensor(w.pos, device="cuda"))
+    ctx.neighbors()
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    prm = S.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=0)
+    pos = torch.as_tensor(w.pos, device="cuda").clone()
+    vel = torch.as_tensor(w.fields["vel"], device="cuda").clone()
+    F = torch.eye(3, device="cuda").repeat(w.n, 1, 1).contiguous()
+    fixed = torch.as_tensor(f["fixed"], device="cuda")
+    _, acc = ctx.tlsph_rhs(prm, vel, F, fixed)
+    ctx.tlsph_step(prm, fixed, pos, vel, F, acc, warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.tlsph_step(prm, fixed, pos, vel, F, acc, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nnz = ctx.nnz
+    ctx.close()
+    return {"n_particles": w.n, "nnz": nnz, "ms_per_step": ms / steps,
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+
+
 def run_cpu_baseline(w, kappa, budget_s):
     import numpy as np
 
@@ -155,6 +219,11 @@ def main():
     ap.add_argument("--no-relax", action="store_true", help="skip the relaxation time-to-residue part")
     ap.add_argument("--relax-epochs", type=int, default=50)
     ap.add_argument("--relax-nside", type=int, default=260)
+    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D Taylor-Green and TLSPH plate lines")
+    ap.add_argument("--nside3d", type=int, default=200)
+    ap.add_argument("--steps3d", type=int, default=50)
+    ap.add_argument("--steps-plate", type=int, default=200)
+    ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
@@ -167,6 +236,10 @@ def main():
     torch.cuda.set_device(0)
     w = I.taylor_green_2d(nside=args.nside)
 
+    if args.kappa:
+        one = run_gpu(w, args.kappa, args.steps, args.warmup)
+        print(json.dumps({"kappa": args.kappa, **one}), flush=True)
+        return
     tw = run_gpu(w, 1.6, args.steps, args.warmup)
     sw = run_gpu(w, 2.0, args.steps, args.warmup)
 
@@ -196,6 +269,13 @@ def main():
                      "kernel": "k_euler<2,stage> (Heun stage, 1.6h)",
                      "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch},
     }
+    if not args.no_extra:
+        tw3, sw3 = run_euler_3d(args.nside3d, 1.6, args.steps3d, 5), run_euler_3d(args.nside3d, 2.0, args.steps3d, 5)
+        out["taylor_green_3d"] = {"nside": args.nside3d, "kappa1.6": tw3, "kappa2": sw3,
+                                  "speedup_tw_over_sw": sw3["ms_per_step"] / tw3["ms_per_step"]}
+        twp, swp = run_plate(1.6, args.steps_plate, 5), run_plate(2.0, args.steps_plate, 5)
+        out["tlsph_plate"] = {"kappa1.6": twp, "kappa2": swp,
+                              "speedup_tw_over_sw": swp["ms_per_step"] / twp["ms_per_step"]}
     if not args.no_relax:
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:

@@ -34,6 +34,7 @@ KernelConsts make_kernel_consts(int type, int dim, double h) {
 
 BoxArgs make_box_args(const sph_domain& d, double rc) {
     BoxArgs b{};
+    b.dim = d.dim;
     for (int a = 0; a < 3; ++a) {
         if (a < d.dim) {
             double L = d.hi[a] - d.lo[a];
@@ -58,7 +59,24 @@ BoxArgs make_box_args(const sph_domain& d, double rc) {
             b.halfLd[a] = 0.5;
         }
     }
+    // Morton keys when the power-of-two key space stays small
+    int m = 1;
+    for (int a = 0; a < d.dim; ++a)
+        while (m < b.nc[a]) m <<= 1;
+    double slots = 1.0;
+    for (int a = 0; a < d.dim; ++a) slots *= m;
+    b.morton = (slots <= (double)(1 << 27) && m <= (d.dim == 2 ? 65536 : 1024)) ? 1 : 0;
     return b;
+}
+
+int64_t cell_slots(const BoxArgs& b) {
+    if (!b.morton) return (int64_t)b.nc[0] * b.nc[1] * b.nc[2];
+    int64_t m = 1;
+    for (int a = 0; a < b.dim; ++a)
+        while (m < b.nc[a]) m <<= 1;
+    int64_t s = 1;
+    for (int a = 0; a < b.dim; ++a) s *= m;
+    return s;
 }
 
 extern "C" {

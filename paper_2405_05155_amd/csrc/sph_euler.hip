@@ -4,7 +4,9 @@
 //
 // State layout: one float4 record per particle (drho, m_x, m_y, m_z), so a
 // neighbour's whole state is one 16-byte gather; geometry comes from the
-// context's cached records (position, V, B upper triangle).
+// context's cached records (position, V, B upper triangle).  All records
+// live in cell-sorted (Morton) order; the caller's arrays are gathered in
+// and scattered out at the caller index.
 #include "sph_internal.h"
 
 #include <cstdlib>
@@ -36,21 +38,24 @@ __device__ __forceinline__ float4 primitive(const float4& u, float rho_ref) {
 }
 
 template <int DIM>
-__global__ void k_pack_state(int32_t n, float rho_ref, const float* __restrict__ drho, const float* __restrict__ mom,
-                             float4* __restrict__ U, float4* __restrict__ P) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void k_pack_state(int32_t n, float rho_ref, const float4* __restrict__ sorted,
+                             const float* __restrict__ drho, const float* __restrict__ mom, float4* __restrict__ U,
+                             float4* __restrict__ P) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t i = __float_as_int(sorted[s].w);
     float4 u = make_float4(drho[i], mom[i], mom[(int64_t)n + i], DIM == 3 ? mom[2 * (int64_t)n + i] : 0.f);
-    U[i] = u;
-    P[i] = primitive<DIM>(u, rho_ref);
+    U[s] = u;
+    P[s] = primitive<DIM>(u, rho_ref);
 }
 
 template <int DIM>
-__global__ void k_unpack_state(int32_t n, const float4* __restrict__ U, float* __restrict__ drho,
-                               float* __restrict__ mom) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 u = U[i];
+__global__ void k_unpack_state(int32_t n, const float4* __restrict__ sorted, const float4* __restrict__ U,
+                               float* __restrict__ drho, float* __restrict__ mom) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t i = __float_as_int(sorted[s].w);
+    float4 u = U[s];
     drho[i] = u.x;
     mom[i] = u.y;
     mom[(int64_t)n + i] = u.z;
@@ -75,9 +80,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
                                                const int32_t* __restrict__ col, const float4* __restrict__ geo0,
                                                const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                                const float4* U, const float4* __restrict__ P, const float4* U0,
-                                               float4* Uout, float4* Pout, float* __restrict__ drho_dt,
-                                               float* __restrict__ dmom_dt) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                               float4* Uout, float4* Pout, const float4* __restrict__ sorted,
+                                               float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
+    // i below is the cell-sorted slot; XCD-contiguous block order
+    int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * blockDim.x + threadIdx.x;
     int32_t i = (int32_t)(t / L);
     const int sub = (int)(t % L);
     // whole groups leave together (n * L is not always a multiple of the block)
@@ -190,9 +196,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     if (DIM == 2) R[3] = 0.f;
     if (sub != 0) return;
     if (STAGE == 0) {
-        drho_dt[i] = R[0];
+        int32_t ic = __float_as_int(sorted[i].w);
+        drho_dt[ic] = R[0];
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) dmom_dt[(int64_t)a * n + i] = R[1 + a];
+        for (int a = 0; a < DIM; ++a) dmom_dt[(int64_t)a * n + ic] = R[1 + a];
         return;
     }
     float4 ui = U[i];
@@ -255,8 +262,8 @@ struct StageIO {
 template <int DIM, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     hipLaunchKernelGGL((k_euler<DIM, STAGE, L>), dim3(grid_for((int64_t)c->n * L, BLK)), dim3(BLK), 0, c->stream, c->n,
-                       ea, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(),
-                       c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout, io.Pout, io.dr, io.dm);
+                       ea, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(),
+                       c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm);
 }
 
 // Lanes per particle: enough lane groups to give every SIMD several waves
@@ -294,11 +301,11 @@ void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
 
 int pack(sph_ctx* c, float rho_ref, const float* drho, const float* mom, float4* U, float4* P) {
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_pack_state<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, rho_ref, drho,
-                           mom, U, P);
+        hipLaunchKernelGGL(k_pack_state<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, rho_ref,
+                           c->sorted.as<float4>(), drho, mom, U, P);
     else
-        hipLaunchKernelGGL(k_pack_state<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, rho_ref, drho,
-                           mom, U, P);
+        hipLaunchKernelGGL(k_pack_state<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, rho_ref,
+                           c->sorted.as<float4>(), drho, mom, U, P);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -351,9 +358,11 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)
-        hipLaunchKernelGGL(k_unpack_state<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, U, drho, mom);
+        hipLaunchKernelGGL(k_unpack_state<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                           c->sorted.as<float4>(), U, drho, mom);
     else
-        hipLaunchKernelGGL(k_unpack_state<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, U, drho, mom);
+        hipLaunchKernelGGL(k_unpack_state<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                           c->sorted.as<float4>(), U, drho, mom);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }

@@ -48,7 +48,46 @@ struct BoxArgs {
     int periodic[3];
     double Ld[3];       // FP64 box lengths for the exact neighbour test
     double halfLd[3];
+    int dim;
+    int morton;         // 1: cell keys are Morton codes; 0: linear (z, y, x)
 };
+
+// Cell keys.  Morton (Z-order) codes of the cell coordinates keep cells that
+// are close in space close in the cell-sorted particle array; the linear
+// key is the fallback for grids whose Morton key space would be too large.
+__host__ __device__ __forceinline__ uint32_t spread2(uint32_t x) {  // 16 bits -> even bits
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t x) {  // 10 bits -> every third bit
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+__host__ __device__ __forceinline__ int32_t cell_key(const BoxArgs& b, int x, int y, int z) {
+    if (b.morton) {
+        if (b.dim == 2) return (int32_t)(spread2((uint32_t)x) | (spread2((uint32_t)y) << 1));
+        return (int32_t)(spread3((uint32_t)x) | (spread3((uint32_t)y) << 1) | (spread3((uint32_t)z) << 2));
+    }
+    return (z * b.nc[1] + y) * b.nc[0] + x;
+}
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin; remapping
+// the block index gives XCD k one contiguous range of the cell-sorted
+// particles, so each XCD's L2 holds the neighbourhood of its own region.
+__device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
+    const int32_t X = 8;
+    int32_t per = nb / X, rem = nb % X;
+    int32_t x = b % X, k = b / X;
+    return x * per + (x < rem ? x : rem) + k;
+}
 
 struct sph_ctx {
     int dim = 0;
@@ -71,8 +110,11 @@ struct sph_ctx {
     DevBuf cell_start;  // int32 [ncell + 1]
     DevBuf sorted;      // float4 [n] (x, y, z, bits(index)) in cell order
     DevBuf cnt;         // int32 [n]
-    DevBuf row_ptr;     // int64 [n + 1]
-    DevBuf col;         // int32 [nnz]
+    DevBuf row_ptr;     // int64 [n + 1]   caller order (export)
+    DevBuf col;         // int32 [nnz]     caller order, caller indices, rows ascending
+    DevBuf cnt_s;       // int32 [n]       per cell-sorted slot
+    DevBuf rp_s;        // int64 [n + 1]   cell-sorted rows
+    DevBuf col_s;       // int32 [nnz]     cell-sorted rows, sorted-slot indices
     DevBuf scan_tmp;    // block sums of the scans
     DevBuf counter;     // small device counters / reductions
 
@@ -91,6 +133,7 @@ struct sph_ctx {
     double tail_h = 0.0, tail_R = 0.0;
     int ntail = 0;
     DevBuf svol;        // float [n] volumes in cell order
+    DevBuf sfield;      // float [n] a caller field in cell order
     DevBuf partials;    // per-block reduction partials
     DevBuf relax_scalars;
 };
@@ -204,3 +247,4 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 
 KernelConsts make_kernel_consts(int type, int dim, double h);
 BoxArgs make_box_args(const sph_domain& d, double rc);
+int64_t cell_slots(const BoxArgs& b);  // size of the cell-key space

@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(128) k_features(int32_t n, int32_t r0, int32_t
                 int x = cxi + ox;
                 if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
                 else if (x < 0 || x >= b.nc[0]) continue;
-                int key = (z * b.nc[1] + y) * b.nc[0] + x;
+                int32_t key = cell_key(b, x, y, z);
                 int t1 = cell_start[key + 1];
                 for (int t = cell_start[key]; t < t1; ++t) {
                     float4 q = sorted[t];

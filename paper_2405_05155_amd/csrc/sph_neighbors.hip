@@ -1,6 +1,12 @@
-// sph_neighbors.hip -- binding a particle configuration: uniform cell grid
-// (counting sort by cell), and the exact neighbour sets N(i) = {j != i :
-// |r_ij|^2 <= (kappa h)^2} stored as CSR in caller order, rows ascending.
+// sph_neighbors.hip -- binding a particle configuration: a uniform cell grid
+// with Morton-ordered cell keys (counting sort by key, members of a cell in
+// ascending caller index), and the exact neighbour sets
+// N(i) = {j != i : |r_ij|^2 <= (kappa h)^2} stored twice:
+//   - in cell-sorted order with sorted-slot column indices (the layout every
+//     pair loop of the library runs on: neighbours of a block of slots lie in
+//     a compact region of the sorted arrays), and
+//   - in caller order with caller indices, each row ascending (the exported
+//     CSR).
 //
 // Neighbour decision.  The compact support of Eq. (5) keeps r = kappa h.  The
 // squared distance is evaluated in FP64 from the FP32 coordinates with the
@@ -32,7 +38,7 @@ __global__ void k_bin(int32_t n, int dim, const float* __restrict__ pos, BoxArgs
     int cx = cell_coord(x, b.lo[0], b.inv_cell[0], b.nc[0]);
     int cy = cell_coord(y, b.lo[1], b.inv_cell[1], b.nc[1]);
     int cz = dim == 3 ? cell_coord(z, b.lo[2], b.inv_cell[2], b.nc[2]) : 0;
-    int32_t key = (cz * b.nc[1] + cy) * b.nc[0] + cx;
+    int32_t key = cell_key(b, cx, cy, cz);
     cell_of[i] = key;
     slot[i] = atomicAdd(&count[key], 1);
 }
@@ -72,7 +78,7 @@ __device__ __forceinline__ double md_image(double d, double L, double halfL, int
     return d;
 }
 
-// Visit every j in the 3^dim block of cells around particle p; call f(j).
+// Visit every sorted slot t in the 3^dim block of cells around p; f(t, q).
 template <int DIM, class F>
 __device__ __forceinline__ void for_each_candidate(const float4& p, const BoxArgs& b,
                                                    const int32_t* __restrict__ cell_start,
@@ -95,9 +101,9 @@ __device__ __forceinline__ void for_each_candidate(const float4& p, const BoxArg
                 int x = cx + ox;
                 if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
                 else if (x < 0 || x >= b.nc[0]) continue;
-                int32_t key = (z * b.nc[1] + y) * b.nc[0] + x;
+                int32_t key = cell_key(b, x, y, z);
                 int32_t s1 = cell_start[key + 1];
-                for (int32_t s = cell_start[key]; s < s1; ++s) f(sorted[s]);
+                for (int32_t s = cell_start[key]; s < s1; ++s) f(s, sorted[s]);
             }
         }
     }
@@ -117,31 +123,37 @@ __device__ __forceinline__ bool is_neighbour(const float4& p, const float4& q, c
     return d2 <= rc2;
 }
 
-// One thread per particle in cell order: count neighbours (pass 0) or write
-// them into the row of the caller index, then sort the row (pass 1).
+// One thread per sorted slot.  PASS 0: neighbour count (stored per slot and
+// per caller index).  PASS 1: the sorted row (sorted-slot indices, in
+// traversal order) and the caller row (caller indices, then sorted).
 template <int DIM, int PASS>
 __global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restrict__ cell_start,
-                        const float4* __restrict__ sorted, int32_t* __restrict__ cnt,
-                        const int64_t* __restrict__ row_ptr, int32_t* __restrict__ col) {
+                        const float4* __restrict__ sorted, int32_t* __restrict__ cnt_s, int32_t* __restrict__ cnt_u,
+                        const int64_t* __restrict__ rp_s, int32_t* __restrict__ col_s,
+                        const int64_t* __restrict__ rp_u, int32_t* __restrict__ col_u) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     float4 p = sorted[s];
     int32_t i = __float_as_int(p.w);
     int32_t c = 0;
-    int64_t base = PASS ? row_ptr[i] : 0;
-    for_each_candidate<DIM>(p, b, cell_start, sorted, [&](const float4& q) {
-        int32_t j = __float_as_int(q.w);
-        if (j != i && is_neighbour<DIM>(p, q, b, rc2)) {
-            if (PASS) col[base + c] = j;
+    int64_t bs = PASS ? rp_s[s] : 0;
+    int64_t bu = PASS ? rp_u[i] : 0;
+    for_each_candidate<DIM>(p, b, cell_start, sorted, [&](int32_t t, const float4& q) {
+        if (t != s && is_neighbour<DIM>(p, q, b, rc2)) {
+            if (PASS) {
+                col_s[bs + c] = t;
+                col_u[bu + c] = __float_as_int(q.w);
+            }
             ++c;
         }
     });
     if (!PASS) {
-        cnt[i] = c;
+        cnt_s[s] = c;
+        cnt_u[i] = c;
         return;
     }
-    // insertion sort of the row (rows are short and arrive cell by cell)
-    int32_t* r = col + base;
+    // the caller row ascending (rows are short and arrive cell by cell)
+    int32_t* r = col_u + bu;
     for (int32_t a = 1; a < c; ++a) {
         int32_t v = r[a];
         int32_t k = a - 1;
@@ -155,21 +167,17 @@ __global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restr
 
 }  // namespace
 
-extern "C" {
-
-}  // extern "C"
-
 // Validate the domain and bin the positions into the cell grid (sorted
-// float4 records + cell offsets).  Used by sph_build_cells and, every
-// iteration, by the relaxation.
+// float4 records with the caller index in .w, and cell offsets).  Used by
+// sph_build_cells and, every iteration, by the relaxation.
 int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
     if (!c) return SPH_ERR_ARG;
     c->bound = false;
     c->geo_valid = false;
     if (!dom) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom is NULL");
-    if (dom->dim != c->dim) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom->dim %d != context dim %d", dom->dim, c->dim);
-    if (!(dom->h > 0.0) || !(dom->kappa > 0.0))
-        return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: h and kappa must be > 0");
+    if (dom->dim != c->dim)
+        return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom->dim %d != context dim %d", dom->dim, c->dim);
+    if (!(dom->h > 0.0) || !(dom->kappa > 0.0)) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: h and kappa must be > 0");
     if (dom->kernel != SPH_WENDLAND && dom->kernel != SPH_LAGUERRE_GAUSS)
         return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: unknown kernel %d", dom->kernel);
     if (n < 0) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: n < 0");
@@ -184,8 +192,9 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
                             L, 3.0 * rc * (1.0 + 1e-3));
     }
     BoxArgs b = make_box_args(*dom, rc);
-    int64_t ncell = (int64_t)b.nc[0] * b.nc[1] * b.nc[2];
-    if (ncell > (int64_t)1 << 30) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: %lld cells exceed the table limit", (long long)ncell);
+    int64_t ncell = cell_slots(b);
+    if (ncell > (int64_t)1 << 30)
+        return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: %lld cells exceed the table limit", (long long)ncell);
 
     c->dom = *dom;
     c->n = n;
@@ -201,9 +210,8 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
     SPH_HIP(c, c->sorted.ensure(nn * sizeof(float4)));
     SPH_HIP(c, c->cnt.ensure((ncell + 1 > nn ? ncell + 1 : nn) * sizeof(int32_t)));
     SPH_HIP(c, c->cell_start.ensure((ncell + 1) * sizeof(int32_t)));
-    SPH_HIP(c, c->row_ptr.ensure((nn + 1) * sizeof(int64_t)));
 
-    int32_t* count = c->cnt.as<int32_t>();  // reused: per-cell counts here, per-row counts below
+    int32_t* count = c->cnt.as<int32_t>();
     SPH_HIP(c, hipMemsetAsync(count, 0, (ncell + 1) * sizeof(int32_t), c->stream));
     if (n > 0) {
         hipLaunchKernelGGL(k_bin, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->dim, pos, b,
@@ -220,7 +228,6 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
                            c->cell_start.as<int32_t>(), c->sorted.as<float4>());
         SPH_LAUNCH_CHECK(c);
     }
-
     return SPH_OK;
 }
 
@@ -230,33 +237,43 @@ int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* p
     int rcode = sph_bin_cells(c, dom, n, pos);
     if (rcode) return rcode;
     BoxArgs b = c->box;
-    // neighbour counts -> row offsets -> rows
-    int32_t* rcnt = c->cnt.as<int32_t>();
+    int64_t nn = n > 0 ? n : 1;
+    SPH_HIP(c, c->cnt_s.ensure(nn * sizeof(int32_t)));
+    SPH_HIP(c, c->rp_s.ensure((nn + 1) * sizeof(int64_t)));
+    SPH_HIP(c, c->row_ptr.ensure((nn + 1) * sizeof(int64_t)));
+    int32_t* cnt_u = c->cnt.as<int32_t>();  // the cell counts are consumed by now
     if (n > 0) {
         if (c->dim == 2)
             hipLaunchKernelGGL((k_neigh<2, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
-                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), rcnt, nullptr, nullptr);
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->cnt_s.as<int32_t>(), cnt_u,
+                               nullptr, nullptr, nullptr, nullptr);
         else
             hipLaunchKernelGGL((k_neigh<3, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
-                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), rcnt, nullptr, nullptr);
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->cnt_s.as<int32_t>(), cnt_u,
+                               nullptr, nullptr, nullptr, nullptr);
         SPH_LAUNCH_CHECK(c);
     }
-    rcode = sph_scan_i32_to_i64(c, rcnt, c->row_ptr.as<int64_t>(), n);
+    rcode = sph_scan_i32_to_i64(c, c->cnt_s.as<int32_t>(), c->rp_s.as<int64_t>(), n);
+    if (rcode) return rcode;
+    rcode = sph_scan_i32_to_i64(c, cnt_u, c->row_ptr.as<int64_t>(), n);
     if (rcode) return rcode;
     int64_t nnz = 0;
     SPH_HIP(c, hipMemcpyAsync(&nnz, c->row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     SPH_HIP(c, hipStreamSynchronize(c->stream));
     c->nnz = nnz;
     SPH_HIP(c, c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+    SPH_HIP(c, c->col_s.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
     if (n > 0 && nnz > 0) {
         if (c->dim == 2)
             hipLaunchKernelGGL((k_neigh<2, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
-                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr,
-                               c->row_ptr.as<int64_t>(), c->col.as<int32_t>());
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr, nullptr,
+                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->row_ptr.as<int64_t>(),
+                               c->col.as<int32_t>());
         else
             hipLaunchKernelGGL((k_neigh<3, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
-                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr,
-                               c->row_ptr.as<int64_t>(), c->col.as<int32_t>());
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr, nullptr,
+                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->row_ptr.as<int64_t>(),
+                               c->col.as<int32_t>());
         SPH_LAUNCH_CHECK(c);
     }
     c->bound = true;
@@ -268,7 +285,8 @@ int sph_neighbors(sph_ctx* c, int64_t* row_ptr, int32_t* col, int64_t cap, int64
     if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_neighbors: no configuration bound (call sph_build_cells)");
     if (nnz) *nnz = c->nnz;
     if (!row_ptr) return sph_fail(c, SPH_ERR_ARG, "sph_neighbors: row_ptr is NULL");
-    if (cap < c->nnz) return sph_fail(c, SPH_ERR_CAPACITY, "sph_neighbors: capacity %lld < nnz %lld", (long long)cap, (long long)c->nnz);
+    if (cap < c->nnz)
+        return sph_fail(c, SPH_ERR_CAPACITY, "sph_neighbors: capacity %lld < nnz %lld", (long long)cap, (long long)c->nnz);
     if (c->nnz > 0 && !col) return sph_fail(c, SPH_ERR_ARG, "sph_neighbors: col is NULL");
     SPH_HIP(c, hipMemcpyAsync(row_ptr, c->row_ptr.as<int64_t>(), (size_t)(c->n + 1) * sizeof(int64_t),
                               hipMemcpyDeviceToDevice, c->stream));

@@ -2,9 +2,11 @@
 // kernel summation, the correction matrix B_i (Eq. 9) with its FP64
 // inversion, the cached geometry records, and the corrected gradient.
 //
-// Mapping: one thread per particle in caller order, looping over its CSR
-// row; all sums are FP32 with Kahan compensation, gathers of neighbour data
-// are 16-byte records.
+// Mapping: one thread per particle in cell-sorted (Morton) order, looping
+// over its sorted CSR row, with the block index remapped so that each XCD
+// works on one contiguous range of slots; all sums are FP32 with Kahan
+// compensation; caller-indexed inputs are gathered once into sorted order
+// and outputs are written back at the caller index.
 #include "sph_internal.h"
 
 namespace {
@@ -18,25 +20,37 @@ __device__ __forceinline__ void pair_d(const float4& pi, const float4& pj, const
     d[2] = DIM == 3 ? min_image(pi.z - pj.z, b.L[2], b.halfL[2], b.periodic[2]) : 0.f;
 }
 
+// dst[s] = src[caller index of slot s]
+__global__ void k_to_sorted(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ src,
+                            float* __restrict__ dst) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    dst[s] = src[__float_as_int(sorted[s].w)];
+}
+
+__device__ __forceinline__ int32_t slot_id() {
+    return xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+}
+
 template <int DIM>
-__global__ void k_kernel_sum(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ pos4,
-                             const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                             const float* __restrict__ vol, float* __restrict__ out) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 pi = pos4[i];
-    Kahan s;
-    s.init(kernel_W(kc, 0.f) * vol[i]);
-    int64_t e = row_ptr[i + 1];
-    for (int64_t k = row_ptr[i]; k < e; ++k) {
-        int32_t j = col[k];
+__global__ void k_kernel_sum(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ sorted,
+                             const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             const float* __restrict__ svol, float* __restrict__ out) {
+    int32_t s = slot_id();
+    if (s >= n) return;
+    float4 pi = sorted[s];
+    Kahan acc;
+    acc.init(kernel_W(kc, 0.f) * svol[s]);
+    int64_t e = rp[s + 1];
+    for (int64_t k = rp[s]; k < e; ++k) {
+        int32_t t = col[k];
         float d[3];
-        pair_d<DIM>(pi, pos4[j], b, d);
+        pair_d<DIM>(pi, sorted[t], b, d);
         float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         float q = sqrtf(r2) * kc.hinv;
-        s.add(kernel_W(kc, q) * vol[j]);
+        acc.add(kernel_W(kc, q) * svol[t]);
     }
-    out[i] = s.value();
+    out[__float_as_int(pi.w)] = acc.value();
 }
 
 // FP64 inverse of the symmetric matrix given by its upper triangle
@@ -90,26 +104,27 @@ __device__ __forceinline__ void store_geo(int32_t i, const float4& p, float V, c
 }
 
 template <int DIM>
-__global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ pos4,
+__global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ sorted,
                              const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                             const float* __restrict__ vol, float* __restrict__ Bout, double* __restrict__ B64,
+                             const float* __restrict__ svol, float* __restrict__ Bout, double* __restrict__ B64,
                              float4* __restrict__ geo0, float4* __restrict__ geo1, float2* __restrict__ geo2,
                              int32_t* __restrict__ ndeg) {
     constexpr int NU = DIM == 2 ? 3 : 6;
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 pi = pos4[i];
+    int32_t s = slot_id();
+    if (s >= n) return;
+    float4 pi = sorted[s];
+    int32_t i = __float_as_int(pi.w);
     Kahan M[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) M[u].init();
-    int64_t e = row_ptr[i + 1];
-    for (int64_t k = row_ptr[i]; k < e; ++k) {
-        int32_t j = col[k];
+    int64_t e = row_ptr[s + 1];
+    for (int64_t k = row_ptr[s]; k < e; ++k) {
+        int32_t t = col[k];
         float d[3];
-        pair_d<DIM>(pi, pos4[j], b, d);
+        pair_d<DIM>(pi, sorted[t], b, d);
         float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         float q = sqrtf(r2) * kc.hinv;
-        float w = kernel_F(kc, q) * vol[j];  // grad W = F d;  r (x) grad W V = F V d d^T
+        float w = kernel_F(kc, q) * svol[t];  // grad W = F d;  r (x) grad W V = F V d d^T
         if (DIM == 2) {
             M[0].add(w * d[0] * d[0]);
             M[1].add(w * d[0] * d[1]);
@@ -157,15 +172,17 @@ __global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4
             if (B64) B64[(int64_t)i * 9 + t] = Bd[idx[t]];
         }
     }
-    store_geo<DIM>(i, pi, vol[i], Bu, geo0, geo1, geo2);
+    store_geo<DIM>(s, pi, svol[s], Bu, geo0, geo1, geo2);
 }
 
 template <int DIM>
-__global__ void k_set_geo(int32_t n, const float4* __restrict__ pos4, const float* __restrict__ vol,
+__global__ void k_set_geo(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ vol,
                           const float* __restrict__ B, float4* __restrict__ geo0, float4* __restrict__ geo1,
                           float2* __restrict__ geo2) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float4 ps = sorted[s];
+    int32_t i = __float_as_int(ps.w);
     float Bu[6];
     if (DIM == 2) {
         const float* m = B + (int64_t)i * 4;
@@ -174,7 +191,7 @@ __global__ void k_set_geo(int32_t n, const float4* __restrict__ pos4, const floa
         const float* m = B + (int64_t)i * 9;
         Bu[0] = m[0]; Bu[1] = m[1]; Bu[2] = m[2]; Bu[3] = m[4]; Bu[4] = m[5]; Bu[5] = m[8];
     }
-    store_geo<DIM>(i, pos4[i], vol[i], Bu, geo0, geo1, geo2);
+    store_geo<DIM>(s, ps, vol[i], Bu, geo0, geo1, geo2);
 }
 
 // Unpack the upper triangle of B_i from the geometry records.
@@ -196,30 +213,32 @@ template <int DIM>
 __global__ void k_gradient(int32_t n, BoxArgs b, float hinv, float cF, const int64_t* __restrict__ row_ptr,
                            const int32_t* __restrict__ col, const float4* __restrict__ geo0,
                            const float4* __restrict__ geo1, const float2* __restrict__ geo2,
-                           const float* __restrict__ f, float* __restrict__ grad) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+                           const float4* __restrict__ sorted, const float* __restrict__ f,
+                           float* __restrict__ grad) {
+    int32_t s = slot_id();
+    if (s >= n) return;
     float4 gi;
     float Bu[6];
-    load_B<DIM>(i, geo0, geo1, geo2, gi, Bu);
-    float fi = f[i];
-    Kahan s[DIM];
+    load_B<DIM>(s, geo0, geo1, geo2, gi, Bu);
+    int32_t i = __float_as_int(sorted[s].w);
+    float fi = f[s];
+    Kahan acc[DIM];
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) s[a].init();
-    int64_t e = row_ptr[i + 1];
-    for (int64_t k = row_ptr[i]; k < e; ++k) {
-        int32_t j = col[k];
-        float4 gj = geo0[j];
+    for (int a = 0; a < DIM; ++a) acc[a].init();
+    int64_t e = row_ptr[s + 1];
+    for (int64_t k = row_ptr[s]; k < e; ++k) {
+        int32_t t = col[k];
+        float4 gj = geo0[t];
         float d[3];
         pair_d<DIM>(gi, gj, b, d);
         float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         float q = sqrtf(r2) * hinv;
         float Vj = DIM == 2 ? gj.z : gj.w;
-        float w = wendland_F(q, cF) * Vj * (f[j] - fi);
+        float w = wendland_F(q, cF) * Vj * (f[t] - fi);
 #pragma unroll
-        for (int a = 0; a < DIM; ++a) s[a].add(w * d[a]);
+        for (int a = 0; a < DIM; ++a) acc[a].add(w * d[a]);
     }
-    float v[3] = {s[0].value(), s[1].value(), DIM == 3 ? s[DIM - 1].value() : 0.f};
+    float v[3] = {acc[0].value(), acc[1].value(), DIM == 3 ? acc[DIM - 1].value() : 0.f};
     if (DIM == 2) {
         grad[i] = Bu[0] * v[0] + Bu[1] * v[1];
         grad[(int64_t)n + i] = Bu[1] * v[0] + Bu[2] * v[1];
@@ -228,6 +247,16 @@ __global__ void k_gradient(int32_t n, BoxArgs b, float hinv, float cF, const int
         grad[(int64_t)n + i] = Bu[1] * v[0] + Bu[3] * v[1] + Bu[4] * v[2];
         grad[2 * (int64_t)n + i] = Bu[2] * v[0] + Bu[4] * v[1] + Bu[5] * v[2];
     }
+}
+
+int to_sorted(sph_ctx* c, const float* src, DevBuf& dst) {
+    SPH_HIP(c, dst.ensure((size_t)(c->n > 0 ? c->n : 1) * sizeof(float)));
+    if (c->n > 0) {
+        hipLaunchKernelGGL(k_to_sorted, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                           c->sorted.as<float4>(), src, dst.as<float>());
+        SPH_LAUNCH_CHECK(c);
+    }
+    return SPH_OK;
 }
 
 int ensure_geo(sph_ctx* c) {
@@ -247,13 +276,17 @@ int sph_kernel_sum(sph_ctx* c, const float* vol, float* out) {
     if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_kernel_sum: no configuration bound");
     if (c->n > 0 && (!vol || !out)) return sph_fail(c, SPH_ERR_ARG, "sph_kernel_sum: NULL array");
     if (c->n == 0) return SPH_OK;
+    int r = to_sorted(c, vol, c->svol);
+    if (r) return r;
     KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_kernel_sum<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                           c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, out);
+                           c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->svol.as<float>(),
+                           out);
     else
         hipLaunchKernelGGL(k_kernel_sum<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                           c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, out);
+                           c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->svol.as<float>(),
+                           out);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -268,15 +301,19 @@ int sph_correction_B(sph_ctx* c, const float* vol, float* B, double* B64, int32_
     int32_t* ndeg = c->counter.as<int32_t>();
     SPH_HIP(c, hipMemsetAsync(ndeg, 0, sizeof(int32_t), c->stream));
     if (c->n > 0) {
+        r = to_sorted(c, vol, c->svol);
+        if (r) return r;
         KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
         if (c->dim == 2)
             hipLaunchKernelGGL(k_correction<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                               c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, B, B64,
-                               c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+                               c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
+                               c->svol.as<float>(), B, B64, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->geo2.as<float2>(), ndeg);
         else
             hipLaunchKernelGGL(k_correction<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                               c->pos4.as<float4>(), c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), vol, B, B64,
-                               c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+                               c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
+                               c->svol.as<float>(), B, B64, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->geo2.as<float2>(), ndeg);
         SPH_LAUNCH_CHECK(c);
     }
     if (n_degenerate) {
@@ -296,11 +333,11 @@ int sph_set_correction(sph_ctx* c, const float* vol, const float* B) {
     if (c->n > 0) {
         if (c->dim == 2)
             hipLaunchKernelGGL(k_set_geo<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
-                               c->pos4.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->sorted.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
                                c->geo2.as<float2>());
         else
             hipLaunchKernelGGL(k_set_geo<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
-                               c->pos4.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
+                               c->sorted.as<float4>(), vol, B, c->geo0.as<float4>(), c->geo1.as<float4>(),
                                c->geo2.as<float2>());
         SPH_LAUNCH_CHECK(c);
     }
@@ -315,15 +352,19 @@ int sph_gradient(sph_ctx* c, const float* f, float* grad) {
     if (c->dom.kernel != SPH_WENDLAND) return sph_fail(c, SPH_ERR_ARG, "sph_gradient: Wendland kernel only");
     if (c->n > 0 && (!f || !grad)) return sph_fail(c, SPH_ERR_ARG, "sph_gradient: NULL array");
     if (c->n == 0) return SPH_OK;
+    int r = to_sorted(c, f, c->sfield);
+    if (r) return r;
     KernelConsts kc = make_kernel_consts(SPH_WENDLAND, c->dim, c->dom.h);
     if (c->dim == 2)
         hipLaunchKernelGGL(k_gradient<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc.hinv,
-                           kc.cF, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), c->geo0.as<float4>(),
-                           c->geo1.as<float4>(), c->geo2.as<float2>(), f, grad);
+                           kc.cF, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->geo0.as<float4>(),
+                           c->geo1.as<float4>(), c->geo2.as<float2>(), c->sorted.as<float4>(), c->sfield.as<float>(),
+                           grad);
     else
         hipLaunchKernelGGL(k_gradient<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc.hinv,
-                           kc.cF, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(), c->geo0.as<float4>(),
-                           c->geo1.as<float4>(), c->geo2.as<float2>(), f, grad);
+                           kc.cF, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->geo0.as<float4>(),
+                           c->geo1.as<float4>(), c->geo2.as<float2>(), c->sorted.as<float4>(), c->sfield.as<float>(),
+                           grad);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }

@@ -2,10 +2,10 @@
 // kernel of Eq. 8) of particles filling a sphere, with the exterior-tail
 // term, an FP64 residue reduction and the damped move + surface bound.
 //
-// Per iteration: re-bin (cells of edge >= 2h), one thread per particle in
-// cell order scans the 3x3x3 cell block (each row of three cells is one
-// contiguous range of the cell-sorted array), a two-stage reduction gives
-// max|g| and the FP64 residue, then one thread per particle moves it.
+// Per iteration: re-bin (cells of edge >= 2h, Morton-ordered keys), one
+// thread per particle in cell order scans the 3x3x3 cell block, a two-stage
+// reduction gives max|g| and the FP64 residue, then one thread per particle
+// moves it.
 #include "sph_internal.h"
 
 #include <vector>
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const 
                                                  float* __restrict__ part_max, double* __restrict__ part_sum) {
     __shared__ float smax[BLK];
     __shared__ double ssum[BLK];
-    int32_t s = blockIdx.x * BLK + threadIdx.x;
+    int32_t s = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
     float gmag = 0.f;
     double gh2 = 0.0;
     if (s < n) {
@@ -179,31 +179,12 @@ __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const 
                 int y = cy + oy;
                 if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
                 else if (y < 0 || y >= b.nc[1]) continue;
-                int row = (z * b.nc[1] + y) * b.nc[0];
-                // the x-cells of this row: one contiguous range unless wrapped
-                int xs[3], nx = 0;
-                if (!b.periodic[0]) {
-                    int x0 = cx > 0 ? cx - 1 : 0;
-                    int x1 = cx < b.nc[0] - 1 ? cx + 1 : b.nc[0] - 1;
-                    xs[0] = x0;
-                    xs[1] = x1;
-                    nx = -1;  // one range [x0, x1]
-                } else {
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        int x = cx + ox;
-                        xs[nx++] = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
-                    }
-                }
-                int nranges = nx < 0 ? 1 : nx;
-                for (int rgi = 0; rgi < nranges; ++rgi) {
-                    int t0, t1;
-                    if (nx < 0) {
-                        t0 = cell_start[row + xs[0]];
-                        t1 = cell_start[row + xs[1] + 1];
-                    } else {
-                        t0 = cell_start[row + xs[rgi]];
-                        t1 = cell_start[row + xs[rgi] + 1];
-                    }
+                for (int ox = -1; ox <= 1; ++ox) {
+                    int x = cx + ox;
+                    if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
+                    else if (x < 0 || x >= b.nc[0]) continue;
+                    int32_t key = cell_key(b, x, y, z);
+                    int t0 = cell_start[key], t1 = cell_start[key + 1];
                     for (int t = t0; t < t1; ++t) {
                         if (t == s) continue;
                         float4 q = sorted[t];

@@ -8,7 +8,9 @@
 //      P(F) and the per-particle record A_i = P_i B0_i^T (9 floats);
 //   B: gather A_j -> acceleration, velocity kick.
 // The stress is evaluated from H = F - I so that small strains keep FP32
-// resolution (no I - C^{-1} or ln J cancellation).
+// resolution (no I - C^{-1} or ln J cancellation).  Velocity, acceleration
+// and A records live in cell-sorted (Morton) order; F and positions stay in
+// the caller's arrays and are accessed at the caller index of each slot.
 #include "sph_internal.h"
 
 namespace {
@@ -111,11 +113,12 @@ template <int MODE>
 __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, BoxArgs b, TlArgs t, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col, const float4* __restrict__ geo0,
                                               const float4* __restrict__ geo1, const float2* __restrict__ geo2,
-                                              const float4* __restrict__ VH, float* __restrict__ F,
-                                              float* __restrict__ dFdt, float* __restrict__ pos,
+                                              const float4* __restrict__ sorted, const float4* __restrict__ VH,
+                                              float* __restrict__ F, float* __restrict__ dFdt, float* __restrict__ pos,
                                               float4* __restrict__ A0, float4* __restrict__ A1, float* __restrict__ A2) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
     if (i >= n) return;
+    const int32_t ic = __float_as_int(sorted[i].w);                                     // caller index
     float4 gi = geo0[i];
     float4 vi = VH[i];
     bool fixed = vi.w != 0.f;
@@ -149,22 +152,22 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, BoxArgs b, TlArgs t, co
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Fd[r * 3 + c] = Ld[r * 3 + 0] * B[c] + Ld[r * 3 + 1] * B[3 + c] + Ld[r * 3 + 2] * B[6 + c];
-    float* Fi = F + (int64_t)i * 9;
+    float* Fi = F + (int64_t)ic * 9;
     float H[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) H[k] = Fi[k];
     if (MODE == 0) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) dFdt[(int64_t)i * 9 + k] = Fd[k];
+        for (int k = 0; k < 9; ++k) dFdt[(int64_t)ic * 9 + k] = Fd[k];
     } else if (!fixed) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             H[k] += t.dt * Fd[k];
             Fi[k] = H[k];
         }
-        pos[i] += t.dt * vi.x;
-        pos[(int64_t)n + i] += t.dt * vi.y;
-        pos[2 * (int64_t)n + i] += t.dt * vi.z;
+        pos[ic] += t.dt * vi.x;
+        pos[(int64_t)n + ic] += t.dt * vi.y;
+        pos[2 * (int64_t)n + ic] += t.dt * vi.z;
     }
     H[0] -= 1.f;
     H[4] -= 1.f;
@@ -187,9 +190,10 @@ template <int MODE>
 __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, BoxArgs b, TlArgs t, const int64_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col, const float4* __restrict__ geo0,
                                               const float4* __restrict__ A0, const float4* __restrict__ A1,
-                                              const float* __restrict__ A2, float4* __restrict__ VH,
-                                              float4* __restrict__ ACC, float* __restrict__ acc) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+                                              const float* __restrict__ A2, const float4* __restrict__ sorted,
+                                              float4* __restrict__ VH, float4* __restrict__ ACC,
+                                              float* __restrict__ acc) {
+    int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
     if (i >= n) return;
     float4 gi = geo0[i];
     float4 a0 = A0[i], a1 = A1[i];
@@ -218,9 +222,10 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, BoxArgs b, TlArgs t, co
     bool fixed = vh.w != 0.f;
     if (fixed) a[0] = a[1] = a[2] = 0.f;
     if (MODE == 0) {
-        acc[i] = a[0];
-        acc[(int64_t)n + i] = a[1];
-        acc[2 * (int64_t)n + i] = a[2];
+        const int32_t ic = __float_as_int(sorted[i].w);
+        acc[ic] = a[0];
+        acc[(int64_t)n + ic] = a[1];
+        acc[2 * (int64_t)n + ic] = a[2];
     } else {
         ACC[i] = make_float4(a[0], a[1], a[2], 0.f);
         if (!fixed) VH[i] = make_float4(vh.x + t.dt * a[0], vh.y + t.dt * a[1], vh.z + t.dt * a[2], 0.f);
@@ -228,25 +233,29 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, BoxArgs b, TlArgs t, co
 }
 
 // VH = v + half_dt * a (0 and flagged on fixed rows); ACC = a
-__global__ void k_tl_init(int32_t n, float half_dt, const float* __restrict__ vel, const float* __restrict__ acc,
-                          const int32_t* __restrict__ fixed, float4* __restrict__ VH, float4* __restrict__ ACC) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__global__ void k_tl_init(int32_t n, float half_dt, const float4* __restrict__ sorted, const float* __restrict__ vel,
+                          const float* __restrict__ acc, const int32_t* __restrict__ fixed, float4* __restrict__ VH,
+                          float4* __restrict__ ACC) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t i = __float_as_int(sorted[s].w);
     bool fx = fixed && fixed[i] != 0;
     float4 a = acc ? make_float4(acc[i], acc[(int64_t)n + i], acc[2 * (int64_t)n + i], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
     if (fx) a = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ACC) ACC[i] = a;
-    VH[i] = fx ? make_float4(0.f, 0.f, 0.f, 1.f)
+    if (ACC) ACC[s] = a;
+    VH[s] = fx ? make_float4(0.f, 0.f, 0.f, 1.f)
                : make_float4(vel[i] + half_dt * a.x, vel[(int64_t)n + i] + half_dt * a.y,
                              vel[2 * (int64_t)n + i] + half_dt * a.z, 0.f);
 }
 
 // v = VH - half_dt ACC; acc = ACC
-__global__ void k_tl_finish(int32_t n, float half_dt, const float4* __restrict__ VH, const float4* __restrict__ ACC,
-                            float* __restrict__ vel, float* __restrict__ acc) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float4 v = VH[i], a = ACC[i];
+__global__ void k_tl_finish(int32_t n, float half_dt, const float4* __restrict__ sorted,
+                            const float4* __restrict__ VH, const float4* __restrict__ ACC, float* __restrict__ vel,
+                            float* __restrict__ acc) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int32_t i = __float_as_int(sorted[s].w);
+    float4 v = VH[s], a = ACC[s];
     bool fx = v.w != 0.f;
     vel[i] = fx ? 0.f : v.x - half_dt * a.x;
     vel[(int64_t)n + i] = fx ? 0.f : v.y - half_dt * a.y;
@@ -307,15 +316,16 @@ int sph_tlsph_rhs(sph_ctx* c, const sph_tlsph_params* p, const float* vel, const
     if (r) return r;
     TlArgs t = make_args(c, p);
     dim3 g(grid_for(c->n, BLK)), bl(BLK);
-    hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, 0.f, vel, (const float*)nullptr, fixed, c->ua.as<float4>(),
-                       (float4*)nullptr);
+    const float4* sorted = c->sorted.as<float4>();
+    hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, 0.f, sorted, vel, (const float*)nullptr, fixed,
+                       c->ua.as<float4>(), (float4*)nullptr);
     // F is only read in MODE 0
-    hipLaunchKernelGGL(k_tl_a<0>, g, bl, 0, c->stream, c->n, c->box, t, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(),
-                       c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), c->ua.as<float4>(),
+    hipLaunchKernelGGL(k_tl_a<0>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
+                       c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), sorted, c->ua.as<float4>(),
                        const_cast<float*>(F), dF_dt, (float*)nullptr, c->ta.as<float4>(), c->tb.as<float4>(),
                        c->tc.as<float>());
-    hipLaunchKernelGGL(k_tl_b<0>, g, bl, 0, c->stream, c->n, c->box, t, c->row_ptr.as<int64_t>(), c->col.as<int32_t>(),
-                       c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(),
+    hipLaunchKernelGGL(k_tl_b<0>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
+                       c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(), sorted,
                        c->ua.as<float4>(), (float4*)nullptr, acc);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
@@ -333,19 +343,20 @@ int sph_tlsph_step(sph_ctx* c, const sph_tlsph_params* p, const int32_t* fixed, 
     if (r) return r;
     TlArgs t = make_args(c, p);
     dim3 g(grid_for(c->n, BLK)), bl(BLK);
-    hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, t.half_dt, vel, acc, fixed, c->ua.as<float4>(),
+    const float4* sorted = c->sorted.as<float4>();
+    hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, t.half_dt, sorted, vel, acc, fixed, c->ua.as<float4>(),
                        c->ub.as<float4>());
     for (int32_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL(k_tl_a<1>, g, bl, 0, c->stream, c->n, c->box, t, c->row_ptr.as<int64_t>(),
-                           c->col.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(),
-                           c->ua.as<float4>(), F, (float*)nullptr, pos, c->ta.as<float4>(), c->tb.as<float4>(),
+        hipLaunchKernelGGL(k_tl_a<1>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(),
+                           c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(),
+                           sorted, c->ua.as<float4>(), F, (float*)nullptr, pos, c->ta.as<float4>(), c->tb.as<float4>(),
                            c->tc.as<float>());
-        hipLaunchKernelGGL(k_tl_b<1>, g, bl, 0, c->stream, c->n, c->box, t, c->row_ptr.as<int64_t>(),
-                           c->col.as<int32_t>(), c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(),
-                           c->tc.as<float>(), c->ua.as<float4>(), c->ub.as<float4>(), (float*)nullptr);
+        hipLaunchKernelGGL(k_tl_b<1>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(),
+                           c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(),
+                           c->tc.as<float>(), sorted, c->ua.as<float4>(), c->ub.as<float4>(), (float*)nullptr);
     }
-    hipLaunchKernelGGL(k_tl_finish, g, bl, 0, c->stream, c->n, t.half_dt, c->ua.as<float4>(), c->ub.as<float4>(), vel,
-                       acc);
+    hipLaunchKernelGGL(k_tl_finish, g, bl, 0, c->stream, c->n, t.half_dt, sorted, c->ua.as<float4>(),
+                       c->ub.as<float4>(), vel, acc);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
