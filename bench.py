@@ -29,14 +29,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def stage_bytes_2d(n: int, nnz: int) -> float:
-    """Algorithmic HBM bytes of one Heun stage launch (2-D), averaged over the
-    two stages: per particle the geometry record (16 B) and B record (8 B),
-    the state record (16 B), the stage-start record (16 B, second stage
-    only), the output record (16 B), the row offset (8 B); per pair the
-    column index (4 B).  Neighbour records are re-reads served by caches and
-    are not counted."""
-    per_particle = 16 + 8 + 16 + 16 + 8 + 0.5 * 16
-    return n * per_particle + 4.0 * nnz
+    """Algorithmic HBM bytes of one RHS evaluation in 2-D: per particle read
+    the position (8 B), V (4 B), density (4 B), velocity (8 B) and the
+    correction matrix (16 B), write the three rates (12 B) and read the row
+    offset (8 B): 60 B; per neighbour pair the column index (4 B).
+    Neighbour records are re-reads served by caches and are not counted."""
+    return 60.0 * n + 4.0 * nnz
 
 
 def run_gpu(w, kappa, steps, warmup):
