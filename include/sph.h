@@ -76,6 +76,16 @@ void sph_ctx_destroy(sph_ctx* ctx);
 const char* sph_last_error(const sph_ctx* ctx);
 /* Re-bind the context to another stream of the same device. */
 int sph_set_stream(sph_ctx* ctx, void* hip_stream);
+/* Execution strategy of the pair loops over a fixed configuration (the
+ * Eulerian stage).  SPH_TILING_OFF (the default): lane groups per particle
+ * gather their neighbours through the caches.  SPH_TILING_ON: workgroups
+ * stage cell tiles (a Morton-aligned block of cells and its one-cell ring)
+ * in LDS and evaluate each unique pair once, wherever the configuration
+ * admits tiles (Morton cell keys, periodic axes long enough for a tile and
+ * its ring, a tile within the LDS budget); elsewhere the per-particle path
+ * runs.  Results agree to rounding.  Returns SPH_ERR_ARG for another mode. */
+enum { SPH_TILING_OFF = 0, SPH_TILING_ON = 1 };
+int sph_set_tiling(sph_ctx* ctx, int mode);
 
 /* ---------------------------------------------------------------- neighbours
  * sph_build_cells: bind a particle configuration.  Bins the n positions

@@ -102,9 +102,12 @@ void sph_ctx_destroy(sph_ctx* c) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf* bufs[] = {&c->pos4, &c->cell_of, &c->slot, &c->cell_start, &c->sorted, &c->cnt,
-                      &c->row_ptr, &c->col, &c->scan_tmp, &c->counter, &c->geo0, &c->geo1,
-                      &c->geo2, &c->ua, &c->ub, &c->ta, &c->tb, &c->tc};
+    DevBuf* bufs[] = {&c->pos4,        &c->cell_of,      &c->slot,           &c->cell_start,  &c->sorted,
+                      &c->cnt,         &c->row_ptr,      &c->col,            &c->cnt_s,       &c->rp_s,
+                      &c->col_s,       &c->scan_tmp,     &c->counter,        &c->geo0,        &c->geo1,
+                      &c->geo2,        &c->ua,           &c->ub,             &c->ta,          &c->tb,
+                      &c->tc,          &c->tail,         &c->svol,           &c->sfield,      &c->partials,
+                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE};
     for (DevBuf* b : bufs) b->release();
     (void)hipSetDevice(prev);
     delete c;
@@ -115,6 +118,14 @@ const char* sph_last_error(const sph_ctx* c) { return c ? c->err : "null context
 int sph_set_stream(sph_ctx* c, void* s) {
     if (!c) return SPH_ERR_ARG;
     c->stream = (hipStream_t)s;
+    return SPH_OK;
+}
+
+int sph_set_tiling(sph_ctx* c, int mode) {
+    if (!c) return SPH_ERR_ARG;
+    if (mode != SPH_TILING_OFF && mode != SPH_TILING_ON)
+        return sph_fail(c, SPH_ERR_ARG, "sph_set_tiling: unknown mode %d", mode);
+    c->tiling = mode;
     return SPH_OK;
 }
 

@@ -17,6 +17,7 @@ constexpr int BLK = 256;
 
 struct EulerArgs {
     float c, c2, c2inv;
+    float hc;       // c / 2
     float rho0;     // EOS reference density
     float rho_ref;  // rho = rho_ref + drho
     float poff;     // rho_ref - rho0 (so p = c^2 (drho + poff))
@@ -33,8 +34,8 @@ struct EulerArgs {
 // loop needs no division; each stage writes both records of its result.
 template <int DIM>
 __device__ __forceinline__ float4 primitive(const float4& u, float rho_ref) {
-    float rho = rho_ref + u.x;
-    return make_float4(u.x, u.y / rho, u.z / rho, DIM == 3 ? u.w / rho : 0.f);
+    float inv = 1.f / (rho_ref + u.x);
+    return make_float4(u.x, u.y * inv, u.z * inv, DIM == 3 ? u.w * inv : 0.f);
 }
 
 template <int DIM>
@@ -67,127 +68,211 @@ __global__ void k_unpack_state(int32_t n, const float4* __restrict__ sorted, con
 // multiples of a power of two, exact.
 __device__ __forceinline__ float wrap(float d, float L, float invL) { return fmaf(-L, rintf(d * invL), d); }
 
-// STAGE 0: write rates; 1: Uout = U + dt R(U); 2: Uout = (U0 + U + dt R(U)) / 2.
-// Stage 1 and 2 also write Pout, the primitive record of Uout.
-// Uout / Pout may alias U0 / the own records of the stage input: each
-// particle's records are read and written only by its own lane group, and
-// neighbours are gathered from P, which a stage never writes in place.
-// L lanes per particle: lane `sub` of the group takes the neighbours
-// row_ptr[i] + sub, + sub + L, ...; the compensated partial sums are combined
-// by group_sum and lane 0 of the group writes the result.
-template <int DIM, int STAGE, int L>
+// Gathered records of one neighbour: geometry (2-D (x, y, V, B00) and
+// (B01, B11); 3-D (x, y, z, V), (B00, B01, B02, B11) and (B12, B22)) and the
+// primitive state (drho, v).
+template <int DIM>
+struct NbrRec {
+    float4 g0, g1, pr;
+    float2 g2;
+};
+
+template <int DIM>
+__device__ __forceinline__ void gather_nbr(int32_t j, const float4* __restrict__ geo0,
+                                           const float4* __restrict__ geo1, const float2* __restrict__ geo2,
+                                           const float4* __restrict__ P, NbrRec<DIM>& r) {
+    r.g0 = geo0[j];
+    if (DIM == 2) {
+        const float2 t = reinterpret_cast<const float2*>(geo1)[j];
+        r.g1 = make_float4(t.x, t.y, 0.f, 0.f);
+        r.g2 = make_float2(0.f, 0.f);
+    } else {
+        r.g1 = geo1[j];
+        r.g2 = geo2[j];
+    }
+    r.pr = P[j];
+}
+
+// Own particle's quantities for its pair loop.
+template <int DIM>
+struct OwnState {
+    float x[3];
+    float B[DIM == 2 ? 3 : 6];  // upper triangle of B
+    float v[3];
+    float rho, p;
+};
+
+// One pair (i, j) of Eq. (19) with the corrected gradient (Eq. 28) and the
+// limited Riemann solution (Eqs. 26-27), accumulated into the particle's
+// compensated sums.  Branch-free: a coincident partner (r = 0, also the
+// particle itself standing in for a padding entry) gets zero weight.
+template <int DIM>
+__device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnState<DIM>& o, const NbrRec<DIM>& nb,
+                                                Kahan& sr, Kahan* sm) {
+    constexpr int NBU = DIM == 2 ? 3 : 6;
+    const float4 gj = nb.g0;
+    float Bs[NBU];
+    if (DIM == 2) {
+        Bs[0] = o.B[0] + gj.w; Bs[1] = o.B[1] + nb.g1.x; Bs[2] = o.B[2] + nb.g1.y;
+    } else {
+        Bs[0] = o.B[0] + nb.g1.x; Bs[1] = o.B[1] + nb.g1.y; Bs[2] = o.B[2] + nb.g1.z;
+        Bs[3] = o.B[3] + nb.g1.w; Bs[4] = o.B[4] + nb.g2.x; Bs[5] = o.B[5] + nb.g2.y;
+    }
+    const float4 pj4 = nb.pr;
+    const float xj[3] = {gj.x, gj.y, gj.z};
+    float d[DIM];
+    float r2 = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        d[a] = wrap(o.x[a] - xj[a], ea.L[a], ea.invL[a]);
+        r2 = fmaf(d[a], d[a], r2);
+    }
+    const bool live = r2 > 0.f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float tq = fmaf(-0.5f * ea.hinv, r2 * rinv, 1.f);  // 1 - q/2
+    const float Fh = ea.cFh * tq * tq * tq;                   // (dW/dr)/r / 2
+    const float Vj = live ? (DIM == 2 ? gj.z : gj.w) : 0.f;
+    // gc = (B_i + B_j)/2 grad W = Fh (B_i + B_j) d
+    float gc[DIM];
+    if (DIM == 2) {
+        gc[0] = Fh * fmaf(Bs[0], d[0], Bs[1] * d[1]);
+        gc[1] = Fh * fmaf(Bs[1], d[0], Bs[2] * d[1]);
+    } else {
+        gc[0] = Fh * fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
+        gc[1] = Fh * fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
+        gc[2] = Fh * fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
+    }
+    // Riemann problem along n = -d / r (from i to j), left = i, right = j
+    const float vj[3] = {pj4.y, pj4.z, pj4.w};
+    float dvd = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) dvd = fmaf(o.v[a] - vj[a], d[a], dvd);
+    const float du_lr = -dvd * rinv;  // u_l - u_r
+    const float rhoj = ea.rho_ref + pj4.x;
+    const float pj = ea.c2 * (pj4.x + ea.poff);
+    const float rhobar_c = 0.5f * ea.c * (o.rho + rhoj);
+    const float beta = fminf(ea.eta_c * fmaxf(du_lr, 0.f), 1.f);
+    const float hb = 0.5f * beta;
+    const float du = hb * beta * (o.p - pj) * fast_rcp(rhobar_c);  // u* - mean
+    const float pstar = fmaf(0.5f, o.p + pj, hb * rhobar_c * du_lr);
+    const float rhostar = fmaf(pstar, ea.c2inv, ea.rho0);
+    // v* = (v_i + v_j)/2 + (u* - mean) n
+    const float dun = -du * rinv;
+    float vs[DIM];
+    float vg = 0.f;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        vs[a] = fmaf(0.5f, o.v[a] + vj[a], dun * d[a]);
+        vg = fmaf(vs[a], gc[a], vg);
+    }
+    const float m2V = -2.f * Vj;
+    const float rvg = rhostar * vg;
+    sr.add(m2V * rvg);
+    const float visc = ea.mu4 * Vj * Fh;  // 2 mu V (dW/dr)/r
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) sm[a].add(fmaf(m2V, fmaf(rvg, vs[a], pstar * gc[a]), visc * (o.v[a] - vj[a])));
+}
+
+// Row layouts of the per-particle kernel.
+enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
+
+// One lane group of L lanes per particle.  STAGE 0: write rates; 1: Uout =
+// U + dt R(U); 2: Uout = (U0 + U + dt R(U)) / 2; stages 1 and 2 also write
+// Pout, the primitive record of Uout.  Uout / Pout may alias U0 / the own
+// records of the stage input: each particle's records are read and written
+// only by its own lane group, and neighbours are gathered from P, which a
+// stage never writes in place.  Lane `sub` of the group takes the row
+// entries sub, sub + L, ...; the compensated partial sums are combined by
+// group_sum and lane 0 of the group writes the result.
+//   ROWS_CSR / ROWS_ELL: a software pipeline over the row: the records of
+//     the next entry are gathered and the column index after it loaded
+//     before the current pair is evaluated.
+//   ROWS_ELL_BATCH: the lane's E entries are loaded at once (all column
+//     indices, then all records) and then evaluated (short rows, where a
+//     pipeline would be too shallow to cover the memory latency).
+// Entries past the end of a row use the particle itself (zero weight).
+template <int DIM, int STAGE, int L, int MODE, int E>
 __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col, const float4* __restrict__ geo0,
+                                               const int32_t* __restrict__ col, int32_t ell_S,
+                                               const float4* __restrict__ geo0,
                                                const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                                const float4* U, const float4* __restrict__ P, const float4* U0,
                                                float4* Uout, float4* Pout, const float4* __restrict__ sorted,
                                                float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
     // i below is the cell-sorted slot; XCD-contiguous block order
-    int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * blockDim.x + threadIdx.x;
-    int32_t i = (int32_t)(t / L);
+    const int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * blockDim.x + threadIdx.x;
+    const int32_t i = (int32_t)(t / L);
     const int sub = (int)(t % L);
     // whole groups leave together (n * L is not always a multiple of the block)
     if (i >= n) return;
-    constexpr int NBU = DIM == 2 ? 3 : 6;  // upper-triangle entries of B
-    float4 gi = geo0[i];
-    float xi[3] = {gi.x, gi.y, gi.z};
-    float Bi[NBU];
-    if (DIM == 2) {
-        float2 t2 = reinterpret_cast<const float2*>(geo1)[i];
-        Bi[0] = gi.w; Bi[1] = t2.x; Bi[2] = t2.y;
-    } else {
-        float4 t4 = geo1[i];
-        float2 u2 = geo2[i];
-        Bi[0] = t4.x; Bi[1] = t4.y; Bi[2] = t4.z; Bi[3] = t4.w; Bi[4] = u2.x; Bi[5] = u2.y;
+
+    // batch mode: the lane's column indices first (they depend on nothing)
+    int32_t jb[E > 0 ? E : 1];
+    if (MODE == ROWS_ELL_BATCH) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int32_t kk = sub + q * L;
+            jb[q] = kk < ell_S ? col[(int64_t)kk * n + i] : i;
+        }
     }
-    float4 pi4 = P[i];
-    float rhoi = ea.rho_ref + pi4.x;
-    float vi[3] = {pi4.y, pi4.z, pi4.w};
-    float pi_ = ea.c2 * (pi4.x + ea.poff);
+
+    OwnState<DIM> o;
+    const float4 gi = geo0[i];
+    o.x[0] = gi.x; o.x[1] = gi.y; o.x[2] = gi.z;
+    if (DIM == 2) {
+        const float2 t2 = reinterpret_cast<const float2*>(geo1)[i];
+        o.B[0] = gi.w; o.B[1] = t2.x; o.B[2] = t2.y;
+    } else {
+        const float4 t4 = geo1[i];
+        const float2 u2 = geo2[i];
+        o.B[0] = t4.x; o.B[1] = t4.y; o.B[2] = t4.z; o.B[3] = t4.w; o.B[4] = u2.x; o.B[5] = u2.y;
+    }
+    const float4 pi4 = P[i];
+    o.rho = ea.rho_ref + pi4.x;
+    o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
+    o.p = ea.c2 * (pi4.x + ea.poff);
+    // the stage update's inputs, loaded now so that their latency overlaps the row
+    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
+    if (STAGE != 0 && sub == 0) {
+        ui = U[i];
+        if (STAGE == 2) u0 = U0[i];
+    }
 
     Kahan sr, sm[DIM];
     sr.init();
 #pragma unroll
     for (int a = 0; a < DIM; ++a) sm[a].init();
 
-    // The next column index is loaded one iteration ahead; the pair is
-    // branch-free (coincident particles get zero weight), so all gathers of
-    // an iteration are issued before its arithmetic.
-    int64_t e = row_ptr[i + 1];
-    int64_t k = row_ptr[i] + sub;
-    int32_t jn = k < e ? col[k] : i;
-    while (k < e) {
-        int32_t j = jn;
-        k += L;
-        jn = k < e ? col[k] : i;
-        float4 gj = geo0[j];
-        float Bs[NBU];
-        if (DIM == 2) {
-            float2 t2 = reinterpret_cast<const float2*>(geo1)[j];
-            Bs[0] = Bi[0] + gj.w; Bs[1] = Bi[1] + t2.x; Bs[2] = Bi[2] + t2.y;
+    if (MODE == ROWS_ELL_BATCH) {
+        NbrRec<DIM> nb[E > 0 ? E : 1];
+#pragma unroll
+        for (int q = 0; q < E; ++q) gather_nbr<DIM>(jb[q], geo0, geo1, geo2, P, nb[q]);
+#pragma unroll
+        for (int q = 0; q < E; ++q) accumulate_pair<DIM>(ea, o, nb[q], sr, sm);
+    } else {
+        int64_t k, e, stride;
+        if (MODE == ROWS_ELL) {
+            k = (int64_t)sub * n + i;
+            stride = n;
+            e = (int64_t)ell_S * n;
         } else {
-            float4 t4 = geo1[j];
-            float2 u2 = geo2[j];
-            Bs[0] = Bi[0] + t4.x; Bs[1] = Bi[1] + t4.y; Bs[2] = Bi[2] + t4.z;
-            Bs[3] = Bi[3] + t4.w; Bs[4] = Bi[4] + u2.x; Bs[5] = Bi[5] + u2.y;
+            k = row_ptr[i] + sub;
+            stride = 1;
+            e = row_ptr[i + 1];
         }
-        float4 pj4 = P[j];
-        float xj[3] = {gj.x, gj.y, gj.z};
-        float d[DIM];
-        float r2 = 0.f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            d[a] = wrap(xi[a] - xj[a], ea.L[a], ea.invL[a]);
-            r2 = fmaf(d[a], d[a], r2);
+        NbrRec<DIM> cur, nxt;
+        {
+            const int32_t j0 = k < e ? col[k] : i;
+            gather_nbr<DIM>(j0, geo0, geo1, geo2, P, cur);
         }
-        const bool live = r2 > 0.f;
-        float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
-        float tq = fmaf(-0.5f * ea.hinv, r2 * rinv, 1.f);  // 1 - q/2
-        float Fh = ea.cFh * tq * tq * tq;                   // (dW/dr)/r / 2
-        float Vj = live ? (DIM == 2 ? gj.z : gj.w) : 0.f;
-        // gc = (B_i + B_j)/2 grad W = Fh (B_i + B_j) d
-        float gc[DIM];
-        if (DIM == 2) {
-            gc[0] = Fh * fmaf(Bs[0], d[0], Bs[1] * d[1]);
-            gc[1] = Fh * fmaf(Bs[1], d[0], Bs[2] * d[1]);
-        } else {
-            gc[0] = Fh * fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
-            gc[1] = Fh * fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
-            gc[2] = Fh * fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
+        int32_t jn = k + L * stride < e ? col[k + L * stride] : i;
+        while (k < e) {
+            gather_nbr<DIM>(jn, geo0, geo1, geo2, P, nxt);
+            jn = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
+            k += L * stride;
+            accumulate_pair<DIM>(ea, o, cur, sr, sm);
+            cur = nxt;
         }
-        // Riemann problem along n = -d / r (from i to j), left = i, right = j
-        float vj[3] = {pj4.y, pj4.z, pj4.w};
-        float dvd = 0.f, svd = 0.f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            dvd = fmaf(vi[a] - vj[a], d[a], dvd);
-            svd = fmaf(vi[a] + vj[a], d[a], svd);
-        }
-        float du_lr = -dvd * rinv;               // u_l - u_r
-        float umean = -0.5f * svd * rinv;        // (u_l + u_r) / 2
-        float rhoj = ea.rho_ref + pj4.x;
-        float pj = ea.c2 * (pj4.x + ea.poff);
-        float rhobar_c = 0.5f * ea.c * (rhoi + rhoj);
-        float beta = fminf(ea.eta_c * fmaxf(du_lr, 0.f), 1.f);
-        float hb = 0.5f * beta;
-        float du = hb * beta * (pi_ - pj) * fast_rcp(rhobar_c);   // u* - mean
-        float pstar = fmaf(0.5f, pi_ + pj, hb * rhobar_c * du_lr);
-        float rhostar = fmaf(pstar, ea.c2inv, ea.rho0);
-        // v* = (v_i + v_j)/2 + (u* - mean) n
-        float dun = -du * rinv;
-        float vs[DIM];
-        float vg = 0.f;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            vs[a] = fmaf(0.5f, vi[a] + vj[a], dun * d[a]);
-            vg = fmaf(vs[a], gc[a], vg);
-        }
-        float m2V = -2.f * Vj;
-        float rvg = rhostar * vg;
-        sr.add(m2V * rvg);
-        float visc = ea.mu4 * Vj * Fh;  // 2 mu V (dW/dr)/r
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) sm[a].add(fmaf(m2V, fmaf(rvg, vs[a], pstar * gc[a]), visc * (vi[a] - vj[a])));
     }
     float R[4];
     R[0] = group_sum<L>(sr);
@@ -196,19 +281,17 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     if (DIM == 2) R[3] = 0.f;
     if (sub != 0) return;
     if (STAGE == 0) {
-        int32_t ic = __float_as_int(sorted[i].w);
+        const int32_t ic = __float_as_int(sorted[i].w);
         drho_dt[ic] = R[0];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) dmom_dt[(int64_t)a * n + ic] = R[1 + a];
         return;
     }
-    float4 ui = U[i];
     float4 un;
     if (STAGE == 1) {
         un = make_float4(ui.x + ea.dt * R[0], ui.y + ea.dt * R[1], ui.z + ea.dt * R[2],
                          DIM == 3 ? ui.w + ea.dt * R[3] : 0.f);
     } else {
-        float4 u0 = U0[i];
         un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * R[0])), 0.5f * (u0.y + (ui.y + ea.dt * R[1])),
                          0.5f * (u0.z + (ui.z + ea.dt * R[2])),
                          DIM == 3 ? 0.5f * (u0.w + (ui.w + ea.dt * R[3])) : 0.f);
@@ -217,9 +300,340 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     Pout[i] = primitive<DIM>(un, ea.rho_ref);
 }
 
+// ------------------------------------------------------------------ tiled stage
+// One workgroup per cell tile (the tile set of the bound configuration).
+//  1. The records of the tile's own particles and of its halo are staged in
+//     LDS: position relative to the tile's first particle (minimum image, so
+//     no wrap is needed per pair; exact for quantised coordinates), V, the
+//     upper triangle of B, p, c rho / 2 and the velocity.
+//  2. Each task (unique neighbour pair) evaluates the Riemann flux once.  The
+//     pair terms are antisymmetric: with Q = (-2 rho* v*.g, -2 (rho* v* (v*.g)
+//     + p* g) + 4 mu (dW/dr)/(2r) (v_i - v_j)), g the corrected gradient,
+//     particle i receives V_j Q and particle j receives -V_i Q.  Both go to
+//     the pair's row entries in LDS.
+//  3. Each own particle sums its row entries in row order (compensated) and
+//     applies the stage update.
+constexpr int TBLK = 256;
+
+template <int DIM>
+constexpr int rec_quads() { return DIM == 2 ? 3 : 4; }
+
+template <int DIM>
+__device__ __forceinline__ void stage_record(float4* rec, const EulerArgs& ea, const float4 org, const float4 g0,
+                                             const float4 g1, const float2 g2, const float4 pr) {
+    constexpr int NQ = rec_quads<DIM>();
+    const float x0 = wrap(g0.x - org.x, ea.L[0], ea.invL[0]);
+    const float x1 = wrap(g0.y - org.y, ea.L[1], ea.invL[1]);
+    const float p = ea.c2 * (pr.x + ea.poff);
+    const float chr = ea.hc * (ea.rho_ref + pr.x);
+    if (DIM == 2) {
+        rec[0] = make_float4(x0, x1, g0.z, g0.w);
+        rec[1] = make_float4(g1.x, g1.y, p, chr);
+        rec[2] = make_float4(pr.y, pr.z, 0.f, 0.f);
+    } else {
+        const float x2 = wrap(g0.z - org.z, ea.L[2], ea.invL[2]);
+        rec[0] = make_float4(x0, x1, x2, g0.w);
+        rec[1] = g1;
+        rec[2] = make_float4(g2.x, g2.y, p, chr);
+        rec[3] = make_float4(pr.y, pr.z, pr.w, 0.f);
+    }
+    (void)NQ;
+}
+
+// Geometry of sorted slot s: 2-D (x, y, V, B00) + (B01, B11); 3-D
+// (x, y, z, V) + (B00, B01, B02, B11) + (B12, B22).
+template <int DIM>
+__device__ __forceinline__ void load_geo(int32_t s, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                                         const float2* __restrict__ geo2, float4& g0, float4& g1, float2& g2) {
+    g0 = geo0[s];
+    if (DIM == 2) {
+        float2 t = reinterpret_cast<const float2*>(geo1)[s];
+        g1 = make_float4(t.x, t.y, 0.f, 0.f);
+        g2 = make_float2(0.f, 0.f);
+    } else {
+        g1 = geo1[s];
+        g2 = geo2[s];
+    }
+}
+
+// The unique-pair flux of task tk, written to both row entries.
+template <int DIM>
+__device__ __forceinline__ void pair_flux(const EulerArgs& ea, const float4* rec, float4* row, uint2 tk) {
+    constexpr int NQ = rec_quads<DIM>();
+    const int32_t a = (int32_t)(tk.x & 0xffffu), b = (int32_t)(tk.x >> 16);
+    const int32_t ea_row = (int32_t)(tk.y & 0xffffu), eb_row = (int32_t)(tk.y >> 16);
+    const float4* ra = rec + a * NQ;
+    const float4* rb = rec + b * NQ;
+    const float4 a0 = ra[0], a1 = ra[1], a2 = ra[2];
+    const float4 b0 = rb[0], b1 = rb[1], b2 = rb[2];
+    float d[3], Bs[6], va[3], vb[3];
+    float Va, Vb, pa, pb, ca, cb;
+    if (DIM == 2) {
+        d[0] = a0.x - b0.x; d[1] = a0.y - b0.y; d[2] = 0.f;
+        Va = a0.z; Vb = b0.z;
+        Bs[0] = a0.w + b0.w; Bs[1] = a1.x + b1.x; Bs[2] = a1.y + b1.y;
+        Bs[3] = Bs[4] = Bs[5] = 0.f;
+        pa = a1.z; pb = b1.z; ca = a1.w; cb = b1.w;
+        va[0] = a2.x; va[1] = a2.y; va[2] = 0.f;
+        vb[0] = b2.x; vb[1] = b2.y; vb[2] = 0.f;
+    } else {
+        const float4 a3 = ra[3], b3 = rb[3];
+        d[0] = a0.x - b0.x; d[1] = a0.y - b0.y; d[2] = a0.z - b0.z;
+        Va = a0.w; Vb = b0.w;
+        Bs[0] = a1.x + b1.x; Bs[1] = a1.y + b1.y; Bs[2] = a1.z + b1.z;
+        Bs[3] = a1.w + b1.w; Bs[4] = a2.x + b2.x; Bs[5] = a2.y + b2.y;
+        pa = a2.z; pb = b2.z; ca = a2.w; cb = b2.w;
+        va[0] = a3.x; va[1] = a3.y; va[2] = a3.z;
+        vb[0] = b3.x; vb[1] = b3.y; vb[2] = b3.z;
+    }
+    float r2 = 0.f;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) r2 = fmaf(d[c], d[c], r2);
+    const bool live = r2 > 0.f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float tq = fmaf(-0.5f * ea.hinv, r2 * rinv, 1.f);  // 1 - q/2
+    const float Fh = live ? ea.cFh * tq * tq * tq : 0.f;      // (dW/dr)/r / 2
+    float gc[DIM];
+    if (DIM == 2) {
+        gc[0] = Fh * fmaf(Bs[0], d[0], Bs[1] * d[1]);
+        gc[1] = Fh * fmaf(Bs[1], d[0], Bs[2] * d[1]);
+    } else {
+        gc[0] = Fh * fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
+        gc[1] = Fh * fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
+        gc[2] = Fh * fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
+    }
+    // Riemann problem along n = -d / r (from a to b), left = a, right = b
+    float dv[DIM], dvd = 0.f;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        dv[c] = va[c] - vb[c];
+        dvd = fmaf(dv[c], d[c], dvd);
+    }
+    const float du_lr = -dvd * rinv;                 // u_l - u_r
+    const float rhobar_c = ca + cb;                  // c (rho_l + rho_r) / 2
+    const float beta = fminf(ea.eta_c * fmaxf(du_lr, 0.f), 1.f);
+    const float hb2 = 0.5f * beta;
+    const float du = hb2 * beta * (pa - pb) * fast_rcp(rhobar_c);  // u* - mean
+    const float pstar = fmaf(0.5f, pa + pb, hb2 * rhobar_c * du_lr);
+    const float rhostar = fmaf(pstar, ea.c2inv, ea.rho0);
+    const float dun = -du * rinv;
+    float vs[DIM], vg = 0.f;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        vs[c] = fmaf(0.5f, va[c] + vb[c], dun * d[c]);
+        vg = fmaf(vs[c], gc[c], vg);
+    }
+    const float rvg = rhostar * vg;
+    const float visc = ea.mu4 * Fh;
+    float Q[4];
+    Q[0] = -2.f * rvg;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) Q[1 + c] = fmaf(-2.f, fmaf(rvg, vs[c], pstar * gc[c]), visc * dv[c]);
+    if (DIM == 2) {
+        row[ea_row] = make_float4(Vb * Q[0], Vb * Q[1], Vb * Q[2], 0.f);
+        if (eb_row != 0xffff) row[eb_row] = make_float4(-Va * Q[0], -Va * Q[1], -Va * Q[2], 0.f);
+    } else {
+        row[ea_row] = make_float4(Vb * Q[0], Vb * Q[1], Vb * Q[2], Vb * Q[3]);
+        if (eb_row != 0xffff) row[eb_row] = make_float4(-Va * Q[0], -Va * Q[1], -Va * Q[2], -Va * Q[3]);
+    }
+}
+
+// Raw inputs of one staged record (geometry and primitive state).
+template <int DIM>
+struct RawRec {
+    float4 g0, g1, pr;
+    float2 g2;
+};
+
+template <int DIM>
+__device__ __forceinline__ void gather_rec(int32_t s, const float4* __restrict__ geo0,
+                                           const float4* __restrict__ geo1, const float2* __restrict__ geo2,
+                                           const float4* __restrict__ P, RawRec<DIM>& q) {
+    load_geo<DIM>(s, geo0, geo1, geo2, q.g0, q.g1, q.g2);
+    q.pr = P[s];
+}
+
+// Field-by-field copy of a tile header (keeps it in registers).
+__device__ __forceinline__ TileHdr load_hdr(const TileHdr* __restrict__ hdr, int32_t t) {
+    const TileHdr* p = hdr + t;
+    TileHdr h;
+    h.ob = p->ob;
+    h.oc = p->oc;
+    h.hb = p->hb;
+    h.hc = p->hc;
+    h.kb = p->kb;
+    h.tb = p->tb;
+    h.ntask = p->ntask;
+    h.rows = p->rows;
+    h.pad0 = h.pad1 = 0;
+    h.ox = p->ox;
+    h.oy = p->oy;
+    h.oz = p->oz;
+    h.ow = 0.f;
+    return h;
+}
+
+__device__ __forceinline__ int32_t rec_slot(const TileHdr& h, int32_t r, const int32_t* __restrict__ halo) {
+    return r < h.oc ? h.ob + r : halo[h.hb + (r - h.oc)];
+}
+
+// Each workgroup runs `tpw` consecutive tiles as a software pipeline: while
+// tile t is evaluated, the header and record slots of tile t + 1 are loaded
+// (during the pair phase) and its records gathered into registers (during
+// the summation phase), so the staging latency overlaps arithmetic.  RPT
+// records per thread are carried in registers; a tile with more records
+// loads the rest when it is staged.  L2 lanes per own row in the summation
+// phase: lane sub of the group sums entries e0 + sub, e0 + sub + L2, ...
+// (neighbouring lanes read neighbouring entries) and the compensated
+// partials are combined by group_sum_rt.
+template <int DIM, int STAGE, int RPT>
+__global__ void __launch_bounds__(TBLK) k_euler_tile(EulerArgs ea, const TileHdr* __restrict__ hdr, int32_t ntile,
+                                                     int32_t tpw, int32_t L2, const int32_t* __restrict__ halo,
+                                                     const uint2* __restrict__ tasks, const int64_t* __restrict__ rp_s,
+                                                     const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                                                     const float2* __restrict__ geo2, const float4* U,
+                                                     const float4* __restrict__ P, const float4* U0, float4* Uout,
+                                                     float4* Pout, const float4* __restrict__ sorted,
+                                                     float* __restrict__ drho_dt, float* __restrict__ dmom_dt,
+                                                     int32_t n) {
+    extern __shared__ float4 lds[];
+    constexpr int NQ = rec_quads<DIM>();
+    const int32_t w = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int32_t t0 = w * tpw;
+    const int32_t t1 = t0 + tpw < ntile ? t0 + tpw : ntile;
+    if (t0 >= t1) return;
+    const int32_t tid = threadIdx.x;
+    const int32_t p0 = tid / L2, sub = tid % L2;
+
+    TileHdr h = load_hdr(hdr, t0);
+    RawRec<DIM> raw[RPT];
+    {
+        const int32_t R = h.oc + h.hc;
+        int32_t sl[RPT];
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int32_t r = tid + j * TBLK;
+            sl[j] = r < R ? rec_slot(h, r, halo) : h.ob;
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) gather_rec<DIM>(sl[j], geo0, geo1, geo2, P, raw[j]);
+    }
+
+    for (int32_t t = t0; t < t1; ++t) {
+        const int32_t R = h.oc + h.hc;
+        float4* rec = lds;
+        float4* row = lds + (size_t)R * NQ;
+        const float4 org = make_float4(h.ox, h.oy, h.oz, 0.f);
+
+        // this tile's first task and first summation row, loaded before the waits
+        uint2 tk = tid < h.ntask ? tasks[h.tb + tid] : make_uint2(0u, 0u);
+        const bool has_p = p0 < h.oc;
+        const int32_t i0 = h.ob + (has_p ? p0 : 0);
+        const int64_t e0g = rp_s[i0], e1g = rp_s[i0 + 1];
+        float4 ui0 = make_float4(0.f, 0.f, 0.f, 0.f), u00 = ui0;
+        if (STAGE != 0 && sub == 0 && has_p) {
+            ui0 = U[i0];
+            if (STAGE == 2) u00 = U0[i0];
+        }
+
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+            const int32_t r = tid + j * TBLK;
+            if (r < R) stage_record<DIM>(rec + r * NQ, ea, org, raw[j].g0, raw[j].g1, raw[j].g2, raw[j].pr);
+        }
+        for (int32_t r = tid + RPT * TBLK; r < R; r += TBLK) {
+            RawRec<DIM> q;
+            gather_rec<DIM>(rec_slot(h, r, halo), geo0, geo1, geo2, P, q);
+            stage_record<DIM>(rec + r * NQ, ea, org, q.g0, q.g1, q.g2, q.pr);
+        }
+        __syncthreads();
+
+        // next tile: header and record slots (in flight during the pair phase)
+        const bool more = t + 1 < t1;
+        const TileHdr hn = load_hdr(hdr, more ? t + 1 : t);
+        int32_t sn[RPT];
+        {
+            const int32_t Rn = more ? hn.oc + hn.hc : 0;
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+                const int32_t r = tid + j * TBLK;
+                sn[j] = r < Rn ? rec_slot(hn, r, halo) : hn.ob;
+            }
+        }
+
+        // unique pairs; the next task is loaded before the current one is evaluated
+        for (int32_t k = tid; k < h.ntask; k += TBLK) {
+            const uint2 cur = tk;
+            if (k + TBLK < h.ntask) tk = tasks[h.tb + k + TBLK];
+            pair_flux<DIM>(ea, rec, row, cur);
+        }
+        // next tile's records (in flight during the summation phase)
+        if (more) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) gather_rec<DIM>(sn[j], geo0, geo1, geo2, P, raw[j]);
+        }
+        __syncthreads();
+
+        for (int32_t p = p0; p < h.oc; p += TBLK / L2) {
+            const int32_t i = h.ob + p;
+            int32_t e0, e1;
+            float4 ui = ui0, u0 = u00;
+            if (p == p0) {
+                e0 = (int32_t)(e0g - h.kb);
+                e1 = (int32_t)(e1g - h.kb);
+            } else {
+                e0 = (int32_t)(rp_s[i] - h.kb);
+                e1 = (int32_t)(rp_s[i + 1] - h.kb);
+                if (STAGE != 0 && sub == 0) {
+                    ui = U[i];
+                    if (STAGE == 2) u0 = U0[i];
+                }
+            }
+            Kahan sr, sm[DIM];
+            sr.init();
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) sm[c].init();
+            for (int32_t e = e0 + sub; e < e1; e += L2) {
+                const float4 v = row[e];
+                sr.add(v.x);
+                sm[0].add(v.y);
+                sm[1].add(v.z);
+                if (DIM == 3) sm[DIM - 1].add(v.w);
+            }
+            float Rr[4];
+            Rr[0] = group_sum_rt(sr, L2);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) Rr[1 + c] = group_sum_rt(sm[c], L2);
+            if (DIM == 2) Rr[3] = 0.f;
+            if (sub != 0) continue;
+            if (STAGE == 0) {
+                const int32_t ic = __float_as_int(sorted[i].w);
+                drho_dt[ic] = Rr[0];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) dmom_dt[(int64_t)c * n + ic] = Rr[1 + c];
+                continue;
+            }
+            float4 un;
+            if (STAGE == 1) {
+                un = make_float4(ui.x + ea.dt * Rr[0], ui.y + ea.dt * Rr[1], ui.z + ea.dt * Rr[2],
+                                 DIM == 3 ? ui.w + ea.dt * Rr[3] : 0.f);
+            } else {
+                un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * Rr[0])), 0.5f * (u0.y + (ui.y + ea.dt * Rr[1])),
+                                 0.5f * (u0.z + (ui.z + ea.dt * Rr[2])),
+                                 DIM == 3 ? 0.5f * (u0.w + (ui.w + ea.dt * Rr[3])) : 0.f);
+            }
+            Uout[i] = un;
+            Pout[i] = primitive<DIM>(un, ea.rho_ref);
+        }
+        __syncthreads();
+        h = hn;
+    }
+}
+
 EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     EulerArgs a{};
     a.c = (float)p->c;
+    a.hc = (float)(0.5 * p->c);
     a.c2 = (float)(p->c * p->c);
     a.c2inv = (float)(1.0 / (p->c * p->c));
     a.rho0 = (float)p->rho0;
@@ -259,11 +673,57 @@ struct StageIO {
     float* dm;
 };
 
+template <int DIM, int STAGE, int L, int MODE, int E>
+void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
+    const bool ell = MODE != ROWS_CSR;
+    hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E>), dim3(grid_for((int64_t)c->n * L, BLK)), dim3(BLK), 0,
+                       c->stream, c->n, ea, ell ? nullptr : c->rp_s.as<int64_t>(),
+                       ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0, c->geo0.as<float4>(),
+                       c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout, io.Pout,
+                       c->sorted.as<float4>(), io.dr, io.dm);
+}
+
 template <int DIM, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    hipLaunchKernelGGL((k_euler<DIM, STAGE, L>), dim3(grid_for((int64_t)c->n * L, BLK)), dim3(BLK), 0, c->stream, c->n,
-                       ea, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(),
-                       c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm);
+    if (c->ell_state == 1) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
+    else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
+}
+
+// Batched short rows: L lanes per particle and E = ceil(S / L) <= 4 entries
+// per lane.  Returns false when the rows are too long for a batch.
+template <int DIM, int STAGE>
+bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
+    const int E = (c->ell_S + L - 1) / L;
+    if (L == 4) {
+        if (E <= 2) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 2>(c, ea, io);
+        else if (E == 3) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 3>(c, ea, io);
+        else if (E == 4) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 4>(c, ea, io);
+        else return false;
+    } else if (L == 8) {
+        if (E <= 2) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 2>(c, ea, io);
+        else if (E == 3) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 3>(c, ea, io);
+        else if (E == 4) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 4>(c, ea, io);
+        else return false;
+    } else {
+        return false;
+    }
+    return true;
+}
+
+// Lanes per particle for the batched rows: 4 when four entries per lane
+// cover the row, else 8 (tuning override SPH_EULER_BATCH_LANES = 4 or 8;
+// 0 turns batching off).  Batching serves configurations whose lane
+// groups are too few to hide memory latency with a pipeline (n <= 2^21).
+int batch_lanes(const sph_ctx* c) {
+    int forced = -1;
+    if (const char* e = getenv("SPH_EULER_BATCH_LANES")) forced = atoi(e);
+    if (forced == 0) return 0;
+    if (c->ell_state != 1) return 0;
+    if (forced == 4 || forced == 8) return (c->ell_S + forced - 1) / forced <= 4 ? forced : 0;
+    if (c->n > (1 << 21)) return 0;
+    if ((c->ell_S + 3) / 4 <= 4) return 4;
+    if ((c->ell_S + 7) / 8 <= 4) return 8;
+    return 0;
 }
 
 // Lanes per particle: enough lane groups to give every SIMD several waves
@@ -283,8 +743,80 @@ int lanes_per_particle(const sph_ctx* c) {
     return L;
 }
 
+// LDS budget of a tile workgroup (bytes); tuning override SPH_TILE_LDS.
+int tile_budget() {
+    const char* e = getenv("SPH_TILE_LDS");
+    int v = e ? atoi(e) : 0;
+    return v >= 4096 && v <= 160 * 1024 ? v : 64 * 1024;
+}
+
+// Whether the stage runs on cell tiles (built on first use for the bound
+// configuration); the per-particle kernel serves configurations that do not
+// admit tiles and contexts with tiling off.
+int prepare_tiles(sph_ctx* c, bool* tiled) {
+    *tiled = false;
+    int r = sph_ell_prepare(c);
+    if (r) return r;
+    if (c->tiling == SPH_TILING_OFF) return SPH_OK;
+    int rec = (c->dim == 2 ? rec_quads<2>() : rec_quads<3>()) * (int)sizeof(float4);
+    r = sph_tiles_prepare(c, rec, (int)sizeof(float4), tile_budget());
+    if (r == 1) return SPH_OK;
+    if (r) return r;
+    *tiled = true;
+    return SPH_OK;
+}
+
+template <int DIM, int STAGE, int RPT>
+void launch_tile_r(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int32_t tpw, int32_t L2) {
+    const TileSet& ts = c->tiles;
+    const size_t lds = (size_t)ts.max_lds;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)k_euler_tile<DIM, STAGE, RPT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int32_t nwg = (ts.ntile + tpw - 1) / tpw;
+    hipLaunchKernelGGL((k_euler_tile<DIM, STAGE, RPT>), dim3(nwg), dim3(TBLK), lds, c->stream, ea,
+                       ts.hdr.as<TileHdr>(), ts.ntile, tpw, L2, ts.halo.as<int32_t>(), ts.tasks.as<uint2>(),
+                       c->rp_s.as<int64_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U,
+                       io.P, io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm, c->n);
+}
+
+// Launch shape of the tiled stage:
+//  - lanes per own row in the summation phase: as many as keep the tile's
+//    rows within one pass of the workgroup (at most 4);
+//  - tiles per workgroup: enough that every workgroup is resident at once
+//    (256 CUs, workgroups per CU bounded by LDS and by 8 waves per SIMD);
+//  - records per thread carried in registers: enough for the largest tile
+//    (at most 3; the rest is loaded when staged).
+template <int DIM, int STAGE>
+void launch_tile(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
+    const TileSet& ts = c->tiles;
+    int L2 = 1;
+    while (L2 < 4 && (int64_t)ts.max_own * (L2 * 2) <= TBLK) L2 <<= 1;
+    int per_cu = ts.max_lds > 0 ? (160 * 1024) / ts.max_lds : 8;
+    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+    int32_t tpw = (int32_t)((ts.ntile + 256LL * per_cu - 1) / (256LL * per_cu));
+    if (const char* e = getenv("SPH_TILE_TPW")) {
+        int v = atoi(e);
+        if (v >= 1 && v <= 4096) tpw = v;
+    }
+    if (tpw < 1) tpw = 1;
+    int rpt = (int)((ts.max_rec + TBLK - 1) / TBLK);
+    if (rpt <= 1) launch_tile_r<DIM, STAGE, 1>(c, ea, io, tpw, L2);
+    else if (rpt == 2) launch_tile_r<DIM, STAGE, 2>(c, ea, io, tpw, L2);
+    else launch_tile_r<DIM, STAGE, 3>(c, ea, io, tpw, L2);
+}
+
 template <int STAGE>
-void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
+void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, bool tiled) {
+    if (tiled) {
+        if (c->dim == 2) launch_tile<2, STAGE>(c, ea, io);
+        else launch_tile<3, STAGE>(c, ea, io);
+        return;
+    }
+    if (int bl = batch_lanes(c)) {
+        bool done = c->dim == 2 ? launch_batch<2, STAGE>(c, ea, io, bl) : launch_batch<3, STAGE>(c, ea, io, bl);
+        if (done) return;
+    }
     int L = lanes_per_particle(c);
     if (c->dim == 2) {
         if (L == 1) launch_l<2, STAGE, 1>(c, ea, io);
@@ -322,11 +854,14 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     if (!drho || !mom || !drho_dt || !dmom_dt) return sph_fail(c, SPH_ERR_ARG, "sph_euler_rhs: NULL array");
     SPH_HIP(c, c->ua.ensure((size_t)c->n * sizeof(float4)));
     SPH_HIP(c, c->ta.ensure((size_t)c->n * sizeof(float4)));
+    bool tiled = false;
+    r = prepare_tiles(c, &tiled);
+    if (r) return r;
     EulerArgs ea = make_args(c, p);
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt};
-    launch<0>(c, ea, io);
+    launch<0>(c, ea, io, tiled);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -346,6 +881,9 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     float4* Us = c->ub.as<float4>();
     float4* P = c->ta.as<float4>();
     float4* Ps = c->tb.as<float4>();
+    bool tiled = false;
+    r = prepare_tiles(c, &tiled);
+    if (r) return r;
     EulerArgs ea = make_args(c, p);
     r = pack(c, ea.rho_ref, drho, mom, U, P);
     if (r) return r;
@@ -353,8 +891,8 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr};
     StageIO s2{Us, Ps, U, U, P, nullptr, nullptr};
     for (int32_t s = 0; s < nsteps; ++s) {
-        launch<1>(c, ea, s1);
-        launch<2>(c, ea, s2);
+        launch<1>(c, ea, s1, tiled);
+        launch<2>(c, ea, s2, tiled);
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)

@@ -79,6 +79,12 @@ __host__ __device__ __forceinline__ int32_t cell_key(const BoxArgs& b, int x, in
     return (z * b.nc[1] + y) * b.nc[0] + x;
 }
 
+// Cell coordinate of a position on one axis (clamped to the grid).
+__host__ __device__ __forceinline__ int cell_coord(float x, float lo, float inv, int nc) {
+    int c = (int)floorf((x - lo) * inv);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
 // Workgroups are handed to the 8 XCDs of the chip round-robin; remapping
 // the block index gives XCD k one contiguous range of the cell-sorted
 // particles, so each XCD's L2 holds the neighbourhood of its own region.
@@ -88,6 +94,46 @@ __device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
     int32_t x = b % X, k = b / X;
     return x * per + (x < rem ? x : rem) + k;
 }
+
+// Cell tiles for the LDS-staged pair loops over a fixed configuration.  A
+// tile is an aligned block of 2^bits consecutive Morton cell keys, i.e. a
+// box of cells; its own particles are one contiguous range of sorted slots
+// and its halo is every particle of the one-cell ring around the box,
+// ascending by slot.  Record q of a tile is own particle q for q < own
+// count, else halo entry q - own count.  A task is one unique neighbour pair
+// of the tile's own rows: (own p, record q, row entry of (p, q), row entry
+// of (q, p) or 0xffff when q is a halo record); pairs of two own particles
+// appear once, with p < q.  Row entries are numbered from the first row
+// entry of the tile (the sorted CSR).
+// Everything a tile's workgroup needs before its first gather (one 64-byte
+// record): own slots [ob, ob + oc), halo entries [hb, hb + hc), first row
+// entry kb and row-entry count, first task tb and task count, and the
+// position of the first own particle (the origin of relative positions).
+struct TileHdr {
+    int32_t ob, oc, hb, hc;
+    int64_t kb, tb;
+    int32_t ntask, rows, pad0, pad1;
+    float ox, oy, oz, ow;  // origin (x, y, z), 0
+};
+static_assert(sizeof(TileHdr) == 64, "TileHdr is one 64-byte record");
+
+struct TileSet {
+    bool valid = false;
+    bool failed = false;     // no tile size fitted (for the request below)
+    int bits = 0;
+    int rec_bytes = 0, row_bytes = 0;  // LDS bytes per record / per row entry
+    int budget = 0;                    // LDS budget of the last request
+    int32_t ntile = 0;
+    int32_t max_lds = 0;     // max LDS bytes of a tile
+    int64_t ntask = 0;
+    DevBuf info;       // int4 [ntile]: own begin (slot), own count, halo begin, halo count
+    DevBuf hdr;        // TileHdr [ntile]
+    int32_t max_own = 0;  // max own particles of a tile
+    int32_t max_rec = 0;  // max own + halo records of a tile
+    DevBuf task_ptr;   // int64 [n + 1]: first task of each sorted slot's row
+    DevBuf halo;       // int32 [sum of halo counts]
+    DevBuf tasks;      // uint2 [ntask]: (p | q << 16, row entry of p | row entry of q << 16)
+};
 
 struct sph_ctx {
     int dim = 0;
@@ -136,7 +182,30 @@ struct sph_ctx {
     DevBuf sfield;      // float [n] a caller field in cell order
     DevBuf partials;    // per-block reduction partials
     DevBuf relax_scalars;
+
+    TileSet tiles;
+    int tiling = SPH_TILING_OFF;
+
+    // fixed-stride neighbour rows over cell-sorted slots (ELLPACK): entry k
+    // of slot i at colE[k * n + i] for k < ell_S, rows shorter than ell_S
+    // padded with i itself (a zero-weight pair); built on first use when the
+    // padding stays small
+    DevBuf colE;
+    int32_t ell_S = 0;
+    int ell_state = 0;  // 0: not built, 1: valid, -1: rows too uneven (CSR is used)
 };
+
+// Build (or reuse) the fixed-stride neighbour rows of the bound
+// configuration.  Sets c->ell_state; returns an error code only on failure.
+int sph_ell_prepare(sph_ctx* c);
+
+// Build (or reuse) the cell tiles of the bound configuration for a pair
+// loop whose tile needs rec_bytes of LDS per record and row_bytes per own
+// row entry, within lds_budget bytes per workgroup.  Returns SPH_OK with
+// c->tiles valid, 1 when the configuration does not admit tiles (linear
+// cell keys, a periodic axis too short for the tile and its ring, or no
+// tile size fits the budget), or an error code.
+int sph_tiles_prepare(sph_ctx* c, int rec_bytes, int row_bytes, int lds_budget);
 
 int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
 
@@ -189,6 +258,23 @@ __device__ __forceinline__ float group_sum(const Kahan& k) {
     float hi = k.s, lo = -k.c;
 #pragma unroll
     for (int m = 1; m < L; m <<= 1) {
+        float ohi = __shfl_xor(hi, m, 64);
+        float olo = __shfl_xor(lo, m, 64);
+        float s = hi + ohi;
+        float bp = s - hi;
+        float e = (hi - (s - bp)) + (ohi - bp);
+        lo = (lo + olo) + e;
+        hi = s;
+    }
+    return hi + lo;
+}
+
+// group_sum for a run-time group size L in {1, 2, 4, 8}.
+__device__ __forceinline__ float group_sum_rt(const Kahan& k, int L) {
+    float hi = k.s, lo = -k.c;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1) {
+        if (m >= L) break;
         float ohi = __shfl_xor(hi, m, 64);
         float olo = __shfl_xor(lo, m, 64);
         float s = hi + ohi;

@@ -17,14 +17,11 @@
 // set is defined independently of the evaluation order.
 #include "sph_internal.h"
 
+#include <cstdlib>
+
 namespace {
 
 constexpr int BLK = 256;
-
-__device__ __forceinline__ int cell_coord(float x, float lo, float inv, int nc) {
-    int c = (int)floorf((x - lo) * inv);
-    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
-}
 
 __global__ void k_bin(int32_t n, int dim, const float* __restrict__ pos, BoxArgs b,
                       float4* __restrict__ pos4, int32_t* __restrict__ cell_of,
@@ -165,7 +162,52 @@ __global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restr
     }
 }
 
+__global__ void k_row_max(int32_t n, const int32_t* __restrict__ cnt, int32_t* out) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicMax(out, cnt[i]);
+}
+
+__global__ void k_fill_ell(int32_t n, int32_t S, const int64_t* __restrict__ rp_s, const int32_t* __restrict__ col_s,
+                           int32_t* __restrict__ colE) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t k0 = rp_s[i];
+    const int32_t len = (int32_t)(rp_s[i + 1] - k0);
+    for (int32_t k = 0; k < S; ++k) colE[(int64_t)k * n + i] = k < len ? col_s[k0 + k] : i;
+}
+
 }  // namespace
+
+int sph_ell_prepare(sph_ctx* c) {
+    if (c->ell_state != 0) return SPH_OK;
+    const int32_t n = c->n;
+    const char* force = getenv("SPH_EULER_ROWS");  // tuning override: "csr" keeps the CSR rows
+    if (n == 0 || c->nnz == 0 || (force && strcmp(force, "csr") == 0)) {
+        c->ell_state = -1;
+        return SPH_OK;
+    }
+    SPH_HIP(c, c->counter.ensure(64));
+    SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
+    hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->cnt_s.as<int32_t>(),
+                       c->counter.as<int32_t>());
+    SPH_LAUNCH_CHECK(c);
+    int32_t S = 0;
+    SPH_HIP(c, hipMemcpyAsync(&S, c->counter.p, 4, hipMemcpyDeviceToHost, c->stream));
+    SPH_HIP(c, hipStreamSynchronize(c->stream));
+    // padding may cost at most half the stored entries
+    if ((double)S * n > 1.5 * (double)c->nnz + 1024.0) {
+        c->ell_state = -1;
+        return SPH_OK;
+    }
+    SPH_HIP(c, c->colE.ensure((size_t)S * n * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_fill_ell, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, S, c->rp_s.as<int64_t>(),
+                       c->col_s.as<int32_t>(), c->colE.as<int32_t>());
+    SPH_LAUNCH_CHECK(c);
+    c->ell_S = S;
+    c->ell_state = 1;
+    return SPH_OK;
+}
 
 // Validate the domain and bin the positions into the cell grid (sorted
 // float4 records with the caller index in .w, and cell offsets).  Used by
@@ -174,6 +216,9 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
     if (!c) return SPH_ERR_ARG;
     c->bound = false;
     c->geo_valid = false;
+    c->tiles.valid = false;
+    c->tiles.failed = false;
+    c->ell_state = 0;
     if (!dom) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom is NULL");
     if (dom->dim != c->dim)
         return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom->dim %d != context dim %d", dom->dim, c->dim);

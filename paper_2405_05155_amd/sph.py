@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 
 SPH_OK, SPH_ERR_ARG, SPH_ERR_CAPACITY, SPH_ERR_HIP, SPH_ERR_STATE = 0, -1, -2, -3, -5
 WENDLAND, LAGUERRE_GAUSS = 0, 1
+TILING_OFF, TILING_ON = 0, 1
 
 
 class SphError(RuntimeError):
@@ -57,6 +58,7 @@ _SIGS = [
     ("sph_ctx_destroy", None, [_vp]),
     ("sph_last_error", C.c_char_p, [_vp]),
     ("sph_set_stream", C.c_int, [_vp, _vp]),
+    ("sph_set_tiling", C.c_int, [_vp, C.c_int]),
     ("sph_build_cells", C.c_int, [_vp, C.POINTER(sph_domain), _i32, _vp]),
     ("sph_neighbors", C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(C.c_int64)]),
     ("sph_kernel_sum", C.c_int, [_vp, _vp, _vp]),
@@ -207,6 +209,10 @@ class Context:
     def _dev(self):
         return torch.device("cuda", torch.cuda.current_device())
 
+    def set_tiling(self, mode: int):
+        """TILING_OFF: per-particle pair loops (default); TILING_ON: LDS cell tiles where admitted."""
+        self._check(lib().sph_set_tiling(self._h, int(mode)))
+
     # ------------------------------------------------------------ neighbours
     def build_cells(self, domain: Domain, pos: torch.Tensor):
         n = pos.shape[-1] if pos.numel() else 0
@@ -337,6 +343,10 @@ class Context:
 
 # Module-level functions named as the C calls (same argument order, with the
 # Context in place of the sph_ctx pointer).
+def sph_set_tiling(ctx: Context, mode):
+    return ctx.set_tiling(mode)
+
+
 def sph_build_cells(ctx: Context, domain: Domain, pos):
     return ctx.build_cells(domain, pos)
 

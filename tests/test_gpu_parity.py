@@ -180,10 +180,12 @@ def _euler_prm(S, w, dt=0.0):
 @pytest.mark.parametrize("seed", [0, 1])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 @pytest.mark.parametrize("mu", [0.0, 0.01])
-def test_euler_rhs_single_step(S, seed, kappa, mu):
+@pytest.mark.parametrize("tiling", [0, 1])
+def test_euler_rhs_single_step(S, seed, kappa, mu, tiling):
     w = I.single_step_2d(seed=seed)
     w.fields["mu"] = mu
     ctx = gpu_ctx(S, w, kappa)
+    ctx.set_tiling(tiling)
     ctx.correction_B(dev(w.vol))
     pg, po = _euler_prm(S, w)
     dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
@@ -195,9 +197,11 @@ def test_euler_rhs_single_step(S, seed, kappa, mu):
 
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-def test_euler_heun_steps_taylor_green(S, kappa):
+@pytest.mark.parametrize("tiling", [0, 1])
+def test_euler_heun_steps_taylor_green(S, kappa, tiling):
     w = I.taylor_green_2d(nside=64, nu=0.01)
     ctx = gpu_ctx(S, w, kappa)
+    ctx.set_tiling(tiling)
     ctx.correction_B(dev(w.vol))
     dt = w.meta["dt"]
     pg, po = _euler_prm(S, w, dt)
@@ -223,6 +227,62 @@ def test_euler_heun_steps_taylor_green(S, kappa):
     r100, m100 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, r1, m1, 99)
     assert normwise(host(m), m100) < 1e-3
     assert normwise(host(d), r100 - 1.0) < 1e-3
+
+
+@pytest.mark.parametrize("rows", ["batch4", "batch8", "ell", "csr"])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_euler_rhs_row_layouts(S, rows, kappa, monkeypatch):
+    """Each row layout of the per-particle kernel against the oracle: short
+    rows batched per lane (4 or 8 lanes per particle), the pipelined loop
+    over fixed-stride rows and over the CSR rows."""
+    env = {"batch4": {"SPH_EULER_BATCH_LANES": "4"}, "batch8": {"SPH_EULER_BATCH_LANES": "8"},
+           "ell": {"SPH_EULER_BATCH_LANES": "0"},
+           "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_EULER_ROWS": "csr"}}[rows]
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    w = I.single_step_2d(seed=1)
+    w.fields["mu"] = 0.01
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    pg, po = _euler_prm(S, w)
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    rho = w.fields["rho_ref"] + w.fields["drho"].astype(np.float64)
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho, w.fields["mom"])
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+
+
+def _mixed_box_3d(nside=24, seed=5):
+    """Jittered 3-D lattice, periodic in x and z, open in y (free surfaces)."""
+    w = I.taylor_green_3d(nside=nside)
+    rng = np.random.default_rng(seed)
+    dx = w.meta["dx"]
+    q = w.meta["quantum"]
+    pos = w.pos.astype(np.float64) + rng.uniform(-0.2 * dx, 0.2 * dx, size=w.pos.shape)
+    w.pos = I.wrap_periodic(pos, 0.0, 1.0, q).astype(np.float32)
+    w.periodic = (1, 0, 1)
+    return w
+
+
+@pytest.mark.parametrize("case", ["mixed3d", "tiny2d"])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+@pytest.mark.parametrize("tiling", [0, 1])
+def test_euler_rhs_tile_geometries(S, case, kappa, tiling):
+    """Tile edge cases against the oracle: a 3-D box with an open axis
+    (rings clipped at the free surfaces, ragged tiles) and a periodic box
+    too small for tiles (the per-particle kernel runs under either mode)."""
+    w = _mixed_box_3d() if case == "mixed3d" else I.taylor_green_2d(nside=16)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.set_tiling(tiling)
+    ctx.correction_B(dev(w.vol))
+    pg, po = _euler_prm(S, w)
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    rho = w.fields["rho_ref"] + w.fields["drho"].astype(np.float64)
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho, w.fields["mom"])
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
 
 
 def test_euler_rhs_full_size_taylor_green_sampled(S):
