@@ -26,6 +26,8 @@ struct EulerArgs {
     float dt;
     float hinv, cFh; // Wendland (dW/dr)/r / 2 = cFh (1 - q/2)^3
     float L[3], invL[3];  // periodic lengths (invL = 0 on open axes)
+    float lo[3];          // box corner
+    float margin;         // a particle this far from every periodic face needs no wrap
 };
 
 // Conserved record U = (drho, m_x, m_y, m_z) and primitive record
@@ -34,7 +36,7 @@ struct EulerArgs {
 // loop needs no division; each stage writes both records of its result.
 template <int DIM>
 __device__ __forceinline__ float4 primitive(const float4& u, float rho_ref) {
-    float inv = 1.f / (rho_ref + u.x);
+    const float inv = fast_rcp(rho_ref + u.x);
     return make_float4(u.x, u.y * inv, u.z * inv, DIM == 3 ? u.w * inv : 0.f);
 }
 
@@ -81,16 +83,17 @@ template <int DIM>
 __device__ __forceinline__ void gather_nbr(int32_t j, const float4* __restrict__ geo0,
                                            const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                            const float4* __restrict__ P, NbrRec<DIM>& r) {
-    r.g0 = geo0[j];
+    const uint32_t u = (uint32_t)j;
+    r.g0 = ld32(geo0, u);
     if (DIM == 2) {
-        const float2 t = reinterpret_cast<const float2*>(geo1)[j];
+        const float2 t = ld32(reinterpret_cast<const float2*>(geo1), u);
         r.g1 = make_float4(t.x, t.y, 0.f, 0.f);
         r.g2 = make_float2(0.f, 0.f);
     } else {
-        r.g1 = geo1[j];
-        r.g2 = geo2[j];
+        r.g1 = ld32(geo1, u);
+        r.g2 = ld32(geo2, u);
     }
-    r.pr = P[j];
+    r.pr = ld32(P, u);
 }
 
 // Own particle's quantities for its pair loop.
@@ -106,7 +109,7 @@ struct OwnState {
 // limited Riemann solution (Eqs. 26-27), accumulated into the particle's
 // compensated sums.  Branch-free: a coincident partner (r = 0, also the
 // particle itself standing in for a padding entry) gets zero weight.
-template <int DIM>
+template <int DIM, bool WRAP>
 __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnState<DIM>& o, const NbrRec<DIM>& nb,
                                                 Kahan& sr, Kahan* sm) {
     constexpr int NBU = DIM == 2 ? 3 : 6;
@@ -124,7 +127,8 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
     float r2 = 0.f;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        d[a] = wrap(o.x[a] - xj[a], ea.L[a], ea.invL[a]);
+        d[a] = o.x[a] - xj[a];
+        if (WRAP) d[a] = wrap(d[a], ea.L[a], ea.invL[a]);
         r2 = fmaf(d[a], d[a], r2);
     }
     const bool live = r2 > 0.f;
@@ -212,22 +216,32 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int32_t kk = sub + q * L;
-            jb[q] = kk < ell_S ? col[(int64_t)kk * n + i] : i;
+            jb[q] = kk < ell_S ? ld32(col, (uint32_t)kk * (uint32_t)n + (uint32_t)i) : i;
         }
     }
 
     OwnState<DIM> o;
-    const float4 gi = geo0[i];
+    NbrRec<DIM> self;
+    gather_nbr<DIM>(i, geo0, geo1, geo2, P, self);
+    const float4 gi = self.g0;
     o.x[0] = gi.x; o.x[1] = gi.y; o.x[2] = gi.z;
     if (DIM == 2) {
-        const float2 t2 = reinterpret_cast<const float2*>(geo1)[i];
-        o.B[0] = gi.w; o.B[1] = t2.x; o.B[2] = t2.y;
+        o.B[0] = gi.w; o.B[1] = self.g1.x; o.B[2] = self.g1.y;
     } else {
-        const float4 t4 = geo1[i];
-        const float2 u2 = geo2[i];
-        o.B[0] = t4.x; o.B[1] = t4.y; o.B[2] = t4.z; o.B[3] = t4.w; o.B[4] = u2.x; o.B[5] = u2.y;
+        o.B[0] = self.g1.x; o.B[1] = self.g1.y; o.B[2] = self.g1.z; o.B[3] = self.g1.w;
+        o.B[4] = self.g2.x; o.B[5] = self.g2.y;
     }
-    const float4 pi4 = P[i];
+    const float4 pi4 = self.pr;
+    // periodic wrap only in waves with a particle near a periodic face
+    bool near = false;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        if (ea.invL[a] != 0.f) {
+            const float off = o.x[a] - ea.lo[a];
+            near = near || off < ea.margin || ea.L[a] - off < ea.margin;
+        }
+    }
+    const bool wrap_wave = __any(near);
     o.rho = ea.rho_ref + pi4.x;
     o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
     o.p = ea.c2 * (pi4.x + ea.poff);
@@ -247,8 +261,13 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
         NbrRec<DIM> nb[E > 0 ? E : 1];
 #pragma unroll
         for (int q = 0; q < E; ++q) gather_nbr<DIM>(jb[q], geo0, geo1, geo2, P, nb[q]);
+        if (wrap_wave) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) accumulate_pair<DIM>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true>(ea, o, nb[q], sr, sm);
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false>(ea, o, nb[q], sr, sm);
+        }
     } else {
         int64_t k, e, stride;
         if (MODE == ROWS_ELL) {
@@ -270,7 +289,8 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
             gather_nbr<DIM>(jn, geo0, geo1, geo2, P, nxt);
             jn = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
-            accumulate_pair<DIM>(ea, o, cur, sr, sm);
+            if (wrap_wave) accumulate_pair<DIM, true>(ea, o, cur, sr, sm);
+            else accumulate_pair<DIM, false>(ea, o, cur, sr, sm);
             cur = nxt;
         }
     }
@@ -648,7 +668,9 @@ EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     for (int ax = 0; ax < 3; ++ax) {
         a.L[ax] = c->box.L[ax];
         a.invL[ax] = c->box.periodic[ax] ? (float)(1.0 / c->box.Ld[ax]) : 0.f;
+        a.lo[ax] = c->box.lo[ax];
     }
+    a.margin = (float)(c->rc * 1.001);
     return a;
 }
 
@@ -660,6 +682,8 @@ int check(sph_ctx* c, const sph_euler_params* p, const char* who) {
     if (!p) return sph_fail(c, SPH_ERR_ARG, "%s: params NULL", who);
     if (!(p->c > 0.0)) return sph_fail(c, SPH_ERR_ARG, "%s: sound speed must be > 0", who);
     if (!(p->eta >= 0.0) || !(p->mu >= 0.0)) return sph_fail(c, SPH_ERR_ARG, "%s: eta and mu must be >= 0", who);
+    if (c->n >= (1 << 28))
+        return sph_fail(c, SPH_ERR_ARG, "%s: %d particles exceed the 2^28 limit of the gathers", who, c->n);
     return SPH_OK;
 }
 

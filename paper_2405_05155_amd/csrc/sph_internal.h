@@ -79,6 +79,13 @@ __host__ __device__ __forceinline__ int32_t cell_key(const BoxArgs& b, int x, in
     return (z * b.nc[1] + y) * b.nc[0] + x;
 }
 
+// Load element idx of an array through a 32-bit byte offset from a uniform
+// base (one shift per gather; needs idx * sizeof(T) < 2^32).
+template <class T>
+__device__ __forceinline__ T ld32(const T* __restrict__ base, uint32_t idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
 // Cell coordinate of a position on one axis (clamped to the grid).
 __host__ __device__ __forceinline__ int cell_coord(float x, float lo, float inv, int nc) {
     int c = (int)floorf((x - lo) * inv);
@@ -173,6 +180,8 @@ struct sph_ctx {
     // state scratch
     DevBuf ua, ub;      // float4 [n] packed states
     DevBuf ta, tb, tc;  // misc per-particle scratch
+    DevBuf fa, fb, fc;  // total Lagrangian: F in cell-sorted order (float4, float4, float)
+    DevBuf pa;          // total Lagrangian: current positions in cell-sorted order (float4)
 
     // relaxation: exterior-tail table and reductions
     DevBuf tail;        // float [ntail]

@@ -182,7 +182,7 @@ __global__ void k_fill_ell(int32_t n, int32_t S, const int64_t* __restrict__ rp_
 int sph_ell_prepare(sph_ctx* c) {
     if (c->ell_state != 0) return SPH_OK;
     const int32_t n = c->n;
-    const char* force = getenv("SPH_EULER_ROWS");  // tuning override: "csr" keeps the CSR rows
+    const char* force = getenv("SPH_PAIR_ROWS");  // tuning override: "csr" keeps the CSR rows
     if (n == 0 || c->nnz == 0 || (force && strcmp(force, "csr") == 0)) {
         c->ell_state = -1;
         return SPH_OK;
@@ -195,8 +195,9 @@ int sph_ell_prepare(sph_ctx* c) {
     int32_t S = 0;
     SPH_HIP(c, hipMemcpyAsync(&S, c->counter.p, 4, hipMemcpyDeviceToHost, c->stream));
     SPH_HIP(c, hipStreamSynchronize(c->stream));
-    // padding may cost at most half the stored entries
-    if ((double)S * n > 1.5 * (double)c->nnz + 1024.0) {
+    // padding may cost at most half the stored entries; entries are
+    // addressed through 32-bit byte offsets
+    if ((double)S * n > 1.5 * (double)c->nnz + 1024.0 || (double)S * n * sizeof(int32_t) >= 4294967296.0) {
         c->ell_state = -1;
         return SPH_OK;
     }

@@ -8,9 +8,10 @@
 //      P(F) and the per-particle record A_i = P_i B0_i^T (9 floats);
 //   B: gather A_j -> acceleration, velocity kick.
 // The stress is evaluated from H = F - I so that small strains keep FP32
-// resolution (no I - C^{-1} or ln J cancellation).  Velocity, acceleration
-// and A records live in cell-sorted (Morton) order; F and positions stay in
-// the caller's arrays and are accessed at the caller index of each slot.
+// resolution (no I - C^{-1} or ln J cancellation).  Velocity, acceleration,
+// A records, F and the current positions live in cell-sorted (Morton) order
+// for the duration of a call (gathered from and scattered back to the
+// caller's arrays at its start and end).
 #include "sph_internal.h"
 
 namespace {
@@ -100,74 +101,141 @@ __device__ __forceinline__ void pk1_from_H(const float* H, const TlArgs& t, floa
 
 __device__ __forceinline__ void load_B3(int32_t i, const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                         float* B) {
-    float4 t = geo1[i];
-    float2 u = geo2[i];
+    const float4 t = ld32(geo1, (uint32_t)i);
+    const float2 u = ld32(geo2, (uint32_t)i);
     B[0] = t.x; B[1] = t.y; B[2] = t.z;
     B[3] = t.y; B[4] = t.w; B[5] = u.x;
     B[6] = t.z; B[7] = u.x; B[8] = u.y;
 }
 
-// Kernel A.  MODE 0: dF/dt -> dFdt (caller), F untouched.  MODE 1: F += dt dF/dt,
-// x += dt v (non-fixed rows).  Both: A_i = P(F_i) B0_i (B0 symmetric).
-template <int MODE>
-__global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, BoxArgs b, TlArgs t, const int64_t* __restrict__ row_ptr,
-                                              const int32_t* __restrict__ col, const float4* __restrict__ geo0,
-                                              const float4* __restrict__ geo1, const float2* __restrict__ geo2,
-                                              const float4* __restrict__ sorted, const float4* __restrict__ VH,
-                                              float* __restrict__ F, float* __restrict__ dFdt, float* __restrict__ pos,
+// Periodic geometry for the pair loops: wrap d - L rint(d / L) on periodic
+// axes (invL = 0 elsewhere), needed only by waves holding a particle within
+// `margin` of a periodic face.
+struct Wrap {
+    float L[3], invL[3], lo[3];
+    float margin;
+};
+
+__device__ __forceinline__ float wrap1(float d, float L, float invL) { return fmaf(-L, rintf(d * invL), d); }
+
+__device__ __forceinline__ bool wave_needs_wrap(const Wrap& w, const float4& x) {
+    bool near = false;
+    const float xs[3] = {x.x, x.y, x.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (w.invL[a] != 0.f) {
+            const float off = xs[a] - w.lo[a];
+            near = near || off < w.margin || w.L[a] - off < w.margin;
+        }
+    }
+    return __any(near);
+}
+
+// Row entries of sorted slot i: ELL (entry k at col[k n + i], k < S) or CSR.
+template <bool ELL>
+__device__ __forceinline__ void row_range(int32_t i, int32_t n, const int64_t* __restrict__ rp, int32_t S, int64_t& k,
+                                          int64_t& e, int64_t& stride) {
+    if (ELL) {
+        k = i;
+        stride = n;
+        e = (int64_t)S * n;
+    } else {
+        k = rp[i];
+        stride = 1;
+        e = rp[i + 1];
+    }
+}
+
+// (dW/dr)/r V_j and the reference separation X_i - X_j of one pair.
+template <bool WRAP>
+__device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, const float4& gi, const float4& gj,
+                                             float* d) {
+    d[0] = gi.x - gj.x;
+    d[1] = gi.y - gj.y;
+    d[2] = gi.z - gj.z;
+    if (WRAP) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = wrap1(d[a], w.L[a], w.invL[a]);
+    }
+    const float r2 = fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2]));
+    const float q = __builtin_amdgcn_sqrtf(r2) * t.hinv;
+    return wendland_F(q, t.cF) * gj.w;
+}
+
+template <bool WRAP>
+__device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const float4& gi, const float4& vi,
+                                      const float4& gj, const float4& vj, Kahan* L) {
+    float d[3];
+    const float wt = pair_weight<WRAP>(t, w, gi, gj, d);
+    const float dv[3] = {(vj.x - vi.x) * wt, (vj.y - vi.y) * wt, (vj.z - vi.z) * wt};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) L[r * 3 + c].add(dv[r] * d[c]);
+}
+
+// Kernel A (Eq. 32 and the stress of Eq. 30 / neo-Hookean).  One thread per
+// sorted slot; the neighbour records (X_j, V_j and v_j) are gathered one
+// entry ahead of the pair being evaluated.  F lives in cell-sorted order
+// (F0, F1, F2).  MODE 0: dF/dt -> dFdt at the caller index, F untouched.
+// MODE 1: F += dt dF/dt, x += dt v (non-fixed rows).  Both: A_i = P(F_i) B0_i
+// (B0 symmetric).
+template <int MODE, bool ELL>
+__global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col, int32_t S,
+                                              const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                                              const float2* __restrict__ geo2, const float4* __restrict__ sorted,
+                                              const float4* __restrict__ VH, float4* __restrict__ F0,
+                                              float4* __restrict__ F1, float* __restrict__ F2,
+                                              float4* __restrict__ posS, float* __restrict__ dFdt,
                                               float4* __restrict__ A0, float4* __restrict__ A1, float* __restrict__ A2) {
-    int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
+    const int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
     if (i >= n) return;
-    const int32_t ic = __float_as_int(sorted[i].w);                                     // caller index
-    float4 gi = geo0[i];
-    float4 vi = VH[i];
-    bool fixed = vi.w != 0.f;
+    const float4 gi = ld32(geo0, (uint32_t)i);
+    const float4 vi = ld32(VH, (uint32_t)i);
+    const bool fixed = vi.w != 0.f;
+    const float4 f0 = F0[i], f1 = F1[i];
+    const float f2 = F2[i];
+    const bool wrap = wave_needs_wrap(w, gi);
     Kahan L[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k].init();
-    int64_t e = row_ptr[i + 1];
-    for (int64_t k = row_ptr[i]; k < e; ++k) {
-        int32_t j = col[k];
-        float4 gj = geo0[j];
-        float4 vj = VH[j];
-        float d0 = min_image(gi.x - gj.x, b.L[0], b.halfL[0], b.periodic[0]);
-        float d1 = min_image(gi.y - gj.y, b.L[1], b.halfL[1], b.periodic[1]);
-        float d2 = min_image(gi.z - gj.z, b.L[2], b.halfL[2], b.periodic[2]);
-        float r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        float q = sqrtf(r2) * t.hinv;
-        float w = wendland_F(q, t.cF) * gj.w;  // V_j (dW/dr)/r
-        float dv[3] = {(vj.x - vi.x) * w, (vj.y - vi.y) * w, (vj.z - vi.z) * w};
-        float d[3] = {d0, d1, d2};
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) L[r * 3 + c].add(dv[r] * d[c]);
+    int64_t k, e, stride;
+    row_range<ELL>(i, n, rp, S, k, e, stride);
+    int32_t j = k < e ? col[k] : i;
+    float4 gj = ld32(geo0, (uint32_t)j), vj = ld32(VH, (uint32_t)j);
+    int32_t jn = k + stride < e ? col[k + stride] : i;
+    while (k < e) {
+        const float4 gn = ld32(geo0, (uint32_t)jn), vn = ld32(VH, (uint32_t)jn);
+        jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
+        k += stride;
+        if (wrap) acc_a<true>(t, w, gi, vi, gj, vj, L);
+        else acc_a<false>(t, w, gi, vi, gj, vj, L);
+        gj = gn;
+        vj = vn;
     }
     float B[9];
     load_B3(i, geo1, geo2, B);
     float Ld[9], Fd[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) Ld[k] = L[k].value();
+    for (int q = 0; q < 9; ++q) Ld[q] = L[q].value();
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int c = 0; c < 3; ++c) Fd[r * 3 + c] = Ld[r * 3 + 0] * B[c] + Ld[r * 3 + 1] * B[3 + c] + Ld[r * 3 + 2] * B[6 + c];
-    float* Fi = F + (int64_t)ic * 9;
-    float H[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) H[k] = Fi[k];
+    float H[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2};
     if (MODE == 0) {
+        const int32_t ic = __float_as_int(sorted[i].w);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) dFdt[(int64_t)ic * 9 + k] = Fd[k];
+        for (int q = 0; q < 9; ++q) dFdt[(int64_t)ic * 9 + q] = Fd[q];
     } else if (!fixed) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            H[k] += t.dt * Fd[k];
-            Fi[k] = H[k];
-        }
-        pos[ic] += t.dt * vi.x;
-        pos[(int64_t)n + ic] += t.dt * vi.y;
-        pos[2 * (int64_t)n + ic] += t.dt * vi.z;
+        for (int q = 0; q < 9; ++q) H[q] += t.dt * Fd[q];
+        F0[i] = make_float4(H[0], H[1], H[2], H[3]);
+        F1[i] = make_float4(H[4], H[5], H[6], H[7]);
+        F2[i] = H[8];
+        const float4 x = posS[i];
+        posS[i] = make_float4(x.x + t.dt * vi.x, x.y + t.dt * vi.y, x.z + t.dt * vi.z, 0.f);
     }
     H[0] -= 1.f;
     H[4] -= 1.f;
@@ -184,42 +252,66 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, BoxArgs b, TlArgs t, co
     A2[i] = Ai[8];
 }
 
-// Kernel B.  MODE 0: acc (caller SoA) = a_i (0 on fixed rows).
-// MODE 1: ACC[i] = a_i, VH[i] += dt a_i (non-fixed rows).
-template <int MODE>
-__global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, BoxArgs b, TlArgs t, const int64_t* __restrict__ row_ptr,
-                                              const int32_t* __restrict__ col, const float4* __restrict__ geo0,
-                                              const float4* __restrict__ A0, const float4* __restrict__ A1,
-                                              const float* __restrict__ A2, const float4* __restrict__ sorted,
-                                              float4* __restrict__ VH, float4* __restrict__ ACC,
-                                              float* __restrict__ acc) {
-    int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
+struct ARec {
+    float4 g, a0, a1;
+    float a2;
+};
+
+__device__ __forceinline__ void gather_a(int32_t j, const float4* __restrict__ geo0, const float4* __restrict__ A0,
+                                         const float4* __restrict__ A1, const float* __restrict__ A2, ARec& r) {
+    const uint32_t u = (uint32_t)j;
+    r.g = ld32(geo0, u);
+    r.a0 = ld32(A0, u);
+    r.a1 = ld32(A1, u);
+    r.a2 = ld32(A2, u);
+}
+
+template <bool WRAP>
+__device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const float4& gi, const float* Ai,
+                                      const ARec& b, Kahan* s) {
+    float d[3];
+    const float wt = pair_weight<WRAP>(t, w, gi, b.g, d);
+    const float g0 = wt * d[0], g1 = wt * d[1], g2 = wt * d[2];
+    s[0].add((Ai[0] + b.a0.x) * g0 + (Ai[1] + b.a0.y) * g1 + (Ai[2] + b.a0.z) * g2);
+    s[1].add((Ai[3] + b.a0.w) * g0 + (Ai[4] + b.a1.x) * g1 + (Ai[5] + b.a1.y) * g2);
+    s[2].add((Ai[6] + b.a1.z) * g0 + (Ai[7] + b.a1.w) * g1 + (Ai[8] + b.a2) * g2);
+}
+
+// Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
+// SoA) = a_i (0 on fixed rows).  MODE 1: ACC[i] = a_i, VH[i] += dt a_i
+// (non-fixed rows).
+template <int MODE, bool ELL>
+__global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const int64_t* __restrict__ rp,
+                                              const int32_t* __restrict__ col, int32_t S,
+                                              const float4* __restrict__ geo0, const float4* __restrict__ A0,
+                                              const float4* __restrict__ A1, const float* __restrict__ A2,
+                                              const float4* __restrict__ sorted, float4* __restrict__ VH,
+                                              float4* __restrict__ ACC, float* __restrict__ acc) {
+    const int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
     if (i >= n) return;
-    float4 gi = geo0[i];
-    float4 a0 = A0[i], a1 = A1[i];
-    float Ai[9] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w, A2[i]};
+    ARec own;
+    gather_a(i, geo0, A0, A1, A2, own);
+    const float4 gi = own.g;
+    const float Ai[9] = {own.a0.x, own.a0.y, own.a0.z, own.a0.w, own.a1.x, own.a1.y, own.a1.z, own.a1.w, own.a2};
+    const float4 vh = VH[i];
+    const bool wrap = wave_needs_wrap(w, gi);
     Kahan s[3];
     s[0].init(); s[1].init(); s[2].init();
-    int64_t e = row_ptr[i + 1];
-    for (int64_t k = row_ptr[i]; k < e; ++k) {
-        int32_t j = col[k];
-        float4 gj = geo0[j];
-        float4 b0 = A0[j], b1 = A1[j];
-        float b2 = A2[j];
-        float d0 = min_image(gi.x - gj.x, b.L[0], b.halfL[0], b.periodic[0]);
-        float d1 = min_image(gi.y - gj.y, b.L[1], b.halfL[1], b.periodic[1]);
-        float d2 = min_image(gi.z - gj.z, b.L[2], b.halfL[2], b.periodic[2]);
-        float r2 = d0 * d0 + d1 * d1 + d2 * d2;
-        float q = sqrtf(r2) * t.hinv;
-        float w = wendland_F(q, t.cF) * gj.w;
-        float g0 = w * d0, g1 = w * d1, g2 = w * d2;
-        s[0].add((Ai[0] + b0.x) * g0 + (Ai[1] + b0.y) * g1 + (Ai[2] + b0.z) * g2);
-        s[1].add((Ai[3] + b0.w) * g0 + (Ai[4] + b1.x) * g1 + (Ai[5] + b1.y) * g2);
-        s[2].add((Ai[6] + b1.z) * g0 + (Ai[7] + b1.w) * g1 + (Ai[8] + b2) * g2);
+    int64_t k, e, stride;
+    row_range<ELL>(i, n, rp, S, k, e, stride);
+    ARec cur, nxt;
+    gather_a(k < e ? col[k] : i, geo0, A0, A1, A2, cur);
+    int32_t jn = k + stride < e ? col[k + stride] : i;
+    while (k < e) {
+        gather_a(jn, geo0, A0, A1, A2, nxt);
+        jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
+        k += stride;
+        if (wrap) acc_b<true>(t, w, gi, Ai, cur, s);
+        else acc_b<false>(t, w, gi, Ai, cur, s);
+        cur = nxt;
     }
     float a[3] = {s[0].value() * t.inv_rho0, s[1].value() * t.inv_rho0, s[2].value() * t.inv_rho0};
-    float4 vh = VH[i];
-    bool fixed = vh.w != 0.f;
+    const bool fixed = vh.w != 0.f;
     if (fixed) a[0] = a[1] = a[2] = 0.f;
     if (MODE == 0) {
         const int32_t ic = __float_as_int(sorted[i].w);
@@ -230,6 +322,37 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, BoxArgs b, TlArgs t, co
         ACC[i] = make_float4(a[0], a[1], a[2], 0.f);
         if (!fixed) VH[i] = make_float4(vh.x + t.dt * a[0], vh.y + t.dt * a[1], vh.z + t.dt * a[2], 0.f);
     }
+}
+
+// F (caller [n][9]) and positions (caller SoA, optional) into sorted order, and back.
+__global__ void k_tl_pack(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ F,
+                          const float* __restrict__ pos, float4* __restrict__ F0, float4* __restrict__ F1,
+                          float* __restrict__ F2, float4* __restrict__ posS) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = __float_as_int(sorted[s].w);
+    const float* f = F + (int64_t)i * 9;
+    F0[s] = make_float4(f[0], f[1], f[2], f[3]);
+    F1[s] = make_float4(f[4], f[5], f[6], f[7]);
+    F2[s] = f[8];
+    if (pos) posS[s] = make_float4(pos[i], pos[(int64_t)n + i], pos[2 * (int64_t)n + i], 0.f);
+}
+
+__global__ void k_tl_unpack(int32_t n, const float4* __restrict__ sorted, const float4* __restrict__ F0,
+                            const float4* __restrict__ F1, const float* __restrict__ F2,
+                            const float4* __restrict__ posS, float* __restrict__ F, float* __restrict__ pos) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = __float_as_int(sorted[s].w);
+    const float4 a = F0[s], b = F1[s];
+    float* f = F + (int64_t)i * 9;
+    f[0] = a.x; f[1] = a.y; f[2] = a.z; f[3] = a.w;
+    f[4] = b.x; f[5] = b.y; f[6] = b.z; f[7] = b.w;
+    f[8] = F2[s];
+    const float4 x = posS[s];
+    pos[i] = x.x;
+    pos[(int64_t)n + i] = x.y;
+    pos[2 * (int64_t)n + i] = x.z;
 }
 
 // VH = v + half_dt * a (0 and flagged on fixed rows); ACC = a
@@ -299,7 +422,51 @@ int ensure_scratch(sph_ctx* c) {
     SPH_HIP(c, c->ta.ensure(n * sizeof(float4)));   // A0
     SPH_HIP(c, c->tb.ensure(n * sizeof(float4)));   // A1
     SPH_HIP(c, c->tc.ensure(n * sizeof(float)));    // A2
-    return SPH_OK;
+    SPH_HIP(c, c->fa.ensure(n * sizeof(float4)));   // F0
+    SPH_HIP(c, c->fb.ensure(n * sizeof(float4)));   // F1
+    SPH_HIP(c, c->fc.ensure(n * sizeof(float)));    // F2
+    SPH_HIP(c, c->pa.ensure(n * sizeof(float4)));   // current positions
+    return sph_ell_prepare(c);
+}
+
+Wrap make_wrap(const sph_ctx* c) {
+    Wrap w{};
+    for (int a = 0; a < 3; ++a) {
+        w.L[a] = c->box.L[a];
+        w.invL[a] = c->box.periodic[a] ? (float)(1.0 / c->box.Ld[a]) : 0.f;
+        w.lo[a] = c->box.lo[a];
+    }
+    w.margin = (float)(c->rc * 1.001);
+    return w;
+}
+
+template <int MODE>
+void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
+    dim3 g(grid_for(c->n, BLK)), bl(BLK);
+    const bool ell = c->ell_state == 1;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
+                           ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
+                           c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), c->sorted.as<float4>(),
+                           c->ua.as<float4>(), c->fa.as<float4>(), c->fb.as<float4>(), c->fc.as<float>(),
+                           c->pa.as<float4>(), dFdt, c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>());
+    };
+    if (ell) go(k_tl_a<MODE, true>);
+    else go(k_tl_a<MODE, false>);
+}
+
+template <int MODE>
+void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
+    dim3 g(grid_for(c->n, BLK)), bl(BLK);
+    const bool ell = c->ell_state == 1;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
+                           ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
+                           c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(),
+                           c->sorted.as<float4>(), c->ua.as<float4>(), c->ub.as<float4>(), acc);
+    };
+    if (ell) go(k_tl_b<MODE, true>);
+    else go(k_tl_b<MODE, false>);
 }
 
 }  // namespace
@@ -315,18 +482,15 @@ int sph_tlsph_rhs(sph_ctx* c, const sph_tlsph_params* p, const float* vel, const
     r = ensure_scratch(c);
     if (r) return r;
     TlArgs t = make_args(c, p);
+    Wrap w = make_wrap(c);
     dim3 g(grid_for(c->n, BLK)), bl(BLK);
     const float4* sorted = c->sorted.as<float4>();
     hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, 0.f, sorted, vel, (const float*)nullptr, fixed,
                        c->ua.as<float4>(), (float4*)nullptr);
-    // F is only read in MODE 0
-    hipLaunchKernelGGL(k_tl_a<0>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
-                       c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), sorted, c->ua.as<float4>(),
-                       const_cast<float*>(F), dF_dt, (float*)nullptr, c->ta.as<float4>(), c->tb.as<float4>(),
-                       c->tc.as<float>());
-    hipLaunchKernelGGL(k_tl_b<0>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
-                       c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(), sorted,
-                       c->ua.as<float4>(), (float4*)nullptr, acc);
+    hipLaunchKernelGGL(k_tl_pack, g, bl, 0, c->stream, c->n, sorted, F, (const float*)nullptr, c->fa.as<float4>(),
+                       c->fb.as<float4>(), c->fc.as<float>(), c->pa.as<float4>());
+    launch_a<0>(c, t, w, dF_dt);
+    launch_b<0>(c, t, w, acc);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -342,21 +506,21 @@ int sph_tlsph_step(sph_ctx* c, const sph_tlsph_params* p, const int32_t* fixed, 
     r = ensure_scratch(c);
     if (r) return r;
     TlArgs t = make_args(c, p);
+    Wrap w = make_wrap(c);
     dim3 g(grid_for(c->n, BLK)), bl(BLK);
     const float4* sorted = c->sorted.as<float4>();
     hipLaunchKernelGGL(k_tl_init, g, bl, 0, c->stream, c->n, t.half_dt, sorted, vel, acc, fixed, c->ua.as<float4>(),
                        c->ub.as<float4>());
+    hipLaunchKernelGGL(k_tl_pack, g, bl, 0, c->stream, c->n, sorted, F, pos, c->fa.as<float4>(), c->fb.as<float4>(),
+                       c->fc.as<float>(), c->pa.as<float4>());
     for (int32_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL(k_tl_a<1>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(),
-                           c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(),
-                           sorted, c->ua.as<float4>(), F, (float*)nullptr, pos, c->ta.as<float4>(), c->tb.as<float4>(),
-                           c->tc.as<float>());
-        hipLaunchKernelGGL(k_tl_b<1>, g, bl, 0, c->stream, c->n, c->box, t, c->rp_s.as<int64_t>(),
-                           c->col_s.as<int32_t>(), c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(),
-                           c->tc.as<float>(), sorted, c->ua.as<float4>(), c->ub.as<float4>(), (float*)nullptr);
+        launch_a<1>(c, t, w, nullptr);
+        launch_b<1>(c, t, w, nullptr);
     }
     hipLaunchKernelGGL(k_tl_finish, g, bl, 0, c->stream, c->n, t.half_dt, sorted, c->ua.as<float4>(),
                        c->ub.as<float4>(), vel, acc);
+    hipLaunchKernelGGL(k_tl_unpack, g, bl, 0, c->stream, c->n, sorted, c->fa.as<float4>(), c->fb.as<float4>(),
+                       c->fc.as<float>(), c->pa.as<float4>(), F, pos);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }

@@ -237,7 +237,7 @@ def test_euler_rhs_row_layouts(S, rows, kappa, monkeypatch):
     over fixed-stride rows and over the CSR rows."""
     env = {"batch4": {"SPH_EULER_BATCH_LANES": "4"}, "batch8": {"SPH_EULER_BATCH_LANES": "8"},
            "ell": {"SPH_EULER_BATCH_LANES": "0"},
-           "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_EULER_ROWS": "csr"}}[rows]
+           "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_PAIR_ROWS": "csr"}}[rows]
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     w = I.single_step_2d(seed=1)
@@ -367,7 +367,10 @@ def _tl_setup(S, w, kappa, model):
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 @pytest.mark.parametrize("model", [0, 1])
-def test_tlsph_rhs(S, kappa, model):
+@pytest.mark.parametrize("rows", ["ell", "csr"])
+def test_tlsph_rhs(S, kappa, model, rows, monkeypatch):
+    if rows == "csr":
+        monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
     w = _plate()
     ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, model)
     rng = np.random.default_rng(2)
@@ -388,7 +391,10 @@ def test_tlsph_rhs(S, kappa, model):
 
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-def test_tlsph_steps(S, kappa):
+@pytest.mark.parametrize("rows", ["ell", "csr"])
+def test_tlsph_steps(S, kappa, rows, monkeypatch):
+    if rows == "csr":
+        monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
     w = _plate()
     ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, 0)
     F0 = np.tile(np.eye(3, dtype=np.float32), (w.n, 1, 1))
