@@ -28,6 +28,27 @@ METRIC = "particle-neighbour interactions/s, 1.6h vs 2h; relax time-to-residue, 
 HBM_PEAK_GBS = 8000.0
 
 
+# HBM traffic per launch of the stage kernel measured with rocprofv3
+# (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors read off a plain 256 MiB copy),
+# keyed by the SHA-256 of the kernel source it was measured on: a changed
+# kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
+TRAFFIC = {}
+
+
+def source_sha(rel: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stage_bytes_3d(n: int, nnz: int) -> float:
+    """Algorithmic HBM bytes of one RHS evaluation in 3-D: per particle read
+    the position (12 B), V (4 B), density (4 B), velocity (12 B) and B
+    (36 B), write the four rates (16 B) and read the row offset (8 B): 92 B;
+    per neighbour pair the column index (4 B)."""
+    return 92.0 * n + 4.0 * nnz
+
+
 def stage_bytes_2d(n: int, nnz: int) -> float:
     """Algorithmic HBM bytes of one RHS evaluation in 2-D: per particle read
     the position (8 B), V (4 B), density (4 B), velocity (8 B) and the
@@ -94,8 +115,11 @@ def run_euler_3d(nside, kappa, steps, warmup):
     ms = e0.elapsed_time(e1)
     nnz = ctx.nnz
     ctx.close()
+    launch_s = ms * 1e-3 / (2 * steps)
+    bytes_launch = stage_bytes_3d(w.n, nnz)
     return {"n_particles": w.n, "nnz": nnz, "ms_per_step": ms / steps,
-            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3), "avg_launch_us": launch_s * 1e6,
+            "bytes_per_launch": bytes_launch, "achieved_GBs": bytes_launch / launch_s / 1e9}
 
 
 def run_plate(kappa, steps, warmup, nx=430):
@@ -222,6 +246,7 @@ def main():
     ap.add_argument("--steps3d", type=int, default=50)
     ap.add_argument("--steps-plate", type=int, default=200)
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
+    ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
@@ -236,7 +261,12 @@ def main():
 
     if args.kappa:
         one = run_gpu(w, args.kappa, args.steps, args.warmup)
-        print(json.dumps({"kappa": args.kappa, **one}), flush=True)
+        print(json.dumps({"kappa": args.kappa, **one, "avg_launch_us": one["ms"] * 1e3 / one["launches"]}),
+              flush=True)
+        return
+    if args.kappa3d:
+        one = run_euler_3d(args.nside3d, args.kappa3d, args.steps3d, min(args.warmup, 5))
+        print(json.dumps({"kappa": args.kappa3d, **one}), flush=True)
         return
     tw = run_gpu(w, 1.6, args.steps, args.warmup)
     sw = run_gpu(w, 2.0, args.steps, args.warmup)
@@ -263,14 +293,20 @@ def main():
         "sw_2h": {"value": sw["interactions_per_s"], "ms_per_step": sw["ms_per_step"]},
         "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_euler<2,stage> (Heun stage, 1.6h)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("2d"),
+                     "kernel": "k_euler (2-D Heun stage, 1.6h)",
                      "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch},
     }
     if not args.no_extra:
         tw3, sw3 = run_euler_3d(args.nside3d, 1.6, args.steps3d, 5), run_euler_3d(args.nside3d, 2.0, args.steps3d, 5)
         out["taylor_green_3d"] = {"nside": args.nside3d, "kappa1.6": tw3, "kappa2": sw3,
                                   "speedup_tw_over_sw": sw3["ms_per_step"] / tw3["ms_per_step"]}
+        out["roofline_3d"] = {"bound": "hbm", "achieved": tw3["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": tw3["achieved_GBs"] / HBM_PEAK_GBS,
+                              "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("3d"),
+                              "kernel": "k_euler (3-D Heun stage, 1.6h, 200^3)",
+                              "avg_launch_us": tw3["avg_launch_us"], "bytes_per_launch": tw3["bytes_per_launch"]}
         twp, swp = run_plate(1.6, args.steps_plate, 5), run_plate(2.0, args.steps_plate, 5)
         out["tlsph_plate"] = {"kappa1.6": twp, "kappa2": swp,
                               "speedup_tw_over_sw": swp["ms_per_step"] / twp["ms_per_step"]}

@@ -735,9 +735,10 @@ bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
 }
 
 // Lanes per particle for the batched rows: 4 when four entries per lane
-// cover the row, else 8 (tuning override SPH_EULER_BATCH_LANES = 4 or 8;
-// 0 turns batching off).  Batching serves configurations whose lane
-// groups are too few to hide memory latency with a pipeline (n <= 2^21).
+// cover the row (measured: with 8 lanes the pipelined loop is faster).
+// Batching serves configurations whose lane groups are too few to hide
+// memory latency with a pipeline (n <= 2^21).  Tuning override
+// SPH_EULER_BATCH_LANES = 4 or 8; 0 turns batching off.
 int batch_lanes(const sph_ctx* c) {
     int forced = -1;
     if (const char* e = getenv("SPH_EULER_BATCH_LANES")) forced = atoi(e);
@@ -746,24 +747,23 @@ int batch_lanes(const sph_ctx* c) {
     if (forced == 4 || forced == 8) return (c->ell_S + forced - 1) / forced <= 4 ? forced : 0;
     if (c->n > (1 << 21)) return 0;
     if ((c->ell_S + 3) / 4 <= 4) return 4;
-    if ((c->ell_S + 7) / 8 <= 4) return 8;
     return 0;
 }
 
-// Lanes per particle: enough lane groups to give every SIMD several waves
-// (the chip holds 256 CUs x 4 SIMDs), and a few neighbours per lane.
+// Lanes per particle: the most (up to 8) that still leave each lane at
+// least five row entries.  More lanes put more of a row's gathers in flight
+// at once; fewer keep the pipeline over the row deep enough and the lane
+// combination cheap (measured on 2-D and 3-D Taylor-Green rows of 12 to 80
+// entries).
 int lanes_per_particle(const sph_ctx* c) {
     // tuning override: SPH_EULER_LANES = 1, 2, 4 or 8
-    static int forced = [] {
-        const char* e = getenv("SPH_EULER_LANES");
-        int v = e ? atoi(e) : 0;
-        return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 0;
-    }();
-    if (forced) return forced;
-    const int64_t target = 256LL * 4 * 16 * 64;  // two rounds of 8 waves per SIMD
-    double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
+    if (const char* e = getenv("SPH_EULER_LANES")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+    }
+    const double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
     int L = 1;
-    while (L < 8 && (int64_t)c->n * L < target && avg / (2 * L) >= 2.0) L <<= 1;
+    while (L < 8 && avg / (2 * L) >= 5.0) L <<= 1;
     return L;
 }
 

@@ -162,10 +162,13 @@ __global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restr
     }
 }
 
+// Largest row length: a wave-level maximum, then one atomic per wave.
 __global__ void k_row_max(int32_t n, const int32_t* __restrict__ cnt, int32_t* out) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    atomicMax(out, cnt[i]);
+    int32_t v = i < n ? cnt[i] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
 }
 
 __global__ void k_fill_ell(int32_t n, int32_t S, const int64_t* __restrict__ rp_s, const int32_t* __restrict__ col_s,

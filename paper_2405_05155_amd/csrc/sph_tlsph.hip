@@ -14,6 +14,8 @@
 // caller's arrays at its start and end).
 #include "sph_internal.h"
 
+#include <cstdlib>
+
 namespace {
 
 constexpr int BLK = 256;
@@ -131,17 +133,18 @@ __device__ __forceinline__ bool wave_needs_wrap(const Wrap& w, const float4& x) 
     return __any(near);
 }
 
-// Row entries of sorted slot i: ELL (entry k at col[k n + i], k < S) or CSR.
-template <bool ELL>
-__device__ __forceinline__ void row_range(int32_t i, int32_t n, const int64_t* __restrict__ rp, int32_t S, int64_t& k,
-                                          int64_t& e, int64_t& stride) {
+// Row entries of sorted slot i taken by lane `sub` of an L-lane group:
+// entries sub, sub + L, ...  ELL (entry k at col[k n + i], k < S) or CSR.
+template <bool ELL, int L>
+__device__ __forceinline__ void row_range(int32_t i, int sub, int32_t n, const int64_t* __restrict__ rp, int32_t S,
+                                          int64_t& k, int64_t& e, int64_t& stride) {
     if (ELL) {
-        k = i;
-        stride = n;
+        k = (int64_t)sub * n + i;
+        stride = (int64_t)L * n;
         e = (int64_t)S * n;
     } else {
-        k = rp[i];
-        stride = 1;
+        k = rp[i] + sub;
+        stride = L;
         e = rp[i + 1];
     }
 }
@@ -180,7 +183,7 @@ __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const floa
 // (F0, F1, F2).  MODE 0: dF/dt -> dFdt at the caller index, F untouched.
 // MODE 1: F += dt dF/dt, x += dt v (non-fixed rows).  Both: A_i = P(F_i) B0_i
 // (B0 symmetric).
-template <int MODE, bool ELL>
+template <int MODE, bool ELL, int LN>
 __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ col, int32_t S,
                                               const float4* __restrict__ geo0, const float4* __restrict__ geo1,
@@ -189,7 +192,9 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
                                               float4* __restrict__ F1, float* __restrict__ F2,
                                               float4* __restrict__ posS, float* __restrict__ dFdt,
                                               float4* __restrict__ A0, float4* __restrict__ A1, float* __restrict__ A2) {
-    const int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
+    const int64_t tt = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
+    const int32_t i = (int32_t)(tt / LN);  // sorted slot
+    const int sub = (int)(tt % LN);
     if (i >= n) return;
     const float4 gi = ld32(geo0, (uint32_t)i);
     const float4 vi = ld32(VH, (uint32_t)i);
@@ -201,7 +206,7 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k].init();
     int64_t k, e, stride;
-    row_range<ELL>(i, n, rp, S, k, e, stride);
+    row_range<ELL, LN>(i, sub, n, rp, S, k, e, stride);
     int32_t j = k < e ? col[k] : i;
     float4 gj = ld32(geo0, (uint32_t)j), vj = ld32(VH, (uint32_t)j);
     int32_t jn = k + stride < e ? col[k + stride] : i;
@@ -214,11 +219,12 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
         gj = gn;
         vj = vn;
     }
-    float B[9];
-    load_B3(i, geo1, geo2, B);
     float Ld[9], Fd[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) Ld[q] = L[q].value();
+    for (int q = 0; q < 9; ++q) Ld[q] = group_sum<LN>(L[q]);
+    if (sub != 0) return;
+    float B[9];
+    load_B3(i, geo1, geo2, B);
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -280,14 +286,16 @@ __device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const floa
 // Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
 // SoA) = a_i (0 on fixed rows).  MODE 1: ACC[i] = a_i, VH[i] += dt a_i
 // (non-fixed rows).
-template <int MODE, bool ELL>
+template <int MODE, bool ELL, int LN>
 __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const int64_t* __restrict__ rp,
                                               const int32_t* __restrict__ col, int32_t S,
                                               const float4* __restrict__ geo0, const float4* __restrict__ A0,
                                               const float4* __restrict__ A1, const float* __restrict__ A2,
                                               const float4* __restrict__ sorted, float4* __restrict__ VH,
                                               float4* __restrict__ ACC, float* __restrict__ acc) {
-    const int32_t i = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;  // sorted slot
+    const int64_t tt = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
+    const int32_t i = (int32_t)(tt / LN);  // sorted slot
+    const int sub = (int)(tt % LN);
     if (i >= n) return;
     ARec own;
     gather_a(i, geo0, A0, A1, A2, own);
@@ -298,7 +306,7 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
     Kahan s[3];
     s[0].init(); s[1].init(); s[2].init();
     int64_t k, e, stride;
-    row_range<ELL>(i, n, rp, S, k, e, stride);
+    row_range<ELL, LN>(i, sub, n, rp, S, k, e, stride);
     ARec cur, nxt;
     gather_a(k < e ? col[k] : i, geo0, A0, A1, A2, cur);
     int32_t jn = k + stride < e ? col[k + stride] : i;
@@ -310,7 +318,9 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
         else acc_b<false>(t, w, gi, Ai, cur, s);
         cur = nxt;
     }
-    float a[3] = {s[0].value() * t.inv_rho0, s[1].value() * t.inv_rho0, s[2].value() * t.inv_rho0};
+    float a[3] = {group_sum<LN>(s[0]) * t.inv_rho0, group_sum<LN>(s[1]) * t.inv_rho0,
+                  group_sum<LN>(s[2]) * t.inv_rho0};
+    if (sub != 0) return;
     const bool fixed = vh.w != 0.f;
     if (fixed) a[0] = a[1] = a[2] = 0.f;
     if (MODE == 0) {
@@ -440,9 +450,25 @@ Wrap make_wrap(const sph_ctx* c) {
     return w;
 }
 
+// Lanes per particle of the total-Lagrangian pair loops: the most (up to
+// 4) that leave each lane at least three row entries (measured on the
+// cantilever plate, rows of 26 and 56 entries).  Tuning override
+// SPH_TLSPH_LANES = 1, 2 or 4.
+int tl_lanes(const sph_ctx* c) {
+    if (const char* e = getenv("SPH_TLSPH_LANES")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4) return v;
+    }
+    const double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
+    int L = 1;
+    while (L < 4 && avg / (2 * L) >= 3.0) L <<= 1;
+    return L;
+}
+
 template <int MODE>
 void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
-    dim3 g(grid_for(c->n, BLK)), bl(BLK);
+    const int LN = tl_lanes(c);
+    dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
     const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
@@ -451,13 +477,21 @@ void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
                            c->ua.as<float4>(), c->fa.as<float4>(), c->fb.as<float4>(), c->fc.as<float>(),
                            c->pa.as<float4>(), dFdt, c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>());
     };
-    if (ell) go(k_tl_a<MODE, true>);
-    else go(k_tl_a<MODE, false>);
+    if (ell) {
+        if (LN == 1) go(k_tl_a<MODE, true, 1>);
+        else if (LN == 2) go(k_tl_a<MODE, true, 2>);
+        else go(k_tl_a<MODE, true, 4>);
+    } else {
+        if (LN == 1) go(k_tl_a<MODE, false, 1>);
+        else if (LN == 2) go(k_tl_a<MODE, false, 2>);
+        else go(k_tl_a<MODE, false, 4>);
+    }
 }
 
 template <int MODE>
 void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
-    dim3 g(grid_for(c->n, BLK)), bl(BLK);
+    const int LN = tl_lanes(c);
+    dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
     const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
@@ -465,8 +499,15 @@ void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
                            c->geo0.as<float4>(), c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(),
                            c->sorted.as<float4>(), c->ua.as<float4>(), c->ub.as<float4>(), acc);
     };
-    if (ell) go(k_tl_b<MODE, true>);
-    else go(k_tl_b<MODE, false>);
+    if (ell) {
+        if (LN == 1) go(k_tl_b<MODE, true, 1>);
+        else if (LN == 2) go(k_tl_b<MODE, true, 2>);
+        else go(k_tl_b<MODE, true, 4>);
+    } else {
+        if (LN == 1) go(k_tl_b<MODE, false, 1>);
+        else if (LN == 2) go(k_tl_b<MODE, false, 2>);
+        else go(k_tl_b<MODE, false, 4>);
+    }
 }
 
 }  // namespace

@@ -367,10 +367,13 @@ def _tl_setup(S, w, kappa, model):
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 @pytest.mark.parametrize("model", [0, 1])
-@pytest.mark.parametrize("rows", ["ell", "csr"])
+@pytest.mark.parametrize("rows", ["ell", "csr", "ell1", "ell4"])
 def test_tlsph_rhs(S, kappa, model, rows, monkeypatch):
+    """rows: fixed-stride or CSR rows; ell1 / ell4 force 1 or 4 lanes per particle."""
     if rows == "csr":
         monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
+    if rows in ("ell1", "ell4"):
+        monkeypatch.setenv("SPH_TLSPH_LANES", rows[-1])
     w = _plate()
     ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, model)
     rng = np.random.default_rng(2)
