@@ -162,6 +162,7 @@ struct sph_ctx {
     DevBuf slot;        // int32 [n]
     DevBuf cell_start;  // int32 [ncell + 1]
     DevBuf sorted;      // float4 [n] (x, y, z, bits(index)) in cell order
+    DevBuf sorted_tmp;  // float4 [n] provisional placement before the in-cell ordering
     DevBuf cnt;         // int32 [n]
     DevBuf row_ptr;     // int64 [n + 1]   caller order (export)
     DevBuf col;         // int32 [nnz]     caller order, caller indices, rows ascending
@@ -187,7 +188,7 @@ struct sph_ctx {
     DevBuf tail;        // float [ntail]
     double tail_h = 0.0, tail_R = 0.0;
     int ntail = 0;
-    DevBuf svol;        // float [n] volumes in cell order
+    DevBuf svol;        // cell-order scratch: volumes (pair loops) or (x, y, z, V) records (relaxation)
     DevBuf sfield;      // float [n] a caller field in cell order
     DevBuf partials;    // per-block reduction partials
     DevBuf relax_scalars;

@@ -50,21 +50,20 @@ __global__ void k_scatter(int32_t n, const float4* __restrict__ pos4, const int3
     sorted[cell_start[cell_of[i]] + slot[i]] = p;
 }
 
-// members of each cell in ascending caller index (deterministic order)
-__global__ void k_sort_cells(int64_t ncell, const int32_t* __restrict__ cell_start, float4* __restrict__ sorted) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    int32_t s0 = cell_start[c], s1 = cell_start[c + 1];
-    for (int32_t a = s0 + 1; a < s1; ++a) {
-        float4 v = sorted[a];
-        int32_t key = __float_as_int(v.w);
-        int32_t b2 = a - 1;
-        while (b2 >= s0 && __float_as_int(sorted[b2].w) > key) {
-            sorted[b2 + 1] = sorted[b2];
-            --b2;
-        }
-        sorted[b2 + 1] = v;
-    }
+// Members of each cell in ascending caller index (deterministic order):
+// slot s of the provisional (atomic) placement goes to cell start + its rank
+// among the cell's members.
+__global__ void k_rank_cells(int32_t n, const int32_t* __restrict__ cell_of, const int32_t* __restrict__ cell_start,
+                             const float4* __restrict__ tmp, float4* __restrict__ sorted) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float4 p = tmp[s];
+    const int32_t i = __float_as_int(p.w);
+    const int32_t key = cell_of[i];
+    const int32_t c0 = cell_start[key], c1 = cell_start[key + 1];
+    int32_t rank = 0;
+    for (int32_t t = c0; t < c1; ++t) rank += __float_as_int(tmp[t].w) < i ? 1 : 0;
+    sorted[c0 + rank] = p;
 }
 
 __device__ __forceinline__ double md_image(double d, double L, double halfL, int periodic) {
@@ -257,6 +256,7 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
     SPH_HIP(c, c->cell_of.ensure(nn * sizeof(int32_t)));
     SPH_HIP(c, c->slot.ensure(nn * sizeof(int32_t)));
     SPH_HIP(c, c->sorted.ensure(nn * sizeof(float4)));
+    SPH_HIP(c, c->sorted_tmp.ensure(nn * sizeof(float4)));
     SPH_HIP(c, c->cnt.ensure((ncell + 1 > nn ? ncell + 1 : nn) * sizeof(int32_t)));
     SPH_HIP(c, c->cell_start.ensure((ncell + 1) * sizeof(int32_t)));
 
@@ -272,9 +272,10 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->pos4.as<float4>(),
                            c->cell_of.as<int32_t>(), c->slot.as<int32_t>(), c->cell_start.as<int32_t>(),
+                           c->sorted_tmp.as<float4>());
+        hipLaunchKernelGGL(k_rank_cells, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n,
+                           c->cell_of.as<int32_t>(), c->cell_start.as<int32_t>(), c->sorted_tmp.as<float4>(),
                            c->sorted.as<float4>());
-        hipLaunchKernelGGL(k_sort_cells, dim3(grid_for(ncell, BLK)), dim3(BLK), 0, c->stream, ncell,
-                           c->cell_start.as<int32_t>(), c->sorted.as<float4>());
         SPH_LAUNCH_CHECK(c);
     }
     return SPH_OK;

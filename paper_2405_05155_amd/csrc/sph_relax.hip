@@ -152,25 +152,27 @@ __device__ __forceinline__ float tail_at(const float* __restrict__ tail, const R
 }
 
 // Residual force g_i (caller order) and per-block partials of max|g| and
-// sum |h g|^2 (FP64).  One thread per particle in cell order.
+// sum |h g|^2 (FP64).  One thread per particle in cell order scans the 3x3x3
+// cell block (cells in (z, y, x) order, members in cell order); the FP32
+// distance test is redone in FP64 within 1e-5 of the cut-off.  rec holds
+// (x, y, z, V) per sorted slot, so a candidate costs one 16-byte load.
 __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const int32_t* __restrict__ cell_start,
-                                                 const float4* __restrict__ sorted, const float* __restrict__ svol,
+                                                 const float4* __restrict__ sorted, const float4* __restrict__ rec,
                                                  const float* __restrict__ tail, float4* __restrict__ gout,
                                                  float* __restrict__ part_max, double* __restrict__ part_sum) {
     __shared__ float smax[BLK];
     __shared__ double ssum[BLK];
-    int32_t s = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
+    const int32_t s = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
     float gmag = 0.f;
     double gh2 = 0.0;
     if (s < n) {
         const BoxArgs& b = ra.b;
-        float4 p = sorted[s];
-        int32_t i = __float_as_int(p.w);
+        const float4 p = ld32(rec, (uint32_t)s);
         Kahan g[3];
         g[0].init(); g[1].init(); g[2].init();
-        int cx = ccoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
-        int cy = ccoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
-        int cz = ccoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]);
+        const int cx = ccoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
+        const int cy = ccoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
+        const int cz = ccoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]);
         for (int oz = -1; oz <= 1; ++oz) {
             int z = cz + oz;
             if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
@@ -183,20 +185,20 @@ __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const 
                     int x = cx + ox;
                     if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
                     else if (x < 0 || x >= b.nc[0]) continue;
-                    int32_t key = cell_key(b, x, y, z);
-                    int t0 = cell_start[key], t1 = cell_start[key + 1];
-                    for (int t = t0; t < t1; ++t) {
+                    const int32_t key = cell_key(b, x, y, z);
+                    const int32_t t0 = cell_start[key], t1 = cell_start[key + 1];
+                    for (int32_t t = t0; t < t1; ++t) {
                         if (t == s) continue;
-                        float4 q = sorted[t];
-                        float d0 = min_image(p.x - q.x, b.L[0], b.halfL[0], b.periodic[0]);
-                        float d1 = min_image(p.y - q.y, b.L[1], b.halfL[1], b.periodic[1]);
-                        float d2 = min_image(p.z - q.z, b.L[2], b.halfL[2], b.periodic[2]);
-                        float r2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+                        const float4 q = ld32(rec, (uint32_t)t);
+                        const float d0 = min_image(p.x - q.x, b.L[0], b.halfL[0], b.periodic[0]);
+                        const float d1 = min_image(p.y - q.y, b.L[1], b.halfL[1], b.periodic[1]);
+                        const float d2 = min_image(p.z - q.z, b.L[2], b.halfL[2], b.periodic[2]);
+                        const float r2 = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
                         bool in = r2 <= ra.rc2f;
                         if (fabsf(r2 - ra.rc2f) <= 1e-5f * ra.rc2f) in = exact_in(p, q, b, ra.rc2d);
                         if (!in) continue;
-                        float q2 = r2 * ra.hinv2;
-                        float w = ra.cF * __expf(-q2) * (12.f - 8.f * q2 + q2 * q2) * svol[t];
+                        const float q2 = r2 * ra.hinv2;
+                        const float w = ra.cF * __expf(-q2) * (12.f - 8.f * q2 + q2 * q2) * q.w;
                         g[0].add(w * d0);
                         g[1].add(w * d1);
                         g[2].add(w * d2);
@@ -205,18 +207,19 @@ __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const 
             }
         }
         // exterior-tail term
-        float ex = p.x - ra.c[0], ey = p.y - ra.c[1], ez = p.z - ra.c[2];
-        float rr = sqrtf(ex * ex + ey * ey + ez * ez);
-        float phi = rr - ra.R;
+        const int32_t i = __float_as_int(sorted[s].w);
+        const float ex = p.x - ra.c[0], ey = p.y - ra.c[1], ez = p.z - ra.c[2];
+        const float rr = sqrtf(ex * ex + ey * ey + ez * ez);
+        const float phi = rr - ra.R;
         if (rr > 0.f) {
-            float T = tail_at(tail, ra, phi) / rr;
+            const float T = tail_at(tail, ra, phi) / rr;
             g[0].add(T * ex);
             g[1].add(T * ey);
             g[2].add(T * ez);
         }
-        float gx = g[0].value(), gy = g[1].value(), gz = g[2].value();
+        const float gx = g[0].value(), gy = g[1].value(), gz = g[2].value();
         gout[i] = make_float4(gx, gy, gz, 0.f);
-        double g2 = (double)gx * gx + (double)gy * gy + (double)gz * gz;
+        const double g2 = (double)gx * gx + (double)gy * gy + (double)gz * gz;
         gh2 = ra.hh * g2;
         gmag = (float)sqrt(g2);
     }
@@ -308,11 +311,13 @@ __global__ void k_relax_move(int32_t n, RelaxArgs ra, const RelaxScalars* __rest
     u[2 * nn + i] = u2;
 }
 
-__global__ void k_sorted_vol(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ vol,
-                             float* __restrict__ svol) {
+// (x, y, z, V) per sorted slot
+__global__ void k_sorted_rec(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ vol,
+                             float4* __restrict__ rec) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    svol[s] = vol[__float_as_int(sorted[s].w)];
+    const float4 p = sorted[s];
+    rec[s] = make_float4(p.x, p.y, p.z, vol[__float_as_int(p.w)]);
 }
 
 __global__ void k_unpack_g(int32_t n, const float4* __restrict__ g4, float* __restrict__ g) {
@@ -375,17 +380,17 @@ int relax_eval(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, int
     *ra_out = ra;
     int64_t nn = n > 0 ? n : 1;
     int nb = (int)grid_for(nn, BLK);
-    SPH_HIP(c, c->svol.ensure(nn * sizeof(float)));
+    SPH_HIP(c, c->svol.ensure(nn * sizeof(float4)));
     SPH_HIP(c, c->ta.ensure(nn * sizeof(float4)));
     SPH_HIP(c, c->partials.ensure((size_t)nb * (sizeof(float) + sizeof(double)) + 64));
     SPH_HIP(c, c->relax_scalars.ensure(sizeof(RelaxScalars)));
     double* psum = c->partials.as<double>();
     float* pmax = reinterpret_cast<float*>(psum + nb);
     if (n > 0) {
-        hipLaunchKernelGGL(k_sorted_vol, dim3(nb), dim3(BLK), 0, c->stream, n, c->sorted.as<float4>(), vol,
-                           c->svol.as<float>());
+        hipLaunchKernelGGL(k_sorted_rec, dim3(nb), dim3(BLK), 0, c->stream, n, c->sorted.as<float4>(), vol,
+                           c->svol.as<float4>());
         hipLaunchKernelGGL(k_relax_g, dim3(nb), dim3(BLK), 0, c->stream, n, ra, c->cell_start.as<int32_t>(),
-                           c->sorted.as<float4>(), c->svol.as<float>(), c->tail.as<float>(), c->ta.as<float4>(),
+                           c->sorted.as<float4>(), c->svol.as<float4>(), c->tail.as<float>(), c->ta.as<float4>(),
                            pmax, psum);
     }
     hipLaunchKernelGGL(k_relax_reduce, dim3(1), dim3(BLK), 0, c->stream, n > 0 ? nb : 0, n, ra, pmax, psum,
