@@ -32,7 +32,10 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors read off a plain 256 MiB copy),
 # keyed by the SHA-256 of the kernel source it was measured on: a changed
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
-TRAFFIC = {}
+# (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
+TRAFFIC = {
+    "115178f9f078daaa09d601910a77870ce1d4f9b80febfd394d67b9e012448729": {"2d": 39134147, "3d": 2206857136},
+}
 
 
 def source_sha(rel: str) -> str:
@@ -247,6 +250,7 @@ def main():
     ap.add_argument("--steps-plate", type=int, default=200)
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
+    ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
@@ -263,6 +267,15 @@ def main():
         one = run_gpu(w, args.kappa, args.steps, args.warmup)
         print(json.dumps({"kappa": args.kappa, **one, "avg_launch_us": one["ms"] * 1e3 / one["launches"]}),
               flush=True)
+        return
+    if args.relax_iters:
+        from paper_2405_05155_amd import sph as S
+        from paper_2405_05155_amd import warmstart as WS
+        ctx = S.Context(3)
+        wr = I.sphere_fill(dx=1.0 / args.relax_nside, seed=2)
+        run, _, _ = WS.relax_plain(ctx, wr, max_iter=args.relax_iters)
+        print(json.dumps({"relax_iterations": run.iterations, "seconds": run.seconds, "residue": run.residue,
+                          "n_particles": wr.n}), flush=True)
         return
     if args.kappa3d:
         one = run_euler_3d(args.nside3d, args.kappa3d, args.steps3d, min(args.warmup, 5))
