@@ -165,7 +165,8 @@ struct sph_ctx {
     DevBuf sorted_tmp;  // float4 [n] provisional placement before the in-cell ordering
     DevBuf cnt;         // int32 [n]
     DevBuf row_ptr;     // int64 [n + 1]   caller order (export)
-    DevBuf col;         // int32 [nnz]     caller order, caller indices, rows ascending
+    DevBuf col;         // int32 [nnz]     caller order, caller indices, rows ascending (built on export)
+    bool export_valid = false;
     DevBuf cnt_s;       // int32 [n]       per cell-sorted slot
     DevBuf rp_s;        // int64 [n + 1]   cell-sorted rows
     DevBuf col_s;       // int32 [nnz]     cell-sorted rows, sorted-slot indices

@@ -1,12 +1,13 @@
 // sph_neighbors.hip -- binding a particle configuration: a uniform cell grid
 // with Morton-ordered cell keys (counting sort by key, members of a cell in
 // ascending caller index), and the exact neighbour sets
-// N(i) = {j != i : |r_ij|^2 <= (kappa h)^2} stored twice:
+// N(i) = {j != i : |r_ij|^2 <= (kappa h)^2} stored
 //   - in cell-sorted order with sorted-slot column indices (the layout every
 //     pair loop of the library runs on: neighbours of a block of slots lie in
-//     a compact region of the sorted arrays), and
-//   - in caller order with caller indices, each row ascending (the exported
-//     CSR).
+//     a compact region of the sorted arrays), found one wave per particle
+//     with ballot compaction, and
+//   - on the first export, in caller order with caller indices, each row
+//     ascending (the exported CSR; a wave-level bitonic sort per row).
 //
 // Neighbour decision.  The compact support of Eq. (5) keeps r = kappa h.  The
 // squared distance is evaluated in FP64 from the FP32 coordinates with the
@@ -17,6 +18,7 @@
 // set is defined independently of the evaluation order.
 #include "sph_internal.h"
 
+#include <climits>
 #include <cstdlib>
 
 namespace {
@@ -74,37 +76,6 @@ __device__ __forceinline__ double md_image(double d, double L, double halfL, int
     return d;
 }
 
-// Visit every sorted slot t in the 3^dim block of cells around p; f(t, q).
-template <int DIM, class F>
-__device__ __forceinline__ void for_each_candidate(const float4& p, const BoxArgs& b,
-                                                   const int32_t* __restrict__ cell_start,
-                                                   const float4* __restrict__ sorted, F&& f) {
-    int cx = cell_coord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
-    int cy = cell_coord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
-    int cz = DIM == 3 ? cell_coord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) : 0;
-    const int zr = DIM == 3 ? 1 : 0;
-    for (int oz = -zr; oz <= zr; ++oz) {
-        int z = cz + oz;
-        if (DIM == 3) {
-            if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
-            else if (z < 0 || z >= b.nc[2]) continue;
-        }
-        for (int oy = -1; oy <= 1; ++oy) {
-            int y = cy + oy;
-            if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
-            else if (y < 0 || y >= b.nc[1]) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int x = cx + ox;
-                if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
-                else if (x < 0 || x >= b.nc[0]) continue;
-                int32_t key = cell_key(b, x, y, z);
-                int32_t s1 = cell_start[key + 1];
-                for (int32_t s = cell_start[key]; s < s1; ++s) f(s, sorted[s]);
-            }
-        }
-    }
-}
-
 template <int DIM>
 __device__ __forceinline__ bool is_neighbour(const float4& p, const float4& q, const BoxArgs& b, double rc2) {
     double dx = md_image(__dsub_rn((double)p.x, (double)q.x), b.Ld[0], b.halfLd[0], b.periodic[0]);
@@ -119,45 +90,157 @@ __device__ __forceinline__ bool is_neighbour(const float4& p, const float4& q, c
     return d2 <= rc2;
 }
 
-// One thread per sorted slot.  PASS 0: neighbour count (stored per slot and
-// per caller index).  PASS 1: the sorted row (sorted-slot indices, in
-// traversal order) and the caller row (caller indices, then sorted).
+// One wave per sorted slot s: the candidates of its 3^dim cell block are
+// numbered in traversal order (cells in (z, y, x) order, members in cell
+// order) and tested 64 at a time, one per lane, with the exact FP64 rule;
+// the hits of each batch are compacted with a wave ballot (a lane's entry is
+// the row length so far plus the number of lower lanes that hit), so the
+// row comes out in traversal order.  PASS 0: the row length (per slot and
+// per caller index).  PASS 1: the sorted row (sorted-slot indices).
+constexpr int WPB = BLK / 64;  // waves per block
+
 template <int DIM, int PASS>
-__global__ void k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restrict__ cell_start,
-                        const float4* __restrict__ sorted, int32_t* __restrict__ cnt_s, int32_t* __restrict__ cnt_u,
-                        const int64_t* __restrict__ rp_s, int32_t* __restrict__ col_s,
-                        const int64_t* __restrict__ rp_u, int32_t* __restrict__ col_u) {
-    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    float4 p = sorted[s];
-    int32_t i = __float_as_int(p.w);
-    int32_t c = 0;
-    int64_t bs = PASS ? rp_s[s] : 0;
-    int64_t bu = PASS ? rp_u[i] : 0;
-    for_each_candidate<DIM>(p, b, cell_start, sorted, [&](int32_t t, const float4& q) {
-        if (t != s && is_neighbour<DIM>(p, q, b, rc2)) {
-            if (PASS) {
-                col_s[bs + c] = t;
-                col_u[bu + c] = __float_as_int(q.w);
-            }
-            ++c;
+__global__ void __launch_bounds__(BLK) k_neigh(int32_t n, BoxArgs b, double rc2, const int32_t* __restrict__ cell_start,
+                                               const float4* __restrict__ sorted, int32_t* __restrict__ cnt_s,
+                                               int32_t* __restrict__ cnt_u, const int64_t* __restrict__ rp_s,
+                                               int32_t* __restrict__ col_s) {
+    constexpr int NC = DIM == 2 ? 9 : 27;
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t s = (int32_t)blockIdx.x * WPB + (int32_t)(threadIdx.x >> 6);
+    if (s >= n) return;  // the whole wave
+    const float4 p = sorted[s];
+    // lane k < NC: cell k of the block and its slot range
+    int32_t c0 = 0, cn = 0;
+    if (lane < NC) {
+        const int cx = cell_coord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
+        const int cy = cell_coord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
+        const int cz = DIM == 3 ? cell_coord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) : 0;
+        int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = DIM == 3 ? cz + lane / 9 - 1 : 0;
+        bool ok = true;
+        if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
+        else ok = ok && x >= 0 && x < b.nc[0];
+        if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
+        else ok = ok && y >= 0 && y < b.nc[1];
+        if (DIM == 3) {
+            if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
+            else ok = ok && z >= 0 && z < b.nc[2];
         }
-    });
-    if (!PASS) {
-        cnt_s[s] = c;
-        cnt_u[i] = c;
-        return;
+        if (ok) {
+            const int32_t key = cell_key(b, x, y, z);
+            c0 = cell_start[key];
+            cn = cell_start[key + 1] - c0;
+        }
     }
-    // the caller row ascending (rows are short and arrive cell by cell)
-    int32_t* r = col_u + bu;
-    for (int32_t a = 1; a < c; ++a) {
-        int32_t v = r[a];
-        int32_t k = a - 1;
-        while (k >= 0 && r[k] > v) {
-            r[k + 1] = r[k];
-            --k;
+    // exclusive prefix of the cell sizes over lanes 0..NC-1 (NC < 32)
+    int32_t inc = cn;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int32_t v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
+    }
+    const int32_t exc = inc - cn;
+    const int32_t total = __shfl(inc, NC - 1, 64);
+    const int64_t bs = PASS ? rp_s[s] : 0;
+    int32_t count = 0;
+    for (int32_t base = 0; base < total; base += 64) {
+        const int32_t cidx = base + lane;
+        // the candidate's cell: the last k < NC whose block starts at or before it
+        int k = 0;
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1) {
+            const int mid = k + step;
+            const int32_t v = __shfl(exc, mid < NC ? mid : NC - 1, 64);
+            if (mid < NC && v <= cidx) k = mid;
         }
-        r[k + 1] = v;
+        const int32_t t = __shfl(c0, k, 64) + (cidx - __shfl(exc, k, 64));
+        bool in = false;
+        if (cidx < total && t != s) in = is_neighbour<DIM>(p, sorted[t], b, rc2);
+        const uint64_t m = __ballot(in);
+        if (PASS && in) col_s[bs + count + __popcll(m & ((1ull << lane) - 1ull))] = t;
+        count += (int32_t)__popcll(m);
+    }
+    if (!PASS && lane == 0) {
+        cnt_s[s] = count;
+        cnt_u[__float_as_int(p.w)] = count;
+    }
+}
+
+// Ascending sort of 64 R values held R per lane (element r * 64 + lane) by a
+// bitonic network: partners 64 apart or more sit in the same lane, closer
+// partners in lane ^ j.
+template <int R>
+__device__ __forceinline__ void wave_sort(int32_t (&x)[R], int lane) {
+    constexpr int E = 64 * R;
+#pragma unroll
+    for (int k = 2; k <= E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int rj = j / 64;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & rj) continue;
+                    const bool asc = ((r * 64 + lane) & k) == 0;
+                    const int32_t lo = min(x[r], x[r ^ rj]), hi = max(x[r], x[r ^ rj]);
+                    x[r] = asc ? lo : hi;
+                    x[r ^ rj] = asc ? hi : lo;
+                }
+            } else {
+                const bool lower = (lane & j) == 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int32_t o = __shfl_xor(x[r], j, 64);
+                    const bool asc = ((r * 64 + lane) & k) == 0;
+                    x[r] = (lower == asc) ? min(x[r], o) : max(x[r], o);
+                }
+            }
+        }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void export_row(int lane, int32_t len, const int32_t* __restrict__ src,
+                                           const float4* __restrict__ sorted, int32_t* __restrict__ dst) {
+    int32_t x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        x[r] = e < len ? __float_as_int(sorted[src[e]].w) : INT32_MAX;
+    }
+    wave_sort<R>(x, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        if (e < len) dst[e] = x[r];
+    }
+}
+
+// The exported CSR: one wave per sorted slot writes its row in caller
+// indices, ascending, at the caller row.  Rows of more than 256 entries
+// (very dense configurations) are sorted by lane 0.
+__global__ void __launch_bounds__(BLK) k_export_rows(int32_t n, const float4* __restrict__ sorted,
+                                                     const int64_t* __restrict__ rp_s, const int32_t* __restrict__ col_s,
+                                                     const int64_t* __restrict__ rp_u, int32_t* __restrict__ col_u) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t s = (int32_t)blockIdx.x * WPB + (int32_t)(threadIdx.x >> 6);
+    if (s >= n) return;
+    const int64_t k0 = rp_s[s];
+    const int32_t len = (int32_t)(rp_s[s + 1] - k0);
+    const int32_t* src = col_s + k0;
+    int32_t* dst = col_u + rp_u[__float_as_int(sorted[s].w)];
+    if (len <= 64) export_row<1>(lane, len, src, sorted, dst);
+    else if (len <= 128) export_row<2>(lane, len, src, sorted, dst);
+    else if (len <= 256) export_row<4>(lane, len, src, sorted, dst);
+    else if (lane == 0) {
+        for (int32_t a = 0; a < len; ++a) {
+            const int32_t v = __float_as_int(sorted[src[a]].w);
+            int32_t q = a - 1;
+            while (q >= 0 && dst[q] > v) {
+                dst[q + 1] = dst[q];
+                --q;
+            }
+            dst[q + 1] = v;
+        }
     }
 }
 
@@ -222,6 +305,7 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
     c->tiles.valid = false;
     c->tiles.failed = false;
     c->ell_state = 0;
+    c->export_valid = false;
     if (!dom) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom is NULL");
     if (dom->dim != c->dim)
         return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom->dim %d != context dim %d", dom->dim, c->dim);
@@ -292,15 +376,16 @@ int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* p
     SPH_HIP(c, c->rp_s.ensure((nn + 1) * sizeof(int64_t)));
     SPH_HIP(c, c->row_ptr.ensure((nn + 1) * sizeof(int64_t)));
     int32_t* cnt_u = c->cnt.as<int32_t>();  // the cell counts are consumed by now
+    const unsigned gw = (unsigned)((n + WPB - 1) / WPB);  // one wave per slot
     if (n > 0) {
         if (c->dim == 2)
-            hipLaunchKernelGGL((k_neigh<2, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+            hipLaunchKernelGGL((k_neigh<2, 0>), dim3(gw), dim3(BLK), 0, c->stream, n, b, c->rc2,
                                c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->cnt_s.as<int32_t>(), cnt_u,
-                               nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_neigh<3, 0>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+            hipLaunchKernelGGL((k_neigh<3, 0>), dim3(gw), dim3(BLK), 0, c->stream, n, b, c->rc2,
                                c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->cnt_s.as<int32_t>(), cnt_u,
-                               nullptr, nullptr, nullptr, nullptr);
+                               nullptr, nullptr);
         SPH_LAUNCH_CHECK(c);
     }
     rcode = sph_scan_i32_to_i64(c, c->cnt_s.as<int32_t>(), c->rp_s.as<int64_t>(), n);
@@ -311,21 +396,19 @@ int sph_build_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* p
     SPH_HIP(c, hipMemcpyAsync(&nnz, c->row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
     SPH_HIP(c, hipStreamSynchronize(c->stream));
     c->nnz = nnz;
-    SPH_HIP(c, c->col.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
     SPH_HIP(c, c->col_s.ensure((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
     if (n > 0 && nnz > 0) {
         if (c->dim == 2)
-            hipLaunchKernelGGL((k_neigh<2, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+            hipLaunchKernelGGL((k_neigh<2, 1>), dim3(gw), dim3(BLK), 0, c->stream, n, b, c->rc2,
                                c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr, nullptr,
-                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->row_ptr.as<int64_t>(),
-                               c->col.as<int32_t>());
+                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>());
         else
-            hipLaunchKernelGGL((k_neigh<3, 1>), dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, b, c->rc2,
+            hipLaunchKernelGGL((k_neigh<3, 1>), dim3(gw), dim3(BLK), 0, c->stream, n, b, c->rc2,
                                c->cell_start.as<int32_t>(), c->sorted.as<float4>(), nullptr, nullptr,
-                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->row_ptr.as<int64_t>(),
-                               c->col.as<int32_t>());
+                               c->rp_s.as<int64_t>(), c->col_s.as<int32_t>());
         SPH_LAUNCH_CHECK(c);
     }
+    c->export_valid = false;
     c->bound = true;
     return SPH_OK;
 }
@@ -338,6 +421,15 @@ int sph_neighbors(sph_ctx* c, int64_t* row_ptr, int32_t* col, int64_t cap, int64
     if (cap < c->nnz)
         return sph_fail(c, SPH_ERR_CAPACITY, "sph_neighbors: capacity %lld < nnz %lld", (long long)cap, (long long)c->nnz);
     if (c->nnz > 0 && !col) return sph_fail(c, SPH_ERR_ARG, "sph_neighbors: col is NULL");
+    if (!c->export_valid && c->n > 0 && c->nnz > 0) {
+        // the caller-order rows, built on the first export
+        SPH_HIP(c, c->col.ensure((size_t)c->nnz * sizeof(int32_t)));
+        hipLaunchKernelGGL(k_export_rows, dim3((unsigned)((c->n + WPB - 1) / WPB)), dim3(BLK), 0, c->stream, c->n,
+                           c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
+                           c->row_ptr.as<int64_t>(), c->col.as<int32_t>());
+        SPH_LAUNCH_CHECK(c);
+    }
+    c->export_valid = true;
     SPH_HIP(c, hipMemcpyAsync(row_ptr, c->row_ptr.as<int64_t>(), (size_t)(c->n + 1) * sizeof(int64_t),
                               hipMemcpyDeviceToDevice, c->stream));
     if (c->nnz > 0)
