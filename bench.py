@@ -220,6 +220,37 @@ def run_relax(epochs, nside=260):
             "train_trajectory_iters": run1.iterations}
 
 
+def run_train(steps, batch=65536, nbatch=20):
+    """MLP training throughput on a synthetic feature set shaped like the
+    relaxation's (nbatch x batch rows of MLP_FEAT_STRIDE BF16 features, the
+    first 100 columns N(0, 0.5^2), targets N(0, 0.08^2)): the training loop
+    of warmstart.train (shuffle, batch gather, train step) for
+    ceil(steps / nbatch) epochs after one warm-up epoch."""
+    import torch
+
+    from paper_2405_05155_amd import sph as S
+    from paper_2405_05155_amd import warmstart as WS
+    ctx = S.Context(3)
+    n = batch * nbatch
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x = torch.zeros((n, S.MLP_FEAT_STRIDE), dtype=torch.float32)
+    x[:, :100] = 0.5 * torch.randn((n, 100), generator=g)
+    feat = x.to(torch.bfloat16).view(torch.int16).to("cuda")
+    targ = (0.08 * torch.randn((n, 3), generator=g)).to("cuda")
+    del x
+    init = init_params(0)
+    WS.train(ctx, feat, targ, epochs=1, batch=batch, init=init)
+    epochs = max(1, -(-steps // nbatch))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, losses = WS.train(ctx, feat, targ, epochs=epochs, batch=batch, init=init)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    nstep = epochs * nbatch
+    return {"train_steps": nstep, "batch": batch, "ms_per_step": secs * 1e3 / nstep,
+            "samples_per_s": nstep * batch / secs, "loss_first_last": [losses[0], losses[-1]]}
+
+
 def init_params(seed):
     """Seeded initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) (PyTorch's
     linear-layer default), drawn on the host and passed in."""
@@ -251,6 +282,7 @@ def main():
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
+    ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
@@ -276,6 +308,9 @@ def main():
         run, _, _ = WS.relax_plain(ctx, wr, max_iter=args.relax_iters)
         print(json.dumps({"relax_iterations": run.iterations, "seconds": run.seconds, "residue": run.residue,
                           "n_particles": wr.n}), flush=True)
+        return
+    if args.train_steps:
+        print(json.dumps(run_train(args.train_steps)), flush=True)
         return
     if args.kappa3d:
         one = run_euler_3d(args.nside3d, args.kappa3d, args.steps3d, min(args.warmup, 5))

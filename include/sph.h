@@ -277,6 +277,18 @@ int sph_mlp_train_step(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step,
                        float* adam_v, int32_t batch, const uint16_t* feat, const float* target, float* loss,
                        float* grad);
 
+/* One epoch of training steps on rows of a resident training set of nrows
+ * rows: step b (b = 0 .. nbatch-1, AdamW step number step0 + b) takes the
+ * batch rows[b * batch .. (b + 1) * batch) (int64 indices into feat
+ * [nrows][SPH_MLP_FEAT_STRIDE] and target [nrows][3]), gathered inside the
+ * training kernel, with the same arithmetic as sph_mlp_train_step on that
+ * batch.  An index outside [0, nrows) is clamped to the nearest row.
+ * lr must be > 0.  losses: device FP32 [nbatch] receiving each step's loss
+ * (nullable). */
+int sph_mlp_train_epoch(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step0, float* params, float* adam_m,
+                        float* adam_v, int32_t batch, int32_t nbatch, int64_t nrows, const int64_t* rows,
+                        const uint16_t* feat, const float* target, float* losses);
+
 /* Warm-start move: features of the current positions, y, then r += h y for
  * every particle and the same projection onto the sphere as the relaxation.
  * pos FP32 [3][n] in place. */

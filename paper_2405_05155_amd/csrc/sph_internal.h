@@ -194,6 +194,8 @@ struct sph_ctx {
     DevBuf partials;    // per-block reduction partials
     DevBuf relax_scalars;
 
+    int num_cu = 0;     // compute units of the device (filled on first use)
+
     TileSet tiles;
     int tiling = SPH_TILING_OFF;
 

@@ -7,11 +7,11 @@
 // backward GEMM operands are rounded to BF16 (nearest-even); bias, GELU,
 // loss and optimizer arithmetic are FP32.
 //
-// GEMMs use v_mfma_f32_16x16x16_bf16: a 256-thread block computes a 64x64
-// tile of C = A B (four waves, each 2x2 MFMA tiles), A and B read as BF16
-// through (row, column) strides so transposed operands need no copies, with
-// the K range optionally split across blocks (partials reduced in a fixed
-// order, so results are deterministic).
+// Two kernels carry the network: a forward pass and a fused training pass
+// (forward, loss, backward and per-workgroup weight-gradient partials in one
+// launch), both on v_mfma_f32_16x16x16_bf16 with the weights held in LDS,
+// then a reduction of the partials in a fixed order (deterministic results)
+// fused with the AdamW update.
 #include "sph_internal.h"
 
 namespace {
@@ -21,230 +21,574 @@ constexpr int FS = SPH_MLP_FEAT_STRIDE;  // feature row stride (zero padded)
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NOUT * NH, NPARAM = OFF_B3 + NOUT;
 static_assert(NPARAM == SPH_MLP_NPARAMS, "parameter count");
-constexpr int CHUNK = 1 << 18;  // samples per forward pass in sph_mlp_forward / sph_mlp_apply
+constexpr int CHUNK = 1 << 18;  // feature rows per chunk in sph_mlp_apply
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    uint32_t r = 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)((u + r) >> 16);
+typedef __bf16 bf16x2h __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// FP32 -> BF16, round to nearest even (v_cvt_pk_bf16_f32), two at a time
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2h));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)(f2bf2(f, 0.f) & 0xffffu); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.f + erff(z * 0.70710678118654752f)); }
-__device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.f + erff(z * 0.70710678118654752f)) + z * __expf(-0.5f * z * z) * 0.39894228040143268f;
+// GELU(z) = z Phi(z) and GELU'(z) = Phi(z) + z phi(z), Phi the standard
+// normal CDF.  Phi comes from the complementary error function,
+// Phi(z) = erfc(-z / sqrt 2) / 2, with erfc(x) ~ t exp(-x^2 + P(t)),
+// t = 1 / (1 + x / 2) for x >= 0: the Chebyshev-fitted approximation of
+// Numerical Recipes (erfcc, fractional error below 1.2e-7 everywhere).  The
+// negative tail is taken as erfc itself rather than 1 + erf(z / sqrt 2), so
+// it keeps its relative accuracy; no branches.
+__device__ __forceinline__ void normal_cdf_pdf(float z, float& Phi, float& e2) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.f));
+    float p = fmaf(t, 0.17087277f, -0.82215223f);
+    p = fmaf(t, p, 1.48851587f);
+    p = fmaf(t, p, -1.13520398f);
+    p = fmaf(t, p, 0.27886807f);
+    p = fmaf(t, p, -0.18628806f);
+    p = fmaf(t, p, 0.09678418f);
+    p = fmaf(t, p, 0.37409196f);
+    p = fmaf(t, p, 1.00002368f);
+    p = fmaf(t, p, -1.26551223f);
+    e2 = __expf(-x * x);                          // exp(-z^2 / 2)
+    const float half_erfc = 0.5f * t * e2 * __expf(p);
+    Phi = z >= 0.f ? 1.f - half_erfc : half_erfc;
+}
+__device__ __forceinline__ float gelu(float z) {
+    float Phi, e2;
+    normal_cdf_pdf(z, Phi, e2);
+    return z * Phi;
+}
+__device__ __forceinline__ void gelu_and_grad(float z, float& g, float& gp) {
+    float Phi, e2;
+    normal_cdf_pdf(z, Phi, e2);
+    g = z * Phi;
+    gp = fmaf(z * e2, 0.39894228040143268f, Phi);
 }
 
-// ------------------------------------------------------------------ GEMM
+// ------------------------------------------------------------------ fused training pass
+//
+// One workgroup of four waves per CU walks 64-sample blocks of the batch
+// (blocks blockIdx.x, blockIdx.x + gridDim.x, ...).  Each wave carries 16
+// samples through the network with the unit index on the MFMA row axis and
+// the sample on the column axis: the accumulator of one layer (lane (g, c)
+// holds rows 4g..4g+3 of a 16-row tile for sample c) is then, unchanged, the
+// B operand of the next layer's 16x16x16 MFMA, so activations never leave
+// registers.  Weights sit in LDS as per-lane MFMA fragments.  Weight
+// gradients contract over samples: their operands are staged in LDS as
+// [unit][sample] BF16 arrays of the block, and each wave accumulates its
+// quarter of dW1, dW2 and dW3 in MFMA accumulators across the blocks; bias
+// gradients are summed per lane.  The workgroup writes one partial record,
+// summed over workgroups in a fixed order by k_train_reduce.
+//
+// dW3 = dY^T bf16(H2) keeps dY in FP32: dY is split into three BF16 parts
+// (hi + mid + lo reproduces the FP32 value) placed in separate B columns, so
+// one MFMA tile yields the three partial products, added in FP32 at the end.
 
-enum { EPI_STORE = 0, EPI_GELU = 1, EPI_BWD_GELU = 2 };
+constexpr int TS = 16;            // samples per wave
+constexpr int TWAVES = 4;         // waves per workgroup
+constexpr int TB = TS * TWAVES;   // samples per block
+constexpr int KS1 = 7;            // layer-1 K steps: feature columns 0..111 (100..111 are zero)
+constexpr int NF1 = 16 * KS1;     // feature columns carried by dW1
+constexpr int HT = NH / 16;       // hidden tiles
+constexpr int SROW = TB + 8;      // staging row stride (BF16 elements)
+// partial record of one workgroup (floats)
+constexpr int PR_W1 = 0, PR_W2 = PR_W1 + NH * NF1, PR_W3 = PR_W2 + NH * NH, PR_B1 = PR_W3 + NOUT * NH,
+              PR_B2 = PR_B1 + NH, PR_B3 = PR_B2 + NH, PR_LEN = ((PR_B3 + NOUT) + 63) & ~63;
 
-struct Epi {
-    float* C;              // FP32 output [M][ldc] (EPI_STORE: + blockIdx.z * split_stride)
-    int ldc;
-    int64_t split_stride;
-    const float* bias;     // per column (EPI_STORE, EPI_GELU), nullable
-    float* Z;              // EPI_GELU: pre-activation out (nullable)
-    uint16_t* Hb;          // EPI_GELU: bf16(GELU(z)); EPI_BWD_GELU: bf16(dz)
-    int ldh;
-    const float* Zin;      // EPI_BWD_GELU: saved pre-activation [M][ldz]
-    int ldz;
+struct TrainLds {
+    bf16x4 w1f[HT][KS1][64];   // layer 1 A: W1b[16t + c][16ks + 4g + e]
+    bf16x4 w2f[HT][HT][64];    // layer 2 A: W2b[16t + c][16ks + 4g + e]
+    bf16x4 w2t[HT][HT][64];    // dH1 A:     W2b[16ks + 4g + e][16t + c]
+    bf16x4 w3f[HT][64];        // layer 3 A: W3b[c][16ks + 4g + e] (rows c >= 3 zero)
+    float w3v[NOUT][NH];       // bf16(W3) as FP32 for dH2 = dY W3b
+    float b1[NH], b2[NH], b3[4];
+    uint16_t xt[NF1][SROW];    // X^T of the block
+    uint16_t h1t[NH][SROW];    // bf16(H1)^T, then bf16(dZ1)^T
+    uint16_t s2t[NH][SROW];    // bf16(H2)^T, then bf16(dZ2)^T
+    uint16_t dyt[16][SROW];    // dY parts: rows 0-2 hi, 3-5 mid, 6-8 lo, 9-15 zero
+};
+static_assert(sizeof(TrainLds) <= 160 * 1024, "LDS budget of the training pass");
+
+__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
+    return __builtin_bit_cast(bf16x4, make_uint2(f2bf2(a, b), f2bf2(c, d)));
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// forward-only LDS: the layer fragments and biases
+struct FwdLds {
+    bf16x4 w1f[HT][KS1][64];
+    bf16x4 w2f[HT][HT][64];
+    bf16x4 w3f[HT][64];
+    float b1[NH], b2[NH], b3[4];
 };
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, int kchunk, const uint16_t* __restrict__ A,
-                                              int64_t sam, int64_t sak, const uint16_t* __restrict__ B, int64_t sbk,
-                                              int64_t sbn, Epi ep) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int m0 = blockIdx.x * 64 + 32 * (w >> 1);
-    const int n0 = blockIdx.y * 64 + 32 * (w & 1);
-    const int kb = blockIdx.z * kchunk;
-    const int ke = min(K, kb + kchunk);
-    const int li = lane & 15, lk = 4 * (lane >> 4);
-    f32x4 acc[2][2];
+// weights -> LDS fragments (all threads of the workgroup)
+template <bool TRAIN, class LDS>
+__device__ void load_weights(LDS& L, const float* __restrict__ p) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i < HT * KS1 * 64; i += blockDim.x) {
+        int t = i / (KS1 * 64), ks = (i / 64) % KS1, ln = i % 64;
+        int row = 16 * t + (ln & 15), k0 = 16 * ks + 4 * (ln >> 4);
+        float4 v = k0 < NIN ? *reinterpret_cast<const float4*>(p + OFF_W1 + row * NIN + k0) : float4{0.f, 0.f, 0.f, 0.f};
+        L.w1f[t][ks][ln] = pack4(v.x, v.y, v.z, v.w);
+    }
+    for (int i = tid; i < HT * HT * 64; i += blockDim.x) {
+        int t = i / (HT * 64), ks = (i / 64) % HT, ln = i % 64;
+        int g = ln >> 4, c = ln & 15;
+        float4 v = *reinterpret_cast<const float4*>(p + OFF_W2 + (16 * t + c) * NH + 16 * ks + 4 * g);
+        L.w2f[t][ks][ln] = pack4(v.x, v.y, v.z, v.w);
+        if constexpr (TRAIN) {
+            const float* q = p + OFF_W2 + (16 * ks + 4 * g) * NH + 16 * t + c;
+            L.w2t[t][ks][ln] = pack4(q[0], q[NH], q[2 * NH], q[3 * NH]);
+        }
+    }
+    for (int i = tid; i < HT * 64; i += blockDim.x) {
+        int ks = i / 64, ln = i % 64, c = ln & 15;
+        float4 v = c < NOUT ? *reinterpret_cast<const float4*>(p + OFF_W3 + c * NH + 16 * ks + 4 * (ln >> 4))
+                            : float4{0.f, 0.f, 0.f, 0.f};
+        L.w3f[ks][ln] = pack4(v.x, v.y, v.z, v.w);
+    }
+    for (int i = tid; i < NH; i += blockDim.x) {
+        L.b1[i] = p[OFF_B1 + i];
+        L.b2[i] = p[OFF_B2 + i];
+    }
+    if (tid < 4) L.b3[tid] = tid < NOUT ? p[OFF_B3 + tid] : 0.f;
+    if constexpr (TRAIN) {
+        for (int i = tid; i < NOUT * NH; i += blockDim.x) L.w3v[i / NH][i % NH] = bf2f(f2bf(p[OFF_W3 + i]));
+        for (int i = tid; i < 16 * SROW; i += blockDim.x) L.dyt[i / SROW][i % SROW] = 0;
+    }
+}
+
+// Forward pass of n samples, 16 per wave (the layer chain of the training
+// pass without its staging): Y FP32 [n][3].
+__global__ void __launch_bounds__(256) k_forward_fused(int n, const float* __restrict__ params,
+                                                       const uint16_t* __restrict__ X, float* __restrict__ Y) {
+    __shared__ FwdLds L;
+    load_weights<false>(L, params);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const int nslab = (n + TS - 1) / TS;
+    for (int sl = blockIdx.x * TWAVES + w; sl < nslab; sl += gridDim.x * TWAVES) {
+        const int s = sl * TS + c;
+        const bool valid = s < n;
+        // an offset the compiler cannot prove loop-invariant: the weight
+        // fragments are read from LDS at their use, not hoisted into registers
+        int oz = 0;
+        asm volatile("" : "+v"(oz));
+        const int wl = lane + oz;
+        bf16x4 xb[KS1];
+        const uint16_t* xr = X + (valid ? (int64_t)s : 0) * FS + 4 * g;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+        for (int ks = 0; ks < KS1; ++ks)
+            xb[ks] = valid ? *reinterpret_cast<const bf16x4*>(xr + 16 * ks) : bf16x4{0, 0, 0, 0};
+        f32x4 z[HT];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k = kb; k < ke; k += 16) {
-        bf16x4 av[2], bv[2];
+        for (int t = 0; t < HT; ++t) {
+            z[t] = zero4;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            int row = m0 + 16 * t + li;
-            int kk = k + lk;
-            if (sak == 1 && row < M && kk + 3 < ke) {
-                av[t] = *reinterpret_cast<const bf16x4*>(A + row * sam + kk);
-            } else {
+            for (int ks = 0; ks < KS1; ++ks) z[t] = mfma16(L.w1f[t][ks][wl], xb[ks], z[t]);
+        }
+        bf16x4 h[HT];
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    av[t][e] = (row < M && kk + e < ke) ? (short)A[row * sam + (int64_t)(kk + e) * sak] : (short)0;
-            }
-            int colb = n0 + 16 * t + li;
-            if (sbk == 1 && colb < N && kk + 3 < ke) {
-                bv[t] = *reinterpret_cast<const bf16x4*>(B + colb * sbn + kk);
-            } else {
+        for (int t = 0; t < HT; ++t) {
+            float4 bb = *reinterpret_cast<const float4*>(&L.b1[16 * t + 4 * g + oz]);
+            h[t] = pack4(gelu(z[t][0] + bb.x), gelu(z[t][1] + bb.y), gelu(z[t][2] + bb.z), gelu(z[t][3] + bb.w));
+        }
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    bv[t][e] = (colb < N && kk + e < ke) ? (short)B[(int64_t)(kk + e) * sbk + colb * sbn] : (short)0;
+        for (int t = 0; t < HT; ++t) {
+            z[t] = zero4;
+#pragma unroll
+            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2f[t][ks][wl], h[ks], z[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            float4 bb = *reinterpret_cast<const float4*>(&L.b2[16 * t + 4 * g + oz]);
+            h[t] = pack4(gelu(z[t][0] + bb.x), gelu(z[t][1] + bb.y), gelu(z[t][2] + bb.z), gelu(z[t][3] + bb.w));
+        }
+        f32x4 y = zero4;
+#pragma unroll
+        for (int ks = 0; ks < HT; ++ks) y = mfma16(L.w3f[ks][wl], h[ks], y);
+        if (g == 0 && valid) {
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) Y[(int64_t)s * NOUT + o] = y[o] + L.b3[o];
+        }
+    }
+}
+
+// sum over the 16 lanes of a lane row (lanes with equal lane >> 4)
+__device__ __forceinline__ float row16_sum(float v) {
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+// X: BF16 rows [nrows][FS]; sample b of the batch is row (idx ? idx[b] : b),
+// an index outside [0, nrows) taken as the nearest valid row.
+// part: [gridDim.x][PR_LEN] floats, lpart: [gridDim.x] doubles.
+__global__ void __launch_bounds__(256) k_train_fused(int B, const float* __restrict__ params,
+                                                     const uint16_t* __restrict__ X, int64_t nrows,
+                                                     const int64_t* __restrict__ idx,
+                                                     const float* __restrict__ T, float* __restrict__ part,
+                                                     double* __restrict__ lpart) {
+    __shared__ TrainLds L;
+    load_weights<true>(L, params);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const float sc = 2.f / (3.f * (float)B);
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+
+    f32x4 aW1[2][KS1], aW2[2][HT], aW3[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int k = 0; k < KS1; ++k) aW1[a][k] = zero4;
+#pragma unroll
+        for (int k = 0; k < HT; ++k) aW2[a][k] = zero4;
+        aW3[a] = zero4;
+    }
+    float db1[HT][4], db2[HT][4], db3[NOUT] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) db1[t][e] = db2[t][e] = 0.f;
+    double lsum = 0.0;
+
+    const int nblk = (B + TB - 1) / TB;
+    const int col = w * TS + c;  // this lane's sample column in the block
+    // the feature fragments of a block are loaded one block ahead
+    auto sample_row = [&](int s) -> int64_t {
+        int64_t r = s < B ? (idx ? idx[s] : (int64_t)s) : 0;
+        return r < 0 ? 0 : (r >= nrows ? nrows - 1 : r);
+    };
+    auto load_x = [&](int s, int64_t r, bf16x4* xv) {
+        const uint16_t* xr = X + r * FS + 4 * g;
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks)
+            xv[ks] = s < B ? *reinterpret_cast<const bf16x4*>(xr + 16 * ks) : bf16x4{0, 0, 0, 0};
+    };
+    auto load_t = [&](int s, int64_t r, float* tv) {
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) tv[o] = (g == 0 && s < B) ? T[r * NOUT + o] : 0.f;
+    };
+    bf16x4 xn[KS1];
+    float tn[NOUT];
+    int64_t rown = 0;
+    if (blockIdx.x < nblk) {
+        rown = sample_row(blockIdx.x * TB + col);
+        load_x(blockIdx.x * TB + col, rown, xn);
+        load_t(blockIdx.x * TB + col, rown, tn);
+    }
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int s = blk * TB + col;
+        const bool valid = s < B;
+        // an offset the compiler cannot prove loop-invariant: the weight
+        // fragments are read from LDS at their use, not hoisted into registers
+        int oz = 0;
+        asm volatile("" : "+v"(oz));
+        const int wl = lane + oz;
+        bf16x4 xb[KS1];
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks) xb[ks] = xn[ks];
+        float tv[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) tv[o] = tn[o];
+        if (blk + (int)gridDim.x < nblk) {
+            const int sn = (blk + gridDim.x) * TB + col;
+            rown = sample_row(sn);
+            load_x(sn, rown, xn);
+            load_t(sn, rown, tn);
+        }
+        // layer 1
+        f32x4 z[HT];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            z[t] = zero4;
+#pragma unroll
+            for (int ks = 0; ks < KS1; ++ks) z[t] = mfma16(L.w1f[t][ks][wl], xb[ks], z[t]);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS1; ++ks)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L.xt[16 * ks + 4 * g + e][col] = (uint16_t)xb[ks][e];
+        bf16x4 h1[HT];
+        float gp1[HT][4];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            float4 bb = *reinterpret_cast<const float4*>(&L.b1[16 * t + 4 * g + oz]);
+            float hv[4];
+            gelu_and_grad(z[t][0] + bb.x, hv[0], gp1[t][0]);
+            gelu_and_grad(z[t][1] + bb.y, hv[1], gp1[t][1]);
+            gelu_and_grad(z[t][2] + bb.z, hv[2], gp1[t][2]);
+            gelu_and_grad(z[t][3] + bb.w, hv[3], gp1[t][3]);
+            h1[t] = pack4(hv[0], hv[1], hv[2], hv[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L.h1t[16 * t + 4 * g + e][col] = (uint16_t)h1[t][e];
+        }
+        // layer 2
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            z[t] = zero4;
+#pragma unroll
+            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2f[t][ks][wl], h1[ks], z[t]);
+        }
+        bf16x4 h2[HT];
+        float gp2[HT][4];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            float4 bb = *reinterpret_cast<const float4*>(&L.b2[16 * t + 4 * g + oz]);
+            float hv[4];
+            gelu_and_grad(z[t][0] + bb.x, hv[0], gp2[t][0]);
+            gelu_and_grad(z[t][1] + bb.y, hv[1], gp2[t][1]);
+            gelu_and_grad(z[t][2] + bb.z, hv[2], gp2[t][2]);
+            gelu_and_grad(z[t][3] + bb.w, hv[3], gp2[t][3]);
+            h2[t] = pack4(hv[0], hv[1], hv[2], hv[3]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L.s2t[16 * t + 4 * g + e][col] = (uint16_t)h2[t][e];
+        }
+        // layer 3 (rows 0..2 of the 16-row tile are the outputs)
+        f32x4 y = zero4;
+#pragma unroll
+        for (int ks = 0; ks < HT; ++ks) y = mfma16(L.w3f[ks][wl], h2[ks], y);
+        // loss and dY = 2 (Y - T) / (3B); lanes of row 0 own the outputs of sample c
+        float dyv[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            float d = 0.f;
+            if (g == 0 && valid) d = (y[o] + L.b3[o]) - tv[o];
+            dyv[o] = sc * d;
+            lsum += (double)d * (double)d;
+            db3[o] += dyv[o];
+            if (g == 0) {
+                uint16_t hi = f2bf(dyv[o]);
+                float r1 = dyv[o] - bf2f(hi);
+                uint16_t mid = f2bf(r1);
+                float r2 = r1 - bf2f(mid);
+                L.dyt[o][col] = hi;
+                L.dyt[NOUT + o][col] = mid;
+                L.dyt[2 * NOUT + o][col] = f2bf(r2);
             }
         }
+        float dyc[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) dyc[o] = __shfl(dyv[o], c);
+        // dZ2 = (dY bf16(W3)) * GELU'(Z2)
+        bf16x4 dz2b[HT];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            float4 v0 = *reinterpret_cast<const float4*>(&L.w3v[0][16 * t + 4 * g + oz]);
+            float4 v1 = *reinterpret_cast<const float4*>(&L.w3v[1][16 * t + 4 * g + oz]);
+            float4 v2 = *reinterpret_cast<const float4*>(&L.w3v[2][16 * t + 4 * g + oz]);
+            float wv[3][4] = {{v0.x, v0.y, v0.z, v0.w}, {v1.x, v1.y, v1.z, v1.w}, {v2.x, v2.y, v2.z, v2.w}};
+            float dz[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float sacc = fmaf(dyc[0], wv[0][e], 0.f);
+                sacc = fmaf(dyc[1], wv[1][e], sacc);
+                sacc = fmaf(dyc[2], wv[2][e], sacc);
+                dz[e] = sacc * gp2[t][e];
+                db2[t][e] += dz[e];
+            }
+            dz2b[t] = pack4(dz[0], dz[1], dz[2], dz[3]);
+        }
+        __syncthreads();  // X^T, H1^T, H2^T and the dY parts of the block are staged
+        // dW3^T tiles: rows j (this wave's two 16-row blocks), columns = dY parts
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+            for (int kk = 0; kk < TB / 16; ++kk) {
+                bf16x4 av = *reinterpret_cast<const bf16x4*>(&L.s2t[16 * (2 * w + a) + c][16 * kk + 4 * g]);
+                bf16x4 bv = *reinterpret_cast<const bf16x4*>(&L.dyt[c][16 * kk + 4 * g]);
+                aW3[a] = mfma16(av, bv, aW3[a]);
+            }
+        __syncthreads();  // H2^T consumed
+#pragma unroll
+        for (int t = 0; t < HT; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L.s2t[16 * t + 4 * g + e][col] = (uint16_t)dz2b[t][e];
+        // dZ1 = (bf16(dZ2) bf16(W2)) * GELU'(Z1)
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            z[t] = zero4;
+#pragma unroll
+            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2t[t][ks][wl], dz2b[ks], z[t]);
+        }
+        bf16x4 dz1b[HT];
+#pragma unroll
+        for (int t = 0; t < HT; ++t) {
+            float dz[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                dz[e] = z[t][e] * gp1[t][e];
+                db1[t][e] += dz[e];
+            }
+            dz1b[t] = pack4(dz[0], dz[1], dz[2], dz[3]);
+        }
+        __syncthreads();  // dZ2^T staged
+        // dW2 = bf16(dZ2)^T bf16(H1)
+#pragma unroll
+        for (int kk = 0; kk < TB / 16; ++kk) {
+            bf16x4 av[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                av[a] = *reinterpret_cast<const bf16x4*>(&L.s2t[16 * (2 * w + a) + c][16 * kk + 4 * g]);
+#pragma unroll
+            for (int kb = 0; kb < HT; ++kb) {
+                bf16x4 bv = *reinterpret_cast<const bf16x4*>(&L.h1t[16 * kb + c][16 * kk + 4 * g]);
+#pragma unroll
+                for (int a = 0; a < 2; ++a) aW2[a][kb] = mfma16(av[a], bv, aW2[a][kb]);
+            }
+        }
+        __syncthreads();  // H1^T consumed
+#pragma unroll
+        for (int t = 0; t < HT; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) L.h1t[16 * t + 4 * g + e][col] = (uint16_t)dz1b[t][e];
+        __syncthreads();  // dZ1^T staged
+        // dW1 = bf16(dZ1)^T X
+#pragma unroll
+        for (int kk = 0; kk < TB / 16; ++kk) {
+            bf16x4 av[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                av[a] = *reinterpret_cast<const bf16x4*>(&L.h1t[16 * (2 * w + a) + c][16 * kk + 4 * g]);
+#pragma unroll
+            for (int kb = 0; kb < KS1; ++kb) {
+                bf16x4 bv = *reinterpret_cast<const bf16x4*>(&L.xt[16 * kb + c][16 * kk + 4 * g]);
+#pragma unroll
+                for (int a = 0; a < 2; ++a) aW1[a][kb] = mfma16(av[a], bv, aW1[a][kb]);
+            }
+        }
+        __syncthreads();  // staging free for the next block
     }
-    // accumulator element e of tile (a, b): row m0+16a+4(lane/16)+e, column n0+16b+lane%16
+
+    // partial record of the workgroup
+    float* pr = part + (int64_t)blockIdx.x * PR_LEN;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            int col = n0 + 16 * b + li;
-            if (col >= N) continue;
+        for (int e = 0; e < 4; ++e) {
+            const int j = 16 * (2 * w + a) + 4 * g + e;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int row = m0 + 16 * a + lk + e;
-                if (row >= M) continue;
-                float v = acc[a][b][e];
-                if (EPI == EPI_STORE) {
-                    if (ep.bias) v += ep.bias[col];
-                    ep.C[(int64_t)blockIdx.z * ep.split_stride + (int64_t)row * ep.ldc + col] = v;
-                } else if (EPI == EPI_GELU) {
-                    float z = v + ep.bias[col];
-                    if (ep.Z) ep.Z[(int64_t)row * ep.ldc + col] = z;
-                    ep.Hb[(int64_t)row * ep.ldh + col] = f2bf(gelu(z));
-                } else {
-                    float dz = v * gelu_grad(ep.Zin[(int64_t)row * ep.ldz + col]);
-                    ep.C[(int64_t)row * ep.ldc + col] = dz;
-                    ep.Hb[(int64_t)row * ep.ldh + col] = f2bf(dz);
-                }
+            for (int kb = 0; kb < KS1; ++kb) pr[PR_W1 + j * NF1 + 16 * kb + c] = aW1[a][kb][e];
+#pragma unroll
+            for (int kb = 0; kb < HT; ++kb) pr[PR_W2 + j * NH + 16 * kb + c] = aW2[a][kb][e];
+            // dW3[o][j] = parts hi + mid + lo (columns o, 3 + o, 6 + o)
+            float v = aW3[a][e];
+            float mid = __shfl(v, (lane + NOUT) & 63);
+            float lo = __shfl(v, (lane + 2 * NOUT) & 63);
+            if (c < NOUT) pr[PR_W3 + c * NH + j] = (lo + mid) + v;
+        }
+    // bias gradients and loss: lane rows, then waves in order
+    float* red = reinterpret_cast<float*>(&L.xt[0][0]);  // [TWAVES][2 NH + 4]
+    double* lred = reinterpret_cast<double*>(&L.h1t[0][0]);
+#pragma unroll
+    for (int t = 0; t < HT; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float s1 = row16_sum(db1[t][e]);
+            float s2 = row16_sum(db2[t][e]);
+            if (c == 0) {
+                red[w * (2 * NH + 4) + 16 * t + 4 * g + e] = s1;
+                red[w * (2 * NH + 4) + NH + 16 * t + 4 * g + e] = s2;
             }
         }
-}
-
-// ------------------------------------------------------------------ small kernels
-
-// masters -> BF16 copies: W1b [128][FS] (K padded with zeros), W2b [128][128], W3b [16][128] (rows >= 3 zero)
-__global__ void k_cast_weights(const float* __restrict__ p, uint16_t* __restrict__ W1b, uint16_t* __restrict__ W2b,
-                               uint16_t* __restrict__ W3b) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < NH * FS) {
-        int r = t / FS, k = t % FS;
-        W1b[t] = k < NIN ? f2bf(p[OFF_W1 + r * NIN + k]) : (uint16_t)0;
-    }
-    if (t < NH * NH) W2b[t] = f2bf(p[OFF_W2 + t]);
-    if (t < 16 * NH) {
-        int r = t / NH;
-        W3b[t] = r < NOUT ? f2bf(p[OFF_W3 + t]) : (uint16_t)0;
-    }
-}
-
-// dY = 2 (Y - T) / (3B); per-block partial sums of (Y - T)^2 in FP64
-__global__ void k_loss_dy(int B, const float* __restrict__ Y, int ldy, const float* __restrict__ T,
-                          float* __restrict__ dY, double* __restrict__ part) {
-    __shared__ double s[256];
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    double acc = 0.0;
-    if (b < B) {
-        float sc = 2.f / (3.f * (float)B);
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-            float d = Y[(int64_t)b * ldy + o] - T[(int64_t)b * NOUT + o];
-            dY[(int64_t)b * NOUT + o] = sc * d;
-            acc += (double)d * d;
-        }
+    for (int o = 0; o < NOUT; ++o) {
+        float s3 = row16_sum(db3[o]);
+        if (lane == 0) red[w * (2 * NH + 4) + 2 * NH + o] = s3;
     }
-    s[threadIdx.x] = acc;
+    double ls = row16_sum(lsum);
+    if (lane == 0) lred[w] = ls;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 2 * NH + NOUT; i += blockDim.x) {
+        float v = 0.f;
+        for (int q = 0; q < TWAVES; ++q) v += red[q * (2 * NH + 4) + i];
+        pr[PR_B1 + i] = v;  // b1, b2, b3 are contiguous in the record
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
-}
-
-__global__ void k_loss_final(int nb, int B, const double* __restrict__ part, float* __restrict__ loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double acc = 0.0;
-    for (int k = 0; k < nb; ++k) acc += part[k];
-    *loss = (float)(acc / (3.0 * (double)B));
-}
-
-// dZ2 = (dY W3b) * GELU'(Z2): FP32 and BF16 copies
-__global__ void k_dz2(int B, const float* __restrict__ dY, const uint16_t* __restrict__ W3b,
-                      const float* __restrict__ Z2, float* __restrict__ dZ2, uint16_t* __restrict__ dZ2b) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)B * NH) return;
-    int64_t b = t / NH;
-    int j = (int)(t % NH);
-    float s = 0.f;
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) s = fmaf(dY[b * NOUT + o], bf2f(W3b[o * NH + j]), s);
-    float dz = s * gelu_grad(Z2[t]);
-    dZ2[t] = dz;
-    dZ2b[t] = f2bf(dz);
-}
-
-// partial column sums of X [rows][ld] over row chunks: part[chunk][col], col < ncols
-__global__ void k_colsum_part(int rows, int ncols, const float* __restrict__ X, int ld, int rows_per_chunk,
-                              float* __restrict__ part) {
-    int col = threadIdx.x;
-    if (col >= ncols) return;
-    int r0 = blockIdx.x * rows_per_chunk;
-    int r1 = min(rows, r0 + rows_per_chunk);
-    float s = 0.f;
-    for (int r = r0; r < r1; ++r) s += X[(int64_t)r * ld + col];
-    part[(int64_t)blockIdx.x * ncols + col] = s;
-}
-
-// dW3 partials: part[chunk][o][j] = sum_{b in chunk} dY[b][o] H2b[b][j]
-__global__ void k_dw3_part(int B, const float* __restrict__ dY, const uint16_t* __restrict__ H2b, int rows_per_chunk,
-                           float* __restrict__ part) {
-    int j = threadIdx.x;  // 128 threads
-    int r0 = blockIdx.x * rows_per_chunk;
-    int r1 = min(B, r0 + rows_per_chunk);
-    float s[NOUT] = {0.f, 0.f, 0.f};
-    for (int r = r0; r < r1; ++r) {
-        float hv = bf2f(H2b[(int64_t)r * NH + j]);
-#pragma unroll
-        for (int o = 0; o < NOUT; ++o) s[o] = fmaf(dY[(int64_t)r * NOUT + o], hv, s[o]);
+    if (tid == 0) {
+        double v = 0.0;
+        for (int q = 0; q < TWAVES; ++q) v += lred[q];
+        lpart[blockIdx.x] = v;
     }
-#pragma unroll
-    for (int o = 0; o < NOUT; ++o) part[((int64_t)blockIdx.x * NOUT + o) * NH + j] = s[o];
 }
-
-// out[e] = sum_s part[s][e] in order s = 0, 1, ...
-__global__ void k_reduce_parts(int nparts, int64_t E, const float* __restrict__ part, float* __restrict__ out) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    float s = 0.f;
-    for (int k = 0; k < nparts; ++k) s += part[(int64_t)k * E + e];
-    out[e] = s;
-}
-
-struct GradPtrs {
-    const float *dW1, *db1, *dW2, *db2, *dW3, *db3;  // dW1 [128][FS]
-};
 
 struct AdamArgs {
     float lr, beta1, beta2, eps, wd, bc1, bc2;  // bc = 1 - beta^step
 };
 
-// gather the packed gradient, AdamW update of the FP32 masters
-__global__ void k_adamw(GradPtrs g, AdamArgs a, float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                        float* __restrict__ gout) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= NPARAM) return;
-    float gr;
-    if (t < OFF_B1) gr = g.dW1[(t / NIN) * FS + t % NIN];
-    else if (t < OFF_W2) gr = g.db1[t - OFF_B1];
-    else if (t < OFF_B2) gr = g.dW2[t - OFF_W2];
-    else if (t < OFF_W3) gr = g.db2[t - OFF_B2];
-    else if (t < OFF_B3) gr = g.dW3[t - OFF_W3];
-    else gr = g.db3[t - OFF_B3];
+// packed parameter index -> offset in a partial record
+__device__ __forceinline__ int record_offset(int t) {
+    if (t < OFF_B1) return PR_W1 + (t / NIN) * NF1 + t % NIN;
+    if (t < OFF_W2) return PR_B1 + (t - OFF_B1);
+    if (t < OFF_B2) return PR_W2 + (t - OFF_W2);
+    if (t < OFF_W3) return PR_B2 + (t - OFF_B2);
+    if (t < OFF_B3) return PR_W3 + (t - OFF_W3);
+    return PR_B3 + (t - OFF_B3);
+}
+
+// Sum of the workgroup partials (records 0, 1, ... in four interleaved
+// groups, the groups then added in order), AdamW update of the FP32 masters.
+// Block: 64 parameters x 4 groups.  The last block also sums the loss.
+__global__ void __launch_bounds__(256) k_train_reduce(int nrec, int B, const float* __restrict__ part,
+                                                      const double* __restrict__ lpart, AdamArgs a,
+                                                      float* __restrict__ p, float* __restrict__ m,
+                                                      float* __restrict__ v, float* __restrict__ gout,
+                                                      float* __restrict__ loss) {
+    __shared__ float sg[4][64];
+    __shared__ double sl[256];
+    const int tid = threadIdx.x, q = tid >> 6, k = tid & 63;
+    const int t = blockIdx.x * 64 + k;
+    float acc = 0.f;
+    if (t < NPARAM) {
+        const int off = record_offset(t);
+        const float* src = part + off;
+        int r = q;
+        for (; r + 60 < nrec; r += 64) {  // 16 loads in flight, added in record order
+            float x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) x[u] = src[(int64_t)(r + 4 * u) * PR_LEN];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += x[u];
+        }
+        for (; r < nrec; r += 4) acc += src[(int64_t)r * PR_LEN];
+    }
+    sg[q][k] = acc;
+    if (loss && blockIdx.x == gridDim.x - 1) {
+        double s = 0.0;
+        for (int r = tid; r < nrec; r += 256) s += lpart[r];
+        sl[tid] = s;
+    }
+    __syncthreads();
+    if (loss && blockIdx.x == gridDim.x - 1) {
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) sl[tid] += sl[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) *loss = (float)(sl[0] / (3.0 * (double)B));
+    }
+    if (q != 0 || t >= NPARAM) return;
+    float gr = ((sg[0][k] + sg[1][k]) + sg[2][k]) + sg[3][k];
     if (gout) gout[t] = gr;
     if (a.lr == 0.f) return;  // gradient only
     float mm = a.beta1 * m[t] + (1.f - a.beta1) * gr;
@@ -377,90 +721,56 @@ __global__ void k_apply_disp(int32_t n, float h, float cx, float cy, float cz, f
 
 // ------------------------------------------------------------------ host helpers
 
-struct MlpScratch {
-    uint16_t *W1b, *W2b, *W3b;
-    float *Z1, *Z2, *Y, *dY, *dZ1, *dZ2;
-    uint16_t *H1b, *H2b, *dZ1b, *dZ2b;
-    float *part, *gW1, *gW2, *gW3, *gb1, *gb2, *gb3;
+int forward_grid(sph_ctx* c, int32_t n) {
+    if (c->num_cu <= 0) {
+        int dev = 0, k = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&k, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            c->num_cu = k > 0 ? k : 1;
+    }
+    const int64_t waves = ((int64_t)n + TS - 1) / TS;
+    const int64_t want = (waves + TWAVES - 1) / TWAVES, cap = 2 * (int64_t)(c->num_cu > 0 ? c->num_cu : 256);
+    return (int)(want < cap ? want : cap);
+}
+
+// training-pass partials: one record per workgroup
+struct TrainScratch {
+    int nwg;
+    float* part;
     double* lpart;
 };
 
-// carve the context's MLP scratch for up to `rows` samples
-int mlp_scratch(sph_ctx* c, int64_t rows, bool train, MlpScratch* s) {
-    const int64_t nchunks = 256;
-    size_t need = 0;
-    auto add = [&](size_t bytes) {
-        size_t off = need;
-        need += (bytes + 255) & ~(size_t)255;
-        return off;
-    };
-    size_t oW1 = add(NH * FS * 2), oW2 = add(NH * NH * 2), oW3 = add(16 * NH * 2);
-    size_t oZ1 = train ? add(rows * NH * 4) : 0, oZ2 = train ? add(rows * NH * 4) : 0;
-    size_t oY = add(rows * NOUT * 4 + 64), odY = train ? add(rows * NOUT * 4) : 0;
-    size_t odZ1 = train ? add(rows * NH * 4) : 0, odZ2 = train ? add(rows * NH * 4) : 0;
-    size_t oH1 = add(rows * NH * 2), oH2 = add(rows * NH * 2);
-    size_t odZ1b = train ? add(rows * NH * 2) : 0, odZ2b = train ? add(rows * NH * 2) : 0;
-    size_t opart = train ? add((size_t)nchunks * NH * FS * 4) : 0;
-    size_t ogW1 = train ? add(NH * FS * 4) : 0, ogW2 = train ? add(NH * NH * 4) : 0, ogW3 = train ? add(NOUT * NH * 4) : 0;
-    size_t ogb1 = train ? add(NH * 4) : 0, ogb2 = train ? add(NH * 4) : 0, ogb3 = train ? add(64) : 0;
-    size_t olp = add((rows / 256 + 2) * 8);
-    SPH_HIP(c, c->tc.ensure(need));
-    char* base = c->tc.as<char>();
-    s->W1b = (uint16_t*)(base + oW1);
-    s->W2b = (uint16_t*)(base + oW2);
-    s->W3b = (uint16_t*)(base + oW3);
-    s->Z1 = train ? (float*)(base + oZ1) : nullptr;
-    s->Z2 = train ? (float*)(base + oZ2) : nullptr;
-    s->Y = (float*)(base + oY);
-    s->dY = train ? (float*)(base + odY) : nullptr;
-    s->dZ1 = train ? (float*)(base + odZ1) : nullptr;
-    s->dZ2 = train ? (float*)(base + odZ2) : nullptr;
-    s->H1b = (uint16_t*)(base + oH1);
-    s->H2b = (uint16_t*)(base + oH2);
-    s->dZ1b = train ? (uint16_t*)(base + odZ1b) : nullptr;
-    s->dZ2b = train ? (uint16_t*)(base + odZ2b) : nullptr;
-    s->part = train ? (float*)(base + opart) : nullptr;
-    s->gW1 = train ? (float*)(base + ogW1) : nullptr;
-    s->gW2 = train ? (float*)(base + ogW2) : nullptr;
-    s->gW3 = train ? (float*)(base + ogW3) : nullptr;
-    s->gb1 = train ? (float*)(base + ogb1) : nullptr;
-    s->gb2 = train ? (float*)(base + ogb2) : nullptr;
-    s->gb3 = train ? (float*)(base + ogb3) : nullptr;
-    s->lpart = (double*)(base + olp);
+int train_scratch(sph_ctx* c, int32_t batch, TrainScratch* ts) {
+    if (c->num_cu <= 0) {
+        int dev = 0, n = 0;
+        SPH_HIP(c, hipGetDevice(&dev));
+        SPH_HIP(c, hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        c->num_cu = n > 0 ? n : 1;
+    }
+    const int nblk = (batch + TB - 1) / TB;
+    ts->nwg = nblk < c->num_cu ? nblk : c->num_cu;
+    const size_t pbytes = ((size_t)ts->nwg * PR_LEN * sizeof(float) + 255) & ~(size_t)255;
+    SPH_HIP(c, c->tc.ensure(pbytes + (size_t)ts->nwg * sizeof(double)));
+    ts->part = c->tc.as<float>();
+    ts->lpart = reinterpret_cast<double*>(c->tc.as<char>() + pbytes);
     return SPH_OK;
 }
 
-template <int EPI>
-void gemm(sph_ctx* c, int M, int N, int K, int splits, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B,
-          int64_t sbk, int64_t sbn, const Epi& ep) {
-    int kchunk = (K + splits - 1) / splits;
-    kchunk = (kchunk + 15) & ~15;
-    int nz = (K + kchunk - 1) / kchunk;
-    dim3 grid((M + 63) / 64, (N + 63) / 64, nz < 1 ? 1 : nz);
-    hipLaunchKernelGGL((k_gemm<EPI>), grid, dim3(256), 0, c->stream, M, N, K, kchunk, A, sam, sak, B, sbk, sbn, ep);
-}
-
-// forward of `rows` samples: X (bf16 [rows][FS]) -> Y (FP32 [rows][3]);
-// with training buffers also keeps Z1, Z2.
-void forward(sph_ctx* c, const MlpScratch& s, const float* params, int rows, const uint16_t* X, float* Yout,
-             bool keep) {
-    Epi e1{};
-    e1.bias = params + OFF_B1;
-    e1.Z = keep ? s.Z1 : nullptr;
-    e1.ldc = NH;
-    e1.Hb = s.H1b;
-    e1.ldh = NH;
-    gemm<EPI_GELU>(c, rows, NH, FS, 1, X, FS, 1, s.W1b, 1, FS, e1);
-    Epi e2 = e1;
-    e2.bias = params + OFF_B2;
-    e2.Z = keep ? s.Z2 : nullptr;
-    e2.Hb = s.H2b;
-    gemm<EPI_GELU>(c, rows, NH, NH, 1, s.H1b, NH, 1, s.W2b, 1, NH, e2);
-    Epi e3{};
-    e3.C = Yout;
-    e3.ldc = NOUT;
-    e3.bias = params + OFF_B3;
-    gemm<EPI_STORE>(c, rows, NOUT, NH, 1, s.H2b, NH, 1, s.W3b, 1, NH, e3);
+void train_launch(sph_ctx* c, const TrainScratch& ts, const sph_adamw_params& ap, int64_t step, float* params,
+                  float* m, float* v, int32_t batch, const uint16_t* feat, int64_t nrows, const int64_t* rows,
+                  const float* target, float* loss, float* grad) {
+    hipLaunchKernelGGL(k_train_fused, dim3(ts.nwg), dim3(256), 0, c->stream, batch, params, feat, nrows, rows, target,
+                       ts.part, ts.lpart);
+    bool update = ap.lr != 0.0;
+    AdamArgs aa{};
+    aa.lr = (float)ap.lr;
+    aa.beta1 = (float)ap.beta1;
+    aa.beta2 = (float)ap.beta2;
+    aa.eps = (float)ap.eps;
+    aa.wd = (float)ap.weight_decay;
+    aa.bc1 = update ? (float)(1.0 - std::pow(ap.beta1, (double)step)) : 1.f;
+    aa.bc2 = update ? (float)(1.0 - std::pow(ap.beta2, (double)step)) : 1.f;
+    hipLaunchKernelGGL(k_train_reduce, dim3((NPARAM + 63) / 64), dim3(256), 0, c->stream, ts.nwg, batch, ts.part,
+                       ts.lpart, aa, params, m, v, grad, loss);
 }
 
 }  // namespace
@@ -491,16 +801,7 @@ int sph_mlp_forward(sph_ctx* c, const float* params, int32_t n, const uint16_t* 
     if (!c) return SPH_ERR_ARG;
     if (n < 0 || !params || (n > 0 && (!feat || !out))) return sph_fail(c, SPH_ERR_ARG, "sph_mlp_forward: bad arrays");
     if (n == 0) return SPH_OK;
-    int rows = n < CHUNK ? n : CHUNK;
-    MlpScratch s;
-    int r = mlp_scratch(c, rows, false, &s);
-    if (r) return r;
-    hipLaunchKernelGGL(k_cast_weights, dim3(grid_for(NH * FS, 256)), dim3(256), 0, c->stream, params, s.W1b, s.W2b,
-                       s.W3b);
-    for (int32_t r0 = 0; r0 < n; r0 += CHUNK) {
-        int m = n - r0 < CHUNK ? n - r0 : CHUNK;
-        forward(c, s, params, m, feat + (int64_t)r0 * FS, out + (int64_t)r0 * NOUT, false);
-    }
+    hipLaunchKernelGGL(k_forward_fused, dim3(forward_grid(c, n)), dim3(256), 0, c->stream, n, params, feat, out);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -514,68 +815,29 @@ int sph_mlp_train_step(sph_ctx* c, const sph_adamw_params* ap, int64_t step, flo
     bool update = ap->lr != 0.0;
     if (update && (!adam_m || !adam_v || step < 1))
         return sph_fail(c, SPH_ERR_ARG, "sph_mlp_train_step: moments and step >= 1 needed for an update");
-    MlpScratch s;
-    int r = mlp_scratch(c, batch, true, &s);
+    TrainScratch ts;
+    int r = train_scratch(c, batch, &ts);
     if (r) return r;
-    const int B = batch;
-    hipLaunchKernelGGL(k_cast_weights, dim3(grid_for(NH * FS, 256)), dim3(256), 0, c->stream, params, s.W1b, s.W2b,
-                       s.W3b);
-    forward(c, s, params, B, feat, s.Y, true);
-    int nb = (int)grid_for(B, 256);
-    hipLaunchKernelGGL(k_loss_dy, dim3(nb), dim3(256), 0, c->stream, B, s.Y, NOUT, target, s.dY, s.lpart);
-    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(1), 0, c->stream, nb, B, s.lpart, loss);
-    // layer 3
-    const int nchunk = 256;
-    int rpc = (B + nchunk - 1) / nchunk;
-    hipLaunchKernelGGL(k_dw3_part, dim3(nchunk), dim3(NH), 0, c->stream, B, s.dY, s.H2b, rpc, s.part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(grid_for(NOUT * NH, 256)), dim3(256), 0, c->stream, nchunk,
-                       (int64_t)NOUT * NH, s.part, s.gW3);
-    hipLaunchKernelGGL(k_colsum_part, dim3(nchunk), dim3(64), 0, c->stream, B, NOUT, s.dY, NOUT, rpc, s.part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, c->stream, nchunk, (int64_t)NOUT, s.part, s.gb3);
-    // layer 2
-    hipLaunchKernelGGL(k_dz2, dim3(grid_for((int64_t)B * NH, 256)), dim3(256), 0, c->stream, B, s.dY, s.W3b, s.Z2,
-                       s.dZ2, s.dZ2b);
-    Epi ew{};
-    ew.C = s.part;
-    ew.ldc = NH;
-    ew.split_stride = (int64_t)NH * NH;
-    gemm<EPI_STORE>(c, NH, NH, B, nchunk, s.dZ2b, 1, NH, s.H1b, NH, 1, ew);  // dW2 = dZ2^T H1
-    int kchunk = (((B + nchunk - 1) / nchunk) + 15) & ~15;
-    int nsplit = (B + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL(k_reduce_parts, dim3(grid_for(NH * NH, 256)), dim3(256), 0, c->stream, nsplit,
-                       (int64_t)NH * NH, s.part, s.gW2);
-    hipLaunchKernelGGL(k_colsum_part, dim3(nchunk), dim3(NH), 0, c->stream, B, NH, s.dZ2, NH, rpc, s.part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(NH), 0, c->stream, nchunk, (int64_t)NH, s.part, s.gb2);
-    // layer 1
-    Epi eb{};
-    eb.C = s.dZ1;
-    eb.ldc = NH;
-    eb.Hb = s.dZ1b;
-    eb.ldh = NH;
-    eb.Zin = s.Z1;
-    eb.ldz = NH;
-    gemm<EPI_BWD_GELU>(c, B, NH, NH, 1, s.dZ2b, NH, 1, s.W2b, NH, 1, eb);  // dH1 = dZ2 W2, times GELU'(Z1)
-    Epi e1{};
-    e1.C = s.part;
-    e1.ldc = FS;
-    e1.split_stride = (int64_t)NH * FS;
-    gemm<EPI_STORE>(c, NH, FS, B, nchunk, s.dZ1b, 1, NH, feat, FS, 1, e1);  // dW1 = dZ1^T X
-    hipLaunchKernelGGL(k_reduce_parts, dim3(grid_for(NH * FS, 256)), dim3(256), 0, c->stream, nsplit,
-                       (int64_t)NH * FS, s.part, s.gW1);
-    hipLaunchKernelGGL(k_colsum_part, dim3(nchunk), dim3(NH), 0, c->stream, B, NH, s.dZ1, NH, rpc, s.part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(NH), 0, c->stream, nchunk, (int64_t)NH, s.part, s.gb1);
-    // gradient and update
-    GradPtrs gp{s.gW1, s.gb1, s.gW2, s.gb2, s.gW3, s.gb3};
-    AdamArgs aa{};
-    aa.lr = (float)ap->lr;
-    aa.beta1 = (float)ap->beta1;
-    aa.beta2 = (float)ap->beta2;
-    aa.eps = (float)ap->eps;
-    aa.wd = (float)ap->weight_decay;
-    aa.bc1 = update ? (float)(1.0 - std::pow(ap->beta1, (double)step)) : 1.f;
-    aa.bc2 = update ? (float)(1.0 - std::pow(ap->beta2, (double)step)) : 1.f;
-    hipLaunchKernelGGL(k_adamw, dim3(grid_for(NPARAM, 256)), dim3(256), 0, c->stream, gp, aa, params, adam_m, adam_v,
-                       grad);
+    train_launch(c, ts, *ap, step, params, adam_m, adam_v, batch, feat, batch, nullptr, target, loss, grad);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+int sph_mlp_train_epoch(sph_ctx* c, const sph_adamw_params* ap, int64_t step0, float* params, float* adam_m,
+                        float* adam_v, int32_t batch, int32_t nbatch, int64_t nrows, const int64_t* rows,
+                        const uint16_t* feat, const float* target, float* losses) {
+    if (!c) return SPH_ERR_ARG;
+    if (!ap || !params || batch <= 0 || nbatch < 0 || (nbatch > 0 && (nrows < 1 || !rows || !feat || !target)))
+        return sph_fail(c, SPH_ERR_ARG, "sph_mlp_train_epoch: bad arguments");
+    if (ap->lr == 0.0 || !adam_m || !adam_v || step0 < 1)
+        return sph_fail(c, SPH_ERR_ARG, "sph_mlp_train_epoch: lr > 0, moments and step0 >= 1 needed");
+    if (nbatch == 0) return SPH_OK;
+    TrainScratch ts;
+    int r = train_scratch(c, batch, &ts);
+    if (r) return r;
+    for (int32_t b = 0; b < nbatch; ++b)
+        train_launch(c, ts, *ap, step0 + b, params, adam_m, adam_v, batch, feat, nrows, rows + (int64_t)b * batch,
+                     target, losses ? losses + b : nullptr, nullptr);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -592,20 +854,16 @@ int sph_mlp_apply(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, 
     int r = sph_bin_cells(c, &d, n, pos);
     if (r) return r;
     int rows = n < CHUNK ? n : CHUNK;
-    MlpScratch s;
-    r = mlp_scratch(c, rows, false, &s);
-    if (r) return r;
     SPH_HIP(c, c->ua.ensure((size_t)rows * FS * sizeof(uint16_t)));  // feature chunk
     SPH_HIP(c, c->ub.ensure((size_t)n * NOUT * sizeof(float)));      // displacements
-    hipLaunchKernelGGL(k_cast_weights, dim3(grid_for(NH * FS, 256)), dim3(256), 0, c->stream, params, s.W1b, s.W2b,
-                       s.W3b);
     for (int32_t r0 = 0; r0 < n; r0 += CHUNK) {
         int m = n - r0 < CHUNK ? n - r0 : CHUNK;
         hipLaunchKernelGGL(k_features, dim3(grid_for(m, 128)), dim3(128), 0, c->stream, n, r0, m, c->box, c->rc2,
                            (float)(1.0 / d.h), (float)p->center[0], (float)p->center[1], (float)p->center[2],
                            (float)p->radius, c->cell_start.as<int32_t>(), c->sorted.as<float4>(),
                            c->pos4.as<float4>(), c->ua.as<uint16_t>());
-        forward(c, s, params, m, c->ua.as<uint16_t>(), c->ub.as<float>() + (int64_t)r0 * NOUT, false);
+        hipLaunchKernelGGL(k_forward_fused, dim3(forward_grid(c, m)), dim3(256), 0, c->stream, m, params,
+                           c->ua.as<uint16_t>(), c->ub.as<float>() + (int64_t)r0 * NOUT);
     }
     hipLaunchKernelGGL(k_apply_disp, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, (float)d.h,
                        (float)p->center[0], (float)p->center[1], (float)p->center[2], (float)p->radius,

@@ -80,6 +80,7 @@ _SIGS += [
     ("sph_mlp_features", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
     ("sph_mlp_forward", C.c_int, [_vp, _vp, _i32, _vp, _vp]),
     ("sph_mlp_train_step", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    ("sph_mlp_train_epoch", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp]),
     ("sph_mlp_apply", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
 ]
 _OPTIONAL_SIGS = []
@@ -334,6 +335,22 @@ class Context:
                                              _ptr(target, torch.float32, B * 3, "target"), _ptr(loss), _ptr(grad)))
         return loss, grad
 
+    def mlp_train_epoch(self, adam, step0, params, m, v, rows, feat, target, batch, want_losses=True):
+        """Steps step0 .. step0 + nbatch - 1 over the batches rows[b*batch:(b+1)*batch]
+        (int64 row indices into feat/target, nbatch = len(rows) // batch)."""
+        nbatch = rows.numel() // batch
+        rows = rows[:nbatch * batch]
+        nrows = feat.shape[0]
+        losses = torch.zeros(nbatch, dtype=torch.float32, device=self._dev()) if want_losses else None
+        self._check(lib().sph_mlp_train_epoch(self._h, C.byref(adam), int(step0),
+                                              _ptr(params, torch.float32, MLP_NPARAMS, "params"),
+                                              _ptr(m, torch.float32, MLP_NPARAMS, "m"),
+                                              _ptr(v, torch.float32, MLP_NPARAMS, "v"), int(batch), int(nbatch),
+                                              int(nrows), _ptr(rows, torch.int64, nbatch * batch, "rows"),
+                                              _ptr(feat, torch.int16, nrows * MLP_FEAT_STRIDE, "feat"),
+                                              _ptr(target, torch.float32, nrows * 3, "target"), _ptr(losses)))
+        return losses
+
     def mlp_apply(self, domain: Domain, prm, pos, params):
         n = pos.shape[-1] if pos.numel() else 0
         self._check(lib().sph_mlp_apply(self._h, C.byref(domain.to_c()), C.byref(prm), n,
@@ -405,6 +422,10 @@ def sph_mlp_forward(ctx: Context, params, feat):
 
 def sph_mlp_train_step(ctx: Context, adam, step, params, m, v, feat, target, want_loss=True, want_grad=False):
     return ctx.mlp_train_step(adam, step, params, m, v, feat, target, want_loss, want_grad)
+
+
+def sph_mlp_train_epoch(ctx: Context, adam, step0, params, m, v, rows, feat, target, batch, want_losses=True):
+    return ctx.mlp_train_epoch(adam, step0, params, m, v, rows, feat, target, batch, want_losses)
 
 
 def sph_mlp_apply(ctx: Context, domain, prm, pos, params):

@@ -130,7 +130,7 @@ def train(ctx: S.Context, feat, target, epochs=50, batch=65536, lr=1e-3, weight_
     """AdamW on shuffled mini-batches (the last partial batch of an epoch is
     dropped).  Returns (params, per-epoch mean loss)."""
     n = feat.shape[0]
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    g = torch.Generator(device="cuda").manual_seed(seed)
     params = torch.as_tensor(init, device="cuda").clone()
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
@@ -139,16 +139,14 @@ def train(ctx: S.Context, feat, target, epochs=50, batch=65536, lr=1e-3, weight_
     losses = []
     nb = n // batch
     for ep in range(epochs):
-        perm = torch.randperm(n, generator=g).to("cuda")
-        tot = torch.zeros(1, dtype=torch.float64, device="cuda")
-        for b in range(nb):
-            idx = perm[b * batch:(b + 1) * batch]
-            xb = feat.index_select(0, idx).contiguous()
-            yb = target.index_select(0, idx).contiguous()
-            step += 1
-            loss, _ = ctx.mlp_train_step(adam, step, params, m, v, xb, yb)
-            tot += loss
-        losses.append(float(tot.item()) / max(nb, 1))
+        perm = torch.randperm(n, generator=g, device="cuda")
+        if nb == 0:
+            losses.append(float("nan"))
+            continue
+        # the nb steps of the epoch in one call; batches gathered by row index inside the kernel
+        ls = ctx.mlp_train_epoch(adam, step + 1, params, m, v, perm, feat, target, batch)
+        step += nb
+        losses.append(float(ls.double().sum().item()) / nb)
         if log_every and (ep + 1) % log_every == 0:
             print(f"epoch {ep + 1} loss {losses[-1]:.4e}", flush=True)
     return params, losses

@@ -161,3 +161,75 @@ def test_apply_moves_like_oracle(S):
     d = host(pos) - new
     disp = w.h * np.abs(y).max()
     assert np.mean(np.abs(d) <= 1e-3 * disp + 2e-7) > 0.999
+
+
+def _batch(rng, B):
+    X = rng.normal(size=(B, 100))
+    Xp = np.zeros((B, 128), dtype=np.int16)
+    Xp[:, :100] = f64_to_bits(X)
+    T = (0.1 * rng.normal(size=(B, 3))).astype(np.float32)
+    return X, Xp, T
+
+
+@pytest.mark.parametrize("B", [1, 17, 1000, 64 * 256 + 40])
+def test_gradient_ragged_batches(S, B):
+    """Batches that leave a partial 16-sample slab and a partial 64-sample
+    block (and, at the largest size, more blocks than workgroups) against the
+    oracle."""
+    rng = np.random.default_rng(B)
+    X, Xp, T = _batch(rng, B)
+    theta = M.init_params(4)
+    ctx = S.Context(3)
+    p = dev(theta)
+    zero = torch.zeros_like(p)
+    loss, grad = ctx.mlp_train_step(S.adamw_params(lr=0.0), 1, p, zero, zero.clone(), dev(Xp, torch.int16), dev(T),
+                                    want_grad=True)
+    lo, go = M.loss_and_grad(theta.astype(np.float64), M.bf16(X), T.astype(np.float64))
+    assert abs(host(loss)[0] - lo) <= 1e-5 * lo
+    gg = host(grad)
+    k = 0
+    for name, shp in M.SHAPES:
+        sz = int(np.prod(shp))
+        assert normwise(gg[k:k + sz], go[k:k + sz]) < 1e-3, (name, B)
+        k += sz
+
+
+def test_gradient_deterministic(S):
+    rng = np.random.default_rng(8)
+    _, Xp, T = _batch(rng, 5000)
+    theta = M.init_params(5)
+    ctx = S.Context(3)
+    out = []
+    for _ in range(2):
+        p = dev(theta)
+        zero = torch.zeros_like(p)
+        _, grad = ctx.mlp_train_step(S.adamw_params(lr=0.0), 1, p, zero, zero.clone(), dev(Xp, torch.int16), dev(T),
+                                     want_grad=True)
+        out.append(host(grad))
+    assert np.array_equal(out[0], out[1])
+
+
+def test_train_epoch_matches_steps(S):
+    """The epoch call (batches gathered by row index in the kernel) against
+    sph_mlp_train_step on the same batches gathered on the host: identical."""
+    rng = np.random.default_rng(9)
+    n, batch = 3 * 2048 + 100, 2048
+    _, Xp, T = _batch(rng, n)
+    X, Tt = dev(Xp, torch.int16), dev(T)
+    theta = M.init_params(6)
+    perm = torch.as_tensor(rng.permutation(n), dtype=torch.int64, device="cuda")
+    adam = S.adamw_params()
+    ctx = S.Context(3)
+    p1, m1, v1 = dev(theta), torch.zeros(S.MLP_NPARAMS, device="cuda"), torch.zeros(S.MLP_NPARAMS, device="cuda")
+    losses = ctx.mlp_train_epoch(adam, 1, p1, m1, v1, perm, X, Tt, batch)
+    p2, m2, v2 = dev(theta), torch.zeros(S.MLP_NPARAMS, device="cuda"), torch.zeros(S.MLP_NPARAMS, device="cuda")
+    ref = []
+    for b in range(3):
+        idx = perm[b * batch:(b + 1) * batch]
+        loss, _ = ctx.mlp_train_step(adam, b + 1, p2, m2, v2, X.index_select(0, idx).contiguous(),
+                                     Tt.index_select(0, idx).contiguous())
+        ref.append(host(loss)[0])
+    assert losses.numel() == 3
+    assert np.array_equal(host(losses), np.array(ref, dtype=np.float32))
+    assert np.array_equal(host(p1), host(p2)) and np.array_equal(host(m1), host(m2)) and np.array_equal(host(v1), host(v2))
+    assert not np.array_equal(host(p1), theta)
