@@ -251,6 +251,45 @@ def run_train(steps, batch=65536, nbatch=20):
             "samples_per_s": nstep * batch / secs, "loss_first_last": [losses[0], losses[-1]]}
 
 
+def run_setup(reps=5):
+    """Set-up path of the fixed-particle workloads (2-D 512^2 and 3-D 200^3
+    Taylor-Green, cut-offs 1.6h and 2h): cell binning and neighbour search
+    (sph_build_cells), the caller-order neighbour export, the kernel sum and
+    the correction matrices; milliseconds per call, best of `reps`."""
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+
+    def best(fn):
+        out = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            out = min(out, (time.perf_counter() - t0) * 1e3)
+        return out
+
+    res = {}
+    for name, w in (("taylor_green_2d_512", I.taylor_green_2d(nside=512)),
+                    ("taylor_green_3d_200", I.taylor_green_3d(nside=200))):
+        pos = torch.as_tensor(w.pos, device="cuda")
+        vol = torch.as_tensor(w.vol, device="cuda")
+        for kappa in (1.6, 2.0):
+            ctx = S.Context(w.dim)
+            dom = S.Domain(dim=w.dim, h=w.h, kappa=kappa)
+            ctx.build_cells(dom, pos)
+            r = {"n_particles": w.n, "nnz": ctx.nnz, "build_cells_ms": best(lambda: ctx.build_cells(dom, pos))}
+            r["export_ms"] = best(lambda: (ctx.build_cells(dom, pos), ctx.neighbors())) - r["build_cells_ms"]
+            r["kernel_sum_ms"] = best(lambda: ctx.kernel_sum(vol))
+            r["correction_B_ms"] = best(lambda: ctx.correction_B(vol))
+            res[f"{name}_kappa{kappa}"] = r
+            ctx.close()
+            torch.cuda.empty_cache()
+    return res
+
+
 def init_params(seed):
     """Seeded initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)) (PyTorch's
     linear-layer default), drawn on the host and passed in."""
@@ -283,6 +322,8 @@ def main():
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
+    ap.add_argument("--setup", action="store_true", help="profile the set-up path only (binning, neighbours, "
+                    "kernel sum, correction matrices)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
@@ -308,6 +349,9 @@ def main():
         run, _, _ = WS.relax_plain(ctx, wr, max_iter=args.relax_iters)
         print(json.dumps({"relax_iterations": run.iterations, "seconds": run.seconds, "residue": run.residue,
                           "n_particles": wr.n}), flush=True)
+        return
+    if args.setup:
+        print(json.dumps(run_setup()), flush=True)
         return
     if args.train_steps:
         print(json.dumps(run_train(args.train_steps)), flush=True)

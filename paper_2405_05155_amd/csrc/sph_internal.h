@@ -282,6 +282,24 @@ __device__ __forceinline__ float group_sum(const Kahan& k) {
     return hi + lo;
 }
 
+// group_sum keeping the combined (hi, lo) pair in FP64 (for sums that feed
+// an FP64 computation).
+template <int L>
+__device__ __forceinline__ double group_sum64(const Kahan& k) {
+    float hi = k.s, lo = -k.c;
+#pragma unroll
+    for (int m = 1; m < L; m <<= 1) {
+        float ohi = __shfl_xor(hi, m, 64);
+        float olo = __shfl_xor(lo, m, 64);
+        float s = hi + ohi;
+        float bp = s - hi;
+        float e = (hi - (s - bp)) + (ohi - bp);
+        lo = (lo + olo) + e;
+        hi = s;
+    }
+    return (double)hi + (double)lo;
+}
+
 // group_sum for a run-time group size L in {1, 2, 4, 8}.
 __device__ __forceinline__ float group_sum_rt(const Kahan& k, int L) {
     float hi = k.s, lo = -k.c;
@@ -347,3 +365,55 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 KernelConsts make_kernel_consts(int type, int dim, double h);
 BoxArgs make_box_args(const sph_domain& d, double rc);
 int64_t cell_slots(const BoxArgs& b);  // size of the cell-key space
+
+// ------------------------------------------------------------------ pair-loop helpers
+
+// Periodic geometry for the pair loops: wrap d - L rint(d / L) on periodic
+// axes (invL = 0 elsewhere), needed only by waves holding a particle within
+// `margin` of a periodic face.
+struct Wrap {
+    float L[3], invL[3], lo[3];
+    float margin;
+};
+
+__device__ __forceinline__ float wrap1(float d, float L, float invL) { return fmaf(-L, rintf(d * invL), d); }
+
+__device__ __forceinline__ bool wave_needs_wrap(const Wrap& w, const float4& x) {
+    bool near = false;
+    const float xs[3] = {x.x, x.y, x.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (w.invL[a] != 0.f) {
+            const float off = xs[a] - w.lo[a];
+            near = near || off < w.margin || w.L[a] - off < w.margin;
+        }
+    }
+    return __any(near);
+}
+
+// Row entries of sorted slot i taken by lane `sub` of an L-lane group:
+// entries sub, sub + L, ...  ELL (entry k at col[k n + i], k < S) or CSR.
+template <bool ELL, int L>
+__device__ __forceinline__ void row_range(int32_t i, int sub, int32_t n, const int64_t* __restrict__ rp, int32_t S,
+                                          int64_t& k, int64_t& e, int64_t& stride) {
+    if (ELL) {
+        k = (int64_t)sub * n + i;
+        stride = (int64_t)L * n;
+        e = (int64_t)S * n;
+    } else {
+        k = rp[i] + sub;
+        stride = L;
+        e = rp[i + 1];
+    }
+}
+
+inline Wrap make_wrap(const sph_ctx* c) {
+    Wrap w{};
+    for (int a = 0; a < 3; ++a) {
+        w.L[a] = c->box.L[a];
+        w.invL[a] = c->box.periodic[a] ? (float)(1.0 / c->box.Ld[a]) : 0.f;
+        w.lo[a] = c->box.lo[a];
+    }
+    w.margin = (float)(c->rc * 1.001);
+    return w;
+}

@@ -2,11 +2,16 @@
 // kernel summation, the correction matrix B_i (Eq. 9) with its FP64
 // inversion, the cached geometry records, and the corrected gradient.
 //
-// Mapping: one thread per particle in cell-sorted (Morton) order, looping
-// over its sorted CSR row, with the block index remapped so that each XCD
-// works on one contiguous range of slots; all sums are FP32 with Kahan
-// compensation; caller-indexed inputs are gathered once into sorted order
-// and outputs are written back at the caller index.
+// Kernel sum and correction matrix: each cell-sorted (Morton) slot is taken
+// by a group of LN lanes that split its row (fixed-stride ELL rows when the
+// padding budget allows them, else the sorted CSR row), read one packed
+// (x, y, z, V) record per neighbour through 32-bit offsets with the next
+// record in flight, and merge their compensated (Kahan) partial sums with a
+// TwoSum butterfly; the periodic wrap is applied only by waves holding a
+// particle within a cut-off of a periodic face.  Blocks are remapped so each
+// XCD works on one contiguous range of slots.  Caller-indexed inputs are
+// gathered once into sorted order and outputs written back at the caller
+// index.
 #include "sph_internal.h"
 
 namespace {
@@ -32,25 +37,64 @@ __device__ __forceinline__ int32_t slot_id() {
     return xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * (int32_t)blockDim.x + (int32_t)threadIdx.x;
 }
 
-template <int DIM>
-__global__ void k_kernel_sum(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ sorted,
-                             const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                             const float* __restrict__ svol, float* __restrict__ out) {
-    int32_t s = slot_id();
+// rec[s] = (x, y, z, V) of sorted slot s (z = 0 in 2-D)
+__global__ void k_pair_rec(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ vol,
+                           float4* __restrict__ rec) {
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    float4 pi = sorted[s];
-    Kahan acc;
-    acc.init(kernel_W(kc, 0.f) * svol[s]);
-    int64_t e = rp[s + 1];
-    for (int64_t k = rp[s]; k < e; ++k) {
-        int32_t t = col[k];
-        float d[3];
-        pair_d<DIM>(pi, sorted[t], b, d);
-        float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        float q = sqrtf(r2) * kc.hinv;
-        acc.add(kernel_W(kc, q) * svol[t]);
+    const float4 p = sorted[s];
+    rec[s] = make_float4(p.x, p.y, p.z, vol[__float_as_int(p.w)]);
+}
+
+// separation r_i - r_j of a pair (wrapped on periodic axes when WRAP)
+template <int DIM, bool WRAP>
+__device__ __forceinline__ void pair_sep(const Wrap& w, const float4& pi, const float4& pj, float d[3]) {
+    d[0] = pi.x - pj.x;
+    d[1] = pi.y - pj.y;
+    d[2] = DIM == 3 ? pi.z - pj.z : 0.f;
+    if (WRAP) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) d[a] = wrap1(d[a], w.L[a], w.invL[a]);
     }
-    out[__float_as_int(pi.w)] = acc.value();
+}
+
+// Kernel sum sum_j W_ij V_j (self term included).  ELL rows are padded with
+// the slot itself; those entries (and only those: rows hold no self entry)
+// are skipped.
+template <int DIM, bool ELL, int LN>
+__global__ void __launch_bounds__(BLK) k_kernel_sum(int32_t n, KernelConsts kc, Wrap w,
+                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    int32_t S, const float4* __restrict__ rec,
+                                                    const float4* __restrict__ sorted, float* __restrict__ out) {
+    const int64_t tt = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
+    const int32_t i = (int32_t)(tt / LN);
+    const int sub = (int)(tt % LN);
+    if (i >= n) return;
+    const float4 pi = ld32(rec, (uint32_t)i);
+    const bool wrap = wave_needs_wrap(w, pi);
+    Kahan acc;
+    acc.init(sub == 0 ? kernel_W(kc, 0.f) * pi.w : 0.f);
+    int64_t k, e, stride;
+    row_range<ELL, LN>(i, sub, n, rp, S, k, e, stride);
+    int32_t j = k < e ? col[k] : i;
+    float4 pj = ld32(rec, (uint32_t)j);
+    int32_t jn = k + stride < e ? col[k + stride] : i;
+    while (k < e) {
+        const float4 pn = ld32(rec, (uint32_t)jn);
+        const int32_t jc = j;
+        j = jn;
+        jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
+        k += stride;
+        float d[3];
+        if (wrap) pair_sep<DIM, true>(w, pi, pj, d);
+        else pair_sep<DIM, false>(w, pi, pj, d);
+        const float r2 = fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2]));
+        const float q = __builtin_amdgcn_sqrtf(r2) * kc.hinv;
+        acc.add(jc != i ? kernel_W(kc, q) * pj.w : 0.f);
+        pj = pn;
+    }
+    const float v = group_sum<LN>(acc);
+    if (sub == 0) out[__float_as_int(sorted[i].w)] = v;
 }
 
 // FP64 inverse of the symmetric matrix given by its upper triangle
@@ -103,44 +147,63 @@ __device__ __forceinline__ void store_geo(int32_t i, const float4& p, float V, c
     }
 }
 
-template <int DIM>
-__global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4* __restrict__ sorted,
-                             const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                             const float* __restrict__ svol, float* __restrict__ Bout, double* __restrict__ B64,
-                             float4* __restrict__ geo0, float4* __restrict__ geo1, float2* __restrict__ geo2,
-                             int32_t* __restrict__ ndeg) {
+// Correction matrix B_i = -(sum_j V_j (r_i - r_j) (x) grad W_ij)^-1 (Eq. 9),
+// the sum in FP32 Kahan partials merged to FP64, inverted in FP64; a
+// degenerate sum (fewer than DIM independent neighbour directions) gives the
+// identity and is counted.  Also writes the cached geometry records.
+template <int DIM, bool ELL, int LN>
+__global__ void __launch_bounds__(BLK) k_correction(int32_t n, KernelConsts kc, Wrap w,
+                                                    const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    int32_t S, const float4* __restrict__ rec,
+                                                    const float4* __restrict__ sorted, float* __restrict__ Bout,
+                                                    double* __restrict__ B64, float4* __restrict__ geo0,
+                                                    float4* __restrict__ geo1, float2* __restrict__ geo2,
+                                                    int32_t* __restrict__ ndeg) {
     constexpr int NU = DIM == 2 ? 3 : 6;
-    int32_t s = slot_id();
+    const int64_t tt = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * BLK + threadIdx.x;
+    const int32_t s = (int32_t)(tt / LN);
+    const int sub = (int)(tt % LN);
     if (s >= n) return;
-    float4 pi = sorted[s];
-    int32_t i = __float_as_int(pi.w);
+    const float4 pi = ld32(rec, (uint32_t)s);
+    const bool wrap = wave_needs_wrap(w, pi);
     Kahan M[NU];
 #pragma unroll
     for (int u = 0; u < NU; ++u) M[u].init();
-    int64_t e = row_ptr[s + 1];
-    for (int64_t k = row_ptr[s]; k < e; ++k) {
-        int32_t t = col[k];
+    int64_t k, e, stride;
+    row_range<ELL, LN>(s, sub, n, rp, S, k, e, stride);
+    int32_t j = k < e ? col[k] : s;
+    float4 pj = ld32(rec, (uint32_t)j);
+    int32_t jn = k + stride < e ? col[k + stride] : s;
+    while (k < e) {
+        const float4 pn = ld32(rec, (uint32_t)jn);
+        jn = k + 2 * stride < e ? col[k + 2 * stride] : s;
+        k += stride;
         float d[3];
-        pair_d<DIM>(pi, sorted[t], b, d);
-        float r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        float q = sqrtf(r2) * kc.hinv;
-        float w = kernel_F(kc, q) * svol[t];  // grad W = F d;  r (x) grad W V = F V d d^T
+        if (wrap) pair_sep<DIM, true>(w, pi, pj, d);
+        else pair_sep<DIM, false>(w, pi, pj, d);
+        const float r2 = fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2]));
+        const float q = __builtin_amdgcn_sqrtf(r2) * kc.hinv;
+        const float wt = kernel_F(kc, q) * pj.w;  // grad W = F d;  r (x) grad W V = F V d d^T (zero for d = 0)
         if (DIM == 2) {
-            M[0].add(w * d[0] * d[0]);
-            M[1].add(w * d[0] * d[1]);
-            M[2].add(w * d[1] * d[1]);
+            M[0].add(wt * d[0] * d[0]);
+            M[1].add(wt * d[0] * d[1]);
+            M[2].add(wt * d[1] * d[1]);
         } else {
-            M[0].add(w * d[0] * d[0]);
-            M[1].add(w * d[0] * d[1]);
-            M[2].add(w * d[0] * d[2]);
-            M[3].add(w * d[1] * d[1]);
-            M[4].add(w * d[1] * d[2]);
-            M[5].add(w * d[2] * d[2]);
+            M[0].add(wt * d[0] * d[0]);
+            M[1].add(wt * d[0] * d[1]);
+            M[2].add(wt * d[0] * d[2]);
+            M[3].add(wt * d[1] * d[1]);
+            M[4].add(wt * d[1] * d[2]);
+            M[5].add(wt * d[2] * d[2]);
         }
+        pj = pn;
     }
     double m[NU], inv[NU];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) m[u] = M[u].value64();
+    for (int u = 0; u < NU; ++u) m[u] = group_sum64<LN>(M[u]);
+    if (sub != 0) return;
+    const float4 ps = sorted[s];
+    const int32_t i = __float_as_int(ps.w);
     double Bd[NU];
     if (inv_sym<DIM>(m, inv)) {
 #pragma unroll
@@ -172,7 +235,7 @@ __global__ void k_correction(int32_t n, BoxArgs b, KernelConsts kc, const float4
             if (B64) B64[(int64_t)i * 9 + t] = Bd[idx[t]];
         }
     }
-    store_geo<DIM>(s, pi, svol[s], Bu, geo0, geo1, geo2);
+    store_geo<DIM>(s, pi, pi.w, Bu, geo0, geo1, geo2);
 }
 
 template <int DIM>
@@ -259,6 +322,79 @@ int to_sorted(sph_ctx* c, const float* src, DevBuf& dst) {
     return SPH_OK;
 }
 
+// Lanes per slot for the kernel-sum and correction loops: the most (up to 8)
+// that leave each lane at least four row entries.  Override SPH_PAIR_LANES =
+// 1, 2, 4 or 8.
+int pair_lanes(const sph_ctx* c) {
+    if (const char* e = getenv("SPH_PAIR_LANES")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+    }
+    const double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
+    int L = 1;
+    while (L < 8 && avg / (2 * L) >= 4.0) L <<= 1;
+    return L;
+}
+
+// Packed records in c->svol and the row layout; the launch helper calls
+// go(kernel, ell) with the kernel instantiated for the lane count.
+int prepare_pair_loop(sph_ctx* c, const float* vol) {
+    if (c->n >= (1 << 28))  // records are addressed through 32-bit byte offsets
+        return sph_fail(c, SPH_ERR_CAPACITY, "pair loops: at most 2^28 - 1 particles");
+    SPH_HIP(c, c->svol.ensure((size_t)c->n * sizeof(float4)));
+    hipLaunchKernelGGL(k_pair_rec, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->sorted.as<float4>(),
+                       vol, c->svol.as<float4>());
+    return sph_ell_prepare(c);
+}
+
+template <int DIM, int LN>
+void launch_kernel_sum_l(sph_ctx* c, const KernelConsts& kc, float* out) {
+    const bool ell = c->ell_state == 1;
+    const Wrap w = make_wrap(c);
+    dim3 g(grid_for((int64_t)c->n * LN, BLK)), b(BLK);
+    if (ell)
+        hipLaunchKernelGGL((k_kernel_sum<DIM, true, LN>), g, b, 0, c->stream, c->n, kc, w, c->rp_s.as<int64_t>(),
+                           c->colE.as<int32_t>(), c->ell_S, c->svol.as<float4>(), c->sorted.as<float4>(), out);
+    else
+        hipLaunchKernelGGL((k_kernel_sum<DIM, false, LN>), g, b, 0, c->stream, c->n, kc, w, c->rp_s.as<int64_t>(),
+                           c->col_s.as<int32_t>(), 0, c->svol.as<float4>(), c->sorted.as<float4>(), out);
+}
+
+template <int DIM>
+void launch_kernel_sum(sph_ctx* c, const KernelConsts& kc, float* out) {
+    switch (pair_lanes(c)) {
+        case 1: launch_kernel_sum_l<DIM, 1>(c, kc, out); break;
+        case 2: launch_kernel_sum_l<DIM, 2>(c, kc, out); break;
+        case 4: launch_kernel_sum_l<DIM, 4>(c, kc, out); break;
+        default: launch_kernel_sum_l<DIM, 8>(c, kc, out); break;
+    }
+}
+
+template <int DIM, int LN>
+void launch_correction_l(sph_ctx* c, const KernelConsts& kc, float* B, double* B64, int32_t* ndeg) {
+    const bool ell = c->ell_state == 1;
+    const Wrap w = make_wrap(c);
+    dim3 g(grid_for((int64_t)c->n * LN, BLK)), b(BLK);
+    if (ell)
+        hipLaunchKernelGGL((k_correction<DIM, true, LN>), g, b, 0, c->stream, c->n, kc, w, c->rp_s.as<int64_t>(),
+                           c->colE.as<int32_t>(), c->ell_S, c->svol.as<float4>(), c->sorted.as<float4>(), B, B64,
+                           c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+    else
+        hipLaunchKernelGGL((k_correction<DIM, false, LN>), g, b, 0, c->stream, c->n, kc, w, c->rp_s.as<int64_t>(),
+                           c->col_s.as<int32_t>(), 0, c->svol.as<float4>(), c->sorted.as<float4>(), B, B64,
+                           c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), ndeg);
+}
+
+template <int DIM>
+void launch_correction(sph_ctx* c, const KernelConsts& kc, float* B, double* B64, int32_t* ndeg) {
+    switch (pair_lanes(c)) {
+        case 1: launch_correction_l<DIM, 1>(c, kc, B, B64, ndeg); break;
+        case 2: launch_correction_l<DIM, 2>(c, kc, B, B64, ndeg); break;
+        case 4: launch_correction_l<DIM, 4>(c, kc, B, B64, ndeg); break;
+        default: launch_correction_l<DIM, 8>(c, kc, B, B64, ndeg); break;
+    }
+}
+
 int ensure_geo(sph_ctx* c) {
     int64_t nn = c->n > 0 ? c->n : 1;
     SPH_HIP(c, c->geo0.ensure(nn * sizeof(float4)));
@@ -276,17 +412,11 @@ int sph_kernel_sum(sph_ctx* c, const float* vol, float* out) {
     if (!c->bound) return sph_fail(c, SPH_ERR_STATE, "sph_kernel_sum: no configuration bound");
     if (c->n > 0 && (!vol || !out)) return sph_fail(c, SPH_ERR_ARG, "sph_kernel_sum: NULL array");
     if (c->n == 0) return SPH_OK;
-    int r = to_sorted(c, vol, c->svol);
+    int r = prepare_pair_loop(c, vol);
     if (r) return r;
     KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
-    if (c->dim == 2)
-        hipLaunchKernelGGL(k_kernel_sum<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                           c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->svol.as<float>(),
-                           out);
-    else
-        hipLaunchKernelGGL(k_kernel_sum<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                           c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), c->svol.as<float>(),
-                           out);
+    if (c->dim == 2) launch_kernel_sum<2>(c, kc, out);
+    else launch_kernel_sum<3>(c, kc, out);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -297,23 +427,18 @@ int sph_correction_B(sph_ctx* c, const float* vol, float* B, double* B64, int32_
     if (c->n > 0 && (!vol || !B)) return sph_fail(c, SPH_ERR_ARG, "sph_correction_B: NULL array");
     int r = ensure_geo(c);
     if (r) return r;
+    // row layout first: its set-up uses the context counter too
+    if (c->n > 0) {
+        r = prepare_pair_loop(c, vol);
+        if (r) return r;
+    }
     SPH_HIP(c, c->counter.ensure(64));
     int32_t* ndeg = c->counter.as<int32_t>();
     SPH_HIP(c, hipMemsetAsync(ndeg, 0, sizeof(int32_t), c->stream));
     if (c->n > 0) {
-        r = to_sorted(c, vol, c->svol);
-        if (r) return r;
         KernelConsts kc = make_kernel_consts(c->dom.kernel, c->dim, c->dom.h);
-        if (c->dim == 2)
-            hipLaunchKernelGGL(k_correction<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                               c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
-                               c->svol.as<float>(), B, B64, c->geo0.as<float4>(), c->geo1.as<float4>(),
-                               c->geo2.as<float2>(), ndeg);
-        else
-            hipLaunchKernelGGL(k_correction<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->box, kc,
-                               c->sorted.as<float4>(), c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(),
-                               c->svol.as<float>(), B, B64, c->geo0.as<float4>(), c->geo1.as<float4>(),
-                               c->geo2.as<float2>(), ndeg);
+        if (c->dim == 2) launch_correction<2>(c, kc, B, B64, ndeg);
+        else launch_correction<3>(c, kc, B, B64, ndeg);
         SPH_LAUNCH_CHECK(c);
     }
     if (n_degenerate) {

@@ -110,45 +110,6 @@ __device__ __forceinline__ void load_B3(int32_t i, const float4* __restrict__ ge
     B[6] = t.z; B[7] = u.x; B[8] = u.y;
 }
 
-// Periodic geometry for the pair loops: wrap d - L rint(d / L) on periodic
-// axes (invL = 0 elsewhere), needed only by waves holding a particle within
-// `margin` of a periodic face.
-struct Wrap {
-    float L[3], invL[3], lo[3];
-    float margin;
-};
-
-__device__ __forceinline__ float wrap1(float d, float L, float invL) { return fmaf(-L, rintf(d * invL), d); }
-
-__device__ __forceinline__ bool wave_needs_wrap(const Wrap& w, const float4& x) {
-    bool near = false;
-    const float xs[3] = {x.x, x.y, x.z};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (w.invL[a] != 0.f) {
-            const float off = xs[a] - w.lo[a];
-            near = near || off < w.margin || w.L[a] - off < w.margin;
-        }
-    }
-    return __any(near);
-}
-
-// Row entries of sorted slot i taken by lane `sub` of an L-lane group:
-// entries sub, sub + L, ...  ELL (entry k at col[k n + i], k < S) or CSR.
-template <bool ELL, int L>
-__device__ __forceinline__ void row_range(int32_t i, int sub, int32_t n, const int64_t* __restrict__ rp, int32_t S,
-                                          int64_t& k, int64_t& e, int64_t& stride) {
-    if (ELL) {
-        k = (int64_t)sub * n + i;
-        stride = (int64_t)L * n;
-        e = (int64_t)S * n;
-    } else {
-        k = rp[i] + sub;
-        stride = L;
-        e = rp[i + 1];
-    }
-}
-
 // (dW/dr)/r V_j and the reference separation X_i - X_j of one pair.
 template <bool WRAP>
 __device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, const float4& gi, const float4& gj,
@@ -437,17 +398,6 @@ int ensure_scratch(sph_ctx* c) {
     SPH_HIP(c, c->fc.ensure(n * sizeof(float)));    // F2
     SPH_HIP(c, c->pa.ensure(n * sizeof(float4)));   // current positions
     return sph_ell_prepare(c);
-}
-
-Wrap make_wrap(const sph_ctx* c) {
-    Wrap w{};
-    for (int a = 0; a < 3; ++a) {
-        w.L[a] = c->box.L[a];
-        w.invL[a] = c->box.periodic[a] ? (float)(1.0 / c->box.Ld[a]) : 0.f;
-        w.lo[a] = c->box.lo[a];
-    }
-    w.margin = (float)(c->rc * 1.001);
-    return w;
 }
 
 // Lanes per particle of the total-Lagrangian pair loops: the most (up to

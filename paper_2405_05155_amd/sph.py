@@ -221,6 +221,9 @@ class Context:
                                           _ptr(pos, torch.float32, self.dim * n, "pos")))
         self.n = n
         self.domain = domain
+        cnt = C.c_int64(0)  # the pair count (no export: row_ptr NULL only reports it)
+        lib().sph_neighbors(self._h, None, None, 0, C.byref(cnt))
+        self.nnz = int(cnt.value)
         return self
 
     def neighbors(self):
