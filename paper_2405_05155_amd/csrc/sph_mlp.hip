@@ -607,93 +607,185 @@ __device__ __forceinline__ int fcoord(float x, float lo, float inv, int nc) {
     return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
 }
 
-// One thread per particle (caller order, rows [r0, r0 + m)): the 32 nearest
-// j != i within 2h by (|r_ij|^2 in FP64, j) (an unrolled insertion network in
-// registers), then offsets (r_j - r_i)/h, phi/h and grad phi, rounded to BF16.
-__global__ void __launch_bounds__(128) k_features(int32_t n, int32_t r0, int32_t m, BoxArgs b, double rc2, float hinv,
-                                                  float cx, float cy, float cz, float R,
-                                                  const int32_t* __restrict__ cell_start,
-                                                  const float4* __restrict__ sorted, const float4* __restrict__ pos4,
-                                                  uint16_t* __restrict__ feat) {
-    int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    int32_t i = r0 + k;
-    float4 p = pos4[i];
-    double kd[32];
-    int kj[32];
-#pragma unroll
-    for (int s = 0; s < 32; ++s) {
-        kd[s] = 1e300;
-        kj[s] = 0x7fffffff;
+// Neighbour selection for the features: keys are (|r_ij|^2 in FP64, j),
+// compared lexicographically (a non-negative double orders like its bit
+// pattern); the empty key is (UINT64_MAX, INT32_MAX).
+constexpr uint64_t KEY_EMPTY = ~0ull;
+constexpr int32_t J_EMPTY = 0x7fffffff;
+
+__device__ __forceinline__ bool key_less(uint64_t ka, int32_t ja, uint64_t kb, int32_t jb) {
+    return ka < kb || (ka == kb && ja < jb);
+}
+
+// compare-exchange with lane ^ m: keep the smaller key when take_min
+__device__ __forceinline__ void key_cx(uint64_t& k, int32_t& j, int m, bool take_min) {
+    const uint64_t ok = __shfl_xor(k, m, 64);
+    const int32_t oj = __shfl_xor(j, m, 64);
+    const bool other_less = key_less(ok, oj, k, j);
+    if (other_less == take_min) {
+        k = ok;
+        j = oj;
     }
-    int cxi = fcoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
-    int cyi = fcoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]);
-    int czi = fcoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]);
-    for (int oz = -1; oz <= 1; ++oz) {
-        int z = czi + oz;
-        if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
-        else if (z < 0 || z >= b.nc[2]) continue;
-        for (int oy = -1; oy <= 1; ++oy) {
-            int y = cyi + oy;
-            if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
-            else if (y < 0 || y >= b.nc[1]) continue;
-            for (int ox = -1; ox <= 1; ++ox) {
-                int x = cxi + ox;
-                if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
-                else if (x < 0 || x >= b.nc[0]) continue;
-                int32_t key = cell_key(b, x, y, z);
-                int t1 = cell_start[key + 1];
-                for (int t = cell_start[key]; t < t1; ++t) {
-                    float4 q = sorted[t];
-                    int j = __float_as_int(q.w);
-                    if (j == i) continue;
-                    double dx = (double)q.x - (double)p.x;
-                    double dy = (double)q.y - (double)p.y;
-                    double dz = (double)q.z - (double)p.z;
-                    if (b.periodic[0]) dx = dx > b.halfLd[0] ? dx - b.Ld[0] : (dx < -b.halfLd[0] ? dx + b.Ld[0] : dx);
-                    if (b.periodic[1]) dy = dy > b.halfLd[1] ? dy - b.Ld[1] : (dy < -b.halfLd[1] ? dy + b.Ld[1] : dy);
-                    if (b.periodic[2]) dz = dz > b.halfLd[2] ? dz - b.Ld[2] : (dz < -b.halfLd[2] ? dz + b.Ld[2] : dz);
-                    double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-                    if (d2 > rc2) continue;
-                    if (d2 > kd[31] || (d2 == kd[31] && j > kj[31])) continue;
-                    double cd = d2;
-                    int cj = j;
+}
+
+// ascending bitonic sort of one key per lane
+__device__ __forceinline__ void key_sort64(uint64_t& k, int32_t& j, int lane) {
 #pragma unroll
-                    for (int s = 0; s < 32; ++s) {
-                        bool lt = cd < kd[s] || (cd == kd[s] && cj < kj[s]);
-                        double td = lt ? kd[s] : cd;
-                        int tj = lt ? kj[s] : cj;
-                        kd[s] = lt ? cd : kd[s];
-                        kj[s] = lt ? cj : kj[s];
-                        cd = td;
-                        cj = tj;
-                    }
-                }
+    for (int kk = 2; kk <= 64; kk <<= 1)
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const bool asc = (lane & kk) == 0;
+            const bool lower = (lane & jj) == 0;
+            key_cx(k, j, jj, lower == asc);
+        }
+}
+
+// A (ascending) := the 64 smallest of A and B (B unordered), ascending
+__device__ __forceinline__ void key_merge(uint64_t& ak, int32_t& aj, uint64_t bk, int32_t bj, int lane) {
+    key_sort64(bk, bj, lane);
+    const uint64_t rk = __shfl(bk, 63 - lane, 64);  // B descending against A ascending:
+    const int32_t rj = __shfl(bj, 63 - lane, 64);   // the lane-wise minima are the 64 smallest
+    if (key_less(rk, rj, ak, aj)) {
+        ak = rk;
+        aj = rj;
+    }
+#pragma unroll
+    for (int jj = 32; jj > 0; jj >>= 1) key_cx(ak, aj, jj, (lane & jj) == 0);  // bitonic -> ascending
+}
+
+// lane holding the r-th set bit (r from 0) of m
+__device__ __forceinline__ int nth_set_lane(uint64_t m, int r) {
+    int src = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int t = src + step;
+        if (__popcll(m & ((1ull << t) - 1ull)) <= r) src = t;
+    }
+    return src;
+}
+
+// One wave per feature row (caller order, rows [r0, r0 + m)).  Lanes test 64
+// candidates of the 3x3x3 cell block at a time with the exact FP64 distance;
+// those within 2h (j != i) are compacted by a ballot into a 64-slot batch,
+// and each full batch is merged into the running 64 nearest (bitonic sort
+// and merge over lanes).  Lanes 0..31 then hold the 32 nearest by
+// (|r_ij|^2, j) and write the offsets (r_j - r_i)/h; then phi/h and grad phi;
+// features rounded to BF16, columns 100.. zero.
+constexpr int FEAT_WPB = 4;  // waves (rows) per block
+
+__global__ void __launch_bounds__(64 * FEAT_WPB) k_features(int32_t n, int32_t r0, int32_t m, BoxArgs b, double rc2,
+                                                            float hinv, float cx, float cy, float cz, float R,
+                                                            const int32_t* __restrict__ cell_start,
+                                                            const float4* __restrict__ sorted,
+                                                            const float4* __restrict__ pos4,
+                                                            uint16_t* __restrict__ feat) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int32_t k = (int32_t)blockIdx.x * FEAT_WPB + (int32_t)(threadIdx.x >> 6);
+    if (k >= m) return;  // the whole wave
+    const int32_t i = r0 + k;
+    const float4 p = pos4[i];
+    // lane < 27: cell of the block and its slot range
+    int32_t c0 = 0, cn = 0;
+    if (lane < 27) {
+        int x = fcoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]) + lane % 3 - 1;
+        int y = fcoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]) + (lane / 3) % 3 - 1;
+        int z = fcoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) + lane / 9 - 1;
+        bool ok = true;
+        if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
+        else ok = ok && x >= 0 && x < b.nc[0];
+        if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
+        else ok = ok && y >= 0 && y < b.nc[1];
+        if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
+        else ok = ok && z >= 0 && z < b.nc[2];
+        if (ok) {
+            const int32_t key = cell_key(b, x, y, z);
+            c0 = cell_start[key];
+            cn = cell_start[key + 1] - c0;
+        }
+    }
+    int32_t inc = cn;
+#pragma unroll
+    for (int d = 1; d < 32; d <<= 1) {
+        const int32_t v = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += v;
+    }
+    const int32_t exc = inc - cn;
+    const int32_t total = __shfl(inc, 26, 64);
+    uint64_t ak = KEY_EMPTY, bk = KEY_EMPTY;
+    int32_t aj = J_EMPTY, bj = J_EMPTY;
+    int nb = 0;  // filled slots of the batch
+    for (int32_t base = 0; base < total; base += 64) {
+        const int32_t cidx = base + lane;
+        int cc = 0;
+#pragma unroll
+        for (int step = 16; step > 0; step >>= 1) {
+            const int mid = cc + step;
+            const int32_t v = __shfl(exc, mid < 27 ? mid : 26, 64);
+            if (mid < 27 && v <= cidx) cc = mid;
+        }
+        const int32_t t = __shfl(c0, cc, 64) + (cidx - __shfl(exc, cc, 64));
+        bool in = false;
+        uint64_t key = KEY_EMPTY;
+        int32_t j = J_EMPTY;
+        if (cidx < total) {
+            const float4 q = sorted[t];
+            j = __float_as_int(q.w);
+            double dx = (double)q.x - (double)p.x;
+            double dy = (double)q.y - (double)p.y;
+            double dz = (double)q.z - (double)p.z;
+            if (b.periodic[0]) dx = dx > b.halfLd[0] ? dx - b.Ld[0] : (dx < -b.halfLd[0] ? dx + b.Ld[0] : dx);
+            if (b.periodic[1]) dy = dy > b.halfLd[1] ? dy - b.Ld[1] : (dy < -b.halfLd[1] ? dy + b.Ld[1] : dy);
+            if (b.periodic[2]) dz = dz > b.halfLd[2] ? dz - b.Ld[2] : (dz < -b.halfLd[2] ? dz + b.Ld[2] : dz);
+            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+            in = j != i && d2 <= rc2;
+            key = (uint64_t)__double_as_longlong(d2);
+        }
+        const uint64_t mk = __ballot(in);
+        const int nin = (int)__popcll(mk);
+        int taken = 0;
+        while (taken < nin) {  // wave-uniform
+            const int put = min(64 - nb, nin - taken);
+            const int src = nth_set_lane(mk, min(max(lane - nb + taken, 0), nin - 1));
+            const uint64_t sk = __shfl(key, src, 64);
+            const int32_t sj = __shfl(j, src, 64);
+            if (lane >= nb && lane < nb + put) {
+                bk = sk;
+                bj = sj;
+            }
+            nb += put;
+            taken += put;
+            if (nb == 64) {
+                key_merge(ak, aj, bk, bj, lane);
+                bk = KEY_EMPTY;
+                bj = J_EMPTY;
+                nb = 0;
             }
         }
     }
+    if (nb > 0) key_merge(ak, aj, bk, bj, lane);
     uint16_t* f = feat + (int64_t)k * FS;
-#pragma unroll
-    for (int s = 0; s < 32; ++s) {
-        float ox = 0.f, oy = 0.f, oz2 = 0.f;
-        if (kj[s] != 0x7fffffff) {
-            float4 q = pos4[kj[s]];
+    if (lane < 32) {
+        float ox = 0.f, oy = 0.f, oz = 0.f;
+        if (aj != J_EMPTY) {
+            const float4 q = pos4[aj];
             ox = min_image(q.x - p.x, b.L[0], b.halfL[0], b.periodic[0]) * hinv;
             oy = min_image(q.y - p.y, b.L[1], b.halfL[1], b.periodic[1]) * hinv;
-            oz2 = min_image(q.z - p.z, b.L[2], b.halfL[2], b.periodic[2]) * hinv;
+            oz = min_image(q.z - p.z, b.L[2], b.halfL[2], b.periodic[2]) * hinv;
         }
-        f[3 * s + 0] = f2bf(ox);
-        f[3 * s + 1] = f2bf(oy);
-        f[3 * s + 2] = f2bf(oz2);
+        f[3 * lane + 0] = f2bf(ox);
+        f[3 * lane + 1] = f2bf(oy);
+        f[3 * lane + 2] = f2bf(oz);
+    } else if (lane == 32) {
+        const float ex = p.x - cx, ey = p.y - cy, ez = p.z - cz;
+        const float rr = sqrtf(ex * ex + ey * ey + ez * ez);
+        const float inv = rr > 0.f ? 1.f / rr : 0.f;
+        f[96] = f2bf((rr - R) * hinv);
+        f[97] = f2bf(ex * inv);
+        f[98] = f2bf(ey * inv);
+        f[99] = f2bf(ez * inv);
+    } else if (lane < 32 + 1 + (FS - NIN)) {
+        f[NIN + (lane - 33)] = 0;
     }
-    float ex = p.x - cx, ey = p.y - cy, ez = p.z - cz;
-    float rr = sqrtf(ex * ex + ey * ey + ez * ez);
-    float inv = rr > 0.f ? 1.f / rr : 0.f;
-    f[96] = f2bf((rr - R) * hinv);
-    f[97] = f2bf(ex * inv);
-    f[98] = f2bf(ey * inv);
-    f[99] = f2bf(ez * inv);
-    for (int s = NIN; s < FS; ++s) f[s] = 0;
 }
 
 // r += h y, then bound to the sphere
@@ -789,7 +881,7 @@ int sph_mlp_features(sph_ctx* c, const sph_domain* dom, const sph_relax_params* 
     int r = sph_bin_cells(c, &d, n, pos);
     if (r) return r;
     if (n == 0) return SPH_OK;
-    hipLaunchKernelGGL(k_features, dim3(grid_for(n, 128)), dim3(128), 0, c->stream, n, 0, n, c->box, c->rc2,
+    hipLaunchKernelGGL(k_features, dim3(grid_for(n, FEAT_WPB)), dim3(64 * FEAT_WPB), 0, c->stream, n, 0, n, c->box, c->rc2,
                        (float)(1.0 / d.h), (float)p->center[0], (float)p->center[1], (float)p->center[2],
                        (float)p->radius, c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->pos4.as<float4>(),
                        feat);
@@ -858,7 +950,8 @@ int sph_mlp_apply(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, 
     SPH_HIP(c, c->ub.ensure((size_t)n * NOUT * sizeof(float)));      // displacements
     for (int32_t r0 = 0; r0 < n; r0 += CHUNK) {
         int m = n - r0 < CHUNK ? n - r0 : CHUNK;
-        hipLaunchKernelGGL(k_features, dim3(grid_for(m, 128)), dim3(128), 0, c->stream, n, r0, m, c->box, c->rc2,
+        hipLaunchKernelGGL(k_features, dim3(grid_for(m, FEAT_WPB)), dim3(64 * FEAT_WPB), 0, c->stream, n, r0, m, c->box,
+                           c->rc2,
                            (float)(1.0 / d.h), (float)p->center[0], (float)p->center[1], (float)p->center[2],
                            (float)p->radius, c->cell_start.as<int32_t>(), c->sorted.as<float4>(),
                            c->pos4.as<float4>(), c->ua.as<uint16_t>());
