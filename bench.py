@@ -89,7 +89,21 @@ def run_gpu(w, kappa, steps, warmup):
     nnz = ctx.nnz
     ctx.close()
     return {"ms": ms, "nnz": nnz, "ms_per_step": ms / steps, "launches": 2 * steps,
-            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3),
+            "vel_l2_err": tgv_velocity_error(w, d, m, (warmup + steps) * w.meta["dt"])}
+
+
+def tgv_velocity_error(w, drho, mom, t):
+    """Normwise relative L2 error of the velocity against the decaying 2-D
+    Taylor-Green solution u0 exp(-8 pi^2 nu t) (not timed)."""
+    import numpy as np
+    rho = 1.0 + drho.double().cpu().numpy()
+    u = mom.double().cpu().numpy() / rho
+    x = w.pos.astype(np.float64)
+    decay = np.exp(-8.0 * np.pi ** 2 * w.fields["nu"] * t)
+    ue = decay * np.stack([np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1]),
+                           -np.cos(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1])])
+    return float(np.linalg.norm(u - ue) / np.linalg.norm(ue))
 
 
 def run_euler_3d(nside, kappa, steps, warmup):
@@ -157,6 +171,37 @@ def run_plate(kappa, steps, warmup, nx=430):
     ctx.close()
     return {"n_particles": w.n, "nnz": nnz, "ms_per_step": ms / steps,
             "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+
+
+def plate_tip_history(kappa, steps, every, nx=430):
+    """Tip deflection (mean y displacement of the free-end layer) of the
+    cantilever plate every `every` kick-drift-kick steps (not timed)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    w = I.cantilever_plate(nx=nx)
+    f = w.fields
+    ctx = S.Context(3)
+    ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=(0, 0, 0)),
+                    torch.as_tensor(w.pos, device="cuda"))
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    prm = S.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=0)
+    pos = torch.as_tensor(w.pos, device="cuda").clone()
+    y0 = pos[1].clone()
+    vel = torch.as_tensor(f["vel"], device="cuda").clone()
+    F = torch.eye(3, device="cuda").repeat(w.n, 1, 1).contiguous()
+    fixed = torch.as_tensor(f["fixed"], device="cuda")
+    xmax = float(w.pos[0].max())
+    tip = torch.as_tensor(w.pos[0] > xmax - 0.5 * w.meta["dx"], device="cuda")
+    _, acc = ctx.tlsph_rhs(prm, vel, F, fixed)
+    hist = []
+    for _ in range(steps // every):
+        ctx.tlsph_step(prm, fixed, pos, vel, F, acc, every)
+        hist.append(float((pos[1] - y0)[tip].double().mean()))
+    ctx.close()
+    return np.array(hist)
 
 
 def run_cpu_baseline(w, kappa, budget_s):
@@ -304,6 +349,7 @@ def init_params(seed):
 
 
 def main():
+    import numpy as np
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
@@ -318,6 +364,8 @@ def main():
     ap.add_argument("--nside3d", type=int, default=200)
     ap.add_argument("--steps3d", type=int, default=50)
     ap.add_argument("--steps-plate", type=int, default=200)
+    ap.add_argument("--plate-accuracy-steps", type=int, default=2000,
+                    help="untimed TW-vs-SW tip-deflection history of the plate (0: skip)")
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
@@ -384,6 +432,9 @@ def main():
                    "nnz_1.6h": tw["nnz"], "nnz_2h": sw["nnz"]},
         "sw_2h": {"value": sw["interactions_per_s"], "ms_per_step": sw["ms_per_step"]},
         "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
+        "accuracy": {"t": (args.warmup + args.steps) * w.meta["dt"], "vel_l2_err_tw": tw["vel_l2_err"],
+                     "vel_l2_err_sw": sw["vel_l2_err"], "ratio_tw_over_sw": tw["vel_l2_err"] / sw["vel_l2_err"],
+                     "reference": "decaying Taylor-Green velocity u0 exp(-8 pi^2 nu t)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("2d"),
@@ -402,6 +453,13 @@ def main():
         twp, swp = run_plate(1.6, args.steps_plate, 5), run_plate(2.0, args.steps_plate, 5)
         out["tlsph_plate"] = {"kappa1.6": twp, "kappa2": swp,
                               "speedup_tw_over_sw": swp["ms_per_step"] / twp["ms_per_step"]}
+        if args.plate_accuracy_steps:
+            ht = plate_tip_history(1.6, args.plate_accuracy_steps, 100)
+            hs = plate_tip_history(2.0, args.plate_accuracy_steps, 100)
+            out["tlsph_plate"]["accuracy"] = {
+                "steps": args.plate_accuracy_steps, "tip_deflection_sw_final": float(hs[-1]),
+                "tip_deflection_tw_final": float(ht[-1]),
+                "tip_history_diff_over_sw_amplitude": float(np.abs(ht - hs).max() / np.abs(hs).max())}
     if not args.no_relax:
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:

@@ -139,7 +139,9 @@ int sph_gradient(sph_ctx* ctx, const float* f, float* grad);
  * limiter (Eqs. 26-27) posed along n = (r_j - r_i)/r (left state i), the
  * interface velocity v* = u* n + ((v_l+v_r)/2 - (u_l+u_r)/2 n) and density
  * rho* = rho0 + p* / c^2, EOS p = c^2 (rho - rho0) (Eq. 18), plus the viscous
- * term 2 mu sum_j V_j (v_i - v_j) (dW/dr)/r (Wendland kernel only).
+ * term 2 mu sum_j V_j c_ij (v_i - v_j) (dW/dr)/r with c_ij = (tr B_i + tr B_j)
+ * / (2 dim), the normalisation that makes the pair-sum Laplacian exact for
+ * quadratic fields on a lattice at either cut-off (Wendland kernel only).
  * State: drho = rho - rho_ref (FP32 [n]; storing the deviation keeps FP32
  * resolution for small density changes) and mom = rho v (FP32 [dim][n]). */
 typedef struct {

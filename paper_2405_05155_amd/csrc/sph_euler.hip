@@ -22,7 +22,7 @@ struct EulerArgs {
     float rho_ref;  // rho = rho_ref + drho
     float poff;     // rho_ref - rho0 (so p = c^2 (drho + poff))
     float eta_c;    // limiter coefficient / c
-    float mu4;      // 4 mu (multiplies (dW/dr)/r / 2)
+    float mu_tr;    // 2 mu / d (multiplies tr(B_i + B_j) V_j (dW/dr)/r / 2)
     float dt;
     float hinv, cFh; // Wendland (dW/dr)/r / 2 = cFh (1 - q/2)^3
     float L[3], invL[3];  // periodic lengths (invL = 0 on open axes)
@@ -172,7 +172,9 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
     const float m2V = -2.f * Vj;
     const float rvg = rhostar * vg;
     sr.add(m2V * rvg);
-    const float visc = ea.mu4 * Vj * Fh;  // 2 mu V (dW/dr)/r
+    // 2 mu c_ij V (dW/dr)/r, c_ij = tr(B_i + B_j) / (2d)
+    const float trB = DIM == 2 ? Bs[0] + Bs[2] : (Bs[0] + Bs[3]) + Bs[5];
+    const float visc = ea.mu_tr * trB * Vj * Fh;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) sm[a].add(fmaf(m2V, fmaf(rvg, vs[a], pstar * gc[a]), visc * (o.v[a] - vj[a])));
 }
@@ -444,7 +446,7 @@ __device__ __forceinline__ void pair_flux(const EulerArgs& ea, const float4* rec
         vg = fmaf(vs[c], gc[c], vg);
     }
     const float rvg = rhostar * vg;
-    const float visc = ea.mu4 * Fh;
+    const float visc = ea.mu_tr * (DIM == 2 ? Bs[0] + Bs[2] : (Bs[0] + Bs[3]) + Bs[5]) * Fh;
     float Q[4];
     Q[0] = -2.f * rvg;
 #pragma unroll
@@ -660,7 +662,7 @@ EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     a.rho_ref = (float)p->rho_ref;
     a.poff = (float)(p->rho_ref - p->rho0);
     a.eta_c = (float)(p->eta / p->c);
-    a.mu4 = (float)(4.0 * p->mu);
+    a.mu_tr = (float)(2.0 * p->mu / c->dim);
     a.dt = (float)p->dt;
     KernelConsts kc = make_kernel_consts(SPH_WENDLAND, c->dim, c->dom.h);
     a.hinv = kc.hinv;

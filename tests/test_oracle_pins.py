@@ -334,6 +334,51 @@ def test_euler_rhs_conserves_mass_and_momentum(kappa):
         assert abs(np.sum(V * dm[a])) < 1e-12 * np.sum(V * sm[a])
 
 
+@pytest.mark.parametrize("dim,kappa", [(2, 2.0), (2, 1.6), (3, 2.0), (3, 1.6)])
+def test_viscous_term_is_the_laplacian_of_quadratic_fields_on_a_lattice(dim, kappa):
+    """The viscous term with c_ij = (tr B_i + tr B_j)/(2d) equals mu lap(v) for
+    a quadratic velocity at interior lattice particles, at either cut-off.
+    The pair sum weighs the field's second derivatives by M_i of Eq. (9)
+    (-m I on a lattice, P-L3); without c_ij the term would be m mu lap(v),
+    m = 0.920 at 1.6h in 2-D."""
+    nside = 16
+    dx = 1.0 / nside
+    axis = (np.arange(nside) + 0.5) * dx
+    grids = np.meshgrid(*([axis] * dim), indexing="ij")
+    pos = np.stack([g.reshape(-1) for g in grids])
+    box = O.make_box(dim, periodic=(0,) * dim)
+    h = 1.3 * dx
+    rc = kappa * h
+    rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+    vol = np.full(pos.shape[1], dx ** dim)
+    B, ndeg = O.correction_B(box, pos, W, h, rp, col, vol)
+    assert ndeg == 0
+    x = pos.astype(np.float64)
+    rho = np.ones(pos.shape[1])
+    # v_x = 0.7 y^2 - 0.4 x y (+ 0.3 z^2), v_y = -1.1 x^2 (+ 0.5 x z), v_z = 0.9 y z
+    v = np.zeros_like(x)
+    v[0] = 0.7 * x[1] ** 2 - 0.4 * x[0] * x[1]
+    v[1] = -1.1 * x[0] ** 2
+    lap = [1.4, -2.2]
+    if dim == 3:
+        v[0] += 0.3 * x[2] ** 2
+        v[1] += 0.5 * x[0] * x[2]
+        v[2] = 0.9 * x[1] * x[2]
+        lap = [2.0, -2.2, 0.0]
+    mom = rho * v
+    out = []
+    for mu in (1.0, 0.0):
+        prm = O.euler_params(c=10.0, rho0=1.0, eta=15.0, mu=mu)
+        _, dm, _, _ = O.euler_rhs(box, pos, h, rp, col, vol, B, prm, rho, mom)
+        out.append(dm)
+    visc = out[0] - out[1]
+    margin = 2.0 * rc + dx
+    inner = np.all((x > margin) & (x < 1.0 - margin), axis=0)
+    assert inner.sum() > 0
+    for a in range(dim):
+        assert np.max(np.abs(visc[a, inner] - lap[a])) < 1e-9, (a, visc[a, inner][:4])
+
+
 def test_euler_rhs_uniform_state_is_steady():
     pos, dx, box = _lattice_box(32, 2)
     h = 1.3 * dx
