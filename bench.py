@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "115178f9f078daaa09d601910a77870ce1d4f9b80febfd394d67b9e012448729": {"2d": 39134147, "3d": 2206857136},
+    "f048b5fe74d1e9094a9eb60c1f4ca08f7346ff8f8fd025eb5732532fd46f01c8": {"2d": 39124444, "3d": 2204777786},
 }
 
 
