@@ -244,15 +244,23 @@ __global__ void __launch_bounds__(BLK) k_export_rows(int32_t n, const float4* __
     }
 }
 
-// Largest row length: a wave-level maximum, then one atomic per wave.
+// Largest row length: a grid-stride maximum per thread, a block maximum,
+// then one atomic per block.
 __global__ void k_row_max(int32_t n, const int32_t* __restrict__ cnt, int32_t* out) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t v = i < n ? cnt[i] : 0;
+    __shared__ int32_t wmax[BLK / 64];
+    int32_t v = 0;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v = max(v, cnt[i]);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, v);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLK / 64; ++w) v = max(v, wmax[w]);
+        atomicMax(out, v);
+    }
 }
 
+// colE[k n + i] = entry k of sorted row i (k < row length), else i
 __global__ void k_fill_ell(int32_t n, int32_t S, const int64_t* __restrict__ rp_s, const int32_t* __restrict__ col_s,
                            int32_t* __restrict__ colE) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,7 +282,8 @@ int sph_ell_prepare(sph_ctx* c) {
     }
     SPH_HIP(c, c->counter.ensure(64));
     SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_row_max, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->cnt_s.as<int32_t>(),
+    const unsigned gmax = grid_for(n, BLK) < 1024u ? grid_for(n, BLK) : 1024u;
+    hipLaunchKernelGGL(k_row_max, dim3(gmax), dim3(BLK), 0, c->stream, n, c->cnt_s.as<int32_t>(),
                        c->counter.as<int32_t>());
     SPH_LAUNCH_CHECK(c);
     int32_t S = 0;

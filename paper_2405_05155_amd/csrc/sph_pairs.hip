@@ -323,8 +323,9 @@ int to_sorted(sph_ctx* c, const float* src, DevBuf& dst) {
 }
 
 // Lanes per slot for the kernel-sum and correction loops: the most (up to 8)
-// that leave each lane at least four row entries.  Override SPH_PAIR_LANES =
-// 1, 2, 4 or 8.
+// that leave each lane at least eight row entries (measured on the 3-D
+// Taylor-Green lattice: rows of 32 entries run fastest on 4 lanes, rows of
+// 80 on 8; 2-D rows of 12 on one).  Override SPH_PAIR_LANES = 1, 2, 4 or 8.
 int pair_lanes(const sph_ctx* c) {
     if (const char* e = getenv("SPH_PAIR_LANES")) {
         const int v = atoi(e);
@@ -332,7 +333,7 @@ int pair_lanes(const sph_ctx* c) {
     }
     const double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
     int L = 1;
-    while (L < 8 && avg / (2 * L) >= 4.0) L <<= 1;
+    while (L < 8 && avg / (2 * L) >= 8.0) L <<= 1;
     return L;
 }
 
