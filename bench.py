@@ -229,6 +229,18 @@ def run_cpu_baseline(w, kappa, budget_s):
                       f"{dt:.1f} s)"}
 
 
+def run_cpu_one_core(kappa, budget_s):
+    """The same oracle leg on one host core, in a child process started with
+    OMP_NUM_THREADS=1 before this process touches the GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-only-json", "--cpu-budget", str(budget_s),
+                        "--kappa", str(kappa)], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def run_relax(epochs, nside=260):
     """Relaxation time-to-residue (R < 1e-4), plain vs learned warm start, on
     the sphere of radius 0.3 (dx = 1/nside; 1,987,776 particles at 260).
@@ -370,12 +382,23 @@ def main():
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
+    ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-one-core-budget", type=float, default=3.0,
+                    help="seconds of single-core oracle time (0: skip)")
     ap.add_argument("--setup", action="store_true", help="profile the set-up path only (binning, neighbours, "
                     "kernel sum, correction matrices)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("multi-GPU runs are not supported: the hot path runs on one GPU; use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_only_json:  # child of run_cpu_one_core: oracle only, no GPU
+        from paper_2405_05155_amd import inputs as I
+        print(json.dumps(run_cpu_baseline(I.taylor_green_2d(nside=args.nside), args.kappa or 1.6, args.cpu_budget)))
+        return
+    one_core = None
+    default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup)
+    if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
+        one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
 
     import torch
 
@@ -464,6 +487,8 @@ def main():
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = run_cpu_baseline(w, 1.6, args.cpu_budget)
+        if one_core is not None:
+            out["cpu_baseline"]["one_core"] = one_core
     print(json.dumps(out), flush=True)
 
 
