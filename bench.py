@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "f048b5fe74d1e9094a9eb60c1f4ca08f7346ff8f8fd025eb5732532fd46f01c8": {"2d": 39124444, "3d": 2204777786},
+    "f8a50d250aa99e57552a7bbad953b4843bfe4df93debff9fc27b7ac7e2e94ed6": {"2d": 39164696, "3d": 2208385169},
 }
 
 
