@@ -32,13 +32,13 @@ KernelConsts make_kernel_consts(int type, int dim, double h) {
     return k;
 }
 
-BoxArgs make_box_args(const sph_domain& d, double rc) {
+BoxArgs make_box_args(const sph_domain& d, double rc, int div, bool linear) {
     BoxArgs b{};
     b.dim = d.dim;
     for (int a = 0; a < 3; ++a) {
         if (a < d.dim) {
             double L = d.hi[a] - d.lo[a];
-            long long nc = (long long)std::floor(L / (rc * (1.0 + 1e-3)));
+            long long nc = (long long)std::floor(L / (rc / div * (1.0 + 1e-3)));
             if (nc < 1) nc = 1;
             b.lo[a] = (float)d.lo[a];
             b.L[a] = (float)L;
@@ -65,7 +65,7 @@ BoxArgs make_box_args(const sph_domain& d, double rc) {
         while (m < b.nc[a]) m <<= 1;
     double slots = 1.0;
     for (int a = 0; a < d.dim; ++a) slots *= m;
-    b.morton = (slots <= (double)(1 << 27) && m <= (d.dim == 2 ? 65536 : 1024)) ? 1 : 0;
+    b.morton = (!linear && slots <= (double)(1 << 27) && m <= (d.dim == 2 ? 65536 : 1024)) ? 1 : 0;
     return b;
 }
 

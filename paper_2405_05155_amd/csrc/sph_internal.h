@@ -238,6 +238,8 @@ int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
 
 // validate the domain and bin positions into cells (no neighbour list)
 int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos);
+// sph_bin_cells on cells at least kappa h / div wide, linear keys when `linear`
+int sph_bin_cells_grid(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos, int div, bool linear);
 
 // exclusive scan of int32 counts into int32 or int64 offsets, out[n] = total
 int sph_scan_i32_to_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
@@ -363,7 +365,9 @@ __device__ __forceinline__ float wendland_F(float q, float cF) {
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 KernelConsts make_kernel_consts(int type, int dim, double h);
-BoxArgs make_box_args(const sph_domain& d, double rc);
+// Cell grid of the box: cells at least rc / div wide; Morton keys unless
+// `linear` (or the Morton key space would be too large), else (z, y, x).
+BoxArgs make_box_args(const sph_domain& d, double rc, int div = 1, bool linear = false);
 int64_t cell_slots(const BoxArgs& b);  // size of the cell-key space
 
 // ------------------------------------------------------------------ pair-loop helpers

@@ -308,6 +308,10 @@ int sph_ell_prepare(sph_ctx* c) {
 // float4 records with the caller index in .w, and cell offsets).  Used by
 // sph_build_cells and, every iteration, by the relaxation.
 int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos) {
+    return sph_bin_cells_grid(c, dom, n, pos, 1, false);
+}
+
+int sph_bin_cells_grid(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos, int div, bool linear) {
     if (!c) return SPH_ERR_ARG;
     c->bound = false;
     c->geo_valid = false;
@@ -332,7 +336,7 @@ int sph_bin_cells(sph_ctx* c, const sph_domain* dom, int32_t n, const float* pos
                             "sph_build_cells: periodic axis %d of length %g is shorter than 3 kappa h (1+1e-3) = %g", a,
                             L, 3.0 * rc * (1.0 + 1e-3));
     }
-    BoxArgs b = make_box_args(*dom, rc);
+    BoxArgs b = make_box_args(*dom, rc, div, linear);
     int64_t ncell = cell_slots(b);
     if (ncell > (int64_t)1 << 30)
         return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: %lld cells exceed the table limit", (long long)ncell);

@@ -233,3 +233,23 @@ def test_train_epoch_matches_steps(S):
     assert np.array_equal(host(losses), np.array(ref, dtype=np.float32))
     assert np.array_equal(host(p1), host(p2)) and np.array_equal(host(m1), host(m2)) and np.array_equal(host(v1), host(v2))
     assert not np.array_equal(host(p1), theta)
+
+
+def test_training_calls_reject_bad_arguments(S):
+    """Checked on the host before anything is enqueued."""
+    ctx = S.Context(3)
+    p = dev(M.init_params(0))
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    X = torch.zeros((64, S.MLP_FEAT_STRIDE), dtype=torch.int16, device="cuda")
+    T = torch.zeros((64, 3), device="cuda")
+    rows = torch.arange(64, dtype=torch.int64, device="cuda")
+    with pytest.raises(S.SphError):  # an update needs step >= 1
+        ctx.mlp_train_step(S.adamw_params(), 0, p, m, v, X, T)
+    with pytest.raises(S.SphError):  # an epoch always updates: lr > 0
+        ctx.mlp_train_epoch(S.adamw_params(lr=0.0), 1, p, m, v, rows, X, T, 32)
+    with pytest.raises(S.SphError):
+        ctx.mlp_train_epoch(S.adamw_params(), 0, p, m, v, rows, X, T, 32)
+    assert np.array_equal(host(p), M.init_params(0))  # nothing ran
+    # an empty epoch (fewer rows than one batch) is a no-op
+    losses = ctx.mlp_train_epoch(S.adamw_params(), 1, p, m, v, rows[:10], X, T, 32)
+    assert losses.numel() == 0 and np.array_equal(host(p), M.init_params(0))
