@@ -729,6 +729,7 @@ bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
         if (E <= 2) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 2>(c, ea, io);
         else if (E == 3) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 3>(c, ea, io);
         else if (E == 4) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 4>(c, ea, io);
+        else if (E == 5) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 5>(c, ea, io);
         else return false;
     } else if (L == 8) {
         if (E <= 2) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 2>(c, ea, io);
@@ -742,11 +743,12 @@ bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
 }
 
 // Lanes per particle for the batched rows: 2 when six entries per lane
-// cover the row, else 4 when four do (measured on the 2-D Taylor-Green rows
-// of 12: 12.9 us per launch on 2 lanes, 13.7-14.3 on 4; the two lanes'
-// records take 110 VGPRs, but the per-particle work and the lane
-// combination are shared by half as many lanes; with 8 lanes the pipelined
-// loop is faster).
+// cover the row, else 4 when five do (measured on the 2-D Taylor-Green rows:
+// rows of 12 take 12.9 us per launch on 2 lanes, 13.7-14.3 on 4 -- the two
+// lanes' records take 110 VGPRs, but the per-particle work and the lane
+// combination are shared by half as many lanes; rows of 20 take 19.1 us on
+// 4 batched lanes against 20.6 pipelined; with 8 lanes the pipelined loop is
+// faster).
 // Batching serves configurations whose lane groups are too few to hide
 // memory latency with a pipeline (n <= 2^21).  Tuning override
 // SPH_EULER_BATCH_LANES = 2 (up to six entries per lane), 4 or 8; 0 turns
@@ -757,10 +759,11 @@ int batch_lanes(const sph_ctx* c) {
     if (forced == 0) return 0;
     if (c->ell_state != 1) return 0;
     if (forced == 2) return (c->ell_S + 1) / 2 <= 6 ? 2 : 0;
-    if (forced == 4 || forced == 8) return (c->ell_S + forced - 1) / forced <= 4 ? forced : 0;
+    if (forced == 4) return (c->ell_S + 3) / 4 <= 5 ? 4 : 0;
+    if (forced == 8) return (c->ell_S + 7) / 8 <= 4 ? 8 : 0;
     if (c->n > (1 << 21)) return 0;
     if ((c->ell_S + 1) / 2 <= 6) return 2;
-    if ((c->ell_S + 3) / 4 <= 4) return 4;
+    if ((c->ell_S + 3) / 4 <= 5) return 4;
     return 0;
 }
 

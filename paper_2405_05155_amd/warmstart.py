@@ -70,11 +70,12 @@ def relax_plain(ctx: S.Context, w: Workload, tol=1e-4, check_every=10, max_iter=
 
 
 def relax_warm(ctx: S.Context, w: Workload, params, tol=1e-4, check_every=10, every=20, max_iter=20000,
-               stop_mlp_below=0.0, max_rejects=2, reset_u=True):
+               stop_mlp_below=0.0, max_rejects=1, reset_u=True):
     """Plain relaxation with the learned move tried every `every` iterations
     (kept only if it lowers the residue; the carried displacement is reset
     after an accepted move).  After `max_rejects` consecutive rejections the
-    learned move is no longer tried."""
+    learned move is no longer tried (a try costs about a dozen iterations:
+    features, inference and two residue evaluations)."""
     dom, prm = setup(w)
     pos = torch.as_tensor(w.pos, device="cuda").clone()
     vol = torch.as_tensor(w.vol, device="cuda")
