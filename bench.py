@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "f8a50d250aa99e57552a7bbad953b4843bfe4df93debff9fc27b7ac7e2e94ed6": {"2d": 39164696, "3d": 2208385169},
+    "9bee081dee51b9dba1b7227a3f2ed1709e54f3d69e6e25ea5371bbfff4840f01": {"2d": 39164882, "3d": 2208371641},
 }
 
 
