@@ -434,6 +434,8 @@ def main():
     tw = run_gpu(w, 1.6, args.steps, args.warmup)
     sw = run_gpu(w, 2.0, args.steps, args.warmup)
 
+    from paper_2405_05155_amd.hbm_copy import copy_bandwidth
+    copy_gbs = copy_bandwidth() / 1e9
     launch_s = tw["ms"] * 1e-3 / tw["launches"]
     bytes_launch = stage_bytes_2d(w.n, tw["nnz"])
     achieved = bytes_launch / launch_s / 1e9
@@ -462,7 +464,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("2d"),
                      "kernel": "k_euler (2-D Heun stage, 1.6h)",
-                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch},
+                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch,
+                     "measured_copy_GBs": copy_gbs},
     }
     if not args.no_extra:
         tw3, sw3 = run_euler_3d(args.nside3d, 1.6, args.steps3d, 5), run_euler_3d(args.nside3d, 2.0, args.steps3d, 5)

@@ -2,10 +2,10 @@
 // kernel of Eq. 8) of particles filling a sphere, with the exterior-tail
 // term, an FP64 residue reduction and the damped move + surface bound.
 //
-// Per iteration: re-bin (cells of edge >= 2h, Morton-ordered keys), one
-// thread per particle in cell order scans the 3x3x3 cell block, a two-stage
-// reduction gives max|g| and the FP64 residue, then one thread per particle
-// moves it.
+// Per iteration: re-bin (cells of edge >= h, linear (z, y, x) keys), one
+// thread per particle in cell order scans the 5 x 5 x 5 cells around its own
+// as 25 contiguous x-runs, a two-stage reduction gives max|g| and the FP64
+// residue, then one thread per particle moves it.
 #include "sph_internal.h"
 
 #include <vector>
