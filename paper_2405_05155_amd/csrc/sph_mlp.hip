@@ -664,14 +664,19 @@ __device__ __forceinline__ int nth_set_lane(uint64_t m, int r) {
     return src;
 }
 
-// One wave per feature row (caller order, rows [r0, r0 + m)).  Lanes test 64
-// candidates of the 3x3x3 cell block at a time with the exact FP64 distance;
-// those within 2h (j != i) are compacted by a ballot into a 64-slot batch,
-// and each full batch is merged into the running 64 nearest (bitonic sort
-// and merge over lanes).  Lanes 0..31 then hold the 32 nearest by
-// (|r_ij|^2, j) and write the offsets (r_j - r_i)/h; then phi/h and grad phi;
-// features rounded to BF16, columns 100.. zero.
-constexpr int FEAT_WPB = 4;  // waves (rows) per block
+// One wave per feature row (caller order, rows [r0, r0 + m)).  The particles
+// are binned on cells at least h wide with linear (z, y, x) keys, so the
+// candidates within 2h lie in 25 (z, y) rows of five cells, each row one
+// contiguous slot range (a periodic x axis splits a row in two: lanes 25..49
+// hold the wrapped pieces).  Lanes test 64 candidates at a time with the
+// exact FP64 distance; those within 2h (j != i) are compacted by a ballot
+// into a 64-slot batch, and each full batch is merged into the running 64
+// nearest (bitonic sort and merge over lanes).  Lanes 0..31 then hold the 32
+// nearest by (|r_ij|^2, j) and write the offsets (r_j - r_i)/h; then phi/h
+// and grad phi; features rounded to BF16, columns 100.. zero.
+constexpr int FEAT_WPB = 4;   // waves (rows) per block
+constexpr int FEAT_DIV = 2;   // cells per 2h
+constexpr int FEAT_ROWS = (2 * FEAT_DIV + 1) * (2 * FEAT_DIV + 1);
 
 __global__ void __launch_bounds__(64 * FEAT_WPB) k_features(int32_t n, int32_t r0, int32_t m, BoxArgs b, double rc2,
                                                             float hinv, float cx, float cy, float cz, float R,
@@ -679,49 +684,71 @@ __global__ void __launch_bounds__(64 * FEAT_WPB) k_features(int32_t n, int32_t r
                                                             const float4* __restrict__ sorted,
                                                             const float4* __restrict__ pos4,
                                                             uint16_t* __restrict__ feat) {
+    constexpr int NR = 2 * FEAT_ROWS;  // ranges: the rows, then their wrapped pieces
     const int lane = (int)(threadIdx.x & 63);
     const int32_t k = (int32_t)blockIdx.x * FEAT_WPB + (int32_t)(threadIdx.x >> 6);
     if (k >= m) return;  // the whole wave
     const int32_t i = r0 + k;
     const float4 p = pos4[i];
-    // lane < 27: cell of the block and its slot range
+    // lane < NR: one slot range of the candidate block
     int32_t c0 = 0, cn = 0;
-    if (lane < 27) {
-        int x = fcoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]) + lane % 3 - 1;
-        int y = fcoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]) + (lane / 3) % 3 - 1;
-        int z = fcoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) + lane / 9 - 1;
+    if (lane < NR) {
+        const int r = lane % FEAT_ROWS, part = lane / FEAT_ROWS;
+        const int px = fcoord(p.x, b.lo[0], b.inv_cell[0], b.nc[0]);
+        int y = fcoord(p.y, b.lo[1], b.inv_cell[1], b.nc[1]) + r % (2 * FEAT_DIV + 1) - FEAT_DIV;
+        int z = fcoord(p.z, b.lo[2], b.inv_cell[2], b.nc[2]) + r / (2 * FEAT_DIV + 1) - FEAT_DIV;
         bool ok = true;
-        if (b.periodic[0]) x = x < 0 ? x + b.nc[0] : (x >= b.nc[0] ? x - b.nc[0] : x);
-        else ok = ok && x >= 0 && x < b.nc[0];
         if (b.periodic[1]) y = y < 0 ? y + b.nc[1] : (y >= b.nc[1] ? y - b.nc[1] : y);
         else ok = ok && y >= 0 && y < b.nc[1];
         if (b.periodic[2]) z = z < 0 ? z + b.nc[2] : (z >= b.nc[2] ? z - b.nc[2] : z);
         else ok = ok && z >= 0 && z < b.nc[2];
         if (ok) {
-            const int32_t key = cell_key(b, x, y, z);
-            c0 = cell_start[key];
-            cn = cell_start[key + 1] - c0;
+            const int nx = b.nc[0];
+            const int32_t row = (z * b.nc[1] + y) * nx;
+            int xa = px - FEAT_DIV, xb = px + FEAT_DIV, wa = 0, wb = -1;
+            if (b.periodic[0]) {  // nx >= 2 FEAT_DIV + 1: at most one side wraps
+                if (xa < 0) {
+                    wa = xa + nx;
+                    wb = nx - 1;
+                    xa = 0;
+                } else if (xb >= nx) {
+                    wa = 0;
+                    wb = xb - nx;
+                    xb = nx - 1;
+                }
+            } else {
+                xa = xa < 0 ? 0 : xa;
+                xb = xb > nx - 1 ? nx - 1 : xb;
+            }
+            if (part == 1) {
+                xa = wa;
+                xb = wb;
+            }
+            if (xb >= xa) {
+                c0 = cell_start[row + xa];
+                cn = cell_start[row + xb + 1] - c0;
+            }
         }
     }
     int32_t inc = cn;
 #pragma unroll
-    for (int d = 1; d < 32; d <<= 1) {
+    for (int d = 1; d < 64; d <<= 1) {
         const int32_t v = __shfl_up(inc, d, 64);
         if (lane >= d) inc += v;
     }
     const int32_t exc = inc - cn;
-    const int32_t total = __shfl(inc, 26, 64);
+    const int32_t total = __shfl(inc, NR - 1, 64);
     uint64_t ak = KEY_EMPTY, bk = KEY_EMPTY;
     int32_t aj = J_EMPTY, bj = J_EMPTY;
     int nb = 0;  // filled slots of the batch
     for (int32_t base = 0; base < total; base += 64) {
         const int32_t cidx = base + lane;
-        int cc = 0;
+        int cc = 0;  // the last range whose block starts at or before cidx
 #pragma unroll
-        for (int step = 16; step > 0; step >>= 1) {
+        for (int step = 32; step > 0; step >>= 1) {
             const int mid = cc + step;
-            const int32_t v = __shfl(exc, mid < 27 ? mid : 26, 64);
-            if (mid < 27 && v <= cidx) cc = mid;
+            const int32_t v = __shfl(exc, mid < NR ? mid : NR - 1, 64);
+            if (mid < NR && v <= cidx) cc = mid;
         }
         const int32_t t = __shfl(c0, cc, 64) + (cidx - __shfl(exc, cc, 64));
         bool in = false;
@@ -878,7 +905,7 @@ int sph_mlp_features(sph_ctx* c, const sph_domain* dom, const sph_relax_params* 
     sph_domain d = *dom;
     d.kernel = SPH_LAGUERRE_GAUSS;
     d.kappa = 2.0;
-    int r = sph_bin_cells(c, &d, n, pos);
+    int r = sph_bin_cells_grid(c, &d, n, pos, FEAT_DIV, true);
     if (r) return r;
     if (n == 0) return SPH_OK;
     hipLaunchKernelGGL(k_features, dim3(grid_for(n, FEAT_WPB)), dim3(64 * FEAT_WPB), 0, c->stream, n, 0, n, c->box, c->rc2,
@@ -943,7 +970,7 @@ int sph_mlp_apply(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, 
     sph_domain d = *dom;
     d.kernel = SPH_LAGUERRE_GAUSS;
     d.kappa = 2.0;
-    int r = sph_bin_cells(c, &d, n, pos);
+    int r = sph_bin_cells_grid(c, &d, n, pos, FEAT_DIV, true);
     if (r) return r;
     int rows = n < CHUNK ? n : CHUNK;
     SPH_HIP(c, c->ua.ensure((size_t)rows * FS * sizeof(uint16_t)));  // feature chunk
