@@ -25,6 +25,14 @@ struct EulerArgs {
     float mu_tr;    // 2 mu / d (multiplies tr(B_i + B_j) V_j (dW/dr)/r / 2)
     float dt;
     float hinv, cFh; // Wendland (dW/dr)/r / 2 = cFh (1 - q/2)^3
+    // per-particle kernel, which evaluates each pair with the factors that
+    // do not depend on the partner taken out of the row sums:
+    float nhh;              // -hinv / 2
+    float c2x2, c2x2poff;   // 2 c^2, 2 c^2 poff (2 p = 2 c^2 drho + 2 c^2 poff)
+    float nec;              // -eta / c
+    float qc2inv;           // 1 / (4 c^2)
+    float kmu;              // -4 mu / d
+    float fr, fm;           // row factors of the continuity and momentum sums: -cFh, -cFh / 2
     float L[3], invL[3];  // periodic lengths (invL = 0 on open axes)
     float lo[3];          // box corner
     float margin;         // a particle this far from every periodic face needs no wrap
@@ -102,14 +110,34 @@ struct OwnState {
     float x[3];
     float B[DIM == 2 ? 3 : 6];  // upper triangle of B
     float v[3];
-    float rho, p;
+    float p2;    // 2 p_i
+    float crho;  // c (rho_i + rho_ref): c (rho_i + rho_j) = crho + c drho_j
 };
 
+// A lane's partial sum of one row: a fused multiply-add into a plain FP32
+// sum where the lane takes at most 32 entries (error at most 31 ulp of the
+// sum of magnitudes, below the rounding of the terms themselves), a
+// compensated sum otherwise.
+template <bool COMP>
+__device__ __forceinline__ void accum(Kahan& k, float w, float x) {
+    if (COMP) k.add(w * x);
+    else k.s = fmaf(w, x, k.s);
+}
+
 // One pair (i, j) of Eq. (19) with the corrected gradient (Eq. 28) and the
-// limited Riemann solution (Eqs. 26-27), accumulated into the particle's
-// compensated sums.  Branch-free: a coincident partner (r = 0, also the
+// limited Riemann solution (Eqs. 26-27).  The factors that do not depend on
+// the partner are applied to the row sums afterwards: with
+// w = V_j (1 - q/2)^3, G = (B_i + B_j) d, d = x_i - x_j and the kernel's
+// (dW/dr)/r = cF (1 - q/2)^3,
+//   drho/dt  = -cF/2 sum_j w rho* (2 v* . G),
+//   dm/dt    = -cF/4 sum_j w [ rho* (2 v* . G) (2 v*) + 4 p* G
+//                             - 4 mu / d tr(B_i + B_j) (v_i - v_j) ],
+// the same terms as -2 V_j (rho* v* v* + p* I) (B_i + B_j)/2 grad W plus the
+// viscous pair term.  The Riemann problem is solved in doubled variables
+// (2 p, c (rho_i + rho_j), 2 (u* - mean), 4 p*) so that each step is one
+// fused multiply-add.  Branch-free: a coincident partner (r = 0, also the
 // particle itself standing in for a padding entry) gets zero weight.
-template <int DIM, bool WRAP>
+template <int DIM, bool WRAP, bool COMP>
 __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnState<DIM>& o, const NbrRec<DIM>& nb,
                                                 Kahan& sr, Kahan* sm) {
     constexpr int NBU = DIM == 2 ? 3 : 6;
@@ -123,63 +151,57 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
     }
     const float4 pj4 = nb.pr;
     const float xj[3] = {gj.x, gj.y, gj.z};
-    float d[DIM];
-    float r2 = 0.f;
+    const float vj[3] = {pj4.y, pj4.z, pj4.w};
+    float d[DIM], dv[DIM];
+    float r2 = 0.f, dvd = 0.f;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         d[a] = o.x[a] - xj[a];
         if (WRAP) d[a] = wrap(d[a], ea.L[a], ea.invL[a]);
         r2 = fmaf(d[a], d[a], r2);
+        dv[a] = o.v[a] - vj[a];
+        dvd = fmaf(dv[a], d[a], dvd);
     }
     const bool live = r2 > 0.f;
     const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
-    const float tq = fmaf(-0.5f * ea.hinv, r2 * rinv, 1.f);  // 1 - q/2
-    const float Fh = ea.cFh * tq * tq * tq;                   // (dW/dr)/r / 2
+    const float tq = fmaf(ea.nhh, r2 * rinv, 1.f);  // 1 - q/2
     const float Vj = live ? (DIM == 2 ? gj.z : gj.w) : 0.f;
-    // gc = (B_i + B_j)/2 grad W = Fh (B_i + B_j) d
-    float gc[DIM];
+    const float w = (Vj * tq) * (tq * tq);
+    float G[DIM];
     if (DIM == 2) {
-        gc[0] = Fh * fmaf(Bs[0], d[0], Bs[1] * d[1]);
-        gc[1] = Fh * fmaf(Bs[1], d[0], Bs[2] * d[1]);
+        G[0] = fmaf(Bs[0], d[0], Bs[1] * d[1]);
+        G[1] = fmaf(Bs[1], d[0], Bs[2] * d[1]);
     } else {
-        gc[0] = Fh * fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
-        gc[1] = Fh * fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
-        gc[2] = Fh * fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
+        G[0] = fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
+        G[1] = fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
+        G[2] = fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
     }
-    // Riemann problem along n = -d / r (from i to j), left = i, right = j
-    const float vj[3] = {pj4.y, pj4.z, pj4.w};
-    float dvd = 0.f;
+    // Riemann problem along n = -d / r (from i to j), left = i, right = j:
+    // a = u_r - u_l, beta = min(eta max(u_l - u_r, 0) / c, 1)
+    const float a = dvd * rinv;
+    const float beta = __builtin_amdgcn_fmed3f(ea.nec * a, 0.f, 1.f);
+    const float pj2 = fmaf(ea.c2x2, pj4.x, ea.c2x2poff);
+    const float crho = fmaf(ea.c, pj4.x, o.crho);
+    const float du2 = ((beta * beta) * (o.p2 - pj2)) * fast_rcp(crho);
+    const float p4 = fmaf(-(beta * crho), a, o.p2 + pj2);
+    const float rhostar = fmaf(p4, ea.qc2inv, ea.rho0);
+    // 2 v* = v_i + v_j + 2 (u* - mean) n
+    const float dn = du2 * rinv;
+    float vs2[DIM];
+    float vg2 = 0.f;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) dvd = fmaf(o.v[a] - vj[a], d[a], dvd);
-    const float du_lr = -dvd * rinv;  // u_l - u_r
-    const float rhoj = ea.rho_ref + pj4.x;
-    const float pj = ea.c2 * (pj4.x + ea.poff);
-    const float rhobar_c = 0.5f * ea.c * (o.rho + rhoj);
-    const float beta = fminf(ea.eta_c * fmaxf(du_lr, 0.f), 1.f);
-    const float hb = 0.5f * beta;
-    const float du = hb * beta * (o.p - pj) * fast_rcp(rhobar_c);  // u* - mean
-    const float pstar = fmaf(0.5f, o.p + pj, hb * rhobar_c * du_lr);
-    const float rhostar = fmaf(pstar, ea.c2inv, ea.rho0);
-    // v* = (v_i + v_j)/2 + (u* - mean) n
-    const float dun = -du * rinv;
-    float vs[DIM];
-    float vg = 0.f;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        vs[a] = fmaf(0.5f, o.v[a] + vj[a], dun * d[a]);
-        vg = fmaf(vs[a], gc[a], vg);
+    for (int a2 = 0; a2 < DIM; ++a2) {
+        vs2[a2] = fmaf(-dn, d[a2], o.v[a2] + vj[a2]);
+        vg2 = fmaf(vs2[a2], G[a2], vg2);
     }
-    const float m2V = -2.f * Vj;
-    const float rvg = rhostar * vg;
-    sr.add(m2V * rvg);
-    // 2 mu c_ij V (dW/dr)/r, c_ij = tr(B_i + B_j) / (2d)
+    const float rh = rhostar * vg2;
+    accum<COMP>(sr, w, rh);
     const float trB = DIM == 2 ? Bs[0] + Bs[2] : (Bs[0] + Bs[3]) + Bs[5];
-    const float visc = ea.mu_tr * trB * Vj * Fh;
+    const float kv = ea.kmu * trB;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) sm[a].add(fmaf(m2V, fmaf(rvg, vs[a], pstar * gc[a]), visc * (o.v[a] - vj[a])));
+    for (int a2 = 0; a2 < DIM; ++a2) accum<COMP>(sm[a2], w, fmaf(rh, vs2[a2], fmaf(p4, G[a2], kv * dv[a2])));
 }
 
-// Row layouts of the per-particle kernel.
 enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 
 // One lane group of L lanes per particle.  STAGE 0: write rates; 1: Uout =
@@ -188,7 +210,7 @@ enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 // records of the stage input: each particle's records are read and written
 // only by its own lane group, and neighbours are gathered from P, which a
 // stage never writes in place.  Lane `sub` of the group takes the row
-// entries sub, sub + L, ...; the compensated partial sums are combined by
+// entries sub, sub + L, ...; the lanes' partial sums are combined by
 // group_sum and lane 0 of the group writes the result.
 //   ROWS_CSR / ROWS_ELL: a software pipeline over the row: the records of
 //     the next entry are gathered and the column index after it loaded
@@ -211,6 +233,9 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     const int sub = (int)(t % L);
     // whole groups leave together (n * L is not always a multiple of the block)
     if (i >= n) return;
+    // compensated row sums on CSR rows, plain ones on fixed-stride rows
+    // (whose lane share is at most 32 entries)
+    constexpr bool COMP = MODE == ROWS_CSR;
 
     // batch mode: the lane's column indices first (they depend on nothing)
     int32_t jb[E > 0 ? E : 1];
@@ -244,9 +269,9 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
         }
     }
     const bool wrap_wave = __any(near);
-    o.rho = ea.rho_ref + pi4.x;
     o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
-    o.p = ea.c2 * (pi4.x + ea.poff);
+    o.p2 = fmaf(ea.c2x2, pi4.x, ea.c2x2poff);
+    o.crho = ea.c * ((ea.rho_ref + pi4.x) + ea.rho_ref);
     // the stage update's inputs, loaded now so that their latency overlaps the row
     float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
     if (STAGE != 0 && sub == 0) {
@@ -265,10 +290,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
         for (int q = 0; q < E; ++q) gather_nbr<DIM>(jb[q], geo0, geo1, geo2, P, nb[q]);
         if (wrap_wave) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true, COMP>(ea, o, nb[q], sr, sm);
         } else {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false, COMP>(ea, o, nb[q], sr, sm);
         }
     } else {
         int64_t k, e, stride;
@@ -291,15 +316,15 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
             gather_nbr<DIM>(jn, geo0, geo1, geo2, P, nxt);
             jn = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
-            if (wrap_wave) accumulate_pair<DIM, true>(ea, o, cur, sr, sm);
-            else accumulate_pair<DIM, false>(ea, o, cur, sr, sm);
+            if (wrap_wave) accumulate_pair<DIM, true, COMP>(ea, o, cur, sr, sm);
+            else accumulate_pair<DIM, false, COMP>(ea, o, cur, sr, sm);
             cur = nxt;
         }
     }
     float R[4];
-    R[0] = group_sum<L>(sr);
+    R[0] = ea.fr * group_sum<L>(sr);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) R[1 + a] = group_sum<L>(sm[a]);
+    for (int a = 0; a < DIM; ++a) R[1 + a] = ea.fm * group_sum<L>(sm[a]);
     if (DIM == 2) R[3] = 0.f;
     if (sub != 0) return;
     if (STAGE == 0) {
@@ -667,6 +692,14 @@ EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     KernelConsts kc = make_kernel_consts(SPH_WENDLAND, c->dim, c->dom.h);
     a.hinv = kc.hinv;
     a.cFh = 0.5f * kc.cF;
+    a.nhh = -0.5f * kc.hinv;
+    a.c2x2 = (float)(2.0 * p->c * p->c);
+    a.c2x2poff = (float)(2.0 * p->c * p->c * (p->rho_ref - p->rho0));
+    a.nec = (float)(-p->eta / p->c);
+    a.qc2inv = (float)(0.25 / (p->c * p->c));
+    a.kmu = (float)(-4.0 * p->mu / c->dim);
+    a.fr = (float)(-0.5 * (double)kc.cF);
+    a.fm = (float)(-0.25 * (double)kc.cF);
     for (int ax = 0; ax < 3; ++ax) {
         a.L[ax] = c->box.L[ax];
         a.invL[ax] = c->box.periodic[ax] ? (float)(1.0 / c->box.Ld[ax]) : 0.f;
@@ -709,9 +742,11 @@ void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
                        c->sorted.as<float4>(), io.dr, io.dm);
 }
 
+// Fixed-stride rows whose lane share exceeds 32 entries take the CSR loop
+// (and its compensated sums).
 template <int DIM, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    if (c->ell_state == 1) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
+    if (c->ell_state == 1 && (c->ell_S + L - 1) / L <= 32) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
     else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
 }
 
