@@ -87,11 +87,20 @@ struct NbrRec {
     float2 g2;
 };
 
-template <int DIM>
+// GA: 3-D geometry interleaved in geo0 (three float4 per particle), so that
+// the three geometry loads of a neighbour share its cache lines.
+template <int DIM, bool GA>
 __device__ __forceinline__ void gather_nbr(int32_t j, const float4* __restrict__ geo0,
                                            const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                            const float4* __restrict__ P, NbrRec<DIM>& r) {
     const uint32_t u = (uint32_t)j;
+    if (GA) {
+        r.g0 = ld32(geo0, 3u * u);
+        r.g1 = ld32(geo0, 3u * u + 1u);
+        r.g2 = ld32(reinterpret_cast<const float2*>(geo0), 6u * u + 4u);
+        r.pr = ld32(P, u);
+        return;
+    }
     r.g0 = ld32(geo0, u);
     if (DIM == 2) {
         const float2 t = ld32(reinterpret_cast<const float2*>(geo1), u);
@@ -219,7 +228,7 @@ enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 //     indices, then all records) and then evaluated (short rows, where a
 //     pipeline would be too shallow to cover the memory latency).
 // Entries past the end of a row use the particle itself (zero weight).
-template <int DIM, int STAGE, int L, int MODE, int E>
+template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
 __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
                                                const int32_t* __restrict__ col, int32_t ell_S,
                                                const float4* __restrict__ geo0,
@@ -249,7 +258,7 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
 
     OwnState<DIM> o;
     NbrRec<DIM> self;
-    gather_nbr<DIM>(i, geo0, geo1, geo2, P, self);
+    gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
     const float4 gi = self.g0;
     o.x[0] = gi.x; o.x[1] = gi.y; o.x[2] = gi.z;
     if (DIM == 2) {
@@ -287,7 +296,7 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     if (MODE == ROWS_ELL_BATCH) {
         NbrRec<DIM> nb[E > 0 ? E : 1];
 #pragma unroll
-        for (int q = 0; q < E; ++q) gather_nbr<DIM>(jb[q], geo0, geo1, geo2, P, nb[q]);
+        for (int q = 0; q < E; ++q) gather_nbr<DIM, GA>(jb[q], geo0, geo1, geo2, P, nb[q]);
         if (wrap_wave) {
 #pragma unroll
             for (int q = 0; q < E; ++q) accumulate_pair<DIM, true, COMP>(ea, o, nb[q], sr, sm);
@@ -309,11 +318,11 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
         NbrRec<DIM> cur, nxt;
         {
             const int32_t j0 = k < e ? col[k] : i;
-            gather_nbr<DIM>(j0, geo0, geo1, geo2, P, cur);
+            gather_nbr<DIM, GA>(j0, geo0, geo1, geo2, P, cur);
         }
         int32_t jn = k + L * stride < e ? col[k + L * stride] : i;
         while (k < e) {
-            gather_nbr<DIM>(jn, geo0, geo1, geo2, P, nxt);
+            gather_nbr<DIM, GA>(jn, geo0, geo1, geo2, P, nxt);
             jn = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
             if (wrap_wave) accumulate_pair<DIM, true, COMP>(ea, o, cur, sr, sm);
@@ -735,11 +744,18 @@ struct StageIO {
 template <int DIM, int STAGE, int L, int MODE, int E>
 void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     const bool ell = MODE != ROWS_CSR;
-    hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E>), dim3(grid_for((int64_t)c->n * L, BLK)), dim3(BLK), 0,
-                       c->stream, c->n, ea, ell ? nullptr : c->rp_s.as<int64_t>(),
-                       ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0, c->geo0.as<float4>(),
-                       c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout, io.Pout,
-                       c->sorted.as<float4>(), io.dr, io.dm);
+    const dim3 grid(grid_for((int64_t)c->n * L, BLK));
+    const int64_t* rp = ell ? nullptr : c->rp_s.as<int64_t>();
+    const int32_t* col = ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>();
+    const int32_t S = ell ? c->ell_S : 0;
+    if (DIM == 3 && c->geoA_gen == c->geo_gen)
+        hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E, DIM == 3>), grid, dim3(BLK), 0, c->stream, c->n, ea, rp,
+                           col, S, c->geoA.as<float4>(), nullptr, nullptr, io.U, io.P, io.U0, io.Uout, io.Pout,
+                           c->sorted.as<float4>(), io.dr, io.dm);
+    else
+        hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E, false>), grid, dim3(BLK), 0, c->stream, c->n, ea, rp,
+                           col, S, c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P,
+                           io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm);
 }
 
 // Fixed-stride rows whose lane share exceeds 32 entries take the CSR loop
@@ -907,6 +923,30 @@ void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, bool tiled) {
     }
 }
 
+__global__ void k_pack_geo3(int32_t n, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                            const float2* __restrict__ geo2, float4* __restrict__ geoA) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float2 t = geo2[i];
+    geoA[3 * i] = geo0[i];
+    geoA[3 * i + 1] = geo1[i];
+    geoA[3 * i + 2] = make_float4(t.x, t.y, 0.f, 0.f);
+}
+
+// 3-D: the interleaved copy of the geometry records the per-particle kernel
+// gathers from, packed once per cached correction (configurations whose
+// 48-byte records exceed 32-bit byte offsets keep the separate arrays).
+int prepare_geo3(sph_ctx* c) {
+    if (c->dim != 3 || c->n == 0 || c->geoA_gen == c->geo_gen) return SPH_OK;
+    if ((uint64_t)c->n * 3u * sizeof(float4) >= (1ull << 32)) return SPH_OK;
+    SPH_HIP(c, c->geoA.ensure((size_t)c->n * 3 * sizeof(float4)));
+    hipLaunchKernelGGL(k_pack_geo3, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->geo0.as<float4>(),
+                       c->geo1.as<float4>(), c->geo2.as<float2>(), c->geoA.as<float4>());
+    SPH_LAUNCH_CHECK(c);
+    c->geoA_gen = c->geo_gen;
+    return SPH_OK;
+}
+
 int pack(sph_ctx* c, float rho_ref, const float* drho, const float* mom, float4* U, float4* P) {
     if (c->dim == 2)
         hipLaunchKernelGGL(k_pack_state<2>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, rho_ref,
@@ -933,6 +973,7 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     bool tiled = false;
     r = prepare_tiles(c, &tiled);
     if (r) return r;
+    if (!tiled && (r = prepare_geo3(c))) return r;
     EulerArgs ea = make_args(c, p);
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
@@ -960,6 +1001,7 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     bool tiled = false;
     r = prepare_tiles(c, &tiled);
     if (r) return r;
+    if (!tiled && (r = prepare_geo3(c))) return r;
     EulerArgs ea = make_args(c, p);
     r = pack(c, ea.rho_ref, drho, mom, U, P);
     if (r) return r;

@@ -315,6 +315,7 @@ int sph_bin_cells_grid(sph_ctx* c, const sph_domain* dom, int32_t n, const float
     if (!c) return SPH_ERR_ARG;
     c->bound = false;
     c->geo_valid = false;
+    ++c->geo_gen;
     c->tiles.valid = false;
     c->tiles.failed = false;
     c->ell_state = 0;

@@ -447,6 +447,7 @@ int sph_correction_B(sph_ctx* c, const float* vol, float* B, double* B64, int32_
         SPH_HIP(c, hipStreamSynchronize(c->stream));
     }
     c->geo_valid = true;
+    ++c->geo_gen;
     return SPH_OK;
 }
 
@@ -468,6 +469,7 @@ int sph_set_correction(sph_ctx* c, const float* vol, const float* B) {
         SPH_LAUNCH_CHECK(c);
     }
     c->geo_valid = true;
+    ++c->geo_gen;
     return SPH_OK;
 }
 
