@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "9bee081dee51b9dba1b7227a3f2ed1709e54f3d69e6e25ea5371bbfff4840f01": {"2d": 39164882, "3d": 2208371641},
+    "bd75fe73e679e0fb458e009e8bc03abf4e4b4ac78652d7c740e0f5c9d51e91e7": {"2d": 39151185, "3d": 2246757267},
 }
 
 

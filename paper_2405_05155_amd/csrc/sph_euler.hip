@@ -10,6 +10,7 @@
 #include "sph_internal.h"
 
 #include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -935,8 +936,14 @@ __global__ void k_pack_geo3(int32_t n, const float4* __restrict__ geo0, const fl
 
 // 3-D: the interleaved copy of the geometry records the per-particle kernel
 // gathers from, packed once per cached correction (configurations whose
-// 48-byte records exceed 32-bit byte offsets keep the separate arrays).
+// 48-byte records exceed 32-bit byte offsets keep the separate arrays, and
+// so does the tuning override SPH_EULER_GEO=split).
 int prepare_geo3(sph_ctx* c) {
+    const char* e = getenv("SPH_EULER_GEO");
+    if (e && strcmp(e, "split") == 0) {
+        c->geoA_gen = ~0ull;
+        return SPH_OK;
+    }
     if (c->dim != 3 || c->n == 0 || c->geoA_gen == c->geo_gen) return SPH_OK;
     if ((uint64_t)c->n * 3u * sizeof(float4) >= (1ull << 32)) return SPH_OK;
     SPH_HIP(c, c->geoA.ensure((size_t)c->n * 3 * sizeof(float4)));
