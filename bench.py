@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "bd75fe73e679e0fb458e009e8bc03abf4e4b4ac78652d7c740e0f5c9d51e91e7": {"2d": 39151185, "3d": 2246757267},
+    "a996037778c9948e50de70492facf61bcd16f9901bd08d3ec43b7e5467db7387": {"2d": 39153376, "3d": 2246522758},
 }
 
 

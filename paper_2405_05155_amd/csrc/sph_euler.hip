@@ -229,37 +229,48 @@ enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 //     indices, then all records) and then evaluated (short rows, where a
 //     pipeline would be too shallow to cover the memory latency).
 // Entries past the end of a row use the particle itself (zero weight).
+// Batch mode: the column indices of a lane's E entries of row i.
+template <int L, int E>
+__device__ __forceinline__ void load_batch_cols(int32_t n, const int32_t* __restrict__ col, int32_t ell_S,
+                                                int32_t i, int sub, int32_t* jb) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int32_t kk = sub + q * L;
+        jb[q] = kk < ell_S ? ld32(col, (uint32_t)kk * (uint32_t)n + (uint32_t)i) : i;
+    }
+}
+
+// One particle's row for lane `sub` of its group (batch mode: the lane's
+// column indices in jb).  Every gather of the row is issued before the own
+// record is waited on.
 template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
-__global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
-                                               const int32_t* __restrict__ col, int32_t ell_S,
-                                               const float4* __restrict__ geo0,
-                                               const float4* __restrict__ geo1, const float2* __restrict__ geo2,
-                                               const float4* U, const float4* __restrict__ P, const float4* U0,
-                                               float4* Uout, float4* Pout, const float4* __restrict__ sorted,
-                                               float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
-    // i below is the cell-sorted slot; XCD-contiguous block order
-    const int64_t t = (int64_t)xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x) * blockDim.x + threadIdx.x;
-    const int32_t i = (int32_t)(t / L);
-    const int sub = (int)(t % L);
-    // whole groups leave together (n * L is not always a multiple of the block)
-    if (i >= n) return;
+__device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const int64_t* __restrict__ row_ptr,
+                                          const int32_t* __restrict__ col, int32_t ell_S,
+                                          const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+                                          const float2* __restrict__ geo2, const float4* U,
+                                          const float4* __restrict__ P, const float4* U0, float4* Uout,
+                                          float4* Pout, const float4* __restrict__ sorted,
+                                          float* __restrict__ drho_dt, float* __restrict__ dmom_dt, int32_t i,
+                                          int sub, const int32_t* jb) {
     // compensated row sums on CSR rows, plain ones on fixed-stride rows
     // (whose lane share is at most 32 entries)
     constexpr bool COMP = MODE == ROWS_CSR;
-
-    // batch mode: the lane's column indices first (they depend on nothing)
-    int32_t jb[E > 0 ? E : 1];
+    NbrRec<DIM> self;
+    gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
+    // batch mode: every record of the lane's entries in flight at once
+    NbrRec<DIM> nb[MODE == ROWS_ELL_BATCH && E > 0 ? E : 1];
     if (MODE == ROWS_ELL_BATCH) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int32_t kk = sub + q * L;
-            jb[q] = kk < ell_S ? ld32(col, (uint32_t)kk * (uint32_t)n + (uint32_t)i) : i;
-        }
+        for (int q = 0; q < E; ++q) gather_nbr<DIM, GA>(jb[q], geo0, geo1, geo2, P, nb[q]);
+    }
+    // the stage update's inputs, loaded now so that their latency overlaps the row
+    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
+    if (STAGE != 0 && sub == 0) {
+        ui = U[i];
+        if (STAGE == 2) u0 = U0[i];
     }
 
     OwnState<DIM> o;
-    NbrRec<DIM> self;
-    gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
     const float4 gi = self.g0;
     o.x[0] = gi.x; o.x[1] = gi.y; o.x[2] = gi.z;
     if (DIM == 2) {
@@ -282,12 +293,6 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
     o.p2 = fmaf(ea.c2x2, pi4.x, ea.c2x2poff);
     o.crho = ea.c * ((ea.rho_ref + pi4.x) + ea.rho_ref);
-    // the stage update's inputs, loaded now so that their latency overlaps the row
-    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
-    if (STAGE != 0 && sub == 0) {
-        ui = U[i];
-        if (STAGE == 2) u0 = U0[i];
-    }
 
     Kahan sr, sm[DIM];
     sr.init();
@@ -295,9 +300,6 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     for (int a = 0; a < DIM; ++a) sm[a].init();
 
     if (MODE == ROWS_ELL_BATCH) {
-        NbrRec<DIM> nb[E > 0 ? E : 1];
-#pragma unroll
-        for (int q = 0; q < E; ++q) gather_nbr<DIM, GA>(jb[q], geo0, geo1, geo2, P, nb[q]);
         if (wrap_wave) {
 #pragma unroll
             for (int q = 0; q < E; ++q) accumulate_pair<DIM, true, COMP>(ea, o, nb[q], sr, sm);
@@ -321,10 +323,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
             const int32_t j0 = k < e ? col[k] : i;
             gather_nbr<DIM, GA>(j0, geo0, geo1, geo2, P, cur);
         }
-        int32_t jn = k + L * stride < e ? col[k + L * stride] : i;
+        int32_t jn1 = k + L * stride < e ? col[k + L * stride] : i;
         while (k < e) {
-            gather_nbr<DIM, GA>(jn, geo0, geo1, geo2, P, nxt);
-            jn = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
+            gather_nbr<DIM, GA>(jn1, geo0, geo1, geo2, P, nxt);
+            jn1 = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
             if (wrap_wave) accumulate_pair<DIM, true, COMP>(ea, o, cur, sr, sm);
             else accumulate_pair<DIM, false, COMP>(ea, o, cur, sr, sm);
@@ -355,6 +357,26 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     }
     Uout[i] = un;
     Pout[i] = primitive<DIM>(un, ea.rho_ref);
+}
+
+// A lane group of L lanes per cell-sorted slot (blocks in XCD-contiguous
+// order; whole groups leave together).
+template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
+__global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col, int32_t ell_S,
+                                               const float4* __restrict__ geo0,
+                                               const float4* __restrict__ geo1, const float2* __restrict__ geo2,
+                                               const float4* U, const float4* __restrict__ P, const float4* U0,
+                                               float4* Uout, float4* Pout, const float4* __restrict__ sorted,
+                                               float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
+    const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int sub = (int)(threadIdx.x % L);
+    const int32_t i = blk * (BLK / L) + (int32_t)(threadIdx.x / L);
+    if (i >= n) return;
+    int32_t jb[E > 0 ? E : 1];
+    if (MODE == ROWS_ELL_BATCH) load_batch_cols<L, E>(n, col, ell_S, i, sub, jb);
+    euler_row<DIM, STAGE, L, MODE, E, GA>(n, ea, row_ptr, col, ell_S, geo0, geo1, geo2, U, P, U0, Uout, Pout,
+                                          sorted, drho_dt, dmom_dt, i, sub, jb);
 }
 
 // ------------------------------------------------------------------ tiled stage
@@ -745,7 +767,7 @@ struct StageIO {
 template <int DIM, int STAGE, int L, int MODE, int E>
 void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     const bool ell = MODE != ROWS_CSR;
-    const dim3 grid(grid_for((int64_t)c->n * L, BLK));
+    const dim3 grid(grid_for(c->n, BLK / L));
     const int64_t* rp = ell ? nullptr : c->rp_s.as<int64_t>();
     const int32_t* col = ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>();
     const int32_t S = ell ? c->ell_S : 0;
@@ -767,8 +789,9 @@ void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
 }
 
-// Batched short rows: L lanes per particle and E = ceil(S / L) <= 4 entries
-// per lane.  Returns false when the rows are too long for a batch.
+// Batched short rows: L lanes per particle and E = ceil(S / L) entries per
+// lane (at most 6, 5 or 4 for 2, 4 or 8 lanes).  Returns false when the rows
+// are too long for a batch.
 template <int DIM, int STAGE>
 bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
     const int E = (c->ell_S + L - 1) / L;

@@ -253,6 +253,44 @@ def test_euler_rhs_row_layouts(S, rows, kappa, monkeypatch):
     scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
 
 
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_euler_batched_rows_ragged(S, kappa):
+    """Batched short rows on a 64^2 lattice with 157 particles removed: 3,939
+    slots (a ragged last workgroup) and rows of 8-12 (1.6h) or 14-20 (2h)
+    entries, padded.  Rates and one Heun step (the stage kernels write the
+    state) against the oracle."""
+    w = I.taylor_green_2d(nside=64, nu=0.01)
+    keep = np.sort(np.random.default_rng(9).choice(w.n, w.n - 157, replace=False))
+    w.pos = np.ascontiguousarray(w.pos[:, keep])
+    w.vol = np.ascontiguousarray(w.vol[keep])
+    w.fields["drho"] = np.ascontiguousarray(w.fields["drho"][keep])
+    w.fields["mom"] = np.ascontiguousarray(w.fields["mom"][:, keep])
+    assert w.n == 3939
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    dt = w.meta["dt"]
+    pg, po = _euler_prm(S, w, dt)
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    assert np.diff(rp).max() <= (12 if kappa == 1.6 else 20)  # short rows: the batched kernel
+    drho0 = w.fields["drho"].astype(np.float64)
+    mom0 = w.fields["mom"].astype(np.float64)
+    rho0 = w.fields["rho_ref"] + drho0
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0)
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+    d = dev(w.fields["drho"])
+    m = dev(w.fields["mom"])
+    ctx.euler_step(pg, d, m, 1)
+    r1, m1 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0, 1)
+    eps = np.finfo(np.float32).eps
+    inc_g, inc_o = host(d) - drho0, (r1 - w.fields["rho_ref"]) - drho0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dr)
+                  + 4 * eps * np.abs(r1 - w.fields["rho_ref"]))
+    inc_g, inc_o = host(m) - mom0, m1 - mom0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(m1))
+
+
 def _mixed_box_3d(nside=24, seed=5):
     """Jittered 3-D lattice, periodic in x and z, open in y (free surfaces)."""
     w = I.taylor_green_3d(nside=nside)
