@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "a996037778c9948e50de70492facf61bcd16f9901bd08d3ec43b7e5467db7387": {"2d": 39153376, "3d": 2246522758},
+    "97fac2063251852088c02d352307034cfab744f07adc5b17001bb668822ff8ce": {"2d": 39153286, "3d": 2246535456},
 }
 
 
@@ -380,6 +380,7 @@ def main():
                     help="untimed TW-vs-SW tip-deflection history of the plate (0: skip)")
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
+    ap.add_argument("--plate", type=float, default=0.0, help="profile the TLSPH plate line only, at this cut-off")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
@@ -396,7 +397,8 @@ def main():
         print(json.dumps(run_cpu_baseline(I.taylor_green_2d(nside=args.nside), args.kappa or 1.6, args.cpu_budget)))
         return
     one_core = None
-    default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup)
+    default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup
+                       or args.plate)
     if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
         one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
 
@@ -423,6 +425,9 @@ def main():
         return
     if args.setup:
         print(json.dumps(run_setup()), flush=True)
+        return
+    if args.plate:
+        print(json.dumps({"kappa": args.plate, **run_plate(args.plate, args.steps_plate, 5)}), flush=True)
         return
     if args.train_steps:
         print(json.dumps(run_train(args.train_steps)), flush=True)

@@ -124,16 +124,6 @@ struct OwnState {
     float crho;  // c (rho_i + rho_ref): c (rho_i + rho_j) = crho + c drho_j
 };
 
-// A lane's partial sum of one row: a fused multiply-add into a plain FP32
-// sum where the lane takes at most 32 entries (error at most 31 ulp of the
-// sum of magnitudes, below the rounding of the terms themselves), a
-// compensated sum otherwise.
-template <bool COMP>
-__device__ __forceinline__ void accum(Kahan& k, float w, float x) {
-    if (COMP) k.add(w * x);
-    else k.s = fmaf(w, x, k.s);
-}
-
 // One pair (i, j) of Eq. (19) with the corrected gradient (Eq. 28) and the
 // limited Riemann solution (Eqs. 26-27).  The factors that do not depend on
 // the partner are applied to the row sums afterwards: with
@@ -785,7 +775,7 @@ void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
 // (and its compensated sums).
 template <int DIM, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    if (c->ell_state == 1 && (c->ell_S + L - 1) / L <= 32) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
+    if (c->ell_state == 1 && (c->ell_S + L - 1) / L <= PLAIN_SUM_MAX) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
     else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
 }
 

@@ -23,6 +23,7 @@ constexpr int BLK = 256;
 struct TlArgs {
     float lam, G, inv_rho0, dt, half_dt;
     float hinv, cF;
+    float nhh;  // -hinv / 2
     int model;
 };
 
@@ -110,7 +111,9 @@ __device__ __forceinline__ void load_B3(int32_t i, const float4* __restrict__ ge
     B[6] = t.z; B[7] = u.x; B[8] = u.y;
 }
 
-// (dW/dr)/r V_j and the reference separation X_i - X_j of one pair.
+// V_j (1 - q/2)^3 -- the Wendland (dW/dr)/r V_j = cF (1 - q/2)^3 V_j
+// without the prefactor cF, which the row sums take once -- and the
+// reference separation X_i - X_j of one pair.
 template <bool WRAP>
 __device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, const float4& gi, const float4& gj,
                                              float* d) {
@@ -122,20 +125,22 @@ __device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, con
         for (int a = 0; a < 3; ++a) d[a] = wrap1(d[a], w.L[a], w.invL[a]);
     }
     const float r2 = fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2]));
-    const float q = __builtin_amdgcn_sqrtf(r2) * t.hinv;
-    return wendland_F(q, t.cF) * gj.w;
+    const float tq = fmaf(t.nhh, __builtin_amdgcn_sqrtf(r2), 1.f);
+    return (gj.w * tq) * (tq * tq);
 }
 
-template <bool WRAP>
+// (v_j - v_i) (x) (X_i - X_j) V_j (1 - q/2)^3 into the nine row sums.
+template <bool WRAP, bool COMP>
 __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const float4& gi, const float4& vi,
                                       const float4& gj, const float4& vj, Kahan* L) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, gj, d);
-    const float dv[3] = {(vj.x - vi.x) * wt, (vj.y - vi.y) * wt, (vj.z - vi.z) * wt};
+    const float dv[3] = {vj.x - vi.x, vj.y - vi.y, vj.z - vi.z};
+    const float dw[3] = {wt * d[0], wt * d[1], wt * d[2]};
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) L[r * 3 + c].add(dv[r] * d[c]);
+        for (int c = 0; c < 3; ++c) accum<COMP>(L[r * 3 + c], dv[r], dw[c]);
 }
 
 // Kernel A (Eq. 32 and the stress of Eq. 30 / neo-Hookean).  One thread per
@@ -163,6 +168,8 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
     const float4 f0 = F0[i], f1 = F1[i];
     const float f2 = F2[i];
     const bool wrap = wave_needs_wrap(w, gi);
+    // compensated row sums on CSR rows, plain ones on fixed-stride rows
+    constexpr bool COMP = !ELL;
     Kahan L[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k].init();
@@ -175,14 +182,14 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
         const float4 gn = ld32(geo0, (uint32_t)jn), vn = ld32(VH, (uint32_t)jn);
         jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
         k += stride;
-        if (wrap) acc_a<true>(t, w, gi, vi, gj, vj, L);
-        else acc_a<false>(t, w, gi, vi, gj, vj, L);
+        if (wrap) acc_a<true, COMP>(t, w, gi, vi, gj, vj, L);
+        else acc_a<false, COMP>(t, w, gi, vi, gj, vj, L);
         gj = gn;
         vj = vn;
     }
     float Ld[9], Fd[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) Ld[q] = group_sum<LN>(L[q]);
+    for (int q = 0; q < 9; ++q) Ld[q] = t.cF * group_sum<LN>(L[q]);
     if (sub != 0) return;
     float B[9];
     load_B3(i, geo1, geo2, B);
@@ -233,15 +240,15 @@ __device__ __forceinline__ void gather_a(int32_t j, const float4* __restrict__ g
     r.a2 = ld32(A2, u);
 }
 
-template <bool WRAP>
+// V_j (1 - q/2)^3 (A_i + A_j)(X_i - X_j) into the three row sums.
+template <bool WRAP, bool COMP>
 __device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const float4& gi, const float* Ai,
                                       const ARec& b, Kahan* s) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, b.g, d);
-    const float g0 = wt * d[0], g1 = wt * d[1], g2 = wt * d[2];
-    s[0].add((Ai[0] + b.a0.x) * g0 + (Ai[1] + b.a0.y) * g1 + (Ai[2] + b.a0.z) * g2);
-    s[1].add((Ai[3] + b.a0.w) * g0 + (Ai[4] + b.a1.x) * g1 + (Ai[5] + b.a1.y) * g2);
-    s[2].add((Ai[6] + b.a1.z) * g0 + (Ai[7] + b.a1.w) * g1 + (Ai[8] + b.a2) * g2);
+    accum<COMP>(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])));
+    accum<COMP>(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])));
+    accum<COMP>(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])));
 }
 
 // Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
@@ -264,6 +271,8 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
     const float Ai[9] = {own.a0.x, own.a0.y, own.a0.z, own.a0.w, own.a1.x, own.a1.y, own.a1.z, own.a1.w, own.a2};
     const float4 vh = VH[i];
     const bool wrap = wave_needs_wrap(w, gi);
+    // compensated row sums on CSR rows, plain ones on fixed-stride rows
+    constexpr bool COMP = !ELL;
     Kahan s[3];
     s[0].init(); s[1].init(); s[2].init();
     int64_t k, e, stride;
@@ -275,12 +284,12 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
         gather_a(jn, geo0, A0, A1, A2, nxt);
         jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
         k += stride;
-        if (wrap) acc_b<true>(t, w, gi, Ai, cur, s);
-        else acc_b<false>(t, w, gi, Ai, cur, s);
+        if (wrap) acc_b<true, COMP>(t, w, gi, Ai, cur, s);
+        else acc_b<false, COMP>(t, w, gi, Ai, cur, s);
         cur = nxt;
     }
-    float a[3] = {group_sum<LN>(s[0]) * t.inv_rho0, group_sum<LN>(s[1]) * t.inv_rho0,
-                  group_sum<LN>(s[2]) * t.inv_rho0};
+    const float fa = t.cF * t.inv_rho0;
+    float a[3] = {group_sum<LN>(s[0]) * fa, group_sum<LN>(s[1]) * fa, group_sum<LN>(s[2]) * fa};
     if (sub != 0) return;
     const bool fixed = vh.w != 0.f;
     if (fixed) a[0] = a[1] = a[2] = 0.f;
@@ -369,6 +378,7 @@ TlArgs make_args(const sph_ctx* c, const sph_tlsph_params* p) {
     KernelConsts kc = make_kernel_consts(SPH_WENDLAND, 3, c->dom.h);
     t.hinv = kc.hinv;
     t.cF = kc.cF;
+    t.nhh = -0.5f * kc.hinv;
     t.model = p->model;
     return t;
 }
@@ -419,7 +429,9 @@ template <int MODE>
 void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
     const int LN = tl_lanes(c);
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
-    const bool ell = c->ell_state == 1;
+    // fixed-stride rows whose lane share exceeds PLAIN_SUM_MAX take the CSR
+    // loop (and its compensated sums)
+    const bool ell = c->ell_state == 1 && (c->ell_S + LN - 1) / LN <= PLAIN_SUM_MAX;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
                            ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
@@ -442,7 +454,9 @@ template <int MODE>
 void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
     const int LN = tl_lanes(c);
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
-    const bool ell = c->ell_state == 1;
+    // fixed-stride rows whose lane share exceeds PLAIN_SUM_MAX take the CSR
+    // loop (and its compensated sums)
+    const bool ell = c->ell_state == 1 && (c->ell_S + LN - 1) / LN <= PLAIN_SUM_MAX;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
                            ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
