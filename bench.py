@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "97fac2063251852088c02d352307034cfab744f07adc5b17001bb668822ff8ce": {"2d": 39153286, "3d": 2246535456},
+    "4a2603e11c8406475d11e16a729814970057f40a9980c45307e715b92e2f37dc": {"2d": 39162784, "3d": 2246543296},
 }
 
 

@@ -126,7 +126,7 @@ struct OwnState {
 
 // One pair (i, j) of Eq. (19) with the corrected gradient (Eq. 28) and the
 // limited Riemann solution (Eqs. 26-27).  The factors that do not depend on
-// the partner are applied to the row sums afterwards: with
+// the partner are applied to the compensated row sums afterwards: with
 // w = V_j (1 - q/2)^3, G = (B_i + B_j) d, d = x_i - x_j and the kernel's
 // (dW/dr)/r = cF (1 - q/2)^3,
 //   drho/dt  = -cF/2 sum_j w rho* (2 v* . G),
@@ -137,7 +137,7 @@ struct OwnState {
 // (2 p, c (rho_i + rho_j), 2 (u* - mean), 4 p*) so that each step is one
 // fused multiply-add.  Branch-free: a coincident partner (r = 0, also the
 // particle itself standing in for a padding entry) gets zero weight.
-template <int DIM, bool WRAP, bool COMP>
+template <int DIM, bool WRAP>
 __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnState<DIM>& o, const NbrRec<DIM>& nb,
                                                 Kahan& sr, Kahan* sm) {
     constexpr int NBU = DIM == 2 ? 3 : 6;
@@ -195,11 +195,11 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
         vg2 = fmaf(vs2[a2], G[a2], vg2);
     }
     const float rh = rhostar * vg2;
-    accum<COMP>(sr, w, rh);
+    accum(sr, w, rh);
     const float trB = DIM == 2 ? Bs[0] + Bs[2] : (Bs[0] + Bs[3]) + Bs[5];
     const float kv = ea.kmu * trB;
 #pragma unroll
-    for (int a2 = 0; a2 < DIM; ++a2) accum<COMP>(sm[a2], w, fmaf(rh, vs2[a2], fmaf(p4, G[a2], kv * dv[a2])));
+    for (int a2 = 0; a2 < DIM; ++a2) accum(sm[a2], w, fmaf(rh, vs2[a2], fmaf(p4, G[a2], kv * dv[a2])));
 }
 
 enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
@@ -242,9 +242,6 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
                                           float4* Pout, const float4* __restrict__ sorted,
                                           float* __restrict__ drho_dt, float* __restrict__ dmom_dt, int32_t i,
                                           int sub, const int32_t* jb) {
-    // compensated row sums on CSR rows, plain ones on fixed-stride rows
-    // (whose lane share is at most 32 entries)
-    constexpr bool COMP = MODE == ROWS_CSR;
     NbrRec<DIM> self;
     gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
     // batch mode: every record of the lane's entries in flight at once
@@ -292,10 +289,10 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
     if (MODE == ROWS_ELL_BATCH) {
         if (wrap_wave) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true, COMP>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true>(ea, o, nb[q], sr, sm);
         } else {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false, COMP>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false>(ea, o, nb[q], sr, sm);
         }
     } else {
         int64_t k, e, stride;
@@ -318,8 +315,8 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
             gather_nbr<DIM, GA>(jn1, geo0, geo1, geo2, P, nxt);
             jn1 = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
-            if (wrap_wave) accumulate_pair<DIM, true, COMP>(ea, o, cur, sr, sm);
-            else accumulate_pair<DIM, false, COMP>(ea, o, cur, sr, sm);
+            if (wrap_wave) accumulate_pair<DIM, true>(ea, o, cur, sr, sm);
+            else accumulate_pair<DIM, false>(ea, o, cur, sr, sm);
             cur = nxt;
         }
     }
@@ -771,11 +768,9 @@ void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
                            io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm);
 }
 
-// Fixed-stride rows whose lane share exceeds 32 entries take the CSR loop
-// (and its compensated sums).
 template <int DIM, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    if (c->ell_state == 1 && (c->ell_S + L - 1) / L <= PLAIN_SUM_MAX) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
+    if (c->ell_state == 1) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
     else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
 }
 

@@ -267,18 +267,8 @@ struct Kahan {
     __device__ __forceinline__ double value64() const { return (double)s - (double)c; }
 };
 
-// A lane's partial sum of one row: a fused multiply-add into a plain FP32
-// sum where the lane takes at most 32 entries (error at most 31 ulp of the
-// sum of magnitudes, below the rounding of the terms themselves), a
-// compensated sum otherwise.
-template <bool COMP>
-__device__ __forceinline__ void accum(Kahan& k, float w, float x) {
-    if (COMP) k.add(w * x);
-    else k.s = fmaf(w, x, k.s);
-}
-
-// Longest lane share of a fixed-stride row that takes plain sums.
-constexpr int PLAIN_SUM_MAX = 32;
+// w x into a lane's compensated partial sum of one row.
+__device__ __forceinline__ void accum(Kahan& k, float w, float x) { k.add(w * x); }
 
 // Combine the compensated partial sums held by the L lanes of an aligned
 // lane group (xor butterfly; every lane ends with the same value).  Each

@@ -129,8 +129,8 @@ __device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, con
     return (gj.w * tq) * (tq * tq);
 }
 
-// (v_j - v_i) (x) (X_i - X_j) V_j (1 - q/2)^3 into the nine row sums.
-template <bool WRAP, bool COMP>
+// (v_j - v_i) (x) (X_i - X_j) V_j (1 - q/2)^3 into the nine compensated row sums.
+template <bool WRAP>
 __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const float4& gi, const float4& vi,
                                       const float4& gj, const float4& vj, Kahan* L) {
     float d[3];
@@ -140,7 +140,7 @@ __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const floa
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) accum<COMP>(L[r * 3 + c], dv[r], dw[c]);
+        for (int c = 0; c < 3; ++c) accum(L[r * 3 + c], dv[r], dw[c]);
 }
 
 // Kernel A (Eq. 32 and the stress of Eq. 30 / neo-Hookean).  One thread per
@@ -168,8 +168,6 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
     const float4 f0 = F0[i], f1 = F1[i];
     const float f2 = F2[i];
     const bool wrap = wave_needs_wrap(w, gi);
-    // compensated row sums on CSR rows, plain ones on fixed-stride rows
-    constexpr bool COMP = !ELL;
     Kahan L[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) L[k].init();
@@ -182,8 +180,8 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
         const float4 gn = ld32(geo0, (uint32_t)jn), vn = ld32(VH, (uint32_t)jn);
         jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
         k += stride;
-        if (wrap) acc_a<true, COMP>(t, w, gi, vi, gj, vj, L);
-        else acc_a<false, COMP>(t, w, gi, vi, gj, vj, L);
+        if (wrap) acc_a<true>(t, w, gi, vi, gj, vj, L);
+        else acc_a<false>(t, w, gi, vi, gj, vj, L);
         gj = gn;
         vj = vn;
     }
@@ -240,15 +238,15 @@ __device__ __forceinline__ void gather_a(int32_t j, const float4* __restrict__ g
     r.a2 = ld32(A2, u);
 }
 
-// V_j (1 - q/2)^3 (A_i + A_j)(X_i - X_j) into the three row sums.
-template <bool WRAP, bool COMP>
+// V_j (1 - q/2)^3 (A_i + A_j)(X_i - X_j) into the three compensated row sums.
+template <bool WRAP>
 __device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const float4& gi, const float* Ai,
                                       const ARec& b, Kahan* s) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, b.g, d);
-    accum<COMP>(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])));
-    accum<COMP>(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])));
-    accum<COMP>(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])));
+    accum(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])));
+    accum(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])));
+    accum(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])));
 }
 
 // Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
@@ -271,8 +269,6 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
     const float Ai[9] = {own.a0.x, own.a0.y, own.a0.z, own.a0.w, own.a1.x, own.a1.y, own.a1.z, own.a1.w, own.a2};
     const float4 vh = VH[i];
     const bool wrap = wave_needs_wrap(w, gi);
-    // compensated row sums on CSR rows, plain ones on fixed-stride rows
-    constexpr bool COMP = !ELL;
     Kahan s[3];
     s[0].init(); s[1].init(); s[2].init();
     int64_t k, e, stride;
@@ -284,8 +280,8 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
         gather_a(jn, geo0, A0, A1, A2, nxt);
         jn = k + 2 * stride < e ? col[k + 2 * stride] : i;
         k += stride;
-        if (wrap) acc_b<true, COMP>(t, w, gi, Ai, cur, s);
-        else acc_b<false, COMP>(t, w, gi, Ai, cur, s);
+        if (wrap) acc_b<true>(t, w, gi, Ai, cur, s);
+        else acc_b<false>(t, w, gi, Ai, cur, s);
         cur = nxt;
     }
     const float fa = t.cF * t.inv_rho0;
@@ -429,9 +425,7 @@ template <int MODE>
 void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
     const int LN = tl_lanes(c);
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
-    // fixed-stride rows whose lane share exceeds PLAIN_SUM_MAX take the CSR
-    // loop (and its compensated sums)
-    const bool ell = c->ell_state == 1 && (c->ell_S + LN - 1) / LN <= PLAIN_SUM_MAX;
+    const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
                            ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
@@ -454,9 +448,7 @@ template <int MODE>
 void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
     const int LN = tl_lanes(c);
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
-    // fixed-stride rows whose lane share exceeds PLAIN_SUM_MAX take the CSR
-    // loop (and its compensated sums)
-    const bool ell = c->ell_state == 1 && (c->ell_S + LN - 1) / LN <= PLAIN_SUM_MAX;
+    const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, g, bl, 0, c->stream, c->n, t, w, ell ? nullptr : c->rp_s.as<int64_t>(),
                            ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>(), ell ? c->ell_S : 0,
