@@ -30,18 +30,57 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM traffic per launch of the stage kernel measured with rocprofv3
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors read off a plain 256 MiB copy),
-# keyed by the SHA-256 of the kernel source it was measured on: a changed
-# kernel reports null until it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
+# keyed by the SHA-256 of the code of the stage kernel's sources (comments and
+# blank lines dropped) it was measured on: a changed kernel reports null until
+# it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "4a2603e11c8406475d11e16a729814970057f40a9980c45307e715b92e2f37dc": {"2d": 39162784, "3d": 2246543296},
+    "cb9d7c287b91c99c7ccdd7213f19ea0b9cb2654aeb945397ec62d9a04b6145c3": {"2d": 39162784, "3d": 2246543296},
 }
 
 
-def source_sha(rel: str) -> str:
+def _code_lines(text: str):
+    """The lines of a C++ source without // comments, trailing blanks and
+    empty lines (string literals are kept whole)."""
+    out = []
+    for line in text.splitlines():
+        keep, in_str, k = [], False, 0
+        while k < len(line):
+            ch = line[k]
+            if in_str:
+                keep.append(ch)
+                if ch == "\\" and k + 1 < len(line):
+                    keep.append(line[k + 1])
+                    k += 1
+                elif ch == '"':
+                    in_str = False
+            elif ch == '"':
+                in_str = True
+                keep.append(ch)
+            elif line.startswith("//", k):
+                break
+            else:
+                keep.append(ch)
+            k += 1
+        code = "".join(keep).rstrip()
+        if code:
+            out.append(code)
+    return out
+
+
+def source_sha(*rels: str) -> str:
+    """SHA-256 of the code (comments and blank lines dropped) of the given
+    sources, in order."""
     import hashlib
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for rel in rels:
+        with open(os.path.join(ROOT, rel)) as f:
+            h.update("\n".join(_code_lines(f.read())).encode())
+        h.update(b"\0")
+    return h.hexdigest()
+
+
+STAGE_SOURCES = ("paper_2405_05155_amd/csrc/sph_euler.hip", "paper_2405_05155_amd/csrc/sph_internal.h")
 
 
 def stage_bytes_3d(n: int, nnz: int) -> float:
@@ -467,7 +506,7 @@ def main():
                      "reference": "decaying Taylor-Green velocity u0 exp(-8 pi^2 nu t)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("2d"),
+                     "traffic": TRAFFIC.get(source_sha(*STAGE_SOURCES), {}).get("2d"),
                      "kernel": "k_euler (2-D Heun stage, 1.6h)",
                      "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch,
                      "measured_copy_GBs": copy_gbs},
@@ -478,7 +517,7 @@ def main():
                                   "speedup_tw_over_sw": sw3["ms_per_step"] / tw3["ms_per_step"]}
         out["roofline_3d"] = {"bound": "hbm", "achieved": tw3["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": tw3["achieved_GBs"] / HBM_PEAK_GBS,
-                              "traffic": TRAFFIC.get(source_sha("paper_2405_05155_amd/csrc/sph_euler.hip"), {}).get("3d"),
+                              "traffic": TRAFFIC.get(source_sha(*STAGE_SOURCES), {}).get("3d"),
                               "kernel": "k_euler (3-D Heun stage, 1.6h, 200^3)",
                               "avg_launch_us": tw3["avg_launch_us"], "bytes_per_launch": tw3["bytes_per_launch"]}
         twp, swp = run_plate(1.6, args.steps_plate, 5), run_plate(2.0, args.steps_plate, 5)

@@ -204,21 +204,6 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
 
 enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 
-// One lane group of L lanes per particle.  STAGE 0: write rates; 1: Uout =
-// U + dt R(U); 2: Uout = (U0 + U + dt R(U)) / 2; stages 1 and 2 also write
-// Pout, the primitive record of Uout.  Uout / Pout may alias U0 / the own
-// records of the stage input: each particle's records are read and written
-// only by its own lane group, and neighbours are gathered from P, which a
-// stage never writes in place.  Lane `sub` of the group takes the row
-// entries sub, sub + L, ...; the lanes' partial sums are combined by
-// group_sum and lane 0 of the group writes the result.
-//   ROWS_CSR / ROWS_ELL: a software pipeline over the row: the records of
-//     the next entry are gathered and the column index after it loaded
-//     before the current pair is evaluated.
-//   ROWS_ELL_BATCH: the lane's E entries are loaded at once (all column
-//     indices, then all records) and then evaluated (short rows, where a
-//     pipeline would be too shallow to cover the memory latency).
-// Entries past the end of a row use the particle itself (zero weight).
 // Batch mode: the column indices of a lane's E entries of row i.
 template <int L, int E>
 __device__ __forceinline__ void load_batch_cols(int32_t n, const int32_t* __restrict__ col, int32_t ell_S,
@@ -346,8 +331,22 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
     Pout[i] = primitive<DIM>(un, ea.rho_ref);
 }
 
-// A lane group of L lanes per cell-sorted slot (blocks in XCD-contiguous
-// order; whole groups leave together).
+// One lane group of L lanes per particle.  STAGE 0: write rates; 1: Uout =
+// U + dt R(U); 2: Uout = (U0 + U + dt R(U)) / 2; stages 1 and 2 also write
+// Pout, the primitive record of Uout.  Uout / Pout may alias U0 / the own
+// records of the stage input: each particle's records are read and written
+// only by its own lane group, and neighbours are gathered from P, which a
+// stage never writes in place.  Lane `sub` of the group takes the row
+// entries sub, sub + L, ...; the lanes' partial sums are combined by
+// group_sum and lane 0 of the group writes the result.
+//   ROWS_CSR / ROWS_ELL: a software pipeline over the row: the records of
+//     the next entry are gathered and the column index after it loaded
+//     before the current pair is evaluated.
+//   ROWS_ELL_BATCH: the lane's E entries are loaded at once (all column
+//     indices, then all records) and then evaluated (short rows, where a
+//     pipeline would be too shallow to cover the memory latency).
+// Entries past the end of a row use the particle itself (zero weight).
+// Blocks run in XCD-contiguous order; whole groups leave together.
 template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
 __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
                                                const int32_t* __restrict__ col, int32_t ell_S,
