@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "cb9d7c287b91c99c7ccdd7213f19ea0b9cb2654aeb945397ec62d9a04b6145c3": {"2d": 39162784, "3d": 2246543296},
+    "fffbe6e999a34949c8d22a79277459965bef2930b37731653d0bc798e8e9c071": {"2d": 39159375, "3d": 2246421978},
 }
 
 
@@ -100,7 +100,7 @@ def stage_bytes_2d(n: int, nnz: int) -> float:
     return 60.0 * n + 4.0 * nnz
 
 
-def run_gpu(w, kappa, steps, warmup):
+def run_gpu(w, kappa, steps, warmup, tgv=True):
     import torch
 
     from paper_2405_05155_amd import sph as S
@@ -127,9 +127,16 @@ def run_gpu(w, kappa, steps, warmup):
     ms = e0.elapsed_time(e1)
     nnz = ctx.nnz
     ctx.close()
-    return {"ms": ms, "nnz": nnz, "ms_per_step": ms / steps, "launches": 2 * steps,
-            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3),
-            "vel_l2_err": tgv_velocity_error(w, d, m, (warmup + steps) * w.meta["dt"])}
+    out = {"ms": ms, "nnz": nnz, "ms_per_step": ms / steps, "launches": 2 * steps,
+           "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
+    if tgv:
+        out["vel_l2_err"] = tgv_velocity_error(w, d, m, (warmup + steps) * w.meta["dt"])
+    return out
+
+
+def run_gpu_plain(w, kappa, steps, warmup):
+    """run_gpu without the Taylor-Green error (any 2-D periodic workload)."""
+    return run_gpu(w, kappa, steps, warmup, tgv=False)
 
 
 def tgv_velocity_error(w, drho, mom, t):
@@ -143,6 +150,77 @@ def tgv_velocity_error(w, drho, mom, t):
     ue = decay * np.stack([np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1]),
                            -np.cos(2 * np.pi * x[0]) * np.sin(2 * np.pi * x[1])])
     return float(np.linalg.norm(u - ue) / np.linalg.norm(ue))
+
+
+def run_shear(nside, kappa, t_marks=(0.8, 1.2)):
+    """Double shear layer (Sec. 4.2) from t = 0 to each of t_marks: time per
+    Heun step (HIP events over the whole run) and, at each mark, the
+    velocity field and the kinetic energy (not timed)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    w = I.double_shear_layer(nside=nside)
+    f = w.fields
+    ctx = S.Context(2)
+    ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa), torch.as_tensor(w.pos, device="cuda"))
+    ctx.neighbors()
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    dt = w.meta["dt"]
+    prm = S.euler_params(c=f["c"], rho0=f["rho0_eos"], rho_ref=f["rho_ref"], eta=f["eta"], mu=f["mu"], dt=dt)
+    d = torch.as_tensor(f["drho"], device="cuda").clone()
+    m = torch.as_tensor(f["mom"], device="cuda").clone()
+    vol = w.vol.astype(np.float64)
+
+    def energy_and_velocity():
+        rho = 1.0 + d.double().cpu().numpy()
+        u = m.double().cpu().numpy() / rho
+        return float(0.5 * np.sum(rho * (u ** 2).sum(0) * vol)), u
+
+    ke0, _ = energy_and_velocity()
+    # untimed warm-up on copies (first launches, row preparation)
+    ctx.euler_step(prm, d.clone(), m.clone(), 5)
+    stream = torch.cuda.current_stream()
+    done, ms, marks = 0, 0.0, []
+    for t in t_marks:
+        steps = int(round(t / dt)) - done
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.euler_step(prm, d, m, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        done += steps
+        ke, u = energy_and_velocity()
+        marks.append({"t": done * dt, "ke_over_ke0": ke / ke0, "u": u})
+    nnz = ctx.nnz
+    ctx.close()
+    return {"n_particles": w.n, "nnz": nnz, "steps": done, "ms_per_step": ms / done,
+            "interactions_per_s": 2.0 * nnz * done / (ms * 1e-3), "marks": marks}
+
+
+def shear_layer_section(nside=128, nside_big=1024, steps_big=400):
+    """TW against SW on the double shear layer: the paper's resolution run
+    to t = 0.8 and 1.2 (time per step, kinetic energy, velocity difference
+    between the two runs), and the time per step at nside_big^2."""
+    import numpy as np
+    from paper_2405_05155_amd import inputs as I
+    tw, sw = run_shear(nside, 1.6), run_shear(nside, 2.0)
+    out = {"nside": nside, "steps": tw["steps"], "ms_per_step_tw": tw["ms_per_step"],
+           "ms_per_step_sw": sw["ms_per_step"], "alpha_gpu": tw["ms_per_step"] / sw["ms_per_step"],
+           "alpha_paper_cpu": 17.83 / 29.99, "marks": []}
+    for a, b in zip(tw["marks"], sw["marks"]):
+        out["marks"].append({"t": a["t"], "ke_over_ke0_tw": a["ke_over_ke0"], "ke_over_ke0_sw": b["ke_over_ke0"],
+                             "vel_rel_diff_tw_sw": float(np.linalg.norm(a["u"] - b["u"]) / np.linalg.norm(b["u"]))})
+    w = I.double_shear_layer(nside=nside_big)
+    big = {k: run_gpu_plain(w, k, steps_big, 10) for k in (1.6, 2.0)}
+    out["large"] = {"nside": nside_big, "steps": steps_big, "ms_per_step_tw": big[1.6]["ms_per_step"],
+                    "ms_per_step_sw": big[2.0]["ms_per_step"],
+                    "alpha_gpu": big[1.6]["ms_per_step"] / big[2.0]["ms_per_step"],
+                    "interactions_per_s_tw": big[1.6]["interactions_per_s"]}
+    return out
 
 
 def run_euler_3d(nside, kappa, steps, warmup):
@@ -420,6 +498,7 @@ def main():
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--plate", type=float, default=0.0, help="profile the TLSPH plate line only, at this cut-off")
+    ap.add_argument("--shear", action="store_true", help="the double shear layer section only")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
@@ -437,7 +516,7 @@ def main():
         return
     one_core = None
     default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup
-                       or args.plate)
+                       or args.plate or args.shear)
     if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
         one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
 
@@ -467,6 +546,9 @@ def main():
         return
     if args.plate:
         print(json.dumps({"kappa": args.plate, **run_plate(args.plate, args.steps_plate, 5)}), flush=True)
+        return
+    if args.shear:
+        print(json.dumps(shear_layer_section()), flush=True)
         return
     if args.train_steps:
         print(json.dumps(run_train(args.train_steps)), flush=True)
@@ -530,6 +612,7 @@ def main():
                 "steps": args.plate_accuracy_steps, "tip_deflection_sw_final": float(hs[-1]),
                 "tip_deflection_tw_final": float(ht[-1]),
                 "tip_history_diff_over_sw_amplitude": float(np.abs(ht - hs).max() / np.abs(hs).max())}
+        out["double_shear_layer"] = shear_layer_section()
     if not args.no_relax:
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:

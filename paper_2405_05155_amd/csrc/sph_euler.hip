@@ -807,7 +807,10 @@ bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
 // lanes' records take 110 VGPRs, but the per-particle work and the lane
 // combination are shared by half as many lanes; rows of 20 take 19.1 us on
 // 4 batched lanes against 20.6 pipelined; with 8 lanes the pipelined loop is
-// faster).
+// faster).  Below 2^15 particles two lanes give fewer than 1,024 waves and
+// a launch lasts as long as its slowest wave: four lanes then (128^2 rows of
+// 12: 7.3 us per Heun step on 4 lanes, 8.5 on 2; from 256^2 on, 2 lanes
+// are faster).
 // Batching serves configurations whose lane groups are too few to hide
 // memory latency with a pipeline (n <= 2^21).  Tuning override
 // SPH_EULER_BATCH_LANES = 2 (up to six entries per lane), 4 or 8; 0 turns
@@ -821,7 +824,7 @@ int batch_lanes(const sph_ctx* c) {
     if (forced == 4) return (c->ell_S + 3) / 4 <= 5 ? 4 : 0;
     if (forced == 8) return (c->ell_S + 7) / 8 <= 4 ? 8 : 0;
     if (c->n > (1 << 21)) return 0;
-    if ((c->ell_S + 1) / 2 <= 6) return 2;
+    if ((c->ell_S + 1) / 2 <= 6 && (c->n >= (1 << 15) || (c->ell_S + 3) / 4 > 5)) return 2;
     if ((c->ell_S + 3) / 4 <= 5) return 4;
     return 0;
 }

@@ -156,6 +156,24 @@ def taylor_green_2d(nside: int = 512, c: float = 10.0, nu: float = 0.01) -> Work
     return w
 
 
+def double_shear_layer(nside: int = 128, c: float = 10.0, width: float = 1.0 / 30.0,
+                       delta: float = 0.05) -> Workload:
+    """Doubly periodic shear layer in the unit square, inviscid (Sec. 4.2):
+    exact lattice, h = 1.3 dx,
+    u_x = tanh((y - 1/4)/width) for y <= 1/2, tanh((3/4 - y)/width) above,
+    u_y = delta sin(2 pi x); uniform density rho = 1 (uniform pressure)."""
+    w = periodic_square_case(nside, 2, 1.3, 0.0, None, f"double_shear_layer_{nside}")
+    x = w.pos.astype(np.float64)
+    ux = np.where(x[1] <= 0.5, np.tanh((x[1] - 0.25) / width), np.tanh((0.75 - x[1]) / width))
+    uy = delta * np.sin(2 * np.pi * x[0])
+    drho = np.zeros(w.n)
+    mom = np.stack([ux, uy])
+    w.fields = {"rho_ref": 1.0, "drho": drho.astype(np.float32), "mom": mom.astype(np.float32),
+                "c": c, "rho0_eos": 1.0, "eta": 15.0, "mu": 0.0, "nu": 0.0}
+    w.meta["dt"] = 0.6 * w.h / (c + 1.0)
+    return w
+
+
 def taylor_green_3d(nside: int = 200, c: float = 10.0, nu: float = 0.01) -> Workload:
     """3-D Taylor-Green field in the periodic unit cube, exact lattice,
     h = 1.3 dx; u = sin cos cos, v = -cos sin cos, w = 0,

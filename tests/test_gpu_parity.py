@@ -229,13 +229,15 @@ def test_euler_heun_steps_taylor_green(S, kappa, tiling):
     assert normwise(host(d), r100 - 1.0) < 1e-3
 
 
-@pytest.mark.parametrize("rows", ["batch4", "batch8", "ell", "csr"])
+@pytest.mark.parametrize("rows", ["batch2", "batch4", "batch8", "ell", "csr"])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 def test_euler_rhs_row_layouts(S, rows, kappa, monkeypatch):
     """Each row layout of the per-particle kernel against the oracle: short
-    rows batched per lane (4 or 8 lanes per particle), the pipelined loop
-    over fixed-stride rows and over the CSR rows."""
-    env = {"batch4": {"SPH_EULER_BATCH_LANES": "4"}, "batch8": {"SPH_EULER_BATCH_LANES": "8"},
+    rows batched per lane (2, 4 or 8 lanes per particle; 2 lanes only where
+    six entries per lane cover the row), the pipelined loop over fixed-stride
+    rows and over the CSR rows."""
+    env = {"batch2": {"SPH_EULER_BATCH_LANES": "2"}, "batch4": {"SPH_EULER_BATCH_LANES": "4"},
+           "batch8": {"SPH_EULER_BATCH_LANES": "8"},
            "ell": {"SPH_EULER_BATCH_LANES": "0"},
            "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_PAIR_ROWS": "csr"}}[rows]
     for k, v in env.items():
@@ -253,12 +255,16 @@ def test_euler_rhs_row_layouts(S, rows, kappa, monkeypatch):
     scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
 
 
+@pytest.mark.parametrize("lanes", ["auto", "2"])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-def test_euler_batched_rows_ragged(S, kappa):
+def test_euler_batched_rows_ragged(S, kappa, lanes, monkeypatch):
     """Batched short rows on a 64^2 lattice with 157 particles removed: 3,939
     slots (a ragged last workgroup) and rows of 8-12 (1.6h) or 14-20 (2h)
-    entries, padded.  Rates and one Heun step (the stage kernels write the
-    state) against the oracle."""
+    entries, padded; lanes per particle as chosen for this size (four) or
+    two (the large-launch choice for rows of up to 12).  Rates and one Heun
+    step (the stage kernels write the state) against the oracle."""
+    if lanes != "auto":
+        monkeypatch.setenv("SPH_EULER_BATCH_LANES", lanes)
     w = I.taylor_green_2d(nside=64, nu=0.01)
     keep = np.sort(np.random.default_rng(9).choice(w.n, w.n - 157, replace=False))
     w.pos = np.ascontiguousarray(w.pos[:, keep])
@@ -289,6 +295,53 @@ def test_euler_batched_rows_ragged(S, kappa):
                   + 4 * eps * np.abs(r1 - w.fields["rho_ref"]))
     inc_g, inc_o = host(m) - mom0, m1 - mom0
     assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(m1))
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_double_shear_layer(S, kappa):
+    """Double shear layer (inviscid, Sec. 4.2) at the paper's 128^2: rates
+    against the oracle element by element; 50 Heun steps to the per-step
+    bar; the full run to t = 1.2 (2,166 steps) through integral quantities.
+    Without viscosity the limiter damps only approaching pairs, and the run
+    amplifies rounding-level differences: two FP64 oracle runs whose initial
+    momenta differ by 1e-7 (relative) end ~10% apart in the momentum field
+    but within ~1e-3 in kinetic energy.  So at t = 1.2: total mass and
+    momentum conserved (the pair fluxes are antisymmetric) and the kinetic
+    energy within 5e-3 of the oracle's."""
+    w = I.double_shear_layer(nside=128)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    dt = w.meta["dt"]
+    pg, po = _euler_prm(S, w, dt)
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    V = w.vol.astype(np.float64)
+    drho0 = w.fields["drho"].astype(np.float64)
+    mom0 = w.fields["mom"].astype(np.float64)
+    rho0 = w.fields["rho_ref"] + drho0
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0)
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+    d = dev(w.fields["drho"])
+    m = dev(w.fields["mom"])
+    ctx.euler_step(pg, d, m, 50)
+    r50, m50 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho0, mom0, 50)
+    assert normwise(host(m), m50) < 1e-5
+    assert normwise(host(d), r50 - w.fields["rho_ref"]) < 1e-3  # drho itself is ~1e-3: 1e-6 of rho
+    steps = int(round(1.2 / dt))
+    ctx.euler_step(pg, d, m, steps - 50)
+    r1, m1 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, r50, m50, steps - 50)
+    rg = w.fields["rho_ref"] + host(d).astype(np.float64)
+    mg = host(m).astype(np.float64)
+    scale_m = np.sum(np.abs(mom0).sum(0) * V)
+    mass_drift = abs(np.sum(rg * V) - np.sum(rho0 * V)) / np.sum(rho0 * V)
+    mom_drift = np.abs(mg @ V - mom0 @ V).max() / scale_m
+    ke = lambda r, mm: 0.5 * np.sum((mm ** 2).sum(0) / r * V)
+    ke_diff = abs(ke(rg, mg) - ke(r1, m1)) / ke(r1, m1)
+    print(f"kappa {kappa}: mass drift {mass_drift:.3g}, momentum drift {mom_drift:.3g}, "
+          f"KE/KE0 {ke(rg, mg) / ke(rho0, mom0):.4f} (oracle {ke(r1, m1) / ke(rho0, mom0):.4f}), KE diff {ke_diff:.3g}")
+    assert mass_drift < 1e-6 and mom_drift < 1e-6
+    assert ke_diff < 5e-3
 
 
 def _mixed_box_3d(nside=24, seed=5):
