@@ -45,6 +45,10 @@ class EulerParams(C.Structure):
                 ("mu", C.c_double), ("dt", C.c_double)]
 
 
+class HllcParams(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("eta", C.c_double), ("dt", C.c_double)]
+
+
 class TlsphParams(C.Structure):
     _fields_ = [("rho0", C.c_double), ("E", C.c_double), ("nu", C.c_double),
                 ("dt", C.c_double), ("model", C.c_int)]
@@ -81,6 +85,9 @@ def lib():
         L.or_gradient.argtypes = [vp, i64, vp, i32, d, i64, vp, vp, vp, vp, vp, vp, vp]
         L.or_euler_rhs.argtypes = [vp, i64, vp, d, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_euler_heun.argtypes = [vp, i64, vp, d, vp, vp, vp, vp, vp, vp, vp, i64]
+        L.or_hllc_interface.argtypes = [i32, vp, d, d, d, vp, d, d, vp, d, vp, vp, vp, vp]
+        L.or_hllc_rhs.argtypes = [vp, i64, vp, d, i64] + [vp] * 15
+        L.or_hllc_heun.argtypes = [vp, i64, vp, d, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.or_tlsph_stress.argtypes = [i32, vp, vp, vp]
         L.or_tlsph_rhs.argtypes = [vp, i64, vp, d, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_tlsph_step.argtypes = [vp, i64, vp, d, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64]
@@ -226,6 +233,46 @@ def euler_heun(box, pos, h, row_ptr, col, vol, B, prm, rho, mom, nsteps):
     lib().or_euler_heun(C.byref(box), pos.shape[1], _p(pos), h, _p(row_ptr), _p(col), _p(vol), _p(B),
                         C.byref(prm), _p(rho), _p(mom), int(nsteps))
     return rho, mom
+
+
+def hllc_params(gamma=1.4, eta=1.0, dt=0.0) -> HllcParams:
+    p = HllcParams()
+    p.gamma, p.eta, p.dt = gamma, eta, dt
+    return p
+
+
+def hllc_interface(nrm, prm, rho_l, v_l, p_l, rho_r, v_r, p_r):
+    """Interface state (rho, v [d], p, E) of one pair's limited HLLC problem
+    along the unit vector nrm (left state l, right state r)."""
+    nrm, v_l, v_r = _f64(nrm), _f64(v_l), _f64(v_r)
+    dim = nrm.shape[0]
+    rI, pI, EI = C.c_double(), C.c_double(), C.c_double()
+    vI = np.zeros(dim)
+    lib().or_hllc_interface(dim, _p(nrm), prm.gamma, prm.eta, float(rho_l), _p(v_l), float(p_l),
+                            float(rho_r), _p(v_r), float(p_r), C.byref(rI), _p(vI), C.byref(pI), C.byref(EI))
+    return rI.value, vI, pI.value, EI.value
+
+
+def hllc_rhs(box, pos, h, row_ptr, col, vol, B, prm, rho, mom, E, rows=None):
+    """Compressible rates: returns (drho [m], dmom [d][m], dE [m], scale_rho,
+    scale_mom, scale_E); rho the density, mom = rho v [d][n], E the total
+    energy per unit volume, B full [n][d][d]."""
+    pos, vol, B, rho, mom, E = _f64(pos), _f64(vol), _f64(B), _f64(rho), _f64(mom), _f64(E)
+    n, d = pos.shape[1], box.dim
+    r, m = _rows(rows, n)
+    dr, dm, de = np.empty(m), np.empty((d, m)), np.empty(m)
+    sr, sm, se = np.empty(m), np.empty((d, m)), np.empty(m)
+    lib().or_hllc_rhs(C.byref(box), n, _p(pos), h, m, _p(r), _p(row_ptr), _p(col), _p(vol), _p(B),
+                      C.byref(prm), _p(rho), _p(mom), _p(E), _p(dr), _p(dm), _p(de), _p(sr), _p(sm), _p(se))
+    return dr, dm, de, sr, sm, se
+
+
+def hllc_heun(box, pos, h, row_ptr, col, vol, B, prm, rho, mom, E, nsteps):
+    pos, vol, B = _f64(pos), _f64(vol), _f64(B)
+    rho, mom, E = _f64(rho).copy(), _f64(mom).copy(), _f64(E).copy()
+    lib().or_hllc_heun(C.byref(box), pos.shape[1], _p(pos), h, _p(row_ptr), _p(col), _p(vol), _p(B),
+                       C.byref(prm), _p(rho), _p(mom), _p(E), int(nsteps))
+    return rho, mom, E
 
 
 def tlsph_params(rho0, E, nu, dt=0.0, model=0) -> TlsphParams:

@@ -588,6 +588,190 @@ void or_euler_heun(const or_box* b, int64_t n, const double* pos, double h,
 }
 
 /* ------------------------------------------------------------------ */
+/* Eulerian compressible SPH: limited HLLC, energy row, ideal gas      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double gamma;   /* ideal gas: p = (gamma - 1) (E - rho |v|^2 / 2), E per unit volume */
+    double eta;     /* limiter coefficient of the HLLC limiter (1 in the paper) */
+    double dt;      /* time step of the Heun integrator */
+} or_hllc_params;
+
+/* Interface state of one pair's Riemann problem along the unit vector nrm
+ * (left state l = particle i, right state r = particle j), Sec. 3.1:
+ *   wave speeds S_l = u_l - c_l, S_r = u_r + c_r (Eq. 24), c = sqrt(gamma p / rho);
+ *   the limited middle state
+ *     u* = (rho_l c_l u_l + rho_r c_r u_r) / (rho_l c_l + rho_r c_r)
+ *          + beta^2 (p_l - p_r) / (rho_l c_l + rho_r c_r),
+ *     p* = (p_l + p_r)/2 + beta/2 [rho_r c_r (u* - u_r) + rho_l c_l (u_l - u*)],
+ *     beta = min(eta max((u_l - u_r) / cbar, 0), 1), cbar = (c_l + c_r)/2;
+ *   (the printed bracket has a minus between its terms; the plus makes p*
+ *   the mean of Eq. (25)'s two expressions p_l + rho_l c_l (u_l - u*) and
+ *   p_r + rho_r c_r (u* - u_r), and gives the linearised solver's
+ *   (p_l + p_r)/2 + beta rho c (u_l - u_r)/2 for equal impedances; with the
+ *   minus a head-on collision would raise no pressure);
+ *   the HLLC star states (Eq. 25) with the normal velocities u_K where the
+ *   printed formulas show |v_K|:
+ *     rho*_K = rho_K (S_K - u_K) / (S_K - u*),
+ *     E*_K   = ((S_K - u_K) E_K - p_K u_K + p* u*) / (S_K - u*),
+ *     v*     = u* n + ((v_l + v_r)/2 - (u_l + u_r)/2 n).
+ * Where the two estimates cross (a pair approaching faster than c_l + c_r)
+ * the fan is bracketed by S_l = min(u_l - c_l, u_r - c_r) and
+ * S_r = max(u_l + c_l, u_r + c_r) instead (Davis's estimates; mirror
+ * symmetric like the printed ones).
+ * The interface (the pair's midpoint) does not move: the state there is the
+ * left state if S_l >= 0, the right state if S_r <= 0, else the left star
+ * state if u* >= 0 and the right star state otherwise.
+ * Outputs rhoI, vI[dim], pI, EI.  Pinned: equal states give the state back;
+ * a supersonic pair gives the upwind state; with beta = 0 the middle state
+ * is the impedance-weighted mean velocity and the mean pressure; the state
+ * is the same with l and r swapped and nrm reversed (conservation). */
+void or_hllc_interface(int dim, const double* nrm, double gamma, double eta,
+                       double rho_l, const double* v_l, double p_l,
+                       double rho_r, const double* v_r, double p_r,
+                       double* rhoI, double* vI, double* pI, double* EI)
+{
+    double ul = 0.0, ur = 0.0, kl = 0.0, kr = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        ul += v_l[a] * nrm[a];
+        ur += v_r[a] * nrm[a];
+        kl += v_l[a] * v_l[a];
+        kr += v_r[a] * v_r[a];
+    }
+    double El = p_l / (gamma - 1.0) + 0.5 * rho_l * kl;
+    double Er = p_r / (gamma - 1.0) + 0.5 * rho_r * kr;
+    double cl = sqrt(gamma * p_l / rho_l), cr = sqrt(gamma * p_r / rho_r);
+    double Sl = ul - cl, Sr = ur + cr;
+    if (Sl > Sr) {  /* approach faster than c_l + c_r: the estimates cross */
+        Sl = fmin(ul - cl, ur - cr);
+        Sr = fmax(ul + cl, ur + cr);
+    }
+    if (Sl >= 0.0) {
+        *rhoI = rho_l; *pI = p_l; *EI = El;
+        for (int a = 0; a < dim; ++a) vI[a] = v_l[a];
+        return;
+    }
+    if (Sr <= 0.0) {
+        *rhoI = rho_r; *pI = p_r; *EI = Er;
+        for (int a = 0; a < dim; ++a) vI[a] = v_r[a];
+        return;
+    }
+    double zl = rho_l * cl, zr = rho_r * cr;
+    double cbar = 0.5 * (cl + cr);
+    double beta = eta * fmax((ul - ur) / cbar, 0.0);
+    if (beta > 1.0) beta = 1.0;
+    double us = (zl * ul + zr * ur) / (zl + zr) + beta * beta * (p_l - p_r) / (zl + zr);
+    double ps = 0.5 * (p_l + p_r) + 0.5 * beta * (zr * (us - ur) + zl * (ul - us));
+    for (int a = 0; a < dim; ++a) vI[a] = us * nrm[a] + (0.5 * (v_l[a] + v_r[a]) - 0.5 * (ul + ur) * nrm[a]);
+    *pI = ps;
+    if (us >= 0.0) {
+        *rhoI = rho_l * (Sl - ul) / (Sl - us);
+        *EI = ((Sl - ul) * El - p_l * ul + ps * us) / (Sl - us);
+    } else {
+        *rhoI = rho_r * (Sr - ur) / (Sr - us);
+        *EI = ((Sr - ur) * Er - p_r * ur + ps * us) / (Sr - us);
+    }
+}
+
+/* Right-hand side of Eq. (19) with all three rows, per unit volume:
+ *   d rho_i/dt     = -2 sum_j w_j rho_I v_I . gradW'_ij
+ *   d (rho v)_i/dt = -2 sum_j w_j [ rho_I v_I (v_I . gradW'_ij) + p_I gradW'_ij ]
+ *   d E_i/dt       = -2 sum_j w_j (E_I + p_I) v_I . gradW'_ij
+ * with gradW'_ij = (B_i + B_j)/2 gradW_ij (Eq. 28) and the interface state
+ * of or_hllc_interface along n = r_ji / r.  E is the total energy per unit
+ * volume.  Optional abs-sum scales as for the weakly compressible rows. */
+void or_hllc_rhs(const or_box* b, int64_t n, const double* pos, double h,
+                 int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
+                 const double* vol, const double* B, const or_hllc_params* prm,
+                 const double* rho, const double* mom, const double* E,
+                 double* drho, double* dmom, double* dE,
+                 double* scale_rho, double* scale_mom, double* scale_E)
+{
+    int dim = b->dim;
+    double gm1 = prm->gamma - 1.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double sr = 0.0, sm[3] = {0, 0, 0}, se = 0.0, ar = 0.0, am[3] = {0, 0, 0}, ae = 0.0;
+        double vi[3] = {0, 0, 0}, ki = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            vi[a] = mom[a * n + i] / rho[i];
+            ki += vi[a] * vi[a];
+        }
+        double pi_ = gm1 * (E[i] - 0.5 * rho[i] * ki);
+        const double* Bi = B + i * dim * dim;
+        for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
+            int64_t j = col[p];
+            double d[3], g[3];
+            pair_vec(b, n, pos, i, j, d);
+            double r = grad_w(OR_WENDLAND, dim, h, d, g);
+            if (r == 0.0) continue;
+            const double* Bj = B + j * dim * dim;
+            double gc[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a)
+                for (int q = 0; q < dim; ++q) gc[a] += 0.5 * (Bi[a * dim + q] + Bj[a * dim + q]) * g[q];
+            double nrm[3] = {0, 0, 0};
+            for (int a = 0; a < dim; ++a) nrm[a] = -d[a] / r;
+            double vj[3] = {0, 0, 0}, kj = 0.0;
+            for (int a = 0; a < dim; ++a) {
+                vj[a] = mom[a * n + j] / rho[j];
+                kj += vj[a] * vj[a];
+            }
+            double pj = gm1 * (E[j] - 0.5 * rho[j] * kj);
+            double rhoI, vI[3] = {0, 0, 0}, pI, EI;
+            or_hllc_interface(dim, nrm, prm->gamma, prm->eta, rho[i], vi, pi_, rho[j], vj, pj,
+                              &rhoI, vI, &pI, &EI);
+            double vg = 0.0;
+            for (int a = 0; a < dim; ++a) vg += vI[a] * gc[a];
+            double tr = -2.0 * vol[j] * rhoI * vg;
+            double te = -2.0 * vol[j] * (EI + pI) * vg;
+            sr += tr; ar += fabs(tr);
+            se += te; ae += fabs(te);
+            for (int a = 0; a < dim; ++a) {
+                double tm = -2.0 * vol[j] * (rhoI * vI[a] * vg + pI * gc[a]);
+                sm[a] += tm;
+                am[a] += fabs(tm);
+            }
+        }
+        drho[k] = sr;
+        dE[k] = se;
+        for (int a = 0; a < dim; ++a) dmom[a * m + k] = sm[a];
+        if (scale_rho) scale_rho[k] = ar;
+        if (scale_E) scale_E[k] = ae;
+        if (scale_mom)
+            for (int a = 0; a < dim; ++a) scale_mom[a * m + k] = am[a];
+    }
+}
+
+/* Heun integration of the compressible system (as or_euler_heun); rho,
+ * mom, E updated in place (full n). */
+void or_hllc_heun(const or_box* b, int64_t n, const double* pos, double h,
+                  const int64_t* row_ptr, const int32_t* col,
+                  const double* vol, const double* B, const or_hllc_params* prm,
+                  double* rho, double* mom, double* E, int64_t nsteps)
+{
+    int dim = b->dim;
+    double* r1 = (double*)malloc((size_t)n * sizeof(double));
+    double* m1 = (double*)malloc((size_t)n * dim * sizeof(double));
+    double* e1 = (double*)malloc((size_t)n * sizeof(double));
+    double* dr = (double*)malloc((size_t)n * sizeof(double));
+    double* dm = (double*)malloc((size_t)n * dim * sizeof(double));
+    double* de = (double*)malloc((size_t)n * sizeof(double));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        or_hllc_rhs(b, n, pos, h, n, NULL, row_ptr, col, vol, B, prm, rho, mom, E, dr, dm, de, NULL, NULL, NULL);
+        for (int64_t i = 0; i < n; ++i) { r1[i] = rho[i] + prm->dt * dr[i]; e1[i] = E[i] + prm->dt * de[i]; }
+        for (int64_t i = 0; i < n * dim; ++i) m1[i] = mom[i] + prm->dt * dm[i];
+        or_hllc_rhs(b, n, pos, h, n, NULL, row_ptr, col, vol, B, prm, r1, m1, e1, dr, dm, de, NULL, NULL, NULL);
+        for (int64_t i = 0; i < n; ++i) {
+            rho[i] = 0.5 * (rho[i] + r1[i] + prm->dt * dr[i]);
+            E[i] = 0.5 * (E[i] + e1[i] + prm->dt * de[i]);
+        }
+        for (int64_t i = 0; i < n * dim; ++i) mom[i] = 0.5 * (mom[i] + m1[i] + prm->dt * dm[i]);
+    }
+    free(r1); free(m1); free(e1); free(dr); free(dm); free(de);
+}
+
+/* ------------------------------------------------------------------ */
 /* Total Lagrangian SPH                                                */
 /* ------------------------------------------------------------------ */
 

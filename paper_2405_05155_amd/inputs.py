@@ -174,6 +174,24 @@ def double_shear_layer(nside: int = 128, c: float = 10.0, width: float = 1.0 / 3
     return w
 
 
+def density_wave_2d(nside: int = 512, amplitude: float = 0.1, U: float = 1.0, p0: float = 1.0,
+                    gamma: float = 1.4) -> Workload:
+    """Compressible ideal gas on the periodic unit square, exact lattice,
+    h = 1.3 dx: a density wave rho = 1 + amplitude sin(2 pi x) carried by the
+    uniform velocity (U, 0) at uniform pressure p0 (exact solution: the
+    profile shifted by U t); E = p0/(gamma - 1) + rho U^2/2 per unit volume."""
+    w = periodic_square_case(nside, 2, 1.3, 0.0, None, f"density_wave_2d_{nside}")
+    x = w.pos.astype(np.float64)
+    rho = 1.0 + amplitude * np.sin(2 * np.pi * x[0])
+    mom = np.stack([rho * U, np.zeros(w.n)])
+    E = p0 / (gamma - 1.0) + 0.5 * rho * U * U
+    w.fields = {"rho": rho.astype(np.float32), "mom": mom.astype(np.float32), "E": E.astype(np.float32),
+                "gamma": gamma, "eta": 1.0, "U": U, "p0": p0, "amplitude": amplitude}
+    c_max = math.sqrt(gamma * p0 / (1.0 - amplitude))
+    w.meta["dt"] = 0.6 * w.h / (abs(U) + c_max)
+    return w
+
+
 def taylor_green_3d(nside: int = 200, c: float = 10.0, nu: float = 0.01) -> Workload:
     """3-D Taylor-Green field in the periodic unit cube, exact lattice,
     h = 1.3 dx; u = sin cos cos, v = -cos sin cos, w = 0,
