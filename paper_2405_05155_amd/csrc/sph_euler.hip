@@ -34,6 +34,10 @@ struct EulerArgs {
     float qc2inv;           // 1 / (4 c^2)
     float kmu;              // -4 mu / d
     float fr, fm;           // row factors of the continuity and momentum sums: -cFh, -cFh / 2
+    // compressible rows (limited HLLC, ideal gas; 2-D)
+    float gamma, ig1, gm1;  // gamma, 1 / (gamma - 1), gamma - 1
+    float eta_h;            // limiter coefficient
+    float fh;               // row factor of the compressible sums: -cF
     float L[3], invL[3];  // periodic lengths (invL = 0 on open axes)
     float lo[3];          // box corner
     float margin;         // a particle this far from every periodic face needs no wrap
@@ -122,6 +126,8 @@ struct OwnState {
     float v[3];
     float p2;    // 2 p_i
     float crho;  // c (rho_i + rho_ref): c (rho_i + rho_j) = crho + c drho_j
+    // compressible rows: density, pressure, sound speed, impedance, total energy
+    float rho, p, c, z, Et;
 };
 
 // One pair (i, j) of Eq. (19) with the corrected gradient (Eq. 28) and the
@@ -202,6 +208,128 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
     for (int a2 = 0; a2 < DIM; ++a2) accum(sm[a2], w, fmaf(rh, vs2[a2], fmaf(p4, G[a2], kv * dv[a2])));
 }
 
+// One pair (i, j) of the compressible system (Eq. 19, all three rows; 2-D)
+// with the corrected gradient (Eq. 28) and the limited HLLC interface state
+// (Eqs. 24-25 and the HLLC limiter, Sec. 3.1), Riemann problem along
+// n = -d / r with left state i.  The limited middle state
+//   u* = (z_l u_l + z_r u_r + beta^2 (p_l - p_r)) / (z_l + z_r),
+//   p* = (p_l + p_r)/2 + beta/2 (z_r (u* - u_r) + z_l (u_l - u*)),
+// z = rho c, beta = min(eta max((u_l - u_r) / cbar, 0), 1); the wave
+// speeds u_l - c_l, u_r + c_r, or min/max estimates where those cross; at
+// the fixed interface the upwind state when the fan is one-sided, else the
+// star state on the side of u*'s sign,
+//   rho*_K = rho_K (S_K - u_K) / (S_K - u*),
+//   E*_K = ((S_K - u_K) E_K - p_K u_K + p* u*) / (S_K - u*),
+// velocity u* n plus the mean tangential velocity.  With w = V_j (1-q/2)^3,
+// G = (B_i + B_j) d and the row factor -cF:
+//   drho/dt = -cF sum_j w rho_I (v_I . G),
+//   dm/dt   = -cF sum_j w [rho_I v_I (v_I . G) + p_I G],
+//   dE/dt   = -cF sum_j w (E_I + p_I) (v_I . G).
+// A padding entry (the particle itself) has w = 0 and finite terms.
+template <bool WRAP>
+__device__ __forceinline__ void accumulate_pair_hllc(const EulerArgs& ea, const OwnState<2>& o, const NbrRec<2>& nb,
+                                                     Kahan& sr, Kahan* sm, Kahan& se) {
+    const float4 gj = nb.g0;  // (x, y, V, B00)
+    const float Bs[3] = {o.B[0] + gj.w, o.B[1] + nb.g1.x, o.B[2] + nb.g1.y};
+    const float4 pj = nb.pr;  // (rho, v_x, v_y, p)
+    float d[2];
+    d[0] = o.x[0] - gj.x;
+    d[1] = o.x[1] - gj.y;
+    if (WRAP) {
+        d[0] = wrap(d[0], ea.L[0], ea.invL[0]);
+        d[1] = wrap(d[1], ea.L[1], ea.invL[1]);
+    }
+    const float r2 = fmaf(d[0], d[0], d[1] * d[1]);
+    const bool live = r2 > 0.f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float tq = fmaf(ea.nhh, r2 * rinv, 1.f);  // 1 - q/2
+    const float Vj = live ? gj.z : 0.f;
+    const float w = (Vj * tq) * (tq * tq);
+    const float G0 = fmaf(Bs[0], d[0], Bs[1] * d[1]);
+    const float G1 = fmaf(Bs[1], d[0], Bs[2] * d[1]);
+    const float n0 = -d[0] * rinv, n1 = -d[1] * rinv;
+    const float ul = fmaf(o.v[0], n0, o.v[1] * n1);
+    const float ur = fmaf(pj.y, n0, pj.z * n1);
+    const float rhor = pj.x, pr = pj.w;
+    const float cr = __builtin_amdgcn_sqrtf(ea.gamma * pr * fast_rcp(rhor));
+    const float zr = rhor * cr;
+    const float Er = fmaf(pr, ea.ig1, 0.5f * rhor * fmaf(pj.y, pj.y, pj.z * pj.z));
+    float Sl = ul - o.c, Sr = ur + cr;
+    const bool cross = Sl > Sr;
+    Sl = cross ? fminf(ul - o.c, ur - cr) : Sl;
+    Sr = cross ? fmaxf(ul + o.c, ur + cr) : Sr;
+    const float izs = fast_rcp(o.z + zr);
+    const float beta = __builtin_amdgcn_fmed3f(2.f * ea.eta_h * (ul - ur) * fast_rcp(o.c + cr), 0.f, 1.f);
+    const float us = (fmaf(o.z, ul, zr * ur) + (beta * beta) * (o.p - pr)) * izs;
+    const float ps = 0.5f * ((o.p + pr) + beta * fmaf(zr, us - ur, o.z * (ul - us)));
+    // star state on the side of u*
+    const bool left = us >= 0.f;
+    const float rhoK = left ? o.rho : rhor, uK = left ? ul : ur, SK = left ? Sl : Sr;
+    const float EK = left ? o.Et : Er, pK = left ? o.p : pr;
+    const float den = fast_rcp(SK - us);
+    float rhoI = rhoK * (SK - uK) * den;
+    float EI = fmaf(SK - uK, EK, fmaf(ps, us, -pK * uK)) * den;
+    float pI = ps;
+    const float um = 0.5f * (ul + ur);
+    float vI0 = fmaf(us - um, n0, 0.5f * (o.v[0] + pj.y));
+    float vI1 = fmaf(us - um, n1, 0.5f * (o.v[1] + pj.z));
+    // one-sided fans: the upwind state
+    const bool upl = Sl >= 0.f, upr = !upl && Sr <= 0.f;
+    rhoI = upl ? o.rho : (upr ? rhor : rhoI);
+    pI = upl ? o.p : (upr ? pr : pI);
+    EI = upl ? o.Et : (upr ? Er : EI);
+    vI0 = upl ? o.v[0] : (upr ? pj.y : vI0);
+    vI1 = upl ? o.v[1] : (upr ? pj.z : vI1);
+    const float vG = fmaf(vI0, G0, vI1 * G1);
+    const float rvG = rhoI * vG;
+    accum(sr, w, rvG);
+    accum(sm[0], w, fmaf(rvG, vI0, pI * G0));
+    accum(sm[1], w, fmaf(rvG, vI1, pI * G1));
+    accum(se, w, (EI + pI) * vG);
+}
+
+// Compressible primitive record (rho, v_x, v_y, p) of U = (rho, m_x, m_y, E).
+__device__ __forceinline__ float4 primitive_hllc(const float4& u, float gm1) {
+    const float inv = fast_rcp(u.x);
+    const float vx = u.y * inv, vy = u.z * inv;
+    return make_float4(u.x, vx, vy, gm1 * (u.w - 0.5f * fmaf(u.y, vx, u.z * vy)));
+}
+
+__global__ void k_pack_hllc(int32_t n, float gm1, const float4* __restrict__ sorted, const float* __restrict__ rho,
+                            const float* __restrict__ mom, const float* __restrict__ E, float4* __restrict__ U,
+                            float4* __restrict__ P) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = __float_as_int(sorted[s].w);
+    const float4 u = make_float4(rho[i], mom[i], mom[(int64_t)n + i], E[i]);
+    U[s] = u;
+    P[s] = primitive_hllc(u, gm1);
+}
+
+__global__ void k_unpack_hllc(int32_t n, const float4* __restrict__ sorted, const float4* __restrict__ U,
+                              float* __restrict__ rho, float* __restrict__ mom, float* __restrict__ E) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = __float_as_int(sorted[s].w);
+    const float4 u = U[s];
+    rho[i] = u.x;
+    mom[i] = u.y;
+    mom[(int64_t)n + i] = u.z;
+    E[i] = u.w;
+}
+
+// Solver of the stage kernel: the weakly compressible rows with the
+// linearised solver (EOS p = c^2 (rho - rho0)) or the compressible rows with
+// the limited HLLC solver (ideal gas, 2-D).
+enum Solver { SOL_LINEARISED = 0, SOL_HLLC = 1 };
+
+template <int DIM, int SOL, bool WRAP>
+__device__ __forceinline__ void pair_terms(const EulerArgs& ea, const OwnState<DIM>& o, const NbrRec<DIM>& nb,
+                                           Kahan& sr, Kahan* sm, Kahan& se) {
+    if constexpr (SOL == SOL_HLLC) accumulate_pair_hllc<WRAP>(ea, o, nb, sr, sm, se);
+    else accumulate_pair<DIM, WRAP>(ea, o, nb, sr, sm);
+}
+
 enum RowMode { ROWS_CSR = 0, ROWS_ELL = 1, ROWS_ELL_BATCH = 2 };
 
 // Batch mode: the column indices of a lane's E entries of row i.
@@ -218,15 +346,15 @@ __device__ __forceinline__ void load_batch_cols(int32_t n, const int32_t* __rest
 // One particle's row for lane `sub` of its group (batch mode: the lane's
 // column indices in jb).  Every gather of the row is issued before the own
 // record is waited on.
-template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
+template <int DIM, int SOL, int STAGE, int L, int MODE, int E, bool GA>
 __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const int64_t* __restrict__ row_ptr,
                                           const int32_t* __restrict__ col, int32_t ell_S,
                                           const float4* __restrict__ geo0, const float4* __restrict__ geo1,
                                           const float2* __restrict__ geo2, const float4* U,
                                           const float4* __restrict__ P, const float4* U0, float4* Uout,
                                           float4* Pout, const float4* __restrict__ sorted,
-                                          float* __restrict__ drho_dt, float* __restrict__ dmom_dt, int32_t i,
-                                          int sub, const int32_t* jb) {
+                                          float* __restrict__ drho_dt, float* __restrict__ dmom_dt,
+                                          float* __restrict__ dE_dt, int32_t i, int sub, const int32_t* jb) {
     NbrRec<DIM> self;
     gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
     // batch mode: every record of the lane's entries in flight at once
@@ -262,22 +390,32 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
         }
     }
     const bool wrap_wave = __any(near);
-    o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
-    o.p2 = fmaf(ea.c2x2, pi4.x, ea.c2x2poff);
-    o.crho = ea.c * ((ea.rho_ref + pi4.x) + ea.rho_ref);
+    if constexpr (SOL == SOL_HLLC) {
+        o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = 0.f;
+        o.rho = pi4.x;
+        o.p = pi4.w;
+        o.c = __builtin_amdgcn_sqrtf(ea.gamma * o.p * fast_rcp(o.rho));
+        o.z = o.rho * o.c;
+        o.Et = fmaf(o.p, ea.ig1, 0.5f * o.rho * fmaf(o.v[0], o.v[0], o.v[1] * o.v[1]));
+    } else {
+        o.v[0] = pi4.y; o.v[1] = pi4.z; o.v[2] = pi4.w;
+        o.p2 = fmaf(ea.c2x2, pi4.x, ea.c2x2poff);
+        o.crho = ea.c * ((ea.rho_ref + pi4.x) + ea.rho_ref);
+    }
 
-    Kahan sr, sm[DIM];
+    Kahan sr, sm[DIM], se;
     sr.init();
+    se.init();
 #pragma unroll
     for (int a = 0; a < DIM; ++a) sm[a].init();
 
     if (MODE == ROWS_ELL_BATCH) {
         if (wrap_wave) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, true>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) pair_terms<DIM, SOL, true>(ea, o, nb[q], sr, sm, se);
         } else {
 #pragma unroll
-            for (int q = 0; q < E; ++q) accumulate_pair<DIM, false>(ea, o, nb[q], sr, sm);
+            for (int q = 0; q < E; ++q) pair_terms<DIM, SOL, false>(ea, o, nb[q], sr, sm, se);
         }
     } else {
         int64_t k, e, stride;
@@ -300,35 +438,46 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
             gather_nbr<DIM, GA>(jn1, geo0, geo1, geo2, P, nxt);
             jn1 = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
-            if (wrap_wave) accumulate_pair<DIM, true>(ea, o, cur, sr, sm);
-            else accumulate_pair<DIM, false>(ea, o, cur, sr, sm);
+            if (wrap_wave) pair_terms<DIM, SOL, true>(ea, o, cur, sr, sm, se);
+            else pair_terms<DIM, SOL, false>(ea, o, cur, sr, sm, se);
             cur = nxt;
         }
     }
+    // R = (rho or drho, m, E or m_z) rates
     float R[4];
-    R[0] = ea.fr * group_sum<L>(sr);
+    if constexpr (SOL == SOL_HLLC) {
+        R[0] = ea.fh * group_sum<L>(sr);
+        R[1] = ea.fh * group_sum<L>(sm[0]);
+        R[2] = ea.fh * group_sum<L>(sm[1]);
+        R[3] = ea.fh * group_sum<L>(se);
+    } else {
+        R[0] = ea.fr * group_sum<L>(sr);
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) R[1 + a] = ea.fm * group_sum<L>(sm[a]);
-    if (DIM == 2) R[3] = 0.f;
+        for (int a = 0; a < DIM; ++a) R[1 + a] = ea.fm * group_sum<L>(sm[a]);
+        if (DIM == 2) R[3] = 0.f;
+    }
+    constexpr bool R4 = DIM == 3 || SOL == SOL_HLLC;  // the fourth record component evolves
     if (sub != 0) return;
     if (STAGE == 0) {
         const int32_t ic = __float_as_int(sorted[i].w);
         drho_dt[ic] = R[0];
 #pragma unroll
         for (int a = 0; a < DIM; ++a) dmom_dt[(int64_t)a * n + ic] = R[1 + a];
+        if (SOL == SOL_HLLC) dE_dt[ic] = R[3];
         return;
     }
     float4 un;
     if (STAGE == 1) {
         un = make_float4(ui.x + ea.dt * R[0], ui.y + ea.dt * R[1], ui.z + ea.dt * R[2],
-                         DIM == 3 ? ui.w + ea.dt * R[3] : 0.f);
+                         R4 ? ui.w + ea.dt * R[3] : 0.f);
     } else {
         un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * R[0])), 0.5f * (u0.y + (ui.y + ea.dt * R[1])),
                          0.5f * (u0.z + (ui.z + ea.dt * R[2])),
-                         DIM == 3 ? 0.5f * (u0.w + (ui.w + ea.dt * R[3])) : 0.f);
+                         R4 ? 0.5f * (u0.w + (ui.w + ea.dt * R[3])) : 0.f);
     }
     Uout[i] = un;
-    Pout[i] = primitive<DIM>(un, ea.rho_ref);
+    if constexpr (SOL == SOL_HLLC) Pout[i] = primitive_hllc(un, ea.gm1);
+    else Pout[i] = primitive<DIM>(un, ea.rho_ref);
 }
 
 // One lane group of L lanes per particle.  STAGE 0: write rates; 1: Uout =
@@ -347,22 +496,23 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
 //     pipeline would be too shallow to cover the memory latency).
 // Entries past the end of a row use the particle itself (zero weight).
 // Blocks run in XCD-contiguous order; whole groups leave together.
-template <int DIM, int STAGE, int L, int MODE, int E, bool GA>
+template <int DIM, int SOL, int STAGE, int L, int MODE, int E, bool GA>
 __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
                                                const int32_t* __restrict__ col, int32_t ell_S,
                                                const float4* __restrict__ geo0,
                                                const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                                const float4* U, const float4* __restrict__ P, const float4* U0,
                                                float4* Uout, float4* Pout, const float4* __restrict__ sorted,
-                                               float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
+                                               float* __restrict__ drho_dt, float* __restrict__ dmom_dt,
+                                               float* __restrict__ dE_dt) {
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int sub = (int)(threadIdx.x % L);
     const int32_t i = blk * (BLK / L) + (int32_t)(threadIdx.x / L);
     if (i >= n) return;
     int32_t jb[E > 0 ? E : 1];
     if (MODE == ROWS_ELL_BATCH) load_batch_cols<L, E>(n, col, ell_S, i, sub, jb);
-    euler_row<DIM, STAGE, L, MODE, E, GA>(n, ea, row_ptr, col, ell_S, geo0, geo1, geo2, U, P, U0, Uout, Pout,
-                                          sorted, drho_dt, dmom_dt, i, sub, jb);
+    euler_row<DIM, SOL, STAGE, L, MODE, E, GA>(n, ea, row_ptr, col, ell_S, geo0, geo1, geo2, U, P, U0, Uout,
+                                               Pout, sorted, drho_dt, dmom_dt, dE_dt, i, sub, jb);
 }
 
 // ------------------------------------------------------------------ tiled stage
@@ -748,9 +898,10 @@ struct StageIO {
     float4* Pout;
     float* dr;
     float* dm;
+    float* de;  // compressible rows: dE/dt (stage 0)
 };
 
-template <int DIM, int STAGE, int L, int MODE, int E>
+template <int DIM, int SOL, int STAGE, int L, int MODE, int E>
 void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     const bool ell = MODE != ROWS_CSR;
     const dim3 grid(grid_for(c->n, BLK / L));
@@ -758,42 +909,42 @@ void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     const int32_t* col = ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>();
     const int32_t S = ell ? c->ell_S : 0;
     if (DIM == 3 && c->geoA_gen == c->geo_gen)
-        hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E, DIM == 3>), grid, dim3(BLK), 0, c->stream, c->n, ea, rp,
-                           col, S, c->geoA.as<float4>(), nullptr, nullptr, io.U, io.P, io.U0, io.Uout, io.Pout,
-                           c->sorted.as<float4>(), io.dr, io.dm);
+        hipLaunchKernelGGL((k_euler<DIM, SOL, STAGE, L, MODE, E, DIM == 3>), grid, dim3(BLK), 0, c->stream, c->n, ea,
+                           rp, col, S, c->geoA.as<float4>(), nullptr, nullptr, io.U, io.P, io.U0, io.Uout, io.Pout,
+                           c->sorted.as<float4>(), io.dr, io.dm, io.de);
     else
-        hipLaunchKernelGGL((k_euler<DIM, STAGE, L, MODE, E, false>), grid, dim3(BLK), 0, c->stream, c->n, ea, rp,
-                           col, S, c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P,
-                           io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm);
+        hipLaunchKernelGGL((k_euler<DIM, SOL, STAGE, L, MODE, E, false>), grid, dim3(BLK), 0, c->stream, c->n, ea,
+                           rp, col, S, c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P,
+                           io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm, io.de);
 }
 
-template <int DIM, int STAGE, int L>
+template <int DIM, int SOL, int STAGE, int L>
 void launch_l(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    if (c->ell_state == 1) launch_k<DIM, STAGE, L, ROWS_ELL, 0>(c, ea, io);
-    else launch_k<DIM, STAGE, L, ROWS_CSR, 0>(c, ea, io);
+    if (c->ell_state == 1) launch_k<DIM, SOL, STAGE, L, ROWS_ELL, 0>(c, ea, io);
+    else launch_k<DIM, SOL, STAGE, L, ROWS_CSR, 0>(c, ea, io);
 }
 
 // Batched short rows: L lanes per particle and E = ceil(S / L) entries per
 // lane (at most 6, 5 or 4 for 2, 4 or 8 lanes).  Returns false when the rows
 // are too long for a batch.
-template <int DIM, int STAGE>
+template <int DIM, int SOL, int STAGE>
 bool launch_batch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int L) {
     const int E = (c->ell_S + L - 1) / L;
     if (L == 2) {
-        if (E <= 4) launch_k<DIM, STAGE, 2, ROWS_ELL_BATCH, 4>(c, ea, io);
-        else if (E == 5) launch_k<DIM, STAGE, 2, ROWS_ELL_BATCH, 5>(c, ea, io);
-        else if (E == 6) launch_k<DIM, STAGE, 2, ROWS_ELL_BATCH, 6>(c, ea, io);
+        if (E <= 4) launch_k<DIM, SOL, STAGE, 2, ROWS_ELL_BATCH, 4>(c, ea, io);
+        else if (E == 5) launch_k<DIM, SOL, STAGE, 2, ROWS_ELL_BATCH, 5>(c, ea, io);
+        else if (E == 6) launch_k<DIM, SOL, STAGE, 2, ROWS_ELL_BATCH, 6>(c, ea, io);
         else return false;
     } else if (L == 4) {
-        if (E <= 2) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 2>(c, ea, io);
-        else if (E == 3) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 3>(c, ea, io);
-        else if (E == 4) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 4>(c, ea, io);
-        else if (E == 5) launch_k<DIM, STAGE, 4, ROWS_ELL_BATCH, 5>(c, ea, io);
+        if (E <= 2) launch_k<DIM, SOL, STAGE, 4, ROWS_ELL_BATCH, 2>(c, ea, io);
+        else if (E == 3) launch_k<DIM, SOL, STAGE, 4, ROWS_ELL_BATCH, 3>(c, ea, io);
+        else if (E == 4) launch_k<DIM, SOL, STAGE, 4, ROWS_ELL_BATCH, 4>(c, ea, io);
+        else if (E == 5) launch_k<DIM, SOL, STAGE, 4, ROWS_ELL_BATCH, 5>(c, ea, io);
         else return false;
     } else if (L == 8) {
-        if (E <= 2) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 2>(c, ea, io);
-        else if (E == 3) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 3>(c, ea, io);
-        else if (E == 4) launch_k<DIM, STAGE, 8, ROWS_ELL_BATCH, 4>(c, ea, io);
+        if (E <= 2) launch_k<DIM, SOL, STAGE, 8, ROWS_ELL_BATCH, 2>(c, ea, io);
+        else if (E == 3) launch_k<DIM, SOL, STAGE, 8, ROWS_ELL_BATCH, 3>(c, ea, io);
+        else if (E == 4) launch_k<DIM, SOL, STAGE, 8, ROWS_ELL_BATCH, 4>(c, ea, io);
         else return false;
     } else {
         return false;
@@ -909,28 +1060,36 @@ void launch_tile(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     else launch_tile_r<DIM, STAGE, 3>(c, ea, io, tpw, L2);
 }
 
-template <int STAGE>
+// One stage of the solver SOL (the compressible rows run on the per-particle
+// kernel in 2-D only; the caller has checked).
+template <int SOL, int STAGE>
 void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, bool tiled) {
-    if (tiled) {
-        if (c->dim == 2) launch_tile<2, STAGE>(c, ea, io);
-        else launch_tile<3, STAGE>(c, ea, io);
-        return;
+    if constexpr (SOL == SOL_LINEARISED) {
+        if (tiled) {
+            if (c->dim == 2) launch_tile<2, STAGE>(c, ea, io);
+            else launch_tile<3, STAGE>(c, ea, io);
+            return;
+        }
     }
     if (int bl = batch_lanes(c)) {
-        bool done = c->dim == 2 ? launch_batch<2, STAGE>(c, ea, io, bl) : launch_batch<3, STAGE>(c, ea, io, bl);
+        bool done;
+        if constexpr (SOL == SOL_LINEARISED)
+            done = c->dim == 2 ? launch_batch<2, SOL, STAGE>(c, ea, io, bl) : launch_batch<3, SOL, STAGE>(c, ea, io, bl);
+        else
+            done = launch_batch<2, SOL, STAGE>(c, ea, io, bl);
         if (done) return;
     }
     int L = lanes_per_particle(c);
     if (c->dim == 2) {
-        if (L == 1) launch_l<2, STAGE, 1>(c, ea, io);
-        else if (L == 2) launch_l<2, STAGE, 2>(c, ea, io);
-        else if (L == 4) launch_l<2, STAGE, 4>(c, ea, io);
-        else launch_l<2, STAGE, 8>(c, ea, io);
-    } else {
-        if (L == 1) launch_l<3, STAGE, 1>(c, ea, io);
-        else if (L == 2) launch_l<3, STAGE, 2>(c, ea, io);
-        else if (L == 4) launch_l<3, STAGE, 4>(c, ea, io);
-        else launch_l<3, STAGE, 8>(c, ea, io);
+        if (L == 1) launch_l<2, SOL, STAGE, 1>(c, ea, io);
+        else if (L == 2) launch_l<2, SOL, STAGE, 2>(c, ea, io);
+        else if (L == 4) launch_l<2, SOL, STAGE, 4>(c, ea, io);
+        else launch_l<2, SOL, STAGE, 8>(c, ea, io);
+    } else if constexpr (SOL == SOL_LINEARISED) {
+        if (L == 1) launch_l<3, SOL, STAGE, 1>(c, ea, io);
+        else if (L == 2) launch_l<3, SOL, STAGE, 2>(c, ea, io);
+        else if (L == 4) launch_l<3, SOL, STAGE, 4>(c, ea, io);
+        else launch_l<3, SOL, STAGE, 8>(c, ea, io);
     }
 }
 
@@ -961,6 +1120,47 @@ int prepare_geo3(sph_ctx* c) {
                        c->geo1.as<float4>(), c->geo2.as<float2>(), c->geoA.as<float4>());
     SPH_LAUNCH_CHECK(c);
     c->geoA_gen = c->geo_gen;
+    return SPH_OK;
+}
+
+EulerArgs make_hllc_args(const sph_ctx* c, const sph_hllc_params* p) {
+    EulerArgs a{};
+    KernelConsts kc = make_kernel_consts(SPH_WENDLAND, c->dim, c->dom.h);
+    a.hinv = kc.hinv;
+    a.nhh = -0.5f * kc.hinv;
+    a.gamma = (float)p->gamma;
+    a.ig1 = (float)(1.0 / (p->gamma - 1.0));
+    a.gm1 = (float)(p->gamma - 1.0);
+    a.eta_h = (float)p->eta;
+    a.fh = -kc.cF;
+    a.dt = (float)p->dt;
+    for (int ax = 0; ax < 3; ++ax) {
+        a.L[ax] = c->box.L[ax];
+        a.invL[ax] = c->box.periodic[ax] ? (float)(1.0 / c->box.Ld[ax]) : 0.f;
+        a.lo[ax] = c->box.lo[ax];
+    }
+    a.margin = (float)(c->rc * 1.001);
+    return a;
+}
+
+int check_hllc(sph_ctx* c, const sph_hllc_params* p, const char* who) {
+    if (!c) return SPH_ERR_ARG;
+    if (!c->bound || !c->geo_valid)
+        return sph_fail(c, SPH_ERR_STATE, "%s: needs a bound configuration and a cached correction", who);
+    if (c->dim != 2) return sph_fail(c, SPH_ERR_ARG, "%s: 2-D contexts only", who);
+    if (c->dom.kernel != SPH_WENDLAND) return sph_fail(c, SPH_ERR_ARG, "%s: Wendland kernel only", who);
+    if (!p) return sph_fail(c, SPH_ERR_ARG, "%s: params NULL", who);
+    if (!(p->gamma > 1.0)) return sph_fail(c, SPH_ERR_ARG, "%s: gamma must be > 1", who);
+    if (!(p->eta >= 0.0)) return sph_fail(c, SPH_ERR_ARG, "%s: eta must be >= 0", who);
+    if (c->n >= (1 << 28))
+        return sph_fail(c, SPH_ERR_ARG, "%s: %d particles exceed the 2^28 limit of the gathers", who, c->n);
+    return SPH_OK;
+}
+
+int pack_hllc(sph_ctx* c, float gm1, const float* rho, const float* mom, const float* E, float4* U, float4* P) {
+    hipLaunchKernelGGL(k_pack_hllc, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, gm1,
+                       c->sorted.as<float4>(), rho, mom, E, U, P);
+    SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
 
@@ -995,7 +1195,7 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt};
-    launch<0>(c, ea, io, tiled);
+    launch<SOL_LINEARISED, 0>(c, ea, io, tiled);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }
@@ -1026,8 +1226,8 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr};
     StageIO s2{Us, Ps, U, U, P, nullptr, nullptr};
     for (int32_t s = 0; s < nsteps; ++s) {
-        launch<1>(c, ea, s1, tiled);
-        launch<2>(c, ea, s2, tiled);
+        launch<SOL_LINEARISED, 1>(c, ea, s1, tiled);
+        launch<SOL_LINEARISED, 2>(c, ea, s2, tiled);
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)
@@ -1036,6 +1236,60 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     else
         hipLaunchKernelGGL(k_unpack_state<3>, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
                            c->sorted.as<float4>(), U, drho, mom);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+int sph_hllc_rhs(sph_ctx* c, const sph_hllc_params* p, const float* rho, const float* mom, const float* E,
+                 float* drho_dt, float* dmom_dt, float* dE_dt) {
+    int r = check_hllc(c, p, "sph_hllc_rhs");
+    if (r) return r;
+    if (c->n == 0) return SPH_OK;
+    if (!rho || !mom || !E || !drho_dt || !dmom_dt || !dE_dt)
+        return sph_fail(c, SPH_ERR_ARG, "sph_hllc_rhs: NULL array");
+    SPH_HIP(c, c->ua.ensure((size_t)c->n * sizeof(float4)));
+    SPH_HIP(c, c->ta.ensure((size_t)c->n * sizeof(float4)));
+    r = sph_ell_prepare(c);
+    if (r) return r;
+    EulerArgs ea = make_hllc_args(c, p);
+    r = pack_hllc(c, ea.gm1, rho, mom, E, c->ua.as<float4>(), c->ta.as<float4>());
+    if (r) return r;
+    StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt, dE_dt};
+    launch<SOL_HLLC, 0>(c, ea, io, false);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+int sph_hllc_step(sph_ctx* c, const sph_hllc_params* p, float* rho, float* mom, float* E, int32_t nsteps) {
+    int r = check_hllc(c, p, "sph_hllc_step");
+    if (r) return r;
+    if (nsteps < 0) return sph_fail(c, SPH_ERR_ARG, "sph_hllc_step: nsteps < 0");
+    if (!(p->dt > 0.0)) return sph_fail(c, SPH_ERR_ARG, "sph_hllc_step: dt must be > 0");
+    if (c->n == 0 || nsteps == 0) return SPH_OK;
+    if (!rho || !mom || !E) return sph_fail(c, SPH_ERR_ARG, "sph_hllc_step: NULL array");
+    SPH_HIP(c, c->ua.ensure((size_t)c->n * sizeof(float4)));
+    SPH_HIP(c, c->ub.ensure((size_t)c->n * sizeof(float4)));
+    SPH_HIP(c, c->ta.ensure((size_t)c->n * sizeof(float4)));
+    SPH_HIP(c, c->tb.ensure((size_t)c->n * sizeof(float4)));
+    float4* U = c->ua.as<float4>();
+    float4* Us = c->ub.as<float4>();
+    float4* P = c->ta.as<float4>();
+    float4* Ps = c->tb.as<float4>();
+    r = sph_ell_prepare(c);
+    if (r) return r;
+    EulerArgs ea = make_hllc_args(c, p);
+    r = pack_hllc(c, ea.gm1, rho, mom, E, U, P);
+    if (r) return r;
+    // stage 1 gathers P, writes (U*, P*); stage 2 gathers P*, writes (U, P) in place
+    StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr, nullptr};
+    StageIO s2{Us, Ps, U, U, P, nullptr, nullptr, nullptr};
+    for (int32_t s = 0; s < nsteps; ++s) {
+        launch<SOL_HLLC, 1>(c, ea, s1, false);
+        launch<SOL_HLLC, 2>(c, ea, s2, false);
+    }
+    SPH_LAUNCH_CHECK(c);
+    hipLaunchKernelGGL(k_unpack_hllc, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
+                       c->sorted.as<float4>(), U, rho, mom, E);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }

@@ -39,6 +39,10 @@ class sph_euler_params(C.Structure):
                 ("mu", C.c_double), ("dt", C.c_double)]
 
 
+class sph_hllc_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("eta", C.c_double), ("dt", C.c_double)]
+
+
 class sph_tlsph_params(C.Structure):
     _fields_ = [("rho0", C.c_double), ("E", C.c_double), ("nu", C.c_double), ("dt", C.c_double),
                 ("model", C.c_int)]
@@ -67,6 +71,8 @@ _SIGS = [
     ("sph_gradient", C.c_int, [_vp, _vp, _vp]),
     ("sph_euler_rhs", C.c_int, [_vp, C.POINTER(sph_euler_params), _vp, _vp, _vp, _vp]),
     ("sph_euler_step", C.c_int, [_vp, C.POINTER(sph_euler_params), _vp, _vp, _i32]),
+    ("sph_hllc_rhs", C.c_int, [_vp, C.POINTER(sph_hllc_params), _vp, _vp, _vp, _vp, _vp, _vp]),
+    ("sph_hllc_step", C.c_int, [_vp, C.POINTER(sph_hllc_params), _vp, _vp, _vp, _i32]),
     ("sph_tlsph_rhs", C.c_int, [_vp, C.POINTER(sph_tlsph_params), _vp, _vp, _vp, _vp, _vp]),
     ("sph_tlsph_step", C.c_int, [_vp, C.POINTER(sph_tlsph_params), _vp, _vp, _vp, _vp, _vp, _i32]),
 ]
@@ -157,6 +163,12 @@ class Domain:
 def euler_params(c, rho0, rho_ref, eta=15.0, mu=0.0, dt=0.0) -> sph_euler_params:
     p = sph_euler_params()
     p.c, p.rho0, p.rho_ref, p.eta, p.mu, p.dt = c, rho0, rho_ref, eta, mu, dt
+    return p
+
+
+def hllc_params(gamma=1.4, eta=1.0, dt=0.0) -> sph_hllc_params:
+    p = sph_hllc_params()
+    p.gamma, p.eta, p.dt = gamma, eta, dt
     return p
 
 
@@ -273,6 +285,20 @@ class Context:
     def euler_step(self, prm, drho, mom, nsteps):
         self._check(lib().sph_euler_step(self._h, C.byref(prm), _ptr(drho, torch.float32, self.n, "drho"),
                                          _ptr(mom, torch.float32, self.dim * self.n, "mom"), int(nsteps)))
+
+    def hllc_rhs(self, prm, rho, mom, E):
+        dr = torch.empty(self.n, dtype=torch.float32, device=self._dev())
+        dm = torch.empty((self.dim, self.n), dtype=torch.float32, device=self._dev())
+        de = torch.empty(self.n, dtype=torch.float32, device=self._dev())
+        self._check(lib().sph_hllc_rhs(self._h, C.byref(prm), _ptr(rho, torch.float32, self.n, "rho"),
+                                       _ptr(mom, torch.float32, self.dim * self.n, "mom"),
+                                       _ptr(E, torch.float32, self.n, "E"), _ptr(dr), _ptr(dm), _ptr(de)))
+        return dr, dm, de
+
+    def hllc_step(self, prm, rho, mom, E, nsteps):
+        self._check(lib().sph_hllc_step(self._h, C.byref(prm), _ptr(rho, torch.float32, self.n, "rho"),
+                                        _ptr(mom, torch.float32, self.dim * self.n, "mom"),
+                                        _ptr(E, torch.float32, self.n, "E"), int(nsteps)))
 
     # ------------------------------------------------------------ total Lagrangian
     def tlsph_rhs(self, prm, vel, F, fixed=None):
@@ -397,6 +423,14 @@ def sph_euler_rhs(ctx: Context, prm, drho, mom):
 
 def sph_euler_step(ctx: Context, prm, drho, mom, nsteps):
     return ctx.euler_step(prm, drho, mom, nsteps)
+
+
+def sph_hllc_rhs(ctx: Context, prm, rho, mom, E):
+    return ctx.hllc_rhs(prm, rho, mom, E)
+
+
+def sph_hllc_step(ctx: Context, prm, rho, mom, E, nsteps):
+    return ctx.hllc_step(prm, rho, mom, E, nsteps)
 
 
 def sph_tlsph_rhs(ctx: Context, prm, vel, F, fixed=None):
