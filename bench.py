@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "fffbe6e999a34949c8d22a79277459965bef2930b37731653d0bc798e8e9c071": {"2d": 39159375, "3d": 2246421978},
+    "744bed47299b95b741a176c65d337506d12951abc5b8835158f6ff9c4b0a6afc": {"2d": 39157260, "3d": 2246588966},
 }
 
 
@@ -221,6 +221,55 @@ def shear_layer_section(nside=128, nside_big=1024, steps_big=400):
                     "alpha_gpu": big[1.6]["ms_per_step"] / big[2.0]["ms_per_step"],
                     "interactions_per_s_tw": big[1.6]["interactions_per_s"]}
     return out
+
+
+def run_hllc(nside, kappa, t_end=0.25):
+    """Compressible rows (limited HLLC, ideal gas) on the advected density
+    wave: time per Heun step over the run to t_end (HIP events, after an
+    untimed warm-up on copies) and the density error against the exact
+    shifted profile (not timed)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    w = I.density_wave_2d(nside=nside)
+    f = w.fields
+    ctx = S.Context(2)
+    ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa), torch.as_tensor(w.pos, device="cuda"))
+    ctx.neighbors()
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    dt = w.meta["dt"]
+    prm = S.hllc_params(f["gamma"], f["eta"], dt)
+    r = torch.as_tensor(f["rho"], device="cuda").clone()
+    m = torch.as_tensor(f["mom"], device="cuda").clone()
+    e = torch.as_tensor(f["E"], device="cuda").clone()
+    ctx.hllc_step(prm, r.clone(), m.clone(), e.clone(), 5)
+    steps = int(round(t_end / dt))
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.hllc_step(prm, r, m, e, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nnz = ctx.nnz
+    ctx.close()
+    x = w.pos[0].astype(np.float64)
+    t = steps * dt
+    exact = 1.0 + f["amplitude"] * np.sin(2 * np.pi * (x - f["U"] * t))
+    rho = r.double().cpu().numpy()
+    return {"n_particles": w.n, "nnz": nnz, "steps": steps, "ms_per_step": ms / steps,
+            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3),
+            "density_rel_l2_err": float(np.linalg.norm(rho - exact) / np.linalg.norm(exact - 1.0))}
+
+
+def compressible_section(nside=512):
+    tw, sw = run_hllc(nside, 1.6), run_hllc(nside, 2.0)
+    return {"workload": f"density_wave_2d_{nside} (ideal gas, limited HLLC, a quarter period)",
+            "kappa1.6": tw, "kappa2": sw, "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
+            "err_ratio_tw_over_sw": tw["density_rel_l2_err"] / sw["density_rel_l2_err"]}
 
 
 def run_euler_3d(nside, kappa, steps, warmup):
@@ -499,6 +548,7 @@ def main():
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--plate", type=float, default=0.0, help="profile the TLSPH plate line only, at this cut-off")
     ap.add_argument("--shear", action="store_true", help="the double shear layer section only")
+    ap.add_argument("--compressible", action="store_true", help="the compressible (HLLC) section only")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
@@ -516,7 +566,7 @@ def main():
         return
     one_core = None
     default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup
-                       or args.plate or args.shear)
+                       or args.plate or args.shear or args.compressible)
     if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
         one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
 
@@ -549,6 +599,9 @@ def main():
         return
     if args.shear:
         print(json.dumps(shear_layer_section()), flush=True)
+        return
+    if args.compressible:
+        print(json.dumps(compressible_section()), flush=True)
         return
     if args.train_steps:
         print(json.dumps(run_train(args.train_steps)), flush=True)
@@ -613,6 +666,7 @@ def main():
                 "tip_deflection_tw_final": float(ht[-1]),
                 "tip_history_diff_over_sw_amplitude": float(np.abs(ht - hs).max() / np.abs(hs).max())}
         out["double_shear_layer"] = shear_layer_section()
+        out["compressible"] = compressible_section()
     if not args.no_relax:
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:
