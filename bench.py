@@ -272,6 +272,40 @@ def compressible_section(nside=512):
             "err_ratio_tw_over_sw": tw["density_rel_l2_err"] / sw["density_rel_l2_err"]}
 
 
+def error_analysis_section():
+    """Sec. 2.3.3 on the lattice (Fig. 2, upper panel) through the GPU's
+    gradient: L2 error of df/dx, f = exp(-x^2/0.1), at dp = D/10, D/20, D/40
+    with and without the correction, and the observed orders."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    out = {"function": "f = exp(-x^2/0.1), D = 2, h = 1.3 dp, lattice", "dp": ["D/10", "D/20", "D/40"]}
+    for kappa, tag in ((2.0, "SW"), (1.6, "TW")):
+        for corrected in (False, True):
+            errs = []
+            for nside in (10, 20, 40):
+                w = I.gradient_lattice_2d(nside)
+                ctx = S.Context(2)
+                ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=w.periodic),
+                                torch.as_tensor(w.pos, device="cuda"))
+                vol = torch.as_tensor(w.vol, device="cuda")
+                if corrected:
+                    ctx.correction_B(vol)
+                else:
+                    ctx.set_correction(vol, torch.eye(2, device="cuda").repeat(w.n, 1, 1).contiguous())
+                g = ctx.gradient(torch.as_tensor(w.fields["f"], device="cuda"))[0].double().cpu().numpy()
+                ctx.close()
+                ex = w.fields["dfdx"]
+                errs.append(float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
+            out[f"{tag} {'with' if corrected else 'without'} B"] = {
+                "l2": errs, "orders": [math.log2(errs[i] / errs[i + 1]) for i in range(2)]}
+    return out
+
+
 def run_euler_3d(nside, kappa, steps, warmup):
     """3-D Taylor-Green in the periodic unit cube (nside^3 particles)."""
     import torch
@@ -667,6 +701,7 @@ def main():
                 "tip_history_diff_over_sw_amplitude": float(np.abs(ht - hs).max() / np.abs(hs).max())}
         out["double_shear_layer"] = shear_layer_section()
         out["compressible"] = compressible_section()
+        out["error_analysis_lattice"] = error_analysis_section()
     if not args.no_relax:
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:

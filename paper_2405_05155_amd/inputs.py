@@ -136,6 +136,24 @@ def adversarial_ties_2d(kappa: float = 2.0, nside: int = 64, seed: int = 0):
                     meta={"dx": dx, "quantum": q, "m": m, "rc_exact": m * q})
 
 
+def gradient_lattice_2d(nside: int) -> Workload:
+    """The error analysis of Sec. 2.3.3 on the lattice distribution: dp = D /
+    nside with D = 2, h = 1.3 dp, f = exp(-x^2 / 0.1).  The lattice fills the
+    periodic square [-1, 1)^2 around the paper's circle of diameter 2 (every
+    particle an interior one, as for Table 1's lattice row; f is periodic to
+    exp(-10) there)."""
+    pos, dp = lattice(nside, 2, L=2.0, lo=-1.0)
+    q = quantum_for(1.0)
+    pos = wrap_periodic(pos, -1.0, 1.0, q)
+    vol = np.full(pos.shape[1], dp * dp)
+    x = pos[0].astype(np.float32).astype(np.float64)
+    f = np.exp(-x ** 2 / 0.1)
+    w = Workload(name=f"gradient_lattice_{nside}", dim=2, pos=pos.astype(np.float32), vol=vol.astype(np.float32),
+                 h=1.3 * dp, lo=(-1.0, -1.0), hi=(1.0, 1.0), periodic=(1, 1), meta={"dx": dp, "quantum": q})
+    w.fields = {"f": f.astype(np.float32), "dfdx": (-20.0 * x * f)}
+    return w
+
+
 # ------------------------------------------------------------------ C1 / C4b
 
 def taylor_green_2d(nside: int = 512, c: float = 10.0, nu: float = 0.01) -> Workload:

@@ -169,6 +169,33 @@ def test_corrected_gradient(S, kappa):
         scaled_check(g, ref, scale[None, :], RTOL, f"gradient {name}")
 
 
+@pytest.mark.parametrize("corrected", [False, True])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_gradient_error_analysis_lattice(S, kappa, corrected):
+    """The error analysis of Sec. 2.3.3 on the lattice (Fig. 2, upper panel):
+    the GPU's gradient of f = exp(-x^2/0.1) at dp = D/10, D/20, D/40, with
+    the correction or with B = I, per element against the oracle, and its
+    L2 error of df/dx (Eq. 10) within 1e-4 of the oracle's."""
+    for nside in (10, 20, 40):
+        w = I.gradient_lattice_2d(nside)
+        ctx = gpu_ctx(S, w, kappa)
+        box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+        if corrected:
+            ctx.correction_B(dev(w.vol))
+        else:
+            Bo = np.tile(np.eye(2), (w.n, 1, 1))
+            ctx.set_correction(dev(w.vol), dev(Bo.astype(np.float32)))
+        f = w.fields["f"]
+        g = host(ctx.gradient(dev(f)))
+        ref = O.gradient(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol, Bo, f)
+        scale = _grad_scale(w, box, rp, col, Bo, f.astype(np.float64), w.h)
+        scaled_check(g, ref, scale[None, :], RTOL, f"gradient {nside}")
+        ex = w.fields["dfdx"]
+        e_gpu = np.linalg.norm(g[0] - ex) / np.linalg.norm(ex)
+        e_ref = np.linalg.norm(ref[0] - ex) / np.linalg.norm(ex)
+        assert abs(e_gpu - e_ref) < 1e-4 * e_ref
+
+
 # ------------------------------------------------------------------ Eulerian RHS
 
 def _euler_prm(S, w, dt=0.0):

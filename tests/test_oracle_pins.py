@@ -137,6 +137,40 @@ def test_table1_lattice_row(kappa, printed, value):
     assert abs(S[0] - value) < 5e-7
 
 
+def _fig2_lattice_errors(kappa, corrected):
+    """L2 error (Eq. 10) of df/dx, f = exp(-x^2/0.1), on the lattice of the
+    error analysis at dp = D/10, D/20, D/40 (weak-form gradient; on a lattice
+    it equals B sum_j (f_j - f_i) grad W_ij V_j, B = I without correction)."""
+    errs = []
+    for nside in (10, 20, 40):
+        w = I.gradient_lattice_2d(nside)
+        box = O.make_box(2, lo=w.lo, hi=w.hi, periodic=w.periodic)
+        rc = kappa * w.h
+        rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+        if corrected:
+            B, _ = O.correction_B(box, w.pos, W, w.h, rp, col, w.vol)
+        else:
+            B = np.tile(np.eye(2), (w.n, 1, 1))
+        g = O.gradient(box, w.pos, W, w.h, rp, col, w.vol, B, w.fields["f"])
+        ex = w.fields["dfdx"]
+        errs.append(np.linalg.norm(g[0] - ex) / np.linalg.norm(ex))
+    return errs
+
+
+def test_fig2_lattice_panel():
+    """Fig. 2, lattice panel (values not printed; its stated findings): the
+    truncation adds error without the correction ("TW Without B" above "SW
+    Without B"); with it the two cut-offs give very similar errors and
+    nearly second-order convergence."""
+    sw0, tw0 = _fig2_lattice_errors(2.0, False), _fig2_lattice_errors(1.6, False)
+    sw1, tw1 = _fig2_lattice_errors(2.0, True), _fig2_lattice_errors(1.6, True)
+    assert tw0[-1] > 1.5 * sw0[-1]
+    assert abs(tw1[-1] - sw1[-1]) < 0.15 * sw1[-1]
+    for e in (sw1, tw1):
+        assert math.log2(e[1] / e[2]) > 1.8
+        assert e[2] < e[1] < e[0]
+
+
 def _count_lattice(radius2, dim):
     r = int(math.isqrt(int(radius2)) + 2)
     rng = range(-r, r + 1)
