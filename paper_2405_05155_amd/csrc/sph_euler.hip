@@ -1,12 +1,16 @@
-// sph_euler.hip -- Riemann-based Eulerian SPH (Eq. 19, mass and momentum
-// rows) with the corrected gradient (Eq. 28) and the limited linearised
-// Riemann solver (Eqs. 26-27), and its Heun time stepping.
+// sph_euler.hip -- Riemann-based Eulerian SPH (Eq. 19) with the corrected
+// gradient (Eq. 28) and its Heun time stepping: the weakly compressible
+// mass and momentum rows with the limited linearised Riemann solver
+// (Eqs. 26-27), and (2-D) the compressible rows with the energy equation and
+// the limited HLLC solver (Eqs. 24-25, Sec. 3.1), one stage kernel for both.
 //
-// State layout: one float4 record per particle (drho, m_x, m_y, m_z), so a
-// neighbour's whole state is one 16-byte gather; geometry comes from the
-// context's cached records (position, V, B upper triangle).  All records
-// live in cell-sorted (Morton) order; the caller's arrays are gathered in
-// and scattered out at the caller index.
+// State layout: one float4 conserved record per particle ((drho, m) or, for
+// the compressible rows, (rho, m_x, m_y, E)) and one float4 primitive record
+// ((drho, v) or (rho, v_x, v_y, p)), so a neighbour's whole state is one
+// 16-byte gather; geometry comes from the context's cached records
+// (position, V, B upper triangle).  All records live in cell-sorted (Morton)
+// order; the caller's arrays are gathered in and scattered out at the caller
+// index.
 #include "sph_internal.h"
 
 #include <cstdlib>
