@@ -265,11 +265,43 @@ def run_hllc(nside, kappa, t_end=0.25):
             "density_rel_l2_err": float(np.linalg.norm(rho - exact) / np.linalg.norm(exact - 1.0))}
 
 
+def sod_error(kappa, nx=512):
+    """Sod's shock tube in a periodic strip (nx x 16) to t = 0.1 on the GPU:
+    mean density error on [1/2, 1) against the exact solution (not timed)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    from paper_2405_05155_amd.exact import sod_density
+    w = I.sod_strip_2d(nx)
+    f = w.fields
+    ctx = S.Context(2)
+    ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=w.periodic),
+                    torch.as_tensor(w.pos, device="cuda"))
+    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    dt = w.meta["dt"]
+    steps = int(round(0.1 / dt))
+    r = torch.as_tensor(f["rho"], device="cuda").clone()
+    m = torch.as_tensor(f["mom"], device="cuda").clone()
+    e = torch.as_tensor(f["E"], device="cuda").clone()
+    ctx.hllc_step(S.hllc_params(f["gamma"], f["eta"], dt), r, m, e, steps)
+    rho = r.double().cpu().numpy()
+    ctx.close()
+    x = w.pos[0].astype(np.float64)
+    sel = x >= 0.5
+    exact = np.array([sod_density((xx - 0.75) / (steps * dt)) for xx in x[sel]])
+    return float(np.mean(np.abs(rho[sel] - exact)))
+
+
 def compressible_section(nside=512):
     tw, sw = run_hllc(nside, 1.6), run_hllc(nside, 2.0)
+    sod_tw, sod_sw = sod_error(1.6), sod_error(2.0)
     return {"workload": f"density_wave_2d_{nside} (ideal gas, limited HLLC, a quarter period)",
             "kappa1.6": tw, "kappa2": sw, "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
-            "err_ratio_tw_over_sw": tw["density_rel_l2_err"] / sw["density_rel_l2_err"]}
+            "err_ratio_tw_over_sw": tw["density_rel_l2_err"] / sw["density_rel_l2_err"],
+            "sod_512x16_t0.1": {"mean_density_err_tw": sod_tw, "mean_density_err_sw": sod_sw,
+                                "reference": "exact Riemann solution"}}
 
 
 def error_analysis_section():

@@ -210,6 +210,35 @@ def density_wave_2d(nside: int = 512, amplitude: float = 0.1, U: float = 1.0, p0
     return w
 
 
+def sod_strip_2d(nx: int = 256, ny: int = 16, gamma: float = 1.4) -> Workload:
+    """Sod's shock tube in a periodic strip [0, 1) x [0, ny/nx) of lattice
+    particles, h = 1.3 dx: rho = 1, p = 1 for 1/4 <= x < 3/4, rho = 0.125,
+    p = 0.1 elsewhere, at rest (two mirror-image Riemann problems at x = 1/4
+    and 3/4 whose waves do not meet before t = 0.2).  Powers of two for nx
+    and ny keep dx and the strip height exact."""
+    dx = 1.0 / nx
+    xs = (np.arange(nx) + 0.5) * dx
+    ys = (np.arange(ny) + 0.5) * dx
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    pos = np.stack([X.T.reshape(-1), Y.T.reshape(-1)])
+    q = quantum_for(1.0)
+    hi_y = ny * dx
+    pos = np.stack([wrap_periodic(pos[0], 0.0, 1.0, q), wrap_periodic(pos[1], 0.0, hi_y, q)])
+    x = pos[0]
+    inside = (x >= 0.25) & (x < 0.75)
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    E = p / (gamma - 1.0)
+    w = Workload(name=f"sod_strip_{nx}x{ny}", dim=2, pos=pos.astype(np.float32),
+                 vol=np.full(pos.shape[1], dx * dx, dtype=np.float32), h=1.3 * dx, lo=(0.0, 0.0),
+                 hi=(1.0, hi_y), periodic=(1, 1), meta={"dx": dx, "quantum": q})
+    w.fields = {"rho": rho.astype(np.float32), "mom": np.zeros((2, w.n), np.float32), "E": E.astype(np.float32),
+                "gamma": gamma, "eta": 1.0}
+    c_max = math.sqrt(gamma)
+    w.meta["dt"] = 0.3 * w.h / c_max
+    return w
+
+
 def taylor_green_3d(nside: int = 200, c: float = 10.0, nu: float = 0.01) -> Workload:
     """3-D Taylor-Green field in the periodic unit cube, exact lattice,
     h = 1.3 dx; u = sin cos cos, v = -cos sin cos, w = 0,

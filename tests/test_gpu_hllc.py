@@ -106,6 +106,33 @@ def test_hllc_steps_density_wave(S, kappa):
     assert normwise(host(e), e50) < 1e-5
 
 
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_hllc_sod_shock_tube(S, kappa):
+    """Sod's shock tube (strip 256 x 16): rates of the discontinuous initial
+    state per element, then the run to t = 0.1 (78 Heun steps) against the
+    oracle's run, normwise."""
+    w = I.sod_strip_2d(256)
+    f = w.fields
+    dt = w.meta["dt"]
+    ctx = _ctx(S, w, kappa)
+    prm = S.hllc_params(GAMMA, 1.0, dt)
+    box, rp, col, B = _oracle_geometry(w, kappa)
+    po = O.hllc_params(GAMMA, 1.0, dt)
+    dr, dm, de = ctx.hllc_rhs(prm, dev(f["rho"]), dev(f["mom"]), dev(f["E"]))
+    r_dr, r_dm, r_de, s_dr, s_dm, s_de = O.hllc_rhs(box, w.pos, w.h, rp, col, w.vol, B, po, f["rho"], f["mom"],
+                                                    f["E"])
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+    scaled_check(host(de), r_de, s_de, RTOL, "dE/dt")
+    steps = int(round(0.1 / dt))
+    r, m, e = dev(f["rho"]), dev(f["mom"]), dev(f["E"])
+    ctx.hllc_step(prm, r, m, e, steps)
+    ro, mo, eo = O.hllc_heun(box, w.pos, w.h, rp, col, w.vol, B, po, f["rho"], f["mom"], f["E"], steps)
+    assert normwise(host(r), ro) < 1e-3
+    assert normwise(host(m), mo) < 1e-3
+    assert normwise(host(e), eo) < 1e-3
+
+
 def test_hllc_arguments(S):
     w = I.density_wave_2d(nside=16)
     ctx = _ctx(S, w, 1.6)

@@ -3,14 +3,18 @@ ideal gas) against things other than itself: special states of the Riemann
 problem whose answer is known without the solver (equal states, supersonic
 pairs, a symmetric collision, mirror symmetry), invariants of the discrete
 equations (zero rates for a uniform state on a lattice, conservation of
-mass, momentum and energy) and the exact solution of an advected density
-wave.
+mass, momentum and energy), the exact solution of an advected density wave
+and the exact solution of Sod's shock tube (paper_2405_05155_amd/exact.py,
+the textbook exact Riemann solver, which shares nothing with the oracle).
 """
+import math
+
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2405_05155_amd import inputs as I
+from paper_2405_05155_amd.exact import sod_density as _exact_sod_density
 
 GAMMA = 1.4
 
@@ -108,7 +112,7 @@ def test_mirror_symmetry(dim):
 
 
 def _setup(w, kappa):
-    box = O.make_box(2, periodic=(1, 1))
+    box = O.make_box(2, lo=w.lo, hi=w.hi, periodic=w.periodic)
     rc = kappa * w.h
     rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
     B, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
@@ -186,3 +190,36 @@ def test_density_wave_is_advected(kappa):
     assert e48 < 0.1 and e96 < 0.6 * e48
     assert max(p48, p96) < 1e-3 and max(v48, v96) < 1e-3
     assert max(d48 + d96) < 1e-11
+
+
+def _sod_error(nx, kappa):
+    w = I.sod_strip_2d(nx)
+    box, rp, col, B = _setup(w, kappa)
+    f = w.fields
+    dt = w.meta["dt"]
+    steps = int(round(0.1 / dt))
+    t = steps * dt
+    rho, mom, E = O.hllc_heun(box, w.pos, w.h, rp, col, w.vol, B, O.hllc_params(GAMMA, 1.0, dt),
+                              f["rho"], f["mom"], f["E"], steps)
+    x = w.pos[0].astype(np.float64)
+    sel = x >= 0.5
+    exact = np.array([_exact_sod_density((xx - 0.75) / t) for xx in x[sel]])
+    V = w.vol.astype(np.float64)
+    drift = (abs(np.sum(V * rho) - np.sum(V * f["rho"].astype(np.float64))),
+             abs(np.sum(V * E) - np.sum(V * f["E"].astype(np.float64))))
+    return float(np.mean(np.abs(rho[sel] - exact))), drift
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_sod_shock_tube(kappa):
+    """Sod's shock tube in a periodic strip: at t = 0.1 the densities on
+    [1/2, 1) (the Riemann problem at x = 3/4: rarefaction, contact, shock)
+    follow the exact solution with a mean error below 1.5e-2 at dx = 1/256
+    that falls at 1/512, with mass and energy conserved.  The exact sampler
+    reproduces the textbook star densities 0.42632 and 0.26557."""
+    assert abs(_exact_sod_density(0.5) - 0.42632) < 1e-4
+    assert abs(_exact_sod_density(1.5) - 0.26557) < 1e-4
+    e256, d256 = _sod_error(256, kappa)
+    e512, d512 = _sod_error(512, kappa)
+    assert e256 < 1.5e-2 and e512 < 0.75 * e256
+    assert max(d256 + d512) < 1e-11
