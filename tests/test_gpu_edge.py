@@ -47,6 +47,11 @@ def test_empty_configuration_every_call(S, dim):
     ctx.euler_step(prm, vol, vec, 3)
     ctx.set_tiling(S.TILING_ON)
     ctx.euler_step(prm, vol, vec, 3)
+    if dim == 2:
+        hp = S.hllc_params(1.4, 1.0, 1e-4)
+        dr, dm, de = ctx.hllc_rhs(hp, vol, vec, vol)
+        assert dr.numel() == 0 and dm.numel() == 0 and de.numel() == 0
+        ctx.hllc_step(hp, vol, vec, vol, 3)
     if dim == 3:
         tp = S.tlsph_params(1000.0, 2e6, 0.3975, dt=1e-6, model=0)
         F = torch.empty((0, 3, 3), device="cuda")
@@ -119,3 +124,17 @@ def test_isolated_particles_and_lone_pair(S, kappa):
     scaled_check(host(dr), r_dr, s_dr, 1e-5, "drho/dt")
     scaled_check(host(dm), r_dm, s_dm, 1e-5, "dmom/dt")
     assert np.all(host(dr)[:3] == 0.0) and np.all(host(dm)[:, :3] == 0.0)
+    # the compressible rows on the same particles
+    rng = np.random.default_rng(8)
+    rho_c = rng.uniform(0.5, 2.0, n)
+    v = rng.normal(size=(2, n))
+    p_c = rng.uniform(0.5, 2.0, n)
+    E = p_c / 0.4 + 0.5 * rho_c * (v ** 2).sum(0)
+    rho_c, mom_c, E = rho_c.astype(np.float32), (rho_c * v).astype(np.float32), E.astype(np.float32)
+    dr, dm, de = ctx.hllc_rhs(S.hllc_params(1.4, 1.0), dev(rho_c), dev(mom_c), dev(E))
+    r_dr, r_dm, r_de, s_dr, s_dm, s_de = O.hllc_rhs(box, pos, h, rp_o, col_o, vol, B_o, O.hllc_params(1.4, 1.0),
+                                                    rho_c, mom_c, E)
+    scaled_check(host(dr), r_dr, s_dr, 1e-5, "hllc drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, 1e-5, "hllc dmom/dt")
+    scaled_check(host(de), r_de, s_de, 1e-5, "hllc dE/dt")
+    assert np.all(host(dr)[:3] == 0.0) and np.all(host(de)[:3] == 0.0)
