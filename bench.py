@@ -335,6 +335,47 @@ def error_analysis_section():
                 errs.append(float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
             out[f"{tag} {'with' if corrected else 'without'} B"] = {
                 "l2": errs, "orders": [math.log2(errs[i] / errs[i + 1]) for i in range(2)]}
+    out["lg_relaxed_sphere"] = relaxed_sphere_errors()
+    return out
+
+
+def relaxed_sphere_errors(nsides=(16, 32, 64)):
+    """Fig. 2's LG-relaxed panel on the 3-D sphere: the seed-2 fill at
+    dx = 1/nside relaxed on the GPU to R < 1e-4, then the GPU's gradient of
+    f = exp(-((x - c)/R)^2/0.1) with and without the correction: L2 error of
+    df/dx and the observed orders."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2405_05155_amd import inputs as I
+    from paper_2405_05155_amd import sph as S
+    from paper_2405_05155_amd import warmstart as WS
+    errs = {}
+    for nside in nsides:
+        w = I.sphere_fill(dx=1.0 / nside, seed=2)
+        rctx = S.Context(3)
+        run, pos, _ = WS.relax_plain(rctx, w)
+        rctx.close()
+        p = pos.cpu().numpy()
+        f, ex = I.sphere_gradient_fields(p, w.fields["center"], w.fields["radius"])
+        for kappa, tag in ((2.0, "SW"), (1.6, "TW")):
+            ctx = S.Context(3)
+            ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, periodic=(0, 0, 0)), pos)
+            vol = torch.as_tensor(w.vol, device="cuda")
+            for corrected in (False, True):
+                if corrected:
+                    ctx.correction_B(vol)
+                else:
+                    ctx.set_correction(vol, torch.eye(3, device="cuda").repeat(w.n, 1, 1).contiguous())
+                g = ctx.gradient(torch.as_tensor(f.astype(np.float32), device="cuda"))[0].double().cpu().numpy()
+                errs.setdefault(f"{tag} {'with' if corrected else 'without'} B", []).append(
+                    float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
+            ctx.close()
+    out = {"dx": [f"1/{k}" for k in nsides], "radius": 0.3}
+    for k, v in errs.items():
+        out[k] = {"l2": v, "orders": [math.log2(v[i] / v[i + 1]) for i in range(len(v) - 1)]}
     return out
 
 

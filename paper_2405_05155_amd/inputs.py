@@ -154,6 +154,15 @@ def gradient_lattice_2d(nside: int) -> Workload:
     return w
 
 
+def sphere_gradient_fields(pos, center, radius):
+    """The error analysis's test function on a filled sphere, scaled to its
+    radius: f = exp(-((x - c_x) / R)^2 / 0.1) (the paper's exp(-x^2/0.1) on a
+    circle of radius 1) and df/dx, at FP32 positions pos [3][n]."""
+    x = (np.asarray(pos, dtype=np.float32).astype(np.float64)[0] - center[0]) / radius
+    f = np.exp(-x ** 2 / 0.1)
+    return f, -2.0 * x / (0.1 * radius) * f
+
+
 # ------------------------------------------------------------------ C1 / C4b
 
 def taylor_green_2d(nside: int = 512, c: float = 10.0, nu: float = 0.01) -> Workload:

@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle as O
+from paper_2405_05155_amd import inputs as I
 
 
 def scaled_check(gpu, ref, scale, rtol, name):
@@ -64,3 +65,22 @@ def sample_rows(n, k, seed):
     rng = np.random.default_rng(seed)
     rows = np.unique(np.concatenate([[0, n - 1], rng.choice(n, size=min(k, n), replace=False)]))
     return rows.astype(np.int64)
+
+
+def oracle_lg_relaxed_sphere(nside, tol=1e-4, max_iter=400):
+    """The oracle's LG relaxation of the seed-2 sphere fill at dx = 1/nside
+    until R < tol (a fresh neighbour search every iteration)."""
+    w = I.sphere_fill(dx=1.0 / nside, seed=2)
+    box = O.make_box(3, periodic=(0, 0, 0))
+    f = w.fields
+    prm = O.relax_params(w.h, f["center"], f["radius"])
+    pos = w.pos.astype(np.float64)
+    u = np.zeros_like(pos)
+    rc = 2.0 * w.h
+    for _ in range(max_iter):
+        rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+        new, u, r, _ = O.relax_step(box, pos, u, prm, rp, col, w.vol)
+        if r < tol:
+            break
+        pos = new
+    return w, box, pos.astype(np.float32)

@@ -13,6 +13,7 @@ import pytest
 from scipy import integrate
 
 import oracle as O
+from gpu_helpers import oracle_lg_relaxed_sphere
 from paper_2405_05155_amd import inputs as I
 
 W, LG = O.WENDLAND, O.LAGUERRE_GAUSS
@@ -169,6 +170,37 @@ def test_fig2_lattice_panel():
     for e in (sw1, tw1):
         assert math.log2(e[1] / e[2]) > 1.8
         assert e[2] < e[1] < e[0]
+
+
+def _relaxed_sphere_errors(nsides=(16, 32, 64)):
+    """L2 error of df/dx on LG-relaxed spheres, per (kappa, corrected)."""
+    out = {}
+    for nside in nsides:
+        w, box, pos = oracle_lg_relaxed_sphere(nside)
+        f, ex = I.sphere_gradient_fields(pos, w.fields["center"], w.fields["radius"])
+        for kappa in (2.0, 1.6):
+            rc = kappa * w.h
+            rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+            Bc, _ = O.correction_B(box, pos, W, w.h, rp, col, w.vol)
+            for corrected, B in ((False, np.tile(np.eye(3), (w.n, 1, 1))), (True, Bc)):
+                g = O.gradient(box, pos, W, w.h, rp, col, w.vol, B, f.astype(np.float32))
+                out.setdefault((kappa, corrected), []).append(np.linalg.norm(g[0] - ex) / np.linalg.norm(ex))
+    return out
+
+
+def test_fig2_lg_relaxed_panel_in_3d():
+    """Fig. 2's bottom panel (LG-relaxed distribution; values not printed),
+    on the 3-D sphere the relaxation here fills (dx = R/4.8, R/9.6, R/19.2,
+    about D/10, D/20, D/40): without the correction the truncated kernel's
+    error is larger; with it the two cut-offs give the same level of error
+    and nearly second-order convergence."""
+    e = _relaxed_sphere_errors()
+    sw0, tw0, sw1, tw1 = e[(2.0, False)], e[(1.6, False)], e[(2.0, True)], e[(1.6, True)]
+    assert tw0[-1] > 1.2 * sw0[-1]
+    assert abs(tw1[-1] - sw1[-1]) < 0.15 * sw1[-1]
+    for v in (sw1, tw1):
+        assert v[2] < v[1] < v[0]
+        assert math.log2(v[1] / v[2]) > 1.7
 
 
 def _count_lattice(radius2, dim):
