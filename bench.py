@@ -336,14 +336,18 @@ def error_analysis_section():
             out[f"{tag} {'with' if corrected else 'without'} B"] = {
                 "l2": errs, "orders": [math.log2(errs[i] / errs[i + 1]) for i in range(2)]}
     out["lg_relaxed_sphere"] = relaxed_sphere_errors()
+    out["wendland_relaxed_sphere"] = relaxed_sphere_errors(kernel="Wendland")
     return out
 
 
-def relaxed_sphere_errors(nsides=(16, 32, 64)):
-    """Fig. 2's LG-relaxed panel on the 3-D sphere: the seed-2 fill at
-    dx = 1/nside relaxed on the GPU to R < 1e-4, then the GPU's gradient of
-    f = exp(-((x - c)/R)^2/0.1) with and without the correction: L2 error of
-    df/dx and the observed orders."""
+def relaxed_sphere_errors(nsides=(16, 32, 64), kernel="LG", iters=400):
+    """Fig. 2's relaxed panels on the 3-D sphere: the seed-2 fill at
+    dx = 1/nside relaxed on the GPU (LG: to R < 1e-4; Wendland: `iters`
+    iterations, the budget in which LG gets there), then the GPU's gradient
+    of f = exp(-((x - c)/R)^2/0.1) with and without the correction: L2 error
+    of df/dx and the observed orders.  At the coarsest dx also Table 1's
+    row: the kernel-sum error (f = 1, no correction) over the particles
+    whose support lies inside the sphere."""
     import math
 
     import numpy as np
@@ -352,18 +356,34 @@ def relaxed_sphere_errors(nsides=(16, 32, 64)):
     from paper_2405_05155_amd import inputs as I
     from paper_2405_05155_amd import sph as S
     from paper_2405_05155_amd import warmstart as WS
-    errs = {}
+    errs, residues, table1 = {}, [], {}
     for nside in nsides:
         w = I.sphere_fill(dx=1.0 / nside, seed=2)
         rctx = S.Context(3)
-        run, pos, _ = WS.relax_plain(rctx, w)
+        vol = torch.as_tensor(w.vol, device="cuda")
+        if kernel == "LG":
+            run, pos, _ = WS.relax_plain(rctx, w)
+            residues.append(run.residue)
+        else:
+            dom, prm = WS.setup(w, kernel=S.WENDLAND)
+            pos = torch.as_tensor(w.pos, device="cuda").clone()
+            u = torch.zeros_like(pos)
+            res = torch.zeros(1, dtype=torch.float64, device="cuda")
+            rctx.relax_step(dom, prm, pos, u, vol, iters, res)
+            r, _ = rctx.relax_residue(dom, prm, pos, vol, want_g=False)
+            residues.append(float(r.item()))
         rctx.close()
         p = pos.cpu().numpy()
         f, ex = I.sphere_gradient_fields(p, w.fields["center"], w.fields["radius"])
+        c = np.asarray(w.fields["center"], dtype=np.float64)[:, None]
+        inner = np.sqrt(((p.astype(np.float64) - c) ** 2).sum(0)) < w.fields["radius"] - 2.0 * w.h
         for kappa, tag in ((2.0, "SW"), (1.6, "TW")):
             ctx = S.Context(3)
             ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, periodic=(0, 0, 0)), pos)
-            vol = torch.as_tensor(w.vol, device="cuda")
+            if nside == nsides[0]:
+                ks = ctx.kernel_sum(vol).double().cpu().numpy()[inner]
+                table1[tag] = math.sqrt(float(np.mean((ks - 1.0) ** 2)))   # Eq. (10), phi = 1
+                table1["interior_particles"] = int(inner.sum())
             for corrected in (False, True):
                 if corrected:
                     ctx.correction_B(vol)
@@ -373,9 +393,12 @@ def relaxed_sphere_errors(nsides=(16, 32, 64)):
                 errs.setdefault(f"{tag} {'with' if corrected else 'without'} B", []).append(
                     float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
             ctx.close()
-    out = {"dx": [f"1/{k}" for k in nsides], "radius": 0.3}
+    out = {"dx": [f"1/{k}" for k in nsides], "radius": 0.3, "relaxation": kernel,
+           "iterations": "to R < 1e-4" if kernel == "LG" else iters, "final_residue": residues}
     for k, v in errs.items():
         out[k] = {"l2": v, "orders": [math.log2(v[i] / v[i + 1]) for i in range(len(v) - 1)]}
+    printed = {"LG": [0.037, 0.031], "Wendland": [0.034, 0.028]}[kernel]
+    out["table1_kernel_sum"] = dict(table1, dx=f"1/{nsides[0]}", printed_sw_tw=printed)
     return out
 
 

@@ -226,11 +226,13 @@ int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fix
                    float* vel, float* F, float* acc, int32_t nsteps);
 
 /* ---------------------------------------------------------------- particle relaxation
- * Laguerre-Gauss particle relaxation (Eq. 7 with the kernel of Eq. 8, 3-D)
- * of particles filling the sphere |r - center| < radius.  The residual
- * force of particle i is
- *   g_i = sum_{j : |r_ij| <= 2h} grad W^LG_ij V_j + T(rho_i) e_i,
- * where the second term is the integral of grad W^LG over the exterior of
+ * Particle relaxation (Eq. 7, 3-D) of particles filling the sphere
+ * |r - center| < radius, with the Laguerre-Gauss kernel of Eq. 8 or the
+ * Wendland C2 kernel of Eq. 6 at its full support (the two relaxed
+ * distributions of the error analysis, Sec. 2.3.3).  The residual force of
+ * particle i is
+ *   g_i = sum_{j : |r_ij| <= 2h} grad W_ij V_j + T(rho_i) e_i,
+ * where the second term is the integral of grad W over the exterior of
  * the sphere within the support (rho_i = |r_i - c|, e_i = (r_i - c)/rho_i;
  * the paper's relaxation has no boundary term: this one makes a uniform
  * fill up to the surface force-free).  T is tabulated on the host in FP64
@@ -243,8 +245,8 @@ int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fix
  * The residue of a configuration is R = sqrt(mean_i |h g_i|^2), reduced in
  * FP64 (two-stage, fixed order: deterministic).
  * The domain supplies h and the box of the cell grid (dom->kernel and
- * dom->kappa are ignored: the call always uses the LG kernel with cut-off
- * 2h). */
+ * dom->kappa are ignored: the kernel is prm->kernel, the cut-off 2h).
+ * SPH_ERR_ARG for a kernel other than the two. */
 typedef struct {
     double p0;          /* background pressure of Eq. (7) */
     double rho;         /* density of Eq. (7) */
@@ -253,6 +255,7 @@ typedef struct {
     double kappa;       /* step coefficient (0.1) */
     double damping;     /* carried-displacement factor (0.9) */
     double max_move;    /* cap on |u_i| per iteration in units of h (0.1) */
+    int32_t kernel;     /* SPH_LAGUERRE_GAUSS or SPH_WENDLAND (set it: 0 is Wendland) */
 } sph_relax_params;
 
 /* niter iterations in place.  pos FP32 [3][n] (in/out), u FP32 [3][n]

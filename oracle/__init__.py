@@ -57,7 +57,7 @@ class TlsphParams(C.Structure):
 class RelaxParams(C.Structure):
     _fields_ = [("p0", C.c_double), ("rho", C.c_double), ("h", C.c_double),
                 ("center", C.c_double * 3), ("radius", C.c_double),
-                ("kappa", C.c_double), ("mu", C.c_double), ("max_move", C.c_double)]
+                ("kappa", C.c_double), ("mu", C.c_double), ("max_move", C.c_double), ("kernel", C.c_int)]
 
 
 _lib = None
@@ -309,10 +309,12 @@ def tlsph_step(box, pos0, h, row_ptr, col, vol0, B0, prm, fixed, pos, vel, F, ac
     return pos, vel, F, acc
 
 
-def relax_params(h, center, radius, p0=1.0, rho=1.0, kappa=0.1, mu=0.9, max_move=0.1) -> RelaxParams:
+def relax_params(h, center, radius, p0=1.0, rho=1.0, kappa=0.1, mu=0.9, max_move=0.1,
+                 kernel=LAGUERRE_GAUSS) -> RelaxParams:
+    """kernel: LAGUERRE_GAUSS (Eq. 8) or WENDLAND (Eq. 6, support 2h)."""
     p = RelaxParams()
     p.p0, p.rho, p.h, p.radius = p0, rho, h, radius
-    p.kappa, p.mu, p.max_move = kappa, mu, max_move
+    p.kappa, p.mu, p.max_move, p.kernel = kappa, mu, max_move, kernel
     for a in range(3):
         p.center[a] = center[a]
     return p

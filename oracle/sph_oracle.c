@@ -914,18 +914,21 @@ void or_tlsph_step(const or_box* b, int64_t n, const double* pos0, double h,
 }
 
 /* ------------------------------------------------------------------ */
-/* Laguerre-Gauss particle relaxation inside a sphere                 */
+/* Particle relaxation inside a sphere (Eq. 7): Laguerre-Gauss kernel */
+/* (Eq. 8), or Wendland C2 (Eq. 6) at its full support 2h, the two    */
+/* relaxed distributions of the error analysis (Sec. 2.3.3)           */
 /* ------------------------------------------------------------------ */
 
 typedef struct {
     double p0;        /* background pressure of Eq. (7) */
     double rho;       /* density of Eq. (7) */
-    double h;         /* smoothing length; LG support radius 2h */
+    double h;         /* smoothing length; support radius 2h for both kernels */
     double center[3]; /* sphere centre */
     double radius;    /* sphere radius; SDF phi = |r - c| - R */
     double kappa;     /* step: displacement per unit acceleration, in h^2 rho / (2 p0) units */
     double mu;        /* damping factor of the carried displacement (0: none carried) */
     double max_move;  /* cap on |u_i| per iteration, in units of h */
+    int kernel;       /* OR_LAGUERRE_GAUSS or OR_WENDLAND */
 } or_relax_params;
 
 /* Exterior kernel-gradient integral for a sphere (a reading: the paper's
@@ -959,7 +962,7 @@ double or_relax_tail(const or_relax_params* prm, double rho_c)
             if (u0 < -1.0) u0 = -1.0;
             if (u0 > 1.0) u0 = 1.0;
             /* ds = 2 t dt */
-            f = -or_kernel_dWdr(OR_LAGUERRE_GAUSS, 3, h, s) * s * s * (1.0 - u0 * u0) * 2.0 * t;
+            f = -or_kernel_dWdr(prm->kernel, 3, h, s) * s * s * (1.0 - u0 * u0) * 2.0 * t;
         }
         double wgt = (k == 0 || k == NP) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
         acc += wgt * f;
@@ -967,8 +970,8 @@ double or_relax_tail(const or_relax_params* prm, double rho_c)
     return M_PI * acc * ht / 3.0;
 }
 
-/* Residual force of the relaxation, Eq. (7) with the LG kernel:
- *   g_i = sum_j grad W^LG_ij V_j + T(rho_i) e_i
+/* Residual force of the relaxation, Eq. (7) with the kernel of prm:
+ *   g_i = sum_j grad W_ij V_j + T(rho_i) e_i
  * (a_i = -(2 p0 / rho) g_i).  Neighbours at cutoff 2h, 3-D, non-periodic.
  * g[a*m + k]. */
 void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_params* prm,
@@ -983,7 +986,7 @@ void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_pa
         for (int64_t p = row_ptr[k]; p < row_ptr[k + 1]; ++p) {
             int64_t j = col[p];
             pair_vec(b, n, pos, i, j, d);
-            grad_w(OR_LAGUERRE_GAUSS, dim, prm->h, d, gw);
+            grad_w(prm->kernel, dim, prm->h, d, gw);
             for (int a = 0; a < dim; ++a) { s[a] += gw[a] * vol[j]; sa[a] += fabs(gw[a] * vol[j]); }
         }
         double e[3] = {0, 0, 0}, rc = 0.0;

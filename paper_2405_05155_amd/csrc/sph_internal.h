@@ -191,7 +191,7 @@ struct sph_ctx {
     // relaxation: exterior-tail table and reductions
     DevBuf tail;        // float [ntail]
     double tail_h = 0.0, tail_R = 0.0;
-    int ntail = 0;
+    int ntail = 0, tail_kernel = -1;
     DevBuf svol;        // cell-order scratch: volumes (pair loops) or (x, y, z, V) records (relaxation)
     DevBuf sfield;      // float [n] a caller field in cell order
     DevBuf partials;    // per-block reduction partials

@@ -1,6 +1,8 @@
-// sph_relax.hip -- Laguerre-Gauss particle relaxation (Eq. 7 with the
-// kernel of Eq. 8) of particles filling a sphere, with the exterior-tail
-// term, an FP64 residue reduction and the damped move + surface bound.
+// sph_relax.hip -- particle relaxation (Eq. 7) of particles filling a
+// sphere, with the Laguerre-Gauss kernel of Eq. 8 or the Wendland C2 kernel
+// of Eq. 6 at its full support 2h (the two relaxed distributions of the
+// error analysis, Sec. 2.3.3), with the exterior-tail term, an FP64 residue
+// reduction and the damped move + surface bound.
 //
 // Per iteration: re-bin (cells of edge >= h, linear (z, y, x) keys), one
 // thread per particle in cell order scans the 5 x 5 x 5 cells around its own
@@ -42,11 +44,12 @@ void gauss_legendre(int m, double* x, double* w) {
 }
 
 // T(phi) = pi int_{|phi|}^{2h} (-dW/ds) s^2 (1 - clamp(u0)^2) ds with
-// u0 = (R^2 - rho^2 - s^2)/(2 rho s), rho = R + phi; the LG kernel in 3-D.
+// u0 = (R^2 - rho^2 - s^2)/(2 rho s), rho = R + phi; the relaxation's
+// kernel in 3-D.
 // Substitution s = s0 + (2h - s0) tau^2 and graded Gauss-Legendre panels in
 // tau (dense near tau = 0, where the integrand rises steeply for particles
 // just inside the surface).
-double tail_integral(double h, double R, double phi) {
+double tail_integral(int kernel, double h, double R, double phi) {
     const double rho = R + phi;
     if (rho <= 0.0) return 0.0;
     const double s0 = std::fabs(phi), s1 = 2.0 * h;
@@ -58,7 +61,7 @@ double tail_integral(double h, double R, double phi) {
     static const GL16 gl;  // thread-safe one-time initialisation
     const double* gx = gl.x;
     const double* gw = gl.w;
-    const double a3 = 8.0 / std::pow(M_PI, 1.5) / (h * h * h);
+    const double a3 = kernel == SPH_WENDLAND ? 21.0 / (16.0 * M_PI * h * h * h) : 8.0 / std::pow(M_PI, 1.5) / (h * h * h);
     const double edges[] = {0.0, 1.0 / 128, 1.0 / 32, 1.0 / 8, 0.25, 0.5, 0.75, 1.0};
     const double span = s1 - s0;
     double acc = 0.0;
@@ -70,8 +73,15 @@ double tail_integral(double h, double R, double phi) {
             if (s <= 0.0) continue;
             double q = s / h;
             double q2 = q * q;
-            // -dW/ds = (a3 / (3 h)) q e^{-q^2} (12 - 8 q^2 + q^4)
-            double mdw = a3 / (3.0 * h) * q * std::exp(-q2) * (12.0 - 8.0 * q2 + q2 * q2);
+            double mdw;
+            if (kernel == SPH_WENDLAND) {
+                // -dW/ds = (a3 / h) 5 q (1 - q/2)^3
+                double t = 1.0 - 0.5 * q;
+                mdw = a3 / h * 5.0 * q * t * t * t;
+            } else {
+                // -dW/ds = (a3 / (3 h)) q e^{-q^2} (12 - 8 q^2 + q^4)
+                mdw = a3 / (3.0 * h) * q * std::exp(-q2) * (12.0 - 8.0 * q2 + q2 * q2);
+            }
             double u0 = (R * R - rho * rho - s * s) / (2.0 * rho * s);
             u0 = u0 < -1.0 ? -1.0 : (u0 > 1.0 ? 1.0 : u0);
             double f = mdw * s * s * (1.0 - u0 * u0) * 2.0 * span * tau;
@@ -81,17 +91,18 @@ double tail_integral(double h, double R, double phi) {
     return M_PI * acc;
 }
 
-int ensure_tail(sph_ctx* c, double h, double R) {
-    if (c->ntail == NTAIL && c->tail_h == h && c->tail_R == R && c->tail.p) return SPH_OK;
+int ensure_tail(sph_ctx* c, int kernel, double h, double R) {
+    if (c->ntail == NTAIL && c->tail_kernel == kernel && c->tail_h == h && c->tail_R == R && c->tail.p) return SPH_OK;
     std::vector<float> tab(NTAIL);
     for (int k = 0; k < NTAIL; ++k) {
         double phi = -2.0 * h + 4.0 * h * k / (NTAIL - 1);
-        tab[k] = (float)tail_integral(h, R, phi);
+        tab[k] = (float)tail_integral(kernel, h, R, phi);
     }
     SPH_HIP(c, c->tail.ensure(NTAIL * sizeof(float)));
     SPH_HIP(c, hipMemcpyAsync(c->tail.p, tab.data(), NTAIL * sizeof(float), hipMemcpyHostToDevice, c->stream));
     SPH_HIP(c, hipStreamSynchronize(c->stream));  // the host vector goes out of scope
     c->ntail = NTAIL;
+    c->tail_kernel = kernel;
     c->tail_h = h;
     c->tail_R = R;
     return SPH_OK;
@@ -108,7 +119,8 @@ constexpr int RELAX_DIV = 2;
 struct RelaxArgs {
     BoxArgs b;
     int D;           // cells per cut-off (the scan reaches D cells each way)
-    float cF;        // LG (dW/dr)/r = cF e^{-q^2} (12 - 8 q^2 + q^4)
+    float cF;        // (dW/dr)/r: LG cF e^{-q^2} (12 - 8 q^2 + q^4); Wendland cF (1 - q/2)^3
+    float hinv;      // 1/h
     float hinv2;     // 1/h^2
     float rc2f;      // (2h)^2 in FP32
     double rc2d;     // (2h)^2 in FP64
@@ -158,7 +170,20 @@ __device__ __forceinline__ float tail_at(const float* __restrict__ tail, const R
     return fmaf(f, tail[k + 1] - tail[k], tail[k]);
 }
 
+// (dW/dr)/r of the relaxation kernel at squared distance r2.
+template <int K>
+__device__ __forceinline__ float relax_dwr(float r2, const RelaxArgs& ra) {
+    if constexpr (K == SPH_WENDLAND) {
+        const float t = 1.f - 0.5f * (sqrtf(r2) * ra.hinv);
+        return ra.cF * t * t * t;
+    } else {
+        const float q2 = r2 * ra.hinv2;
+        return ra.cF * __expf(-q2) * (12.f - 8.f * q2 + q2 * q2);
+    }
+}
+
 // One slot range of candidates of particle s (slot) at p.
+template <int K>
 __device__ __forceinline__ void relax_range(int32_t t0, int32_t t1, int32_t s, const float4& p, const RelaxArgs& ra,
                                             const float4* __restrict__ rec, Kahan* g) {
     const BoxArgs& b = ra.b;
@@ -172,8 +197,7 @@ __device__ __forceinline__ void relax_range(int32_t t0, int32_t t1, int32_t s, c
         bool in = r2 <= ra.rc2f;
         if (fabsf(r2 - ra.rc2f) <= 1e-5f * ra.rc2f) in = exact_in(p, q, b, ra.rc2d);
         if (!in) continue;
-        const float q2 = r2 * ra.hinv2;
-        const float w = ra.cF * __expf(-q2) * (12.f - 8.f * q2 + q2 * q2) * q.w;
+        const float w = relax_dwr<K>(r2, ra) * q.w;
         g[0].add(w * d0);
         g[1].add(w * d1);
         g[2].add(w * d2);
@@ -186,6 +210,7 @@ __device__ __forceinline__ void relax_range(int32_t t0, int32_t t1, int32_t s, c
 // slot range, split in two where a periodic x axis wraps); the FP32 distance
 // test is redone in FP64 within 1e-5 of the cut-off.  rec holds (x, y, z, V)
 // per sorted slot, so a candidate costs one 16-byte load.
+template <int K>
 __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const int32_t* __restrict__ cell_start,
                                                  const float4* __restrict__ sorted, const float4* __restrict__ rec,
                                                  const float* __restrict__ tail, float4* __restrict__ gout,
@@ -216,17 +241,17 @@ __global__ void __launch_bounds__(BLK) k_relax_g(int32_t n, RelaxArgs ra, const 
                 int xa = cx - D, xb = cx + D;
                 if (b.periodic[0]) {  // nx >= 2 D + 1: at most one side wraps
                     if (xa < 0) {
-                        relax_range(cell_start[row + xa + nx], cell_start[row + nx], s, p, ra, rec, g);
+                        relax_range<K>(cell_start[row + xa + nx], cell_start[row + nx], s, p, ra, rec, g);
                         xa = 0;
                     } else if (xb >= nx) {
-                        relax_range(cell_start[row], cell_start[row + xb - nx + 1], s, p, ra, rec, g);
+                        relax_range<K>(cell_start[row], cell_start[row + xb - nx + 1], s, p, ra, rec, g);
                         xb = nx - 1;
                     }
                 } else {
                     xa = xa < 0 ? 0 : xa;
                     xb = xb > nx - 1 ? nx - 1 : xb;
                 }
-                relax_range(cell_start[row + xa], cell_start[row + xb + 1], s, p, ra, rec, g);
+                relax_range<K>(cell_start[row + xa], cell_start[row + xb + 1], s, p, ra, rec, g);
             }
         }
         // exterior-tail term
@@ -363,6 +388,8 @@ int check(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, int32_t 
         return sph_fail(c, SPH_ERR_ARG, "%s: need radius, p0, rho > 0", who);
     if (!(p->kappa > 0.0) || !(p->damping >= 0.0 && p->damping < 1.0) || !(p->max_move > 0.0))
         return sph_fail(c, SPH_ERR_ARG, "%s: need kappa > 0, 0 <= damping < 1, max_move > 0", who);
+    if (p->kernel != SPH_LAGUERRE_GAUSS && p->kernel != SPH_WENDLAND)
+        return sph_fail(c, SPH_ERR_ARG, "%s: kernel must be SPH_LAGUERRE_GAUSS or SPH_WENDLAND", who);
     return SPH_OK;
 }
 
@@ -371,8 +398,9 @@ RelaxArgs make_args(const sph_ctx* c, const sph_relax_params* p) {
     double h = c->dom.h;
     ra.b = c->box;
     ra.D = RELAX_DIV;
-    KernelConsts kc = make_kernel_consts(SPH_LAGUERRE_GAUSS, 3, h);
+    KernelConsts kc = make_kernel_consts(p->kernel, 3, h);
     ra.cF = kc.cF;
+    ra.hinv = kc.hinv;
     ra.hinv2 = (float)(1.0 / (h * h));
     ra.rc2d = c->rc2;
     ra.rc2f = (float)c->rc2;
@@ -394,11 +422,11 @@ RelaxArgs make_args(const sph_ctx* c, const sph_relax_params* p) {
 int relax_eval(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, int32_t n, const float* pos,
                const float* vol, double* residue, RelaxArgs* ra_out) {
     sph_domain d = *dom;
-    d.kernel = SPH_LAGUERRE_GAUSS;
+    d.kernel = p->kernel;
     d.kappa = 2.0;
     int r = sph_bin_cells_grid(c, &d, n, pos, RELAX_DIV, true);
     if (r) return r;
-    r = ensure_tail(c, d.h, p->radius);
+    r = ensure_tail(c, p->kernel, d.h, p->radius);
     if (r) return r;
     RelaxArgs ra = make_args(c, p);
     *ra_out = ra;
@@ -413,9 +441,14 @@ int relax_eval(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, int
     if (n > 0) {
         hipLaunchKernelGGL(k_sorted_rec, dim3(nb), dim3(BLK), 0, c->stream, n, c->sorted.as<float4>(), vol,
                            c->svol.as<float4>());
-        hipLaunchKernelGGL(k_relax_g, dim3(nb), dim3(BLK), 0, c->stream, n, ra, c->cell_start.as<int32_t>(),
-                           c->sorted.as<float4>(), c->svol.as<float4>(), c->tail.as<float>(), c->ta.as<float4>(),
-                           pmax, psum);
+        if (p->kernel == SPH_WENDLAND)
+            hipLaunchKernelGGL(k_relax_g<SPH_WENDLAND>, dim3(nb), dim3(BLK), 0, c->stream, n, ra,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->svol.as<float4>(),
+                               c->tail.as<float>(), c->ta.as<float4>(), pmax, psum);
+        else
+            hipLaunchKernelGGL(k_relax_g<SPH_LAGUERRE_GAUSS>, dim3(nb), dim3(BLK), 0, c->stream, n, ra,
+                               c->cell_start.as<int32_t>(), c->sorted.as<float4>(), c->svol.as<float4>(),
+                               c->tail.as<float>(), c->ta.as<float4>(), pmax, psum);
     }
     hipLaunchKernelGGL(k_relax_reduce, dim3(1), dim3(BLK), 0, c->stream, n > 0 ? nb : 0, n, ra, pmax, psum,
                        c->relax_scalars.as<RelaxScalars>(), residue);

@@ -50,7 +50,7 @@ class sph_tlsph_params(C.Structure):
 
 class sph_relax_params(C.Structure):
     _fields_ = [("p0", C.c_double), ("rho", C.c_double), ("center", C.c_double * 3), ("radius", C.c_double),
-                ("kappa", C.c_double), ("damping", C.c_double), ("max_move", C.c_double)]
+                ("kappa", C.c_double), ("damping", C.c_double), ("max_move", C.c_double), ("kernel", C.c_int32)]
 
 
 _lib = None
@@ -178,9 +178,12 @@ def tlsph_params(rho0, E, nu, dt=0.0, model=0) -> sph_tlsph_params:
     return p
 
 
-def relax_params(center, radius, p0=1.0, rho=1.0, kappa=0.1, damping=0.9, max_move=0.1) -> sph_relax_params:
+def relax_params(center, radius, p0=1.0, rho=1.0, kappa=0.1, damping=0.9, max_move=0.1,
+                 kernel=LAGUERRE_GAUSS) -> sph_relax_params:
+    """kernel: LAGUERRE_GAUSS (Eq. 8) or WENDLAND (Eq. 6, support 2h)."""
     p = sph_relax_params()
     p.p0, p.rho, p.radius, p.kappa, p.damping, p.max_move = p0, rho, radius, kappa, damping, max_move
+    p.kernel = kernel
     for a in range(3):
         p.center[a] = center[a]
     return p

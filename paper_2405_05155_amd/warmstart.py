@@ -30,10 +30,10 @@ class RelaxRun:
     attempted: int = 0
 
 
-def setup(w: Workload):
+def setup(w: Workload, kernel=S.LAGUERRE_GAUSS):
     f = w.fields
     dom = S.Domain(dim=3, h=w.h, kappa=2.0, lo=w.lo, hi=w.hi, periodic=(0, 0, 0), kernel=S.LAGUERRE_GAUSS)
-    prm = S.relax_params(f["center"], f["radius"], p0=f["p0"], rho=f["rho"])
+    prm = S.relax_params(f["center"], f["radius"], p0=f["p0"], rho=f["rho"], kernel=kernel)
     return dom, prm
 
 

@@ -2,6 +2,8 @@
 the scaled tolerance.  Imported by tests only."""
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 import oracle as O
@@ -67,20 +69,35 @@ def sample_rows(n, k, seed):
     return rows.astype(np.int64)
 
 
-def oracle_lg_relaxed_sphere(nside, tol=1e-4, max_iter=400):
-    """The oracle's LG relaxation of the seed-2 sphere fill at dx = 1/nside
-    until R < tol (a fresh neighbour search every iteration)."""
+@functools.lru_cache(maxsize=None)
+def oracle_relaxed_sphere(nside, kernel=O.LAGUERRE_GAUSS, tol=1e-4, max_iter=400):
+    """The oracle's relaxation (kernel LG or Wendland) of the seed-2 sphere
+    fill at dx = 1/nside until R < tol or max_iter iterations (a fresh
+    neighbour search every iteration).  Returns (workload, box, FP32
+    positions, residue of the returned positions); cached: callers must not
+    modify the arrays."""
     w = I.sphere_fill(dx=1.0 / nside, seed=2)
     box = O.make_box(3, periodic=(0, 0, 0))
     f = w.fields
-    prm = O.relax_params(w.h, f["center"], f["radius"])
+    prm = O.relax_params(w.h, f["center"], f["radius"], kernel=kernel)
     pos = w.pos.astype(np.float64)
     u = np.zeros_like(pos)
     rc = 2.0 * w.h
+    r = float("nan")
     for _ in range(max_iter):
         rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
         new, u, r, _ = O.relax_step(box, pos, u, prm, rp, col, w.vol)
         if r < tol:
             break
         pos = new
-    return w, box, pos.astype(np.float32)
+    else:
+        rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+        _, _, r, _ = O.relax_step(box, pos, np.zeros_like(pos), prm, rp, col, w.vol)
+    return w, box, pos.astype(np.float32), r
+
+
+def oracle_lg_relaxed_sphere(nside, tol=1e-4, max_iter=400):
+    """The oracle's LG relaxation of the seed-2 sphere fill at dx = 1/nside
+    until R < tol: (workload, box, FP32 positions)."""
+    w, box, pos, _ = oracle_relaxed_sphere(nside, O.LAGUERRE_GAUSS, tol, max_iter)
+    return w, box, pos

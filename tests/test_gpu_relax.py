@@ -1,4 +1,6 @@
-"""GPU parity of the Laguerre-Gauss relaxation against the FP64 oracle."""
+"""GPU parity of the particle relaxation (Laguerre-Gauss kernel; Wendland
+kernel for the error analysis's second relaxed distribution) against the
+FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -30,19 +32,20 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def _setup(S, w):
+def _setup(S, w, kernel=O.LAGUERRE_GAUSS):
     dom = S.Domain(dim=3, h=w.h, kappa=2.0, lo=w.lo, hi=w.hi, periodic=w.periodic, kernel=S.LAGUERRE_GAUSS)
     f = w.fields
-    pg = S.relax_params(f["center"], f["radius"], p0=f["p0"], rho=f["rho"])
-    po = O.relax_params(w.h, f["center"], f["radius"], p0=f["p0"], rho=f["rho"])
+    pg = S.relax_params(f["center"], f["radius"], p0=f["p0"], rho=f["rho"], kernel=kernel)
+    po = O.relax_params(w.h, f["center"], f["radius"], p0=f["p0"], rho=f["rho"], kernel=kernel)
     box = O.make_box(3, lo=w.lo, hi=w.hi, periodic=(0, 0, 0))
     return dom, pg, po, box
 
 
+@pytest.mark.parametrize("kernel", [O.LAGUERRE_GAUSS, O.WENDLAND])
 @pytest.mark.parametrize("dx", [1.0 / 32, 1.0 / 48])
-def test_relax_residual_force_and_residue(S, dx):
+def test_relax_residual_force_and_residue(S, dx, kernel):
     w = I.sphere_fill(dx=dx, seed=2)
-    dom, pg, po, box = _setup(S, w)
+    dom, pg, po, box = _setup(S, w, kernel)
     ctx = S.Context(3)
     res, g = ctx.relax_residue(dom, pg, dev(w.pos), dev(w.vol))
     rc = 2.0 * w.h
@@ -53,9 +56,10 @@ def test_relax_residual_force_and_residue(S, dx):
     assert abs(host(res)[0] - r_o) <= 1e-4 * r_o
 
 
-def test_relax_one_iteration_and_tracking(S):
+@pytest.mark.parametrize("kernel", [O.LAGUERRE_GAUSS, O.WENDLAND])
+def test_relax_one_iteration_and_tracking(S, kernel):
     w = I.sphere_fill(dx=1.0 / 40, seed=3)
-    dom, pg, po, box = _setup(S, w)
+    dom, pg, po, box = _setup(S, w, kernel)
     ctx = S.Context(3)
     pos = dev(w.pos)
     u = torch.zeros_like(pos)
@@ -117,3 +121,13 @@ def test_relax_full_size_sphere_sampled(S):
     gh = host(g).astype(np.float64)
     r_gpu_from_g = np.sqrt(np.mean(w.h ** 2 * (gh ** 2).sum(0)))
     assert abs(host(res)[0] - r_gpu_from_g) <= 1e-9 * r_gpu_from_g  # FP64 reduction of the same g
+
+
+def test_relax_kernel_argument(S):
+    """A kernel other than the two is refused before any launch."""
+    w = I.sphere_fill(dx=1.0 / 16, seed=2)
+    dom, pg, po, box = _setup(S, w)
+    pg.kernel = 7
+    ctx = S.Context(3)
+    with pytest.raises(S.SphError, match="kernel"):
+        ctx.relax_residue(dom, pg, dev(w.pos), dev(w.vol))
