@@ -661,7 +661,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps first (the GPU clock settles over the first ~10 ms of work); "
+                         "warmup + steps = 1000 is the workload's run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--nside", type=int, default=512)
@@ -725,7 +727,7 @@ def main():
         print(json.dumps(run_setup()), flush=True)
         return
     if args.plate:
-        print(json.dumps({"kappa": args.plate, **run_plate(args.plate, args.steps_plate, 5)}), flush=True)
+        print(json.dumps({"kappa": args.plate, **run_plate(args.plate, args.steps_plate, 40)}), flush=True)
         return
     if args.shear:
         print(json.dumps(shear_layer_section()), flush=True)
@@ -785,7 +787,7 @@ def main():
                               "traffic": TRAFFIC.get(source_sha(*STAGE_SOURCES), {}).get("3d"),
                               "kernel": "k_euler (3-D Heun stage, 1.6h, 200^3)",
                               "avg_launch_us": tw3["avg_launch_us"], "bytes_per_launch": tw3["bytes_per_launch"]}
-        twp, swp = run_plate(1.6, args.steps_plate, 5), run_plate(2.0, args.steps_plate, 5)
+        twp, swp = run_plate(1.6, args.steps_plate, 40), run_plate(2.0, args.steps_plate, 40)
         out["tlsph_plate"] = {"kappa1.6": twp, "kappa2": swp,
                               "speedup_tw_over_sw": swp["ms_per_step"] / twp["ms_per_step"]}
         if args.plate_accuracy_steps:
