@@ -672,8 +672,8 @@ def main():
     ap.add_argument("--relax-nside", type=int, default=260)
     ap.add_argument("--no-extra", action="store_true", help="skip the 3-D Taylor-Green and TLSPH plate lines")
     ap.add_argument("--nside3d", type=int, default=200)
-    ap.add_argument("--steps3d", type=int, default=50)
-    ap.add_argument("--steps-plate", type=int, default=200)
+    ap.add_argument("--steps3d", type=int, default=200, help="timed 3-D Taylor-Green steps (the workload runs 200)")
+    ap.add_argument("--steps-plate", type=int, default=2000, help="timed plate steps (the workload runs 2000)")
     ap.add_argument("--plate-accuracy-steps", type=int, default=2000,
                     help="untimed TW-vs-SW tip-deflection history of the plate (0: skip)")
     ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
