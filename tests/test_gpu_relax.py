@@ -131,3 +131,24 @@ def test_relax_kernel_argument(S):
     ctx = S.Context(3)
     with pytest.raises(S.SphError, match="kernel"):
         ctx.relax_residue(dom, pg, dev(w.pos), dev(w.vol))
+
+
+def test_relax_wendland_run_tracks_oracle(S):
+    """The Wendland relaxation of the error analysis (dx = 1/16, 400
+    iterations, stalling near R = 4e-4): residue history and final
+    displacement against the oracle's run.  The Wendland gradient vanishes
+    at the cut-off, so the FP32 and FP64 trajectories stay together."""
+    w = I.sphere_fill(dx=1.0 / 16, seed=2)
+    dom, pg, po, box = _setup(S, w, O.WENDLAND)
+    ctx = S.Context(3)
+    pos, vol = dev(w.pos), dev(w.vol)
+    u = torch.zeros_like(pos)
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    hist = []
+    for _ in range(8):
+        ctx.relax_step(dom, pg, pos, u, vol, 50, res)
+        hist.append(float(host(res)[0]))
+    pos_o, _, res_o = O.relax_run(box, w.pos, po, w.vol, 400)
+    ref = res_o[49::50]
+    assert np.all(np.abs(np.array(hist) - ref) <= 0.02 * ref), (hist, ref.tolist())
+    assert normwise(host(pos).astype(np.float64) - w.pos, pos_o - w.pos) < 1e-3
