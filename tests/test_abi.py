@@ -60,3 +60,39 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         S.lib()
+
+
+def _c_struct_layouts(tmp_path, structs):
+    """sizeof and offsetof of each field, as the C compiler lays out the
+    header's structs (gcc, host ABI)."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sph.h"', "int main(void) {"]
+    for name, fields in structs.items():
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for f in fields:
+            lines.append(f'    printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    return {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+
+
+def test_binding_structs_match_header(tmp_path):
+    """Every parameter struct of the binding has the header's size and field
+    offsets (a field added on one side only would shift the others)."""
+    from paper_2405_05155_amd import sph as S
+    classes = {n: getattr(S, n) for n in dir(S) if n.startswith("sph_") and isinstance(getattr(S, n), type)
+               and issubclass(getattr(S, n), ctypes.Structure)}
+    assert {"sph_domain", "sph_euler_params", "sph_hllc_params", "sph_tlsph_params", "sph_relax_params",
+            "sph_adamw_params"} <= set(classes)
+    header = open(os.path.join(ROOT, "include", "sph.h")).read()
+    for n in classes:
+        assert re.search(r"\}\s*" + n + r"\s*;", header), n
+    structs = {n: [f[0] for f in c._fields_] for n, c in classes.items()}
+    lay = _c_struct_layouts(tmp_path, structs)
+    for n, c in classes.items():
+        assert lay[(n, "size")] == ctypes.sizeof(c), n
+        for f in structs[n]:
+            assert lay[(n, f)] == getattr(c, f).offset, (n, f)
