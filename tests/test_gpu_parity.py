@@ -597,6 +597,44 @@ def test_tlsph_steps(S, kappa, rows, monkeypatch):
     assert np.all(host(vel)[:, fixed.astype(bool)] == 0.0)
 
 
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_tlsph_full_size_plate_sampled(S, kappa):
+    """The 1,604,932-particle plate of the bench (dx = 0.2/430, neo-Hookean)
+    in the launch configuration the bench times: deformation rate and
+    acceleration of 32 sampled particles against the oracle, with every
+    particle's F perturbed (the sampled rows' neighbours' stresses enter)."""
+    w = I.cantilever_plate(nx=430)
+    assert w.n == 1604932
+    box = oracle_box(w)
+    rc = kappa * w.h
+    rows = sample_rows(w.n, 32, seed=11)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    rp_o, col_o = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=rows)
+    ring = np.unique(np.concatenate([rows, col_o.astype(np.int64)]))
+    rp_r, col_r = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=ring)
+    B_r, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp_r, col_r, w.vol, rows=ring)
+    B_full = np.zeros((w.n, 3, 3))
+    B_full[ring] = B_r
+    f = w.fields
+    pg = S.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=0)
+    po = O.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=0)
+    rng = np.random.default_rng(5)
+    F = (np.eye(3, dtype=np.float32)[None] + 0.01 * rng.standard_normal((w.n, 3, 3)).astype(np.float32))
+    vel, fixed = f["vel"], f["fixed"]
+    dF, acc = ctx.tlsph_rhs(pg, dev(vel), dev(F), dev(fixed, torch.int32))
+    r_dF, r_acc, s_acc = O.tlsph_rhs(box, w.pos, w.h, rp_o, col_o, w.vol, B_full, po, vel, F, fixed, rows=rows)
+    scaled_check(host(acc)[:, rows], r_acc, s_acc, RTOL, "acc sampled")
+    pos = w.pos.astype(np.float64)
+    owner = np.repeat(rows, np.diff(rp_o))
+    d = pos[:, owner] - pos[:, col_o]
+    r = np.sqrt((d ** 2).sum(0))
+    t = np.abs(vel[:, col_o] - vel[:, owner]).max(0) * np.abs(O.kernel_dWdr(O.WENDLAND, 3, w.h, r)) * w.vol[col_o]
+    sc = np.bincount(np.repeat(np.arange(len(rows)), np.diff(rp_o)), weights=t, minlength=len(rows))
+    sc = sc * np.abs(B_full[rows]).reshape(len(rows), -1).max(1) * 3
+    scaled_check(host(dF)[rows], r_dF, sc[:, None, None], RTOL, "dF/dt sampled")
+
+
 def test_truncated_kernel_equal_accuracy_taylor_green():
     """At equal time step and step count, the 1.6h run's velocity error
     against the decaying Taylor-Green solution is within 10% of the 2h
