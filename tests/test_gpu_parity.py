@@ -496,6 +496,48 @@ def test_euler_rhs_full_size_taylor_green_sampled(S):
         scaled_check(host(dm)[:, rows], r_dm, s_dm, RTOL, "dmom/dt sampled")
 
 
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_euler_heun_step_full_size_sampled(S, kappa):
+    """One Heun step of the 512^2 Taylor-Green workload through the stage
+    kernels the bench times, on 24 sampled particles: the oracle evaluates
+    the first stage on the samples and their neighbours, then the second
+    stage on the samples (U* = U + dt R(U), U' = (U + U* + dt R(U*)) / 2),
+    with B on the two rings of neighbours around them."""
+    w = I.taylor_green_2d(nside=512)
+    box = oracle_box(w)
+    rc = kappa * w.h
+    dt = w.meta["dt"]
+    rows = sample_rows(w.n, 24, seed=9)
+    rp_s, col_s = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=rows)
+    ring1 = np.unique(np.concatenate([rows, col_s.astype(np.int64)]))
+    rp_1, col_1 = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=ring1)
+    ring2 = np.unique(np.concatenate([ring1, col_1.astype(np.int64)]))
+    rp_2, col_2 = O.neighbors_grid(box, w.pos, rc, rc * rc, rows=ring2)
+    B_2, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp_2, col_2, w.vol, rows=ring2)
+    B_full = np.zeros((w.n, 2, 2))
+    B_full[ring2] = B_2
+    pg, po = _euler_prm(S, w, dt)
+    drho0 = w.fields["drho"].astype(np.float64)
+    mom0 = w.fields["mom"].astype(np.float64)
+    rho0 = 1.0 + drho0
+    d1, m1, _, _ = O.euler_rhs(box, w.pos, w.h, rp_1, col_1, w.vol, B_full, po, rho0, mom0, rows=ring1)
+    rho_s, mom_s = rho0.copy(), mom0.copy()
+    rho_s[ring1] += dt * d1
+    mom_s[:, ring1] += dt * m1
+    d2, m2, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp_s, col_s, w.vol, B_full, po, rho_s, mom_s, rows=rows)
+    rho_n = 0.5 * (rho0[rows] + rho_s[rows] + dt * d2)
+    mom_n = 0.5 * (mom0[:, rows] + mom_s[:, rows] + dt * m2)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    d, m = dev(w.fields["drho"]), dev(w.fields["mom"])
+    ctx.euler_step(pg, d, m, 1)
+    eps = np.finfo(np.float32).eps
+    inc_g, inc_o = host(d)[rows] - drho0[rows], (rho_n - 1.0) - drho0[rows]
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dr) + 4 * eps * np.abs(rho_n - 1.0))
+    inc_g, inc_o = host(m)[:, rows] - mom0[:, rows], mom_n - mom0[:, rows]
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(mom_n))
+
+
 @pytest.mark.parametrize("nside", [80, 104])
 def test_euler_rhs_3d_taylor_green_sampled(S, nside):
     """3-D Taylor-Green at 80^3 and 104^3 (the two sizes take different
