@@ -538,10 +538,11 @@ def test_euler_heun_step_full_size_sampled(S, kappa):
     assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(mom_n))
 
 
-@pytest.mark.parametrize("nside", [80, 104])
+@pytest.mark.parametrize("nside", [80, 104, 200])
 def test_euler_rhs_3d_taylor_green_sampled(S, nside):
     """3-D Taylor-Green at 80^3 and 104^3 (the two sizes take different
-    lanes-per-particle mappings: 2 and 1)."""
+    lanes-per-particle mappings: 2 and 1) and at the 200^3 of the bench's
+    3-D line (8M particles, its launch configuration)."""
     w = I.taylor_green_3d(nside=nside)
     box = oracle_box(w)
     rows = sample_rows(w.n, 24, seed=3)
