@@ -171,11 +171,11 @@ def _batch(rng, B):
     return X, Xp, T
 
 
-@pytest.mark.parametrize("B", [1, 17, 1000, 64 * 256 + 40])
+@pytest.mark.parametrize("B", [1, 17, 1000, 64 * 256 + 40, 65536])
 def test_gradient_ragged_batches(S, B):
     """Batches that leave a partial 16-sample slab and a partial 64-sample
-    block (and, at the largest size, more blocks than workgroups) against the
-    oracle."""
+    block (and, from 16,424 on, more blocks than workgroups) against the
+    oracle; 65,536 is the training batch of the bench."""
     rng = np.random.default_rng(B)
     X, Xp, T = _batch(rng, B)
     theta = M.init_params(4)
