@@ -735,3 +735,30 @@ def test_relax_sphere_reaches_residue_threshold():
     assert res[-1] < 1e-4
     phi = np.sqrt(((pos - np.array(w.fields["center"])[:, None]) ** 2).sum(0)) - w.fields["radius"]
     assert np.max(phi) <= 1e-12
+
+
+def test_oracle_binding_structs_match_c(tmp_path):
+    """The oracle's ctypes structs have the C structs' sizes and field
+    offsets (the C source compiled into a probe that prints them)."""
+    import ctypes
+    import os
+    import subprocess
+    pairs = {"or_box": O.Box, "or_euler_params": O.EulerParams, "or_hllc_params": O.HllcParams,
+             "or_tlsph_params": O.TlsphParams, "or_relax_params": O.RelaxParams}
+    src = os.path.join(os.path.dirname(os.path.abspath(O.__file__)), "sph_oracle.c")
+    lines = ['#include "' + src + '"', "#include <stddef.h>", "int main(void) {"]
+    for cname, cls in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'    printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["    return 0;", "}"]
+    probe = tmp_path / "probe.c"
+    probe.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-fopenmp", str(probe), "-o", str(exe), "-lm"], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    lay = {tuple(line.split()[:2]): int(line.split()[2]) for line in out.splitlines()}
+    for cname, cls in pairs.items():
+        assert lay[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert lay[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
