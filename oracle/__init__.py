@@ -93,6 +93,8 @@ def lib():
         L.or_tlsph_step.argtypes = [vp, i64, vp, d, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64]
         L.or_relax_tail.restype = d
         L.or_relax_tail.argtypes = [vp, d]
+        L.or_relax_tail2.restype = d
+        L.or_relax_tail2.argtypes = [vp, d]
         L.or_relax_g.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp]
         L.or_relax_step.restype = d
         L.or_relax_step.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp]
@@ -320,12 +322,14 @@ def relax_params(h, center, radius, p0=1.0, rho=1.0, kappa=0.1, mu=0.9, max_move
     return p
 
 
-def relax_tail(prm, rho_c):
-    return lib().or_relax_tail(C.byref(prm), float(rho_c))
+def relax_tail(prm, rho_c, dim=3):
+    """Exterior kernel-gradient integral T(rho_c): sphere (dim 3) or circle (dim 2)."""
+    f = lib().or_relax_tail2 if dim == 2 else lib().or_relax_tail
+    return f(C.byref(prm), float(rho_c))
 
 
 def relax_g(box, pos, prm, row_ptr, col, vol, rows=None):
-    """Returns (g [3][m], scale [3][m])."""
+    """Returns (g [dim][m], scale [dim][m])."""
     pos, vol = _f64(pos), _f64(vol)
     n = pos.shape[1]
     r, m = _rows(rows, n)

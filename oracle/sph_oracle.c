@@ -599,18 +599,18 @@ typedef struct {
 
 /* Interface state of one pair's Riemann problem along the unit vector nrm
  * (left state l = particle i, right state r = particle j), Sec. 3.1:
- *   wave speeds S_l = u_l - c_l, S_r = u_r + c_r (Eq. 24), c = sqrt(gamma p / rho);
- *   the limited middle state
+ *   wave speeds S_l = u_l - c_l, S_r = u_r + c_r (Eq. 20), c = sqrt(gamma p / rho);
+ *   the limited middle state (Eq. 24, beta of Eq. 25)
  *     u* = (rho_l c_l u_l + rho_r c_r u_r) / (rho_l c_l + rho_r c_r)
  *          + beta^2 (p_l - p_r) / (rho_l c_l + rho_r c_r),
  *     p* = (p_l + p_r)/2 + beta/2 [rho_r c_r (u* - u_r) + rho_l c_l (u_l - u*)],
  *     beta = min(eta max((u_l - u_r) / cbar, 0), 1), cbar = (c_l + c_r)/2;
  *   (the printed bracket has a minus between its terms; the plus makes p*
- *   the mean of Eq. (25)'s two expressions p_l + rho_l c_l (u_l - u*) and
+ *   the mean of Eq. (22)'s two expressions p_l + rho_l c_l (u_l - u*) and
  *   p_r + rho_r c_r (u* - u_r), and gives the linearised solver's
  *   (p_l + p_r)/2 + beta rho c (u_l - u_r)/2 for equal impedances; with the
  *   minus a head-on collision would raise no pressure);
- *   the HLLC star states (Eq. 25) with the normal velocities u_K where the
+ *   the HLLC star states (Eq. 22) with the normal velocities u_K where the
  *   printed formulas show |v_K|:
  *     rho*_K = rho_K (S_K - u_K) / (S_K - u*),
  *     E*_K   = ((S_K - u_K) E_K - p_K u_K + p* u*) / (S_K - u*),
@@ -970,9 +970,46 @@ double or_relax_tail(const or_relax_params* prm, double rho_c)
     return M_PI * acc * ht / 3.0;
 }
 
+/* The same exterior integral in 2-D, for a circle of radius R (the error
+ * analysis's geometry, Sec. 2.3.3):
+ *   t_i = int_{|r - c| > R} grad_i W(r_i - r) dA = T(rho_i) e_i.
+ * In polar coordinates about r_i (theta from e_i) the point r_i + s (cos,
+ * sin) lies outside where cos(theta) > u0, and only the radial component
+ * -dW/ds cos(theta) survives the angular integral:
+ *   T = 2 int_{s0}^{2h} (-dW/ds) s sqrt(1 - clamp(u0, -1, 1)^2) ds
+ * with u0 and s0 as in 3-D; the same substitution t = sqrt(s - s0) and
+ * Simpson rule.  Pinned against the half-plane limit and a direct 2-D
+ * quadrature. */
+double or_relax_tail2(const or_relax_params* prm, double rho_c)
+{
+    double h = prm->h, R = prm->radius;
+    if (rho_c <= 0.0) return 0.0;
+    double s0 = fabs(R - rho_c);
+    double s1 = 2.0 * h;
+    if (s0 >= s1) return 0.0;
+    const int NP = 2000;
+    double t1 = sqrt(s1 - s0);
+    double ht = t1 / NP, acc = 0.0;
+    for (int k = 0; k <= NP; ++k) {
+        double t = ht * k;
+        double s = s0 + t * t;
+        double f = 0.0;
+        if (s > 0.0) {
+            double u0 = (R * R - rho_c * rho_c - s * s) / (2.0 * rho_c * s);
+            if (u0 < -1.0) u0 = -1.0;
+            if (u0 > 1.0) u0 = 1.0;
+            f = -or_kernel_dWdr(prm->kernel, 2, h, s) * s * sqrt(1.0 - u0 * u0) * 2.0 * t;
+        }
+        double wgt = (k == 0 || k == NP) ? 1.0 : ((k & 1) ? 4.0 : 2.0);
+        acc += wgt * f;
+    }
+    return 2.0 * acc * ht / 3.0;
+}
+
 /* Residual force of the relaxation, Eq. (7) with the kernel of prm:
  *   g_i = sum_j grad W_ij V_j + T(rho_i) e_i
- * (a_i = -(2 p0 / rho) g_i).  Neighbours at cutoff 2h, 3-D, non-periodic.
+ * (a_i = -(2 p0 / rho) g_i), the sphere's T in 3-D and the circle's in
+ * 2-D.  Neighbours at cutoff 2h, non-periodic.
  * g[a*m + k]. */
 void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_params* prm,
                 int64_t m, const int64_t* rows, const int64_t* row_ptr, const int32_t* col,
@@ -992,7 +1029,7 @@ void or_relax_g(const or_box* b, int64_t n, const double* pos, const or_relax_pa
         double e[3] = {0, 0, 0}, rc = 0.0;
         for (int a = 0; a < dim; ++a) { e[a] = pos[a * n + i] - prm->center[a]; rc += e[a] * e[a]; }
         rc = sqrt(rc);
-        double T = or_relax_tail(prm, rc);
+        double T = dim == 2 ? or_relax_tail2(prm, rc) : or_relax_tail(prm, rc);
         for (int a = 0; a < dim; ++a) {
             double t = rc > 0.0 ? T * e[a] / rc : 0.0;
             g[a * m + k] = s[a] + t;

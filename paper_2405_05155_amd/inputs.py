@@ -248,11 +248,13 @@ def sod_strip_2d(nx: int = 256, ny: int = 16, gamma: float = 1.4) -> Workload:
     return w
 
 
-def taylor_green_3d(nside: int = 200, c: float = 10.0, nu: float = 0.01) -> Workload:
-    """3-D Taylor-Green field in the periodic unit cube, exact lattice,
-    h = 1.3 dx; u = sin cos cos, v = -cos sin cos, w = 0,
+def taylor_green_3d(nside: int = 200, c: float = 10.0, nu: float = 0.01, jitter: float = 0.0,
+                    seed: int | None = None) -> Workload:
+    """3-D Taylor-Green field in the periodic unit cube, h = 1.3 dx, on the
+    exact lattice (or jittered by seeded uniform +-jitter dx per component);
+    u = sin cos cos, v = -cos sin cos, w = 0,
     p = (cos 4pi x + cos 4pi y)(cos 4pi z + 2)/16, rho = 1 + p/c^2."""
-    w = periodic_square_case(nside, 3, 1.3, 0.0, None, f"taylor_green_3d_{nside}")
+    w = periodic_square_case(nside, 3, 1.3, jitter, seed, f"taylor_green_3d_{nside}")
     x = w.pos.astype(np.float64)
     sx, sy, sz = (np.sin(2 * np.pi * x[a]) for a in range(3))
     cx, cy, cz = (np.cos(2 * np.pi * x[a]) for a in range(3))
@@ -340,6 +342,39 @@ def sphere_fill(dx: float = 1.0 / 260, radius: float = 0.3, center=(0.5, 0.5, 0.
                     vol=vol.astype(np.float32), h=h, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0),
                     periodic=(0, 0, 0), fields={"center": tuple(center), "radius": radius, "p0": 1.0, "rho": 1.0},
                     meta={"dx": dx, "quantum": q, "seed": seed})
+
+
+def circle_fill(dx: float = 0.2, radius: float = 1.0, jitter: float = 0.4, seed: int = 2) -> Workload:
+    """2-D counterpart of sphere_fill for the error analysis's circle
+    (diameter D = 2 R, centre at the origin): cell-centred lattice points
+    (i + 1/2) dx of the square [-R, R]^2 with |r| < R, perturbed by seeded
+    uniform +-jitter*dx per component and quantised; box [-1.5 R, 1.5 R]^2,
+    open; h = 1.3 dx, V = dx^2."""
+    nside = int(round(2.0 * radius / dx))
+    axis = -radius + (np.arange(nside) + 0.5) * dx
+    Y, X = np.meshgrid(axis, axis, indexing="ij")
+    m = X ** 2 + Y ** 2 < radius ** 2
+    pos = np.stack([X[m], Y[m]])
+    rng = np.random.default_rng(seed)
+    pos = pos + rng.uniform(-jitter * dx, jitter * dx, size=pos.shape)
+    q = quantum_for(2.0 * radius)
+    pos = quantise(pos, q)
+    n = pos.shape[1]
+    vol = np.full(n, dx ** 2)
+    b = 1.5 * radius
+    return Workload(name=f"circle_relax_{nside}_seed{seed}", dim=2, pos=pos.astype(np.float32),
+                    vol=vol.astype(np.float32), h=1.3 * dx, lo=(-b, -b), hi=(b, b), periodic=(0, 0),
+                    fields={"center": (0.0, 0.0, 0.0), "radius": radius, "p0": 1.0, "rho": 1.0},
+                    meta={"dx": dx, "quantum": q, "seed": seed})
+
+
+def circle_gradient_fields(pos):
+    """The error analysis's function on the circle of diameter 2 about the
+    origin: f = exp(-x^2/0.1) and its exact df/dx = -20 x f, at FP32
+    positions [2][n] (FP64 values)."""
+    x = np.asarray(pos, dtype=np.float64)[0]
+    f = np.exp(-x * x / 0.1)
+    return f, -20.0 * x * f
 
 
 def random_points(n: int, dim: int, seed: int, periodic: bool = True, h_over_dx: float = 1.3) -> Workload:

@@ -101,3 +101,34 @@ def oracle_lg_relaxed_sphere(nside, tol=1e-4, max_iter=400):
     until R < tol: (workload, box, FP32 positions)."""
     w, box, pos, _ = oracle_relaxed_sphere(nside, O.LAGUERRE_GAUSS, tol, max_iter)
     return w, box, pos
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_relaxed_circle(ndiv, kernel=O.LAGUERRE_GAUSS, tol=1e-4, max_iter=None, seed=2):
+    """The oracle's relaxation of the circle of the error analysis (D = 2,
+    dp = D / ndiv, seeded fill jittered by +-0.4 dp) with `kernel` until
+    R < tol or max_iter iterations (400 for Wendland, which stalls near
+    6e-4; 3000 for LG), a fresh neighbour search every iteration.  Returns
+    (workload, box, FP32 positions, residue of the returned positions,
+    iterations); cached: callers must not modify the arrays."""
+    if max_iter is None:
+        max_iter = 400 if kernel == O.WENDLAND else 3000
+    w = I.circle_fill(dx=2.0 / ndiv, seed=seed)
+    box = O.make_box(2, lo=w.lo + (0.0,), hi=w.hi + (0.0,), periodic=(0, 0, 0))
+    f = w.fields
+    prm = O.relax_params(w.h, f["center"], f["radius"], kernel=kernel)
+    pos = w.pos.astype(np.float64)
+    u = np.zeros_like(pos)
+    rc = 2.0 * w.h
+    r = float("nan")
+    it = 0
+    for it in range(1, max_iter + 1):
+        rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+        new, u, r, _ = O.relax_step(box, pos, u, prm, rp, col, w.vol)
+        if r < tol:
+            break
+        pos = new
+    else:
+        rp, col = O.neighbors_grid(box, pos, rc, rc * rc)
+        _, _, r, _ = O.relax_step(box, pos, np.zeros_like(pos), prm, rp, col, w.vol)
+    return w, box, pos.astype(np.float32), r, it
