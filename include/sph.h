@@ -165,18 +165,18 @@ int sph_euler_step(sph_ctx* ctx, const sph_euler_params* prm, float* drho, float
 
 /* Compressible Eulerian SPH, 2-D: Eq. (19) with all three rows (mass,
  * momentum, total energy) and the corrected gradient of Eq. (28), the HLLC
- * Riemann solver (Eqs. 24-25) with its dissipation limiter (Sec. 3.1) posed
+ * Riemann solver (Eqs. 20-22) with its dissipation limiter (Eqs. 24-25) posed
  * along n = (r_j - r_i)/r (left state i), ideal gas p = (gamma - 1)
- * (E - rho |v|^2 / 2).  The limited middle state is
+ * (E - rho |v|^2 / 2).  The limited middle state (Eq. 24) is
  *   u* = (z_l u_l + z_r u_r + beta^2 (p_l - p_r)) / (z_l + z_r),
  *   p* = (p_l + p_r)/2 + beta/2 (z_r (u* - u_r) + z_l (u_l - u*)),
  * z = rho c, c = sqrt(gamma p / rho), beta = min(eta max((u_l - u_r) /
  * cbar, 0), 1), cbar = (c_l + c_r)/2 (the printed bracket's minus between
- * its terms is read as a plus: p* is then the mean of Eq. (25)'s two
- * expressions).  Wave speeds S_l = u_l - c_l, S_r = u_r + c_r (Eq. 24), or
+ * its terms is read as a plus: p* is then the mean of Eq. (22)'s two
+ * expressions).  Wave speeds S_l = u_l - c_l, S_r = u_r + c_r (Eq. 20), or
  * min(u_l - c_l, u_r - c_r) and max(u_l + c_l, u_r + c_r) where those cross.
  * At the fixed interface: the left (right) state if S_l >= 0 (S_r <= 0),
- * else the star state of Eq. (25) on the side of u*'s sign (with the normal
+ * else the star state of Eq. (22) on the side of u*'s sign (with the normal
  * velocity u_K where the printed formulas show |v_K|), velocity u* n plus the
  * mean tangential velocity.  Wendland kernel, 2-D contexts only
  * (SPH_ERR_ARG otherwise); the per-particle kernel runs whatever the tiling

@@ -107,7 +107,7 @@ void sph_ctx_destroy(sph_ctx* c) {
                       &c->col_s,       &c->scan_tmp,     &c->counter,        &c->geo0,        &c->geo1,
                       &c->geo2,        &c->ua,           &c->ub,             &c->ta,          &c->tb,
                       &c->tc,          &c->tail,         &c->svol,           &c->sfield,      &c->partials,
-                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->geoA};
+                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->rec3};
     for (DevBuf* b : bufs) b->release();
     (void)hipSetDevice(prev);
     delete c;

@@ -2,7 +2,8 @@
 // gradient (Eq. 28) and its Heun time stepping: the weakly compressible
 // mass and momentum rows with the limited linearised Riemann solver
 // (Eqs. 26-27), and (2-D) the compressible rows with the energy equation and
-// the limited HLLC solver (Eqs. 24-25, Sec. 3.1), one stage kernel for both.
+// the HLLC solver (Eqs. 20-22) with its limiter (Eqs. 24-25), one stage
+// kernel for both.
 //
 // State layout: one float4 conserved record per particle ((drho, m) or, for
 // the compressible rows, (rho, m_x, m_y, E)) and one float4 primitive record
@@ -38,6 +39,7 @@ struct EulerArgs {
     float qc2inv;           // 1 / (4 c^2)
     float kmu;              // -4 mu / d
     float fr, fm;           // row factors of the continuity and momentum sums: -cFh, -cFh / 2
+    float inv2c, crho0x2;   // 1 / (2 c), 2 c rho0 (3-D records: c rho_j = 2 p_j / (2 c) + c rho0)
     // compressible rows (limited HLLC, ideal gas; 2-D)
     float gamma, ig1, gm1;  // gamma, 1 / (gamma - 1), gamma - 1
     float eta_h;            // limiter coefficient
@@ -96,20 +98,11 @@ struct NbrRec {
     float2 g2;
 };
 
-// GA: 3-D geometry interleaved in geo0 (three float4 per particle), so that
-// the three geometry loads of a neighbour share its cache lines.
-template <int DIM, bool GA>
+template <int DIM>
 __device__ __forceinline__ void gather_nbr(int32_t j, const float4* __restrict__ geo0,
                                            const float4* __restrict__ geo1, const float2* __restrict__ geo2,
                                            const float4* __restrict__ P, NbrRec<DIM>& r) {
     const uint32_t u = (uint32_t)j;
-    if (GA) {
-        r.g0 = ld32(geo0, 3u * u);
-        r.g1 = ld32(geo0, 3u * u + 1u);
-        r.g2 = ld32(reinterpret_cast<const float2*>(geo0), 6u * u + 4u);
-        r.pr = ld32(P, u);
-        return;
-    }
     r.g0 = ld32(geo0, u);
     if (DIM == 2) {
         const float2 t = ld32(reinterpret_cast<const float2*>(geo1), u);
@@ -214,7 +207,7 @@ __device__ __forceinline__ void accumulate_pair(const EulerArgs& ea, const OwnSt
 
 // One pair (i, j) of the compressible system (Eq. 19, all three rows; 2-D)
 // with the corrected gradient (Eq. 28) and the limited HLLC interface state
-// (Eqs. 24-25 and the HLLC limiter, Sec. 3.1), Riemann problem along
+// (Eqs. 20-22, limited by Eqs. 24-25), Riemann problem along
 // n = -d / r with left state i.  The limited middle state
 //   u* = (z_l u_l + z_r u_r + beta^2 (p_l - p_r)) / (z_l + z_r),
 //   p* = (p_l + p_r)/2 + beta/2 (z_r (u* - u_r) + z_l (u_l - u*)),
@@ -350,7 +343,7 @@ __device__ __forceinline__ void load_batch_cols(int32_t n, const int32_t* __rest
 // One particle's row for lane `sub` of its group (batch mode: the lane's
 // column indices in jb).  Every gather of the row is issued before the own
 // record is waited on.
-template <int DIM, int SOL, int STAGE, int L, int MODE, int E, bool GA>
+template <int DIM, int SOL, int STAGE, int L, int MODE, int E>
 __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const int64_t* __restrict__ row_ptr,
                                           const int32_t* __restrict__ col, int32_t ell_S,
                                           const float4* __restrict__ geo0, const float4* __restrict__ geo1,
@@ -360,12 +353,12 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
                                           float* __restrict__ drho_dt, float* __restrict__ dmom_dt,
                                           float* __restrict__ dE_dt, int32_t i, int sub, const int32_t* jb) {
     NbrRec<DIM> self;
-    gather_nbr<DIM, GA>(i, geo0, geo1, geo2, P, self);
+    gather_nbr<DIM>(i, geo0, geo1, geo2, P, self);
     // batch mode: every record of the lane's entries in flight at once
     NbrRec<DIM> nb[MODE == ROWS_ELL_BATCH && E > 0 ? E : 1];
     if (MODE == ROWS_ELL_BATCH) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) gather_nbr<DIM, GA>(jb[q], geo0, geo1, geo2, P, nb[q]);
+        for (int q = 0; q < E; ++q) gather_nbr<DIM>(jb[q], geo0, geo1, geo2, P, nb[q]);
     }
     // the stage update's inputs, loaded now so that their latency overlaps the row
     float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
@@ -435,11 +428,11 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
         NbrRec<DIM> cur, nxt;
         {
             const int32_t j0 = k < e ? col[k] : i;
-            gather_nbr<DIM, GA>(j0, geo0, geo1, geo2, P, cur);
+            gather_nbr<DIM>(j0, geo0, geo1, geo2, P, cur);
         }
         int32_t jn1 = k + L * stride < e ? col[k + L * stride] : i;
         while (k < e) {
-            gather_nbr<DIM, GA>(jn1, geo0, geo1, geo2, P, nxt);
+            gather_nbr<DIM>(jn1, geo0, geo1, geo2, P, nxt);
             jn1 = k + 2 * L * stride < e ? col[k + 2 * L * stride] : i;
             k += L * stride;
             if (wrap_wave) pair_terms<DIM, SOL, true>(ea, o, cur, sr, sm, se);
@@ -500,7 +493,7 @@ __device__ __forceinline__ void euler_row(int32_t n, const EulerArgs& ea, const 
 //     pipeline would be too shallow to cover the memory latency).
 // Entries past the end of a row use the particle itself (zero weight).
 // Blocks run in XCD-contiguous order; whole groups leave together.
-template <int DIM, int SOL, int STAGE, int L, int MODE, int E, bool GA>
+template <int DIM, int SOL, int STAGE, int L, int MODE, int E>
 __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const int64_t* __restrict__ row_ptr,
                                                const int32_t* __restrict__ col, int32_t ell_S,
                                                const float4* __restrict__ geo0,
@@ -515,8 +508,241 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
     if (i >= n) return;
     int32_t jb[E > 0 ? E : 1];
     if (MODE == ROWS_ELL_BATCH) load_batch_cols<L, E>(n, col, ell_S, i, sub, jb);
-    euler_row<DIM, SOL, STAGE, L, MODE, E, GA>(n, ea, row_ptr, col, ell_S, geo0, geo1, geo2, U, P, U0, Uout,
+    euler_row<DIM, SOL, STAGE, L, MODE, E>(n, ea, row_ptr, col, ell_S, geo0, geo1, geo2, U, P, U0, Uout,
                                                Pout, sorted, drho_dt, dmom_dt, dE_dt, i, sub, jb);
+}
+
+// ------------------------------------------------------------------ 3-D stage on packed records
+// In 3-D the per-particle stage gathers each neighbour from one 64-byte
+// record (one cache-line half) in cell-sorted order:
+//   q0 = (x, y, z, V), q1 = (B00, B01, B02, B11), q2 = (B12, B22, tr B, 0),
+//   q3 = (2 p, v_x, v_y, v_z),  2 p = 2 c^2 (drho + rho_ref - rho0),
+// so that a pair needs no per-partner arithmetic for the pressure or the
+// trace of B.  Two record sets carry the stage input and output; geometry
+// is written into both when the state is packed, and a stage writes only
+// the q3 quad of its output (with the conserved record U).
+
+// q3 of a conserved record u = (drho, m): (2 p, v) with 2 p = 2 c^2 (drho +
+// rho_ref - rho0) and v = m / (rho_ref + drho).
+__device__ __forceinline__ float4 state_quad3(const EulerArgs& ea, const float4& u) {
+    const float inv = fast_rcp(ea.rho_ref + u.x);
+    return make_float4(fmaf(ea.c2x2, u.x, ea.c2x2poff), u.y * inv, u.z * inv, u.w * inv);
+}
+
+// Records of the stage input from the caller's state (gathered at the caller
+// index of each sorted slot) and the cached geometry: conserved U, and the
+// full records in both record sets.
+__global__ void k_pack3(int32_t n, EulerArgs ea, const float4* __restrict__ sorted, const float* __restrict__ drho,
+                        const float* __restrict__ mom, const float4* __restrict__ geo0,
+                        const float4* __restrict__ geo1, const float2* __restrict__ geo2, float4* __restrict__ U,
+                        float4* __restrict__ Ra, float4* __restrict__ Rb) {
+    const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int32_t i = __float_as_int(sorted[s].w);
+    const float4 u = make_float4(drho[i], mom[i], mom[(int64_t)n + i], mom[2 * (int64_t)n + i]);
+    U[s] = u;
+    const float4 g0 = geo0[s], g1 = geo1[s];
+    const float2 g2 = geo2[s];
+    const float4 q2 = make_float4(g2.x, g2.y, (g1.x + g1.w) + g2.y, 0.f);
+    const float4 q3 = state_quad3(ea, u);
+    const int64_t b = 4 * (int64_t)s;
+    Ra[b] = g0; Ra[b + 1] = g1; Ra[b + 2] = q2; Ra[b + 3] = q3;
+    Rb[b] = g0; Rb[b + 1] = g1; Rb[b + 2] = q2; Rb[b + 3] = q3;
+}
+
+struct Rec3 {
+    float4 q0, q1, q2, q3;
+};
+
+__device__ __forceinline__ void gather3(const float4* __restrict__ R, int32_t j, Rec3& r) {
+    const uint32_t b = (uint32_t)j << 2;
+    r.q0 = ld32(R, b);
+    r.q1 = ld32(R, b + 1u);
+    r.q2 = ld32(R, b + 2u);
+    r.q3 = ld32(R, b + 3u);
+}
+
+struct Own3 {
+    float x[3], B[6], v[3];
+    float p2;     // 2 p_i
+    float crho;   // c rho_i + c rho0 (so that c (rho_i + rho_j) = crho + 2 p_j / (2 c))
+    float trB;
+};
+
+// One pair (i, j) of Eq. (19) in 3-D with the corrected gradient (Eq. 28)
+// and the limited linearised Riemann solution (Eqs. 26-27): the terms of
+// accumulate_pair, with 2 p_j and tr B_j read from the partner's record
+// and c (rho_i + rho_j) = (c rho_i + c rho0) + 2 p_j / (2 c).
+template <bool WRAP>
+__device__ __forceinline__ void pair3(const EulerArgs& ea, const Own3& o, const Rec3& nb, Kahan& sr, Kahan* sm) {
+    float d[3], dv[3];
+    d[0] = o.x[0] - nb.q0.x;
+    d[1] = o.x[1] - nb.q0.y;
+    d[2] = o.x[2] - nb.q0.z;
+    if (WRAP) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = wrap(d[a], ea.L[a], ea.invL[a]);
+    }
+    dv[0] = o.v[0] - nb.q3.y;
+    dv[1] = o.v[1] - nb.q3.z;
+    dv[2] = o.v[2] - nb.q3.w;
+    const float r2 = fmaf(d[0], d[0], fmaf(d[1], d[1], d[2] * d[2]));
+    const float dvd = fmaf(dv[0], d[0], fmaf(dv[1], d[1], dv[2] * d[2]));
+    const bool live = r2 > 0.f;
+    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float tq = fmaf(ea.nhh, r2 * rinv, 1.f);  // 1 - q/2
+    const float Vj = live ? nb.q0.w : 0.f;
+    const float w = (Vj * tq) * (tq * tq);
+    const float B0 = o.B[0] + nb.q1.x, B1 = o.B[1] + nb.q1.y, B2 = o.B[2] + nb.q1.z;
+    const float B3 = o.B[3] + nb.q1.w, B4 = o.B[4] + nb.q2.x, B5 = o.B[5] + nb.q2.y;
+    const float G0 = fmaf(B0, d[0], fmaf(B1, d[1], B2 * d[2]));
+    const float G1 = fmaf(B1, d[0], fmaf(B3, d[1], B4 * d[2]));
+    const float G2 = fmaf(B2, d[0], fmaf(B4, d[1], B5 * d[2]));
+    const float a = dvd * rinv;
+    const float beta = __builtin_amdgcn_fmed3f(ea.nec * a, 0.f, 1.f);
+    const float pj2 = nb.q3.x;
+    const float crho = fmaf(pj2, ea.inv2c, o.crho);
+    const float du2 = ((beta * beta) * (o.p2 - pj2)) * fast_rcp(crho);
+    const float p4 = fmaf(-(beta * crho), a, o.p2 + pj2);
+    const float rhostar = fmaf(p4, ea.qc2inv, ea.rho0);
+    const float dn = du2 * rinv;
+    const float vs0 = fmaf(-dn, d[0], o.v[0] + nb.q3.y);
+    const float vs1 = fmaf(-dn, d[1], o.v[1] + nb.q3.z);
+    const float vs2 = fmaf(-dn, d[2], o.v[2] + nb.q3.w);
+    const float vg2 = fmaf(vs0, G0, fmaf(vs1, G1, vs2 * G2));
+    const float rh = rhostar * vg2;
+    accum(sr, w, rh);
+    const float kv = ea.kmu * (o.trB + nb.q2.z);
+    accum(sm[0], w, fmaf(rh, vs0, fmaf(p4, G0, kv * dv[0])));
+    accum(sm[1], w, fmaf(rh, vs1, fmaf(p4, G1, kv * dv[1])));
+    accum(sm[2], w, fmaf(rh, vs2, fmaf(p4, G2, kv * dv[2])));
+}
+
+// The lane's entries t = 0 .. m-1 of row i (entry t at e0 + t es), taken in
+// chunks of M pairs over a wave-uniform count mu >= m (entries past the
+// lane's end stand for the particle itself: a zero-weight pair, so every
+// lane runs the same straight-line code).  A chunk's column indices are
+// loaded first (no gather then waits behind an index load issued after
+// it), then its records are gathered two ahead of the pair being evaluated,
+// into two register sets refilled in turn (no register copies); scheduling
+// barriers keep each gather where it is issued.
+template <bool WRAP, int M>
+__device__ __forceinline__ void row3(const EulerArgs& ea, const Own3& o, const float4* __restrict__ R,
+                                     const int32_t* __restrict__ col, int32_t i, uint32_t e0, uint32_t es, int32_t m,
+                                     int32_t mu, Kahan& sr, Kahan* sm) {
+    for (int32_t base = 0; base < mu; base += M) {
+        int32_t jb[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int32_t t = base + q < m ? base + q : m - 1;
+            const int32_t v = ld32(col, m > 0 ? e0 + (uint32_t)t * es : 0u);  // always an entry of the array
+            jb[q] = base + q < m ? v : i;
+        }
+        Rec3 A, B;
+        gather3(R, jb[0], A);
+        gather3(R, jb[1], B);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < M; q += 2) {
+            pair3<WRAP>(ea, o, A, sr, sm);
+            if (q + 2 < M) gather3(R, jb[q + 2], A);
+            __builtin_amdgcn_sched_barrier(0);
+            pair3<WRAP>(ea, o, B, sr, sm);
+            if (q + 3 < M) gather3(R, jb[q + 3], B);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// One lane group of L lanes per particle (sorted slot i).  STAGE 0 writes
+// the rates at the caller index; 1: Uout = U + dt R(U); 2: Uout = (U0 + U +
+// dt R(U)) / 2, and both write q3 of Rout for Uout.  Rout may be the
+// record set of U0: each particle's records are read and written only by
+// its own group, and neighbours are gathered from R, which a stage never
+// writes.  ELL rows: entry k of slot i at col[k n + i] (k < S); CSR rows:
+// rp.  Lane sub takes entries sub, sub + L, ...
+template <int STAGE, int L, bool ELL, int M>
+__global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const int64_t* __restrict__ rp,
+                                                const int32_t* __restrict__ col, int32_t S,
+                                                const float4* __restrict__ R, float4* Rout, const float4* U,
+                                                const float4* U0, float4* Uout, const float4* __restrict__ sorted,
+                                                float* __restrict__ drho_dt, float* __restrict__ dmom_dt) {
+    const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int sub = (int)(threadIdx.x % L);
+    const int32_t ig = blk * (BLK / L) + (int32_t)(threadIdx.x / L);
+    // every lane of the wave stays to the end (the wave-wide maximum below
+    // reads all of them); groups past the last particle take its row and
+    // write nothing
+    const bool valid = ig < n;
+    const int32_t i = valid ? ig : n - 1;
+    uint32_t e0, es;
+    int32_t m, mu;
+    if (ELL) {
+        e0 = (uint32_t)sub * (uint32_t)n + (uint32_t)i;
+        es = (uint32_t)L * (uint32_t)n;
+        m = (S - sub + L - 1) / L;
+        mu = (S + L - 1) / L;
+    } else {
+        const int64_t b = rp[i], e = rp[i + 1];
+        e0 = (uint32_t)b + (uint32_t)sub;
+        es = (uint32_t)L;
+        m = (int32_t)((e - b - sub + L - 1) / L);
+        m = m > 0 ? m : 0;
+        mu = m;
+#pragma unroll
+        for (int k = 1; k < 64; k <<= 1) mu = max(mu, __shfl_xor(mu, k, 64));  // the wave's longest share
+    }
+    Rec3 self;
+    gather3(R, i, self);
+    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
+    if (STAGE != 0 && sub == 0) {
+        ui = U[i];
+        if (STAGE == 2) u0 = U0[i];
+    }
+    Own3 o;
+    o.x[0] = self.q0.x; o.x[1] = self.q0.y; o.x[2] = self.q0.z;
+    o.B[0] = self.q1.x; o.B[1] = self.q1.y; o.B[2] = self.q1.z; o.B[3] = self.q1.w;
+    o.B[4] = self.q2.x; o.B[5] = self.q2.y;
+    o.trB = self.q2.z;
+    o.p2 = self.q3.x;
+    o.v[0] = self.q3.y; o.v[1] = self.q3.z; o.v[2] = self.q3.w;
+    o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);
+    // periodic wrap only in waves with a particle near a periodic face
+    bool near = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (ea.invL[a] != 0.f) {
+            const float off = o.x[a] - ea.lo[a];
+            near = near || off < ea.margin || ea.L[a] - off < ea.margin;
+        }
+    }
+    Kahan sr, sm[3];
+    sr.init();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sm[a].init();
+    if (__any(near)) row3<true, M>(ea, o, R, col, i, e0, es, m, mu, sr, sm);
+    else row3<false, M>(ea, o, R, col, i, e0, es, m, mu, sr, sm);
+    float Rt[4];
+    Rt[0] = ea.fr * group_sum<L>(sr);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Rt[1 + a] = ea.fm * group_sum<L>(sm[a]);
+    if (sub != 0 || !valid) return;
+    if (STAGE == 0) {
+        const int32_t ic = __float_as_int(sorted[i].w);
+        drho_dt[ic] = Rt[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dmom_dt[(int64_t)a * n + ic] = Rt[1 + a];
+        return;
+    }
+    float4 un;
+    if (STAGE == 1) {
+        un = make_float4(ui.x + ea.dt * Rt[0], ui.y + ea.dt * Rt[1], ui.z + ea.dt * Rt[2], ui.w + ea.dt * Rt[3]);
+    } else {
+        un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * Rt[0])), 0.5f * (u0.y + (ui.y + ea.dt * Rt[1])),
+                         0.5f * (u0.z + (ui.z + ea.dt * Rt[2])), 0.5f * (u0.w + (ui.w + ea.dt * Rt[3])));
+    }
+    Uout[i] = un;
+    Rout[4 * (int64_t)i + 3] = state_quad3(ea, un);
 }
 
 // ------------------------------------------------------------------ tiled stage
@@ -872,6 +1098,8 @@ EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     a.kmu = (float)(-4.0 * p->mu / c->dim);
     a.fr = (float)(-0.5 * (double)kc.cF);
     a.fm = (float)(-0.25 * (double)kc.cF);
+    a.inv2c = (float)(0.5 / p->c);
+    a.crho0x2 = (float)(2.0 * p->c * p->rho0);
     for (int ax = 0; ax < 3; ++ax) {
         a.L[ax] = c->box.L[ax];
         a.invL[ax] = c->box.periodic[ax] ? (float)(1.0 / c->box.Ld[ax]) : 0.f;
@@ -912,14 +1140,9 @@ void launch_k(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     const int64_t* rp = ell ? nullptr : c->rp_s.as<int64_t>();
     const int32_t* col = ell ? c->colE.as<int32_t>() : c->col_s.as<int32_t>();
     const int32_t S = ell ? c->ell_S : 0;
-    if (DIM == 3 && c->geoA_gen == c->geo_gen)
-        hipLaunchKernelGGL((k_euler<DIM, SOL, STAGE, L, MODE, E, DIM == 3>), grid, dim3(BLK), 0, c->stream, c->n, ea,
-                           rp, col, S, c->geoA.as<float4>(), nullptr, nullptr, io.U, io.P, io.U0, io.Uout, io.Pout,
-                           c->sorted.as<float4>(), io.dr, io.dm, io.de);
-    else
-        hipLaunchKernelGGL((k_euler<DIM, SOL, STAGE, L, MODE, E, false>), grid, dim3(BLK), 0, c->stream, c->n, ea,
-                           rp, col, S, c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P,
-                           io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm, io.de);
+    hipLaunchKernelGGL((k_euler<DIM, SOL, STAGE, L, MODE, E>), grid, dim3(BLK), 0, c->stream, c->n, ea, rp, col, S,
+                       c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U, io.P, io.U0, io.Uout,
+                       io.Pout, c->sorted.as<float4>(), io.dr, io.dm, io.de);
 }
 
 template <int DIM, int SOL, int STAGE, int L>
@@ -1097,33 +1320,83 @@ void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, bool tiled) {
     }
 }
 
-__global__ void k_pack_geo3(int32_t n, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
-                            const float2* __restrict__ geo2, float4* __restrict__ geoA) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float2 t = geo2[i];
-    geoA[3 * i] = geo0[i];
-    geoA[3 * i + 1] = geo1[i];
-    geoA[3 * i + 2] = make_float4(t.x, t.y, 0.f, 0.f);
+// 3-D records path: used when the records and the row entries fit the
+// 32-bit gathers (n < 2^26 particles, fewer than 2^30 row entries), unless
+// the tuning override SPH_EULER_GEO=split selects the separate geometry
+// arrays of the generic kernel.
+bool use_rec3(const sph_ctx* c) {
+    if (c->dim != 3) return false;
+    const char* e = getenv("SPH_EULER_GEO");
+    if (e && strcmp(e, "split") == 0) return false;
+    if ((uint64_t)c->n >= (1ull << 26)) return false;
+    const uint64_t entries = c->ell_state == 1 ? (uint64_t)c->ell_S * (uint64_t)c->n : (uint64_t)c->nnz;
+    return entries < (1ull << 30);
 }
 
-// 3-D: the interleaved copy of the geometry records the per-particle kernel
-// gathers from, packed once per cached correction (configurations whose
-// 48-byte records exceed 32-bit byte offsets keep the separate arrays, and
-// so does the tuning override SPH_EULER_GEO=split).
-int prepare_geo3(sph_ctx* c) {
-    const char* e = getenv("SPH_EULER_GEO");
-    if (e && strcmp(e, "split") == 0) {
-        c->geoA_gen = ~0ull;
-        return SPH_OK;
+struct Stage3 {
+    const float4* R;
+    float4* Rout;
+    const float4* U;
+    const float4* U0;
+    float4* Uout;
+    float* dr;
+    float* dm;
+};
+
+template <int STAGE, int L, int M>
+void launch3_m(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const dim3 grid(grid_for(c->n, BLK / L));
+    if (c->ell_state == 1)
+        hipLaunchKernelGGL((k_euler3<STAGE, L, true, M>), grid, dim3(BLK), 0, c->stream, c->n, ea, nullptr,
+                           c->colE.as<int32_t>(), c->ell_S, io.R, io.Rout, io.U, io.U0, io.Uout,
+                           c->sorted.as<float4>(), io.dr, io.dm);
+    else
+        hipLaunchKernelGGL((k_euler3<STAGE, L, false, M>), grid, dim3(BLK), 0, c->stream, c->n, ea,
+                           c->rp_s.as<int64_t>(), c->col_s.as<int32_t>(), 0, io.R, io.Rout, io.U, io.U0, io.Uout,
+                           c->sorted.as<float4>(), io.dr, io.dm);
+}
+
+// Pairs per chunk: for fixed-stride rows the M in {6, 8, 10, 12, 16} whose
+// chunks cover a lane's ceil(S / L) entries with the fewest padding pairs
+// (the larger on a tie); CSR rows take chunks of 8.
+template <int STAGE, int L>
+void launch3_l(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    if (c->ell_state != 1) {
+        launch3_m<STAGE, L, 8>(c, ea, io);
+        return;
     }
-    if (c->dim != 3 || c->n == 0 || c->geoA_gen == c->geo_gen) return SPH_OK;
-    if ((uint64_t)c->n * 3u * sizeof(float4) >= (1ull << 32)) return SPH_OK;
-    SPH_HIP(c, c->geoA.ensure((size_t)c->n * 3 * sizeof(float4)));
-    hipLaunchKernelGGL(k_pack_geo3, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, c->geo0.as<float4>(),
-                       c->geo1.as<float4>(), c->geo2.as<float2>(), c->geoA.as<float4>());
+    const int mu = (c->ell_S + L - 1) / L;
+    const int cand[5] = {16, 12, 10, 8, 6};
+    int best = 16, cost = 1 << 30;
+    for (int M : cand) {
+        const int k = (mu + M - 1) / M * M;
+        if (k < cost) cost = k, best = M;
+    }
+    if (best == 16) launch3_m<STAGE, L, 16>(c, ea, io);
+    else if (best == 12) launch3_m<STAGE, L, 12>(c, ea, io);
+    else if (best == 10) launch3_m<STAGE, L, 10>(c, ea, io);
+    else if (best == 8) launch3_m<STAGE, L, 8>(c, ea, io);
+    else launch3_m<STAGE, L, 6>(c, ea, io);
+}
+
+template <int STAGE>
+void launch3(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const int L = lanes_per_particle(c);
+    if (L == 1) launch3_l<STAGE, 1>(c, ea, io);
+    else if (L == 2) launch3_l<STAGE, 2>(c, ea, io);
+    else if (L == 4) launch3_l<STAGE, 4>(c, ea, io);
+    else launch3_l<STAGE, 8>(c, ea, io);
+}
+
+// Pack the caller's state into U and both record sets (64 B per particle
+// each).
+int pack3(sph_ctx* c, const EulerArgs& ea, const float* drho, const float* mom, float4* U) {
+    SPH_HIP(c, c->rec3.ensure((size_t)c->n * 8 * sizeof(float4)));
+    float4* Ra = c->rec3.as<float4>();
+    hipLaunchKernelGGL(k_pack3, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n, ea, c->sorted.as<float4>(),
+                       drho, mom, c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), U, Ra,
+                       Ra + 4 * (size_t)c->n);
     SPH_LAUNCH_CHECK(c);
-    c->geoA_gen = c->geo_gen;
     return SPH_OK;
 }
 
@@ -1194,8 +1467,15 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     bool tiled = false;
     r = prepare_tiles(c, &tiled);
     if (r) return r;
-    if (!tiled && (r = prepare_geo3(c))) return r;
     EulerArgs ea = make_args(c, p);
+    if (!tiled && use_rec3(c)) {
+        r = pack3(c, ea, drho, mom, c->ua.as<float4>());
+        if (r) return r;
+        Stage3 io{c->rec3.as<float4>(), nullptr, nullptr, nullptr, nullptr, drho_dt, dmom_dt};
+        launch3<0>(c, ea, io);
+        SPH_LAUNCH_CHECK(c);
+        return SPH_OK;
+    }
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt};
@@ -1222,16 +1502,29 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     bool tiled = false;
     r = prepare_tiles(c, &tiled);
     if (r) return r;
-    if (!tiled && (r = prepare_geo3(c))) return r;
     EulerArgs ea = make_args(c, p);
-    r = pack(c, ea.rho_ref, drho, mom, U, P);
-    if (r) return r;
-    // stage 1 gathers P, writes (U*, P*); stage 2 gathers P*, writes (U, P) in place
-    StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr};
-    StageIO s2{Us, Ps, U, U, P, nullptr, nullptr};
-    for (int32_t s = 0; s < nsteps; ++s) {
-        launch<SOL_LINEARISED, 1>(c, ea, s1, tiled);
-        launch<SOL_LINEARISED, 2>(c, ea, s2, tiled);
+    if (!tiled && use_rec3(c)) {
+        r = pack3(c, ea, drho, mom, U);
+        if (r) return r;
+        float4* Ra = c->rec3.as<float4>();
+        float4* Rb = Ra + 4 * (size_t)c->n;
+        // stage 1 gathers Ra, writes (U*, Rb); stage 2 gathers Rb, writes (U, Ra) in place
+        Stage3 s1{Ra, Rb, U, nullptr, Us, nullptr, nullptr};
+        Stage3 s2{Rb, Ra, Us, U, U, nullptr, nullptr};
+        for (int32_t s = 0; s < nsteps; ++s) {
+            launch3<1>(c, ea, s1);
+            launch3<2>(c, ea, s2);
+        }
+    } else {
+        r = pack(c, ea.rho_ref, drho, mom, U, P);
+        if (r) return r;
+        // stage 1 gathers P, writes (U*, P*); stage 2 gathers P*, writes (U, P) in place
+        StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr};
+        StageIO s2{Us, Ps, U, U, P, nullptr, nullptr};
+        for (int32_t s = 0; s < nsteps; ++s) {
+            launch<SOL_LINEARISED, 1>(c, ea, s1, tiled);
+            launch<SOL_LINEARISED, 2>(c, ea, s2, tiled);
+        }
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)

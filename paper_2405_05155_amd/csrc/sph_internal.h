@@ -179,8 +179,7 @@ struct sph_ctx {
     DevBuf geo1;  // float4 [n]: 3-D (B00, B01, B02, B11); 2-D float2 (B01, B11)
     DevBuf geo2;  // float2 [n]: 3-D (B12, B22)
     uint64_t geo_gen = 0;        // bumped whenever geo0..geo2 change or go stale
-    DevBuf geoA;                 // float4 [3n]: 3-D records (x, y, z, V), (B00, B01, B02, B11), (B12, B22, 0, 0)
-    uint64_t geoA_gen = ~0ull;   // geo_gen that geoA was packed from
+    DevBuf rec3;                 // 3-D Eulerian stage records: two sets of float4 [4n] (geometry and state)
 
     // state scratch
     DevBuf ua, ub;      // float4 [n] packed states

@@ -414,15 +414,19 @@ def _mixed_box_3d(nside=24, seed=5):
     return w
 
 
+@pytest.mark.parametrize("geo", ["records", "split"])
 @pytest.mark.parametrize("rows", ["ell", "csr"])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-def test_euler_rhs_3d_geometry_records(S, rows, kappa, monkeypatch):
-    """3-D rates through the interleaved copy of the geometry records: against
-    the oracle, again after the correction is recomputed for new volumes (the
-    copy must be repacked), and bit for bit against the separate arrays
-    (SPH_EULER_GEO=split; same arithmetic, other addresses)."""
+def test_euler_rhs_3d_geometry_records(S, rows, kappa, geo, monkeypatch):
+    """3-D rates on a jittered box with an open axis: through the packed
+    per-particle records (geometry and state in one 64-byte record, packed
+    from the cached correction at each call) and through the separate
+    geometry arrays of the generic kernel (SPH_EULER_GEO=split), against the
+    oracle, again after the correction is recomputed for new volumes."""
     if rows == "csr":
         monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
+    if geo == "split":
+        monkeypatch.setenv("SPH_EULER_GEO", "split")
     w = _mixed_box_3d()
     ctx = gpu_ctx(S, w, kappa)
     pg, po = _euler_prm(S, w)
@@ -439,9 +443,44 @@ def test_euler_rhs_3d_geometry_records(S, rows, kappa, monkeypatch):
         r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, vol, Bo, po, rho, w.fields["mom"])
         scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
         scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
-    monkeypatch.setenv("SPH_EULER_GEO", "split")
-    dr2, dm2 = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
-    assert np.array_equal(host(dr2), host(dr)) and np.array_equal(host(dm2), host(dm))
+
+
+@pytest.mark.parametrize("lanes", ["1", "2", "4", "8"])
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
+def test_euler_3d_lanes_and_chunks(S, kappa, lanes, monkeypatch):
+    """The 3-D stage on every lanes-per-particle mapping (1, 2, 4, 8 lanes;
+    the chunk of pairs per lane follows the row length) against the oracle:
+    rates on the jittered open box and one Heun step of a jittered periodic
+    Taylor-Green cube."""
+    monkeypatch.setenv("SPH_EULER_LANES", lanes)
+    w = _mixed_box_3d()
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    pg, po = _euler_prm(S, w)
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    rho = w.fields["rho_ref"] + w.fields["drho"].astype(np.float64)
+    dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+    r_dr, r_dm, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, rho, w.fields["mom"])
+    scaled_check(host(dr), r_dr, s_dr, RTOL, "drho/dt")
+    scaled_check(host(dm), r_dm, s_dm, RTOL, "dmom/dt")
+    ctx.close()
+    w = I.taylor_green_3d(nside=24, jitter=0.1, seed=4)
+    ctx = gpu_ctx(S, w, kappa)
+    ctx.correction_B(dev(w.vol))
+    dt = w.meta["dt"]
+    pg, po = _euler_prm(S, w, dt)
+    box, rp, col, Bo, _ = _c0_oracle(w, kappa)
+    drho0 = w.fields["drho"].astype(np.float64)
+    mom0 = w.fields["mom"].astype(np.float64)
+    d, m = dev(w.fields["drho"]), dev(w.fields["mom"])
+    ctx.euler_step(pg, d, m, 1)
+    r1, m1 = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, Bo, po, 1.0 + drho0, mom0, 1)
+    _, _, s_dr, s_dm = O.euler_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, 1.0 + drho0, mom0)
+    eps = np.finfo(np.float32).eps
+    inc_g, inc_o = host(d) - drho0, (r1 - 1.0) - drho0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dr) + 4 * eps * np.abs(r1 - 1.0))
+    inc_g, inc_o = host(m) - mom0, m1 - mom0
+    assert np.all(np.abs(inc_g - inc_o) <= 1e-5 * (np.abs(inc_o) + 1.5 * dt * s_dm) + 4 * eps * np.abs(m1))
 
 
 @pytest.mark.parametrize("case", ["mixed3d", "tiny2d"])
