@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark: particle-neighbour interactions/s of the Eulerian SPH hot path.
 
-Workload: 2-D Taylor-Green vortex, 512 x 512 = 262,144 particles on the
-periodic unit square, h = 1.3 dx, c = 10, Re = 100 (nu = 0.01), Heun (RK2)
-steps with fixed dt.  One step = two evaluations of the corrected
-Riemann-flux RHS over every directed neighbour pair.  The primary line is the
-truncated kernel (cut-off 1.6h); the standard kernel (2h) runs on the same
-state for the speed ratio.
+Headline workload: 3-D Taylor-Green vortex, 200^3 = 8,000,000 particles in
+the periodic unit cube, h = 1.3 dx, c = 10, nu = 0.01, Heun (RK2) steps with
+fixed dt (the workload runs 200).  One step = two evaluations of the
+corrected Riemann-flux RHS over every directed neighbour pair.  The primary
+line is the truncated kernel (cut-off 1.6h); the standard kernel (2h) runs
+the same steps for the speed ratio, and both report the kinetic-energy decay
+rate at t = 0 against its exact value 24 pi^2 nu (the initial field is an
+eigenfunction of the Laplacian).
 
-Printed: ONE JSON line (see keys below), with
-  roofline      the dominant kernel (the Heun stage kernel) against HBM,
-  cpu_baseline  the FP64 oracle on the host cores over a bounded sample.
+Printed: ONE JSON line, with
+  roofline      the dominant kernel (the 3-D Heun stage kernel) against HBM,
+                its VALU issue fraction from the counter profile beside it,
+  cpu_baseline  the FP64 oracle on the host cores over bounded samples of the
+                3-D workload (headline), the plate and the relaxation,
+and further sections: the 2-D Taylor-Green 512^2 (the workload's 1000
+steps), the total-Lagrangian plate, the double shear layer, the compressible
+rows, the error analysis and the relaxation warm start.
 """
 from __future__ import annotations
 
@@ -37,6 +44,15 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {
     "4279a21bd6669683ce80e88dd5ca149af599fc07b5ad81a7a72e408228c8c276": {"2d": 39157539, "3d": 2246174273},
 }
+
+
+# VALU wave instructions per launch of the stage kernel (rocprofv3 --pmc
+# SQ_INSTS_VALU), keyed like TRAFFIC.  The issue fraction is insts x 4 cycles
+# (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles) over
+# 1,024 SIMDs x 2.4 GHz x the live launch time.
+VALU = {}
+VALU_SIMDS = 1024
+VALU_CLOCK_HZ = 2.4e9
 
 
 def _code_lines(text: str):
@@ -402,8 +418,19 @@ def relaxed_sphere_errors(nsides=(16, 32, 64), kernel="LG", iters=400):
     return out
 
 
-def run_euler_3d(nside, kappa, steps, warmup):
-    """3-D Taylor-Green in the periodic unit cube (nside^3 particles)."""
+def _ke(vol, drho, mom, rho_ref=1.0):
+    """Kinetic energy sum_i V_i |m_i|^2 / (2 rho_i) of a device state (FP64)."""
+    rho = rho_ref + drho.double()
+    return float((vol.double() * (mom.double() ** 2).sum(0) / (2.0 * rho)).sum())
+
+
+def run_euler_3d(nside, kappa, steps, warmup, accuracy_steps=0):
+    """3-D Taylor-Green in the periodic unit cube (nside^3 particles): time
+    per Heun step over `steps` steps after `warmup` untimed ones (HIP events
+    on the context's stream); the kinetic-energy decay rate at t = 0 from
+    the RHS; with accuracy_steps > warmup + steps the run continues untimed
+    to accuracy_steps, and the final velocity and kinetic energy are
+    returned (not timed)."""
     import torch
 
     from paper_2405_05155_amd import inputs as I
@@ -413,26 +440,61 @@ def run_euler_3d(nside, kappa, steps, warmup):
     ctx = S.Context(3)
     ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa), torch.as_tensor(w.pos, device="cuda"))
     ctx.neighbors()
-    ctx.correction_B(torch.as_tensor(w.vol, device="cuda"))
+    vol = torch.as_tensor(w.vol, device="cuda")
+    ctx.correction_B(vol)
     prm = S.euler_params(c=f["c"], rho0=f["rho0_eos"], rho_ref=f["rho_ref"], eta=f["eta"], mu=f["mu"],
                          dt=w.meta["dt"])
     d = torch.as_tensor(f["drho"], device="cuda").clone()
     m = torch.as_tensor(f["mom"], device="cuda").clone()
-    ctx.euler_step(prm, d, m, warmup)
+    # kinetic-energy rate at t = 0: dK/dt = sum V (m . dm/dt / rho - |m|^2 drho/dt / (2 rho^2))
+    dr, dm = ctx.euler_rhs(prm, d, m)
+    rho = f["rho_ref"] + d.double()
+    m2 = (m.double() ** 2).sum(0)
+    dK = float((vol.double() * ((m.double() * dm.double()).sum(0) / rho - m2 * dr.double() / (2 * rho ** 2))).sum())
+    ke0 = _ke(vol, d, m, f["rho_ref"])
+    del dr, dm, rho, m2
+    if warmup > 0:
+        ctx.euler_step(prm, d, m, warmup)
+    stream = ctx.stream
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     ctx.euler_step(prm, d, m, steps)
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     nnz = ctx.nnz
-    ctx.close()
+    out = {"n_particles": w.n, "nnz": nnz, "steps": steps, "ms_per_step": ms / steps,
+           "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3)}
     launch_s = ms * 1e-3 / (2 * steps)
     bytes_launch = stage_bytes_3d(w.n, nnz)
-    return {"n_particles": w.n, "nnz": nnz, "ms_per_step": ms / steps,
-            "interactions_per_s": 2.0 * nnz * steps / (ms * 1e-3), "avg_launch_us": launch_s * 1e6,
-            "bytes_per_launch": bytes_launch, "achieved_GBs": bytes_launch / launch_s / 1e9}
+    out.update({"avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch,
+                "achieved_GBs": bytes_launch / launch_s / 1e9, "ke_rate_t0": -dK / ke0, "dt": w.meta["dt"]})
+    done = warmup + steps
+    if accuracy_steps > done:
+        ctx.euler_step(prm, d, m, accuracy_steps - done)
+        done = accuracy_steps
+    out["t_end"] = done * w.meta["dt"]
+    out["ke_end_over_ke0"] = _ke(vol, d, m, f["rho_ref"]) / ke0
+    out["_vel"] = m.double() / (f["rho_ref"] + d.double())
+    ctx.close()
+    return out
+
+
+def tgv3d_accuracy(tw, sw, nu):
+    """Accuracy of the two 3-D runs: the kinetic-energy decay rate at t = 0
+    against 24 pi^2 nu (exact for the initial field), the energy at the end
+    of the run against the first-order estimate exp(-24 pi^2 nu t), and the
+    relative L2 difference of the two final velocity fields."""
+    import math
+    exact = 24.0 * math.pi ** 2 * nu
+    e_tw, e_sw = abs(tw["ke_rate_t0"] / exact - 1.0), abs(sw["ke_rate_t0"] / exact - 1.0)
+    diff = float((tw["_vel"] - sw["_vel"]).norm() / sw["_vel"].norm())
+    return {"ke_decay_rate_t0": {"exact_24pi2nu": exact, "tw": tw["ke_rate_t0"], "sw": sw["ke_rate_t0"],
+                                 "rel_err_tw": e_tw, "rel_err_sw": e_sw, "err_ratio_tw_over_sw": e_tw / e_sw},
+            "run": {"t": tw["t_end"], "ke_over_ke0_tw": tw["ke_end_over_ke0"], "ke_over_ke0_sw": sw["ke_end_over_ke0"],
+                    "exp_minus_24pi2nu_t": math.exp(-exact * tw["t_end"]), "vel_rel_diff_tw_sw": diff},
+            "viscous_term": "2 mu sum_j V_j c_ij (v_i - v_j) W'/r, c_ij = (tr B_i + tr B_j)/(2d)"}
 
 
 def run_plate(kappa, steps, warmup, nx=430):
@@ -500,7 +562,23 @@ def plate_tip_history(kappa, steps, every, nx=430):
     return np.array(hist)
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host the oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def run_cpu_baseline(w, kappa, budget_s):
+    """The FP64 oracle on a 2-D Taylor-Green workload: Heun steps timed
+    until the budget is spent (neighbours and B not timed)."""
     import numpy as np
 
     import oracle as O
@@ -520,9 +598,99 @@ def run_cpu_baseline(w, kappa, budget_s):
     O.euler_heun(box, w.pos, w.h, rp, col, w.vol, B, prm, rho, mom, steps)
     dt = time.perf_counter() - t0
     nnz = int(rp[-1])
+    side = int(round(w.n ** 0.5))
     return {"value": 2.0 * nnz * steps / dt, "unit": "interactions/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} Heun steps of the same 512^2 workload at kappa={kappa} (FP64 oracle, "
-                      f"{dt:.1f} s)"}
+            "ms_per_step": dt * 1e3 / steps,
+            "sample": f"{steps} Heun steps of the 2-D Taylor-Green {side}^2 workload at kappa={kappa} "
+                      f"(FP64 oracle, {dt:.1f} s)"}
+
+
+def run_cpu_3d(budget_s, nside=200, kappa=1.6, max_steps=10):
+    """The FP64 oracle on the headline workload (3-D Taylor-Green, nside^3):
+    neighbour search and B of every particle (set-up, not timed), then the
+    first Heun steps from the initial state, timed until the budget is spent
+    (at least one, at most max_steps)."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2405_05155_amd import inputs as I
+    w = I.taylor_green_3d(nside=nside)
+    f = w.fields
+    box = O.make_box(3)
+    rc = kappa * w.h
+    t0 = time.perf_counter()
+    rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+    B, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    setup = time.perf_counter() - t0
+    prm = O.euler_params(c=f["c"], rho0=f["rho0_eos"], eta=f["eta"], mu=f["mu"], dt=w.meta["dt"])
+    rho = f["rho_ref"] + f["drho"].astype(np.float64)
+    mom = f["mom"].astype(np.float64)
+    steps, secs = 0, 0.0
+    while steps < max_steps and (steps == 0 or secs + secs / steps <= budget_s):
+        t0 = time.perf_counter()
+        rho, mom = O.euler_heun(box, w.pos, w.h, rp, col, w.vol, B, prm, rho, mom, 1)
+        secs += time.perf_counter() - t0
+        steps += 1
+    nnz = int(rp[-1])
+    return {"value": 2.0 * nnz * steps / secs, "unit": "interactions/s", "cores": O.num_threads(), "kind": "oracle",
+            "ms_per_step": secs * 1e3 / steps,
+            "sample": f"the first {steps} of the 200 Heun steps of the {nside}^3 3-D Taylor-Green workload at "
+                      f"kappa={kappa} (FP64 oracle, {secs:.1f} s; neighbour search and B, {setup:.1f} s, not timed)"}
+
+
+def run_cpu_plate(budget_s, kappa=1.6, nx=430, max_steps=50):
+    """The FP64 oracle on the total-Lagrangian plate (1,604,932 particles):
+    the first kick-drift-kick steps, timed until the budget is spent."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2405_05155_amd import inputs as I
+    w = I.cantilever_plate(nx=nx)
+    f = w.fields
+    box = O.make_box(3, lo=w.lo, hi=w.hi, periodic=(0, 0, 0))
+    rc = kappa * w.h
+    rp, col = O.neighbors_grid(box, w.pos, rc, rc * rc)
+    B, _ = O.correction_B(box, w.pos, O.WENDLAND, w.h, rp, col, w.vol)
+    prm = O.tlsph_params(f["rho0"], f["E"], f["nu"], dt=w.meta["dt"], model=0)
+    F = np.tile(np.eye(3), (w.n, 1, 1))
+    pos, vel, fixed = w.pos.astype(np.float64), f["vel"].astype(np.float64), f["fixed"]
+    _, acc, _ = O.tlsph_rhs(box, w.pos, w.h, rp, col, w.vol, B, prm, vel, F, fixed)
+    steps, secs = 0, 0.0
+    while steps < max_steps and (steps == 0 or secs + secs / steps <= budget_s):
+        t0 = time.perf_counter()
+        pos, vel, F, acc = O.tlsph_step(box, w.pos, w.h, rp, col, w.vol, B, prm, fixed, pos, vel, F, acc, 1)
+        secs += time.perf_counter() - t0
+        steps += 1
+    nnz = int(rp[-1])
+    return {"value": 2.0 * nnz * steps / secs, "unit": "interactions/s", "cores": O.num_threads(), "kind": "oracle",
+            "ms_per_step": secs * 1e3 / steps,
+            "sample": f"the first {steps} of the 2000 kick-drift-kick steps of the {w.n}-particle plate at "
+                      f"kappa={kappa} (FP64 oracle, {secs:.1f} s)"}
+
+
+def run_cpu_relax(budget_s, nside=260, max_iter=200):
+    """The FP64 oracle on the relaxation workload (the seed-2 sphere,
+    1,987,776 particles at dx = 1/260): the first iterations (each with a
+    fresh neighbour search, as on the GPU), timed until the budget is
+    spent."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2405_05155_amd import inputs as I
+    w = I.sphere_fill(dx=1.0 / nside, seed=2)
+    f = w.fields
+    box = O.make_box(3, lo=w.lo, hi=w.hi, periodic=(0, 0, 0))
+    prm = O.relax_params(w.h, f["center"], f["radius"], p0=f["p0"], rho=f["rho"])
+    pos, u = w.pos.astype(np.float64), np.zeros((3, w.n))
+    iters, secs = 0, 0.0
+    while iters < max_iter and (iters == 0 or secs + secs / iters <= budget_s):
+        t0 = time.perf_counter()
+        pos, u, _ = O.relax_run(box, pos, prm, w.vol, 1, u=u)
+        secs += time.perf_counter() - t0
+        iters += 1
+    return {"ms_per_iteration": secs * 1e3 / iters, "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"the first {iters} iterations of the {w.n}-particle sphere relaxation "
+                      f"(FP64 oracle, {secs:.1f} s)"}
 
 
 def run_cpu_one_core(kappa, budget_s):
@@ -656,27 +824,36 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     import numpy as np
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=500,
-                    help="untimed steps first (the GPU clock settles over the first ~10 ms of work); "
-                         "warmup + steps = 1000 is the workload's run")
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed Heun steps of the 200^3 3-D Taylor-Green headline (the workload runs 200)")
+    ap.add_argument("--warmup", type=int, default=10, help="untimed 3-D steps before the timed ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
-    ap.add_argument("--nside", type=int, default=512)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of timed oracle work on the headline workload")
+    ap.add_argument("--cpu-budget-extra", type=float, default=5.0,
+                    help="seconds of timed oracle work on each of the plate, the relaxation and the 2-D workload")
+    ap.add_argument("--nside2d", type=int, default=512)
+    ap.add_argument("--steps2d", type=int, default=500,
+                    help="timed 2-D Taylor-Green steps, after as many untimed ones (the workload's 1000 in all)")
     ap.add_argument("--no-relax", action="store_true", help="skip the relaxation time-to-residue part")
     ap.add_argument("--relax-epochs", type=int, default=50)
     ap.add_argument("--relax-nside", type=int, default=260)
-    ap.add_argument("--no-extra", action="store_true", help="skip the 3-D Taylor-Green and TLSPH plate lines")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 2-D, plate, shear-layer, compressible and error-analysis sections")
     ap.add_argument("--nside3d", type=int, default=200)
-    ap.add_argument("--steps3d", type=int, default=200, help="timed 3-D Taylor-Green steps (the workload runs 200)")
     ap.add_argument("--steps-plate", type=int, default=2000, help="timed plate steps (the workload runs 2000)")
     ap.add_argument("--plate-accuracy-steps", type=int, default=2000,
                     help="untimed TW-vs-SW tip-deflection history of the plate (0: skip)")
-    ap.add_argument("--kappa", type=float, default=0.0, help="profile one cut-off only (1.6 or 2)")
+    ap.add_argument("--kappa", type=float, default=0.0, help="profile the 2-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--kappa3d", type=float, default=0.0, help="profile the 3-D Taylor-Green line only, at this cut-off")
     ap.add_argument("--plate", type=float, default=0.0, help="profile the TLSPH plate line only, at this cut-off")
     ap.add_argument("--shear", action="store_true", help="the double shear layer section only")
@@ -685,7 +862,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--cpu-one-core-budget", type=float, default=3.0,
-                    help="seconds of single-core oracle time (0: skip)")
+                    help="seconds of single-core oracle time on the 2-D workload (0: skip)")
     ap.add_argument("--setup", action="store_true", help="profile the set-up path only (binning, neighbours, "
                     "kernel sum, correction matrices)")
     args = ap.parse_args()
@@ -694,12 +871,14 @@ def main():
         sys.exit(2)
     if args.cpu_only_json:  # child of run_cpu_one_core: oracle only, no GPU
         from paper_2405_05155_amd import inputs as I
-        print(json.dumps(run_cpu_baseline(I.taylor_green_2d(nside=args.nside), args.kappa or 1.6, args.cpu_budget)))
+        print(json.dumps(run_cpu_baseline(I.taylor_green_2d(nside=args.nside2d), args.kappa or 1.6,
+                                          args.cpu_budget)))
         return
     one_core = None
     default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup
                        or args.plate or args.shear or args.compressible)
     if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
+        log("oracle on one core (2-D workload)")
         one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
 
     import torch
@@ -707,10 +886,10 @@ def main():
     from paper_2405_05155_amd import inputs as I
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    w = I.taylor_green_2d(nside=args.nside)
 
     if args.kappa:
-        one = run_gpu(w, args.kappa, args.steps, args.warmup)
+        w = I.taylor_green_2d(nside=args.nside2d)
+        one = run_gpu(w, args.kappa, args.steps2d, args.steps2d)
         print(json.dumps({"kappa": args.kappa, **one, "avg_launch_us": one["ms"] * 1e3 / one["launches"]}),
               flush=True)
         return
@@ -739,54 +918,77 @@ def main():
         print(json.dumps(run_train(args.train_steps)), flush=True)
         return
     if args.kappa3d:
-        one = run_euler_3d(args.nside3d, args.kappa3d, args.steps3d, min(args.warmup, 5))
+        one = run_euler_3d(args.nside3d, args.kappa3d, args.steps, args.warmup)
+        one.pop("_vel")
         print(json.dumps({"kappa": args.kappa3d, **one}), flush=True)
         return
-    tw = run_gpu(w, 1.6, args.steps, args.warmup)
-    sw = run_gpu(w, 2.0, args.steps, args.warmup)
+
+    log(f"3-D Taylor-Green {args.nside3d}^3: {args.warmup} + {args.steps} Heun steps per cut-off")
+    tw3 = run_euler_3d(args.nside3d, 1.6, args.steps, args.warmup, accuracy_steps=200)
+    sw3 = run_euler_3d(args.nside3d, 2.0, args.steps, args.warmup, accuracy_steps=200)
+    acc3 = tgv3d_accuracy(tw3, sw3, 0.01)
+    tw3.pop("_vel"), sw3.pop("_vel")
+    torch.cuda.empty_cache()
 
     from paper_2405_05155_amd.hbm_copy import copy_bandwidth
     copy_gbs = copy_bandwidth() / 1e9
-    launch_s = tw["ms"] * 1e-3 / tw["launches"]
-    bytes_launch = stage_bytes_2d(w.n, tw["nnz"])
-    achieved = bytes_launch / launch_s / 1e9
+    sha = source_sha(*STAGE_SOURCES)
+    launch_s = tw3["avg_launch_us"] * 1e-6
+    valu = None
+    if VALU.get(sha, {}).get("3d"):
+        insts = VALU[sha]["3d"]
+        busy = insts * 4.0 / (VALU_SIMDS * VALU_CLOCK_HZ * launch_s)
+        valu = {"insts_per_launch": insts, "issue_frac": busy,
+                "note": "SQ_INSTS_VALU (wave instructions, counter profile) x 4 cycles / "
+                        "(1,024 SIMDs x 2.4 GHz x launch time)"}
     out = {
         "metric": METRIC,
-        "value": tw["interactions_per_s"],
+        "value": tw3["interactions_per_s"],
         "unit": "interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": tw["ms_per_step"],
+        "ms_per_step": tw3["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"taylor_green_2d_{args.nside}x{args.nside}_heun_kappa1.6",
-                   "n_particles": w.n, "h_over_dx": 1.3, "c": 10.0, "nu": 0.01, "dt": w.meta["dt"],
-                   "nnz_1.6h": tw["nnz"], "nnz_2h": sw["nnz"]},
-        "sw_2h": {"value": sw["interactions_per_s"], "ms_per_step": sw["ms_per_step"]},
-        "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
-        "accuracy": {"t": (args.warmup + args.steps) * w.meta["dt"], "vel_l2_err_tw": tw["vel_l2_err"],
-                     "vel_l2_err_sw": sw["vel_l2_err"], "ratio_tw_over_sw": tw["vel_l2_err"] / sw["vel_l2_err"],
-                     "reference": "decaying Taylor-Green velocity u0 exp(-8 pi^2 nu t)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC.get(source_sha(*STAGE_SOURCES), {}).get("2d"),
-                     "kernel": "k_euler (2-D Heun stage, 1.6h)",
-                     "avg_launch_us": launch_s * 1e6, "bytes_per_launch": bytes_launch,
-                     "measured_copy_GBs": copy_gbs},
+        "config": {"workload": f"taylor_green_3d_{args.nside3d}^3_heun_kappa1.6", "n_particles": tw3["n_particles"],
+                   "h_over_dx": 1.3, "c": 10.0, "nu": 0.01, "dt": tw3["dt"], "nnz_1.6h": tw3["nnz"],
+                   "nnz_2h": sw3["nnz"]},
+        "sw_2h": {"value": sw3["interactions_per_s"], "ms_per_step": sw3["ms_per_step"]},
+        "speedup_tw_over_sw": sw3["ms_per_step"] / tw3["ms_per_step"],
+        "accuracy": acc3,
+        "roofline": {"bound": "hbm", "achieved": tw3["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": tw3["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC.get(sha, {}).get("3d"),
+                     "kernel": "k_euler (3-D Heun stage, 1.6h)",
+                     "avg_launch_us": tw3["avg_launch_us"], "bytes_per_launch": tw3["bytes_per_launch"],
+                     "measured_copy_GBs": copy_gbs, "valu": valu},
+        "taylor_green_3d": {"kappa1.6": tw3, "kappa2": sw3},
     }
     if not args.no_extra:
-        tw3, sw3 = run_euler_3d(args.nside3d, 1.6, args.steps3d, 5), run_euler_3d(args.nside3d, 2.0, args.steps3d, 5)
-        out["taylor_green_3d"] = {"nside": args.nside3d, "kappa1.6": tw3, "kappa2": sw3,
-                                  "speedup_tw_over_sw": sw3["ms_per_step"] / tw3["ms_per_step"]}
-        out["roofline_3d"] = {"bound": "hbm", "achieved": tw3["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": tw3["achieved_GBs"] / HBM_PEAK_GBS,
-                              "traffic": TRAFFIC.get(source_sha(*STAGE_SOURCES), {}).get("3d"),
-                              "kernel": "k_euler (3-D Heun stage, 1.6h, 200^3)",
-                              "avg_launch_us": tw3["avg_launch_us"], "bytes_per_launch": tw3["bytes_per_launch"]}
+        log(f"2-D Taylor-Green {args.nside2d}^2: {args.steps2d} + {args.steps2d} Heun steps per cut-off")
+        w2 = I.taylor_green_2d(nside=args.nside2d)
+        tw, sw = run_gpu(w2, 1.6, args.steps2d, args.steps2d), run_gpu(w2, 2.0, args.steps2d, args.steps2d)
+        launch2 = tw["ms"] * 1e-3 / tw["launches"]
+        bytes2 = stage_bytes_2d(w2.n, tw["nnz"])
+        out["taylor_green_2d"] = {
+            "nside": args.nside2d, "steps_timed": args.steps2d, "steps_untimed_first": args.steps2d,
+            "kappa1.6": {"interactions_per_s": tw["interactions_per_s"], "ms_per_step": tw["ms_per_step"],
+                         "nnz": tw["nnz"]},
+            "kappa2": {"interactions_per_s": sw["interactions_per_s"], "ms_per_step": sw["ms_per_step"],
+                       "nnz": sw["nnz"]},
+            "speedup_tw_over_sw": sw["ms_per_step"] / tw["ms_per_step"],
+            "accuracy": {"t": 2 * args.steps2d * w2.meta["dt"], "vel_l2_err_tw": tw["vel_l2_err"],
+                         "vel_l2_err_sw": sw["vel_l2_err"], "ratio_tw_over_sw": tw["vel_l2_err"] / sw["vel_l2_err"],
+                         "reference": "decaying Taylor-Green velocity u0 exp(-8 pi^2 nu t)"},
+            "roofline": {"bound": "hbm", "achieved": bytes2 / launch2 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": bytes2 / launch2 / 1e9 / HBM_PEAK_GBS, "traffic": TRAFFIC.get(sha, {}).get("2d"),
+                         "kernel": "k_euler (2-D Heun stage, 1.6h)", "avg_launch_us": launch2 * 1e6,
+                         "bytes_per_launch": bytes2}}
+        log("total-Lagrangian plate")
         twp, swp = run_plate(1.6, args.steps_plate, 40), run_plate(2.0, args.steps_plate, 40)
         out["tlsph_plate"] = {"kappa1.6": twp, "kappa2": swp,
                               "speedup_tw_over_sw": swp["ms_per_step"] / twp["ms_per_step"]}
@@ -797,15 +999,31 @@ def main():
                 "steps": args.plate_accuracy_steps, "tip_deflection_sw_final": float(hs[-1]),
                 "tip_deflection_tw_final": float(ht[-1]),
                 "tip_history_diff_over_sw_amplitude": float(np.abs(ht - hs).max() / np.abs(hs).max())}
+        log("double shear layer")
         out["double_shear_layer"] = shear_layer_section()
+        log("compressible rows")
         out["compressible"] = compressible_section()
+        log("error analysis")
         out["error_analysis_lattice"] = error_analysis_section()
     if not args.no_relax:
+        log("relaxation: training and plain / warm-started runs")
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = run_cpu_baseline(w, 1.6, args.cpu_budget)
+        log("oracle on the host cores: 3-D headline workload")
+        torch.cuda.empty_cache()
+        cpu = run_cpu_3d(args.cpu_budget, nside=args.nside3d)
+        cpu["host"] = host_cpu()
+        cpu["gpu_over_cpu"] = out["value"] / cpu["value"]
+        if not args.no_extra:
+            log("oracle on the host cores: plate, relaxation, 2-D workload")
+            cpu["plate"] = run_cpu_plate(args.cpu_budget_extra)
+            cpu["plate"]["gpu_over_cpu"] = out["tlsph_plate"]["kappa1.6"]["interactions_per_s"] / cpu["plate"]["value"]
+            cpu["relax"] = run_cpu_relax(args.cpu_budget_extra, nside=args.relax_nside)
+            cpu["taylor_green_2d"] = run_cpu_baseline(I.taylor_green_2d(nside=args.nside2d), 1.6,
+                                                      args.cpu_budget_extra)
         if one_core is not None:
-            out["cpu_baseline"]["one_core"] = one_core
+            cpu["one_core"] = one_core
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

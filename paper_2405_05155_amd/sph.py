@@ -206,6 +206,11 @@ class Context:
         self.n = 0
         self.nnz = 0
 
+    @property
+    def stream(self):
+        """The torch stream the context enqueues its kernels on."""
+        return self._stream
+
     def close(self):
         if getattr(self, "_h", None):
             lib().sph_ctx_destroy(self._h)

@@ -1,8 +1,22 @@
 """GPU parity of the learned warm start (features, BF16-MFMA forward,
 backward, AdamW, application) against the FP64 oracle with the same BF16
-rounding points.  Tolerances: features bit-exact up to rare single-ulp BF16
-rounding flips; tensors normwise relative 1e-3 and 99.9% of elements within
-1e-4 of the tensor's scale."""
+rounding points.  Tolerances (element errors relative to |x| plus the
+tensor's RMS):
+* features: bit-exact up to rare single-ulp BF16 rounding flips (>= 99.9%
+  exact);
+* forward outputs: normwise 1e-3; >= 99.5% of elements within 1e-4,
+  >= 99.9% within 1e-3, all within 1e-2.  A hidden activation rounds to the
+  other BF16 neighbour when its FP32 and FP64 pre-activations straddle a
+  rounding boundary (about 3e-5 of the activations, so about one sample in
+  a hundred carries a flip somewhere in its 256 activations); a flip moves
+  the sample's output by up to ~1e-3 of its scale.  Measured on the GPU:
+  99.69% within 1e-4, 99.91% within 3e-4, 99.99% within 1e-3, worst 1.3e-3;
+* gradients: normwise 1e-3 and every element within 1e-3 (measured worst
+  6e-4, on dW1 at batch 4,096); at the training batch of 65,536, where the
+  flips average out over many samples, every element within 1e-4 (measured
+  worst 6e-5).
+The survey's reading asks 99.9% within 1e-4; the flip rate above bounds the
+forward pass at about 99.7%."""
 import numpy as np
 import pytest
 
@@ -85,6 +99,8 @@ def test_forward_matches_oracle(S):
     # apart): about one sample in a few hundred carries such a flip
     ok, frac = close_elementwise(y, yo, frac=0.995)
     assert ok, frac
+    ok, frac = close_elementwise(y, yo, frac=0.999, rtol=1e-3)
+    assert ok, frac
     ok, frac = close_elementwise(y, yo, frac=1.0, rtol=1e-2)
     assert ok, frac
 
@@ -109,7 +125,7 @@ def test_gradient_matches_oracle(S):
     for name, shp in M.SHAPES:
         sz = int(np.prod(shp))
         assert normwise(gg[k:k + sz], go[k:k + sz]) < 1e-3, name
-        ok, frac = close_elementwise(gg[k:k + sz], go[k:k + sz], frac=0.99, rtol=1e-3)
+        ok, frac = close_elementwise(gg[k:k + sz], go[k:k + sz], frac=1.0, rtol=1e-3)
         assert ok, (name, frac)
         k += sz
     assert np.array_equal(host(p), theta)  # lr = 0 leaves the masters untouched
@@ -191,6 +207,9 @@ def test_gradient_ragged_batches(S, B):
     for name, shp in M.SHAPES:
         sz = int(np.prod(shp))
         assert normwise(gg[k:k + sz], go[k:k + sz]) < 1e-3, (name, B)
+        if B >= 1000:  # a flip in one of a few samples is not averaged out
+            ok, frac = close_elementwise(gg[k:k + sz], go[k:k + sz], frac=1.0, rtol=1e-3 if B < 65536 else 1e-4)
+            assert ok, (name, B, frac)
         k += sz
 
 
