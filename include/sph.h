@@ -226,14 +226,16 @@ int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fix
                    float* vel, float* F, float* acc, int32_t nsteps);
 
 /* ---------------------------------------------------------------- particle relaxation
- * Particle relaxation (Eq. 7, 3-D) of particles filling the sphere
- * |r - center| < radius, with the Laguerre-Gauss kernel of Eq. 8 or the
- * Wendland C2 kernel of Eq. 6 at its full support (the two relaxed
+ * Particle relaxation (Eq. 7) of particles filling the sphere (3-D
+ * contexts) or the circle (2-D contexts; the geometry of the error
+ * analysis) |r - center| < radius, with the Laguerre-Gauss kernel of Eq. 8
+ * or the Wendland C2 kernel of Eq. 6 at its full support (the two relaxed
  * distributions of the error analysis, Sec. 2.3.3).  The residual force of
  * particle i is
  *   g_i = sum_{j : |r_ij| <= 2h} grad W_ij V_j + T(rho_i) e_i,
  * where the second term is the integral of grad W over the exterior of
- * the sphere within the support (rho_i = |r_i - c|, e_i = (r_i - c)/rho_i;
+ * the sphere (circle) within the support (rho_i = |r_i - c|, e_i = (r_i -
+ * c)/rho_i;
  * the paper's relaxation has no boundary term: this one makes a uniform
  * fill up to the surface force-free).  T is tabulated on the host in FP64
  * by Gauss-Legendre quadrature (16385 entries over phi in [-2h, 2h], linear
@@ -250,15 +252,15 @@ int sph_tlsph_step(sph_ctx* ctx, const sph_tlsph_params* prm, const int32_t* fix
 typedef struct {
     double p0;          /* background pressure of Eq. (7) */
     double rho;         /* density of Eq. (7) */
-    double center[3];   /* sphere centre */
-    double radius;      /* sphere radius */
+    double center[3];   /* sphere (circle) centre; 2-D reads center[0..1] */
+    double radius;      /* sphere (circle) radius */
     double kappa;       /* step coefficient (0.1) */
     double damping;     /* carried-displacement factor (0.9) */
     double max_move;    /* cap on |u_i| per iteration in units of h (0.1) */
     int32_t kernel;     /* SPH_LAGUERRE_GAUSS or SPH_WENDLAND (set it: 0 is Wendland) */
 } sph_relax_params;
 
-/* niter iterations in place.  pos FP32 [3][n] (in/out), u FP32 [3][n]
+/* niter iterations in place.  pos FP32 [dim][n] (in/out), u FP32 [dim][n]
  * carried displacement (in/out; zero to start), vol FP32 [n].
  * residue: device FP64 scalar (nullable) receiving the residue of the
  * configuration at the start of the last iteration.  The cell grid is
@@ -267,7 +269,7 @@ int sph_relax_step(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* 
                    float* u, const float* vol, double* residue, int32_t niter);
 
 /* Residual force and residue of a configuration without moving it.
- * g FP32 [3][n] (nullable), residue device FP64 scalar (nullable). */
+ * g FP32 [dim][n] (nullable), residue device FP64 scalar (nullable). */
 int sph_relax_residue(sph_ctx* ctx, const sph_domain* dom, const sph_relax_params* prm, int32_t n,
                       const float* pos, const float* vol, float* g, double* residue);
 

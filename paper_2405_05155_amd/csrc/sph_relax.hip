@@ -1,13 +1,14 @@
 // sph_relax.hip -- particle relaxation (Eq. 7) of particles filling a
-// sphere, with the Laguerre-Gauss kernel of Eq. 8 or the Wendland C2 kernel
-// of Eq. 6 at its full support 2h (the two relaxed distributions of the
-// error analysis, Sec. 2.3.3), with the exterior-tail term, an FP64 residue
-// reduction and the damped move + surface bound.
+// sphere (3-D) or a circle (2-D, the error analysis's geometry), with the
+// Laguerre-Gauss kernel of Eq. 8 or the Wendland C2 kernel of Eq. 6 at its
+// full support 2h (the two relaxed distributions of the error analysis,
+// Sec. 2.3.3), with the exterior-tail term, an FP64 residue reduction and
+// the damped move + surface bound.
 //
 // Per iteration: re-bin (cells of edge >= h, linear (z, y, x) keys), one
-// thread per particle in cell order scans the 5 x 5 x 5 cells around its own
-// as 25 contiguous x-runs, a two-stage reduction gives max|g| and the FP64
-// residue, then one thread per particle moves it.
+// thread per particle in cell order scans the 5 x 5 x 5 cells (2-D: 5 x 5)
+// around its own as contiguous x-runs, a two-stage reduction gives max|g|
+// and the FP64 residue, then one thread per particle moves it.
 #include "sph_internal.h"
 
 #include <vector>
@@ -43,13 +44,16 @@ void gauss_legendre(int m, double* x, double* w) {
     }
 }
 
-// T(phi) = pi int_{|phi|}^{2h} (-dW/ds) s^2 (1 - clamp(u0)^2) ds with
-// u0 = (R^2 - rho^2 - s^2)/(2 rho s), rho = R + phi; the relaxation's
-// kernel in 3-D.
+// T(phi), the exterior integral of grad W along e_i, with u0 = (R^2 - rho^2
+// - s^2)/(2 rho s), rho = R + phi, and the relaxation's kernel:
+//   3-D (sphere): T = pi int_{|phi|}^{2h} (-dW/ds) s^2 (1 - clamp(u0)^2) ds,
+//   2-D (circle): T = 2 int_{|phi|}^{2h} (-dW/ds) s sqrt(1 - clamp(u0)^2) ds
+// (the exterior arc about r_i at distance s is cos(theta) > u0, and the
+// radial component of grad W is -dW/ds cos(theta)).
 // Substitution s = s0 + (2h - s0) tau^2 and graded Gauss-Legendre panels in
 // tau (dense near tau = 0, where the integrand rises steeply for particles
 // just inside the surface).
-double tail_integral(int kernel, double h, double R, double phi) {
+double tail_integral(int kernel, int dim, double h, double R, double phi) {
     const double rho = R + phi;
     if (rho <= 0.0) return 0.0;
     const double s0 = std::fabs(phi), s1 = 2.0 * h;
@@ -61,7 +65,9 @@ double tail_integral(int kernel, double h, double R, double phi) {
     static const GL16 gl;  // thread-safe one-time initialisation
     const double* gx = gl.x;
     const double* gw = gl.w;
-    const double a3 = kernel == SPH_WENDLAND ? 21.0 / (16.0 * M_PI * h * h * h) : 8.0 / std::pow(M_PI, 1.5) / (h * h * h);
+    // kernel normalisation a_d h^-d (Eq. 6: 7/(4 pi), 21/(16 pi); Eq. 8: 3/pi, 8/pi^(3/2))
+    const double a3 = dim == 2 ? (kernel == SPH_WENDLAND ? 7.0 / (4.0 * M_PI) : 3.0 / M_PI) / (h * h)
+                               : (kernel == SPH_WENDLAND ? 21.0 / (16.0 * M_PI) : 8.0 / std::pow(M_PI, 1.5)) / (h * h * h);
     const double edges[] = {0.0, 1.0 / 128, 1.0 / 32, 1.0 / 8, 0.25, 0.5, 0.75, 1.0};
     const double span = s1 - s0;
     double acc = 0.0;
@@ -84,25 +90,27 @@ double tail_integral(int kernel, double h, double R, double phi) {
             }
             double u0 = (R * R - rho * rho - s * s) / (2.0 * rho * s);
             u0 = u0 < -1.0 ? -1.0 : (u0 > 1.0 ? 1.0 : u0);
-            double f = mdw * s * s * (1.0 - u0 * u0) * 2.0 * span * tau;
-            acc += 0.5 * (b - a) * gw[k] * f;
+            double f = dim == 2 ? mdw * s * std::sqrt(1.0 - u0 * u0) : mdw * s * s * (1.0 - u0 * u0);
+            acc += 0.5 * (b - a) * gw[k] * f * 2.0 * span * tau;
         }
     }
-    return M_PI * acc;
+    return dim == 2 ? 2.0 * acc : M_PI * acc;
 }
 
 int ensure_tail(sph_ctx* c, int kernel, double h, double R) {
-    if (c->ntail == NTAIL && c->tail_kernel == kernel && c->tail_h == h && c->tail_R == R && c->tail.p) return SPH_OK;
+    // the table's key: kernel and dimension (tail_kernel = kernel + 4 dim), h, R
+    const int key = kernel + 4 * c->dim;
+    if (c->ntail == NTAIL && c->tail_kernel == key && c->tail_h == h && c->tail_R == R && c->tail.p) return SPH_OK;
     std::vector<float> tab(NTAIL);
     for (int k = 0; k < NTAIL; ++k) {
         double phi = -2.0 * h + 4.0 * h * k / (NTAIL - 1);
-        tab[k] = (float)tail_integral(kernel, h, R, phi);
+        tab[k] = (float)tail_integral(kernel, c->dim, h, R, phi);
     }
     SPH_HIP(c, c->tail.ensure(NTAIL * sizeof(float)));
     SPH_HIP(c, hipMemcpyAsync(c->tail.p, tab.data(), NTAIL * sizeof(float), hipMemcpyHostToDevice, c->stream));
     SPH_HIP(c, hipStreamSynchronize(c->stream));  // the host vector goes out of scope
     c->ntail = NTAIL;
-    c->tail_kernel = kernel;
+    c->tail_kernel = key;
     c->tail_h = h;
     c->tail_R = R;
     return SPH_OK;
@@ -124,7 +132,7 @@ struct RelaxArgs {
     float hinv2;     // 1/h^2
     float rc2f;      // (2h)^2 in FP32
     double rc2d;     // (2h)^2 in FP64
-    float c[3], R;   // sphere
+    float c[3], R;   // sphere (2-D: circle, c[2] = 0)
     float h, phi_lo, inv_dphi;
     double hh;       // h^2 (FP64, residue)
     float kappa_h2;  // kappa h^2
@@ -321,7 +329,8 @@ __global__ void k_relax_reduce(int32_t nb, int32_t n, RelaxArgs ra, const float*
     }
 }
 
-// u = damping u - step g (capped), r += u, bound to the sphere.
+// u = damping u - step g (capped), r += u, bound to the sphere (circle).
+template <int DIM>
 __global__ void k_relax_move(int32_t n, RelaxArgs ra, const RelaxScalars* __restrict__ sc,
                              const float4* __restrict__ g, float* __restrict__ pos, float* __restrict__ u) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,7 +341,7 @@ __global__ void k_relax_move(int32_t n, RelaxArgs ra, const RelaxScalars* __rest
     int64_t nn = n;
     float u0 = ra.damping * u[i] - step * gi.x;
     float u1 = ra.damping * u[nn + i] - step * gi.y;
-    float u2 = ra.damping * u[2 * nn + i] - step * gi.z;
+    float u2 = DIM == 3 ? ra.damping * u[2 * nn + i] - step * gi.z : 0.f;
     float un = sqrtf(u0 * u0 + u1 * u1 + u2 * u2);
     if (un > ra.cap) {
         float f = ra.cap / un;
@@ -340,7 +349,7 @@ __global__ void k_relax_move(int32_t n, RelaxArgs ra, const RelaxScalars* __rest
         u1 *= f;
         u2 *= f;
     }
-    float x = pos[i] + u0, y = pos[nn + i] + u1, z = pos[2 * nn + i] + u2;
+    float x = pos[i] + u0, y = pos[nn + i] + u1, z = DIM == 3 ? pos[2 * nn + i] + u2 : 0.f;
     float ex = x - ra.c[0], ey = y - ra.c[1], ez = z - ra.c[2];
     float rr = sqrtf(ex * ex + ey * ey + ez * ez);
     float phi = rr - ra.R;
@@ -353,10 +362,12 @@ __global__ void k_relax_move(int32_t n, RelaxArgs ra, const RelaxScalars* __rest
     }
     pos[i] = x;
     pos[nn + i] = y;
-    pos[2 * nn + i] = z;
     u[i] = u0;
     u[nn + i] = u1;
-    u[2 * nn + i] = u2;
+    if (DIM == 3) {
+        pos[2 * nn + i] = z;
+        u[2 * nn + i] = u2;
+    }
 }
 
 // (x, y, z, V) per sorted slot
@@ -368,19 +379,19 @@ __global__ void k_sorted_rec(int32_t n, const float4* __restrict__ sorted, const
     rec[s] = make_float4(p.x, p.y, p.z, vol[__float_as_int(p.w)]);
 }
 
-__global__ void k_unpack_g(int32_t n, const float4* __restrict__ g4, float* __restrict__ g) {
+__global__ void k_unpack_g(int32_t n, int dim, const float4* __restrict__ g4, float* __restrict__ g) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float4 v = g4[i];
     g[i] = v.x;
     g[(int64_t)n + i] = v.y;
-    g[2 * (int64_t)n + i] = v.z;
+    if (dim == 3) g[2 * (int64_t)n + i] = v.z;
 }
 
 int check(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p, int32_t n, const void* pos,
           const float* vol, const char* who) {
     if (!c) return SPH_ERR_ARG;
-    if (c->dim != 3) return sph_fail(c, SPH_ERR_ARG, "%s: 3-D only", who);
+
     if (!dom || !p) return sph_fail(c, SPH_ERR_ARG, "%s: NULL domain or params", who);
     if (n < 0) return sph_fail(c, SPH_ERR_ARG, "%s: n < 0", who);
     if (n > 0 && (!pos || !vol)) return sph_fail(c, SPH_ERR_ARG, "%s: NULL array", who);
@@ -398,13 +409,13 @@ RelaxArgs make_args(const sph_ctx* c, const sph_relax_params* p) {
     double h = c->dom.h;
     ra.b = c->box;
     ra.D = RELAX_DIV;
-    KernelConsts kc = make_kernel_consts(p->kernel, 3, h);
+    KernelConsts kc = make_kernel_consts(p->kernel, c->dim, h);
     ra.cF = kc.cF;
     ra.hinv = kc.hinv;
     ra.hinv2 = (float)(1.0 / (h * h));
     ra.rc2d = c->rc2;
     ra.rc2f = (float)c->rc2;
-    for (int a = 0; a < 3; ++a) ra.c[a] = (float)p->center[a];
+    for (int a = 0; a < 3; ++a) ra.c[a] = a < c->dim ? (float)p->center[a] : 0.f;
     ra.R = (float)p->radius;
     ra.h = (float)h;
     ra.phi_lo = (float)(-2.0 * h);
@@ -471,8 +482,12 @@ int sph_relax_step(sph_ctx* c, const sph_domain* dom, const sph_relax_params* p,
         r = relax_eval(c, dom, p, n, pos, vol, it == niter - 1 ? residue : nullptr, &ra);
         if (r) return r;
         if (n > 0) {
-            hipLaunchKernelGGL(k_relax_move, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, ra,
-                               c->relax_scalars.as<RelaxScalars>(), c->ta.as<float4>(), pos, u);
+            if (c->dim == 2)
+                hipLaunchKernelGGL(k_relax_move<2>, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, ra,
+                                   c->relax_scalars.as<RelaxScalars>(), c->ta.as<float4>(), pos, u);
+            else
+                hipLaunchKernelGGL(k_relax_move<3>, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, ra,
+                                   c->relax_scalars.as<RelaxScalars>(), c->ta.as<float4>(), pos, u);
             SPH_LAUNCH_CHECK(c);
         }
     }
@@ -487,7 +502,8 @@ int sph_relax_residue(sph_ctx* c, const sph_domain* dom, const sph_relax_params*
     r = relax_eval(c, dom, p, n, pos, vol, residue, &ra);
     if (r) return r;
     if (g && n > 0) {
-        hipLaunchKernelGGL(k_unpack_g, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->ta.as<float4>(), g);
+        hipLaunchKernelGGL(k_unpack_g, dim3(grid_for(n, BLK)), dim3(BLK), 0, c->stream, n, c->dim, c->ta.as<float4>(),
+                           g);
         SPH_LAUNCH_CHECK(c);
     }
     return SPH_OK;

@@ -327,19 +327,22 @@ class Context:
 
     # ------------------------------------------------------------ relaxation
     def relax_step(self, domain: Domain, prm, pos, u, vol, niter, residue=None):
-        """niter iterations in place; residue: optional device float64 tensor [1]."""
+        """niter iterations in place (pos, u: [dim][n]); residue: optional
+        device float64 tensor [1]."""
+        d = self.dim
         n = pos.shape[-1] if pos.numel() else 0
         self._check(lib().sph_relax_step(self._h, C.byref(domain.to_c()), C.byref(prm), n,
-                                         _ptr(pos, torch.float32, 3 * n, "pos"), _ptr(u, torch.float32, 3 * n, "u"),
+                                         _ptr(pos, torch.float32, d * n, "pos"), _ptr(u, torch.float32, d * n, "u"),
                                          _ptr(vol, torch.float32, n, "vol"), _ptr(residue, torch.float64, 1, "residue"),
                                          int(niter)))
 
     def relax_residue(self, domain: Domain, prm, pos, vol, want_g=True):
+        d = self.dim
         n = pos.shape[-1] if pos.numel() else 0
         res = torch.zeros(1, dtype=torch.float64, device=self._dev())
-        g = torch.empty((3, n), dtype=torch.float32, device=self._dev()) if want_g else None
+        g = torch.empty((d, n), dtype=torch.float32, device=self._dev()) if want_g else None
         self._check(lib().sph_relax_residue(self._h, C.byref(domain.to_c()), C.byref(prm), n,
-                                            _ptr(pos, torch.float32, 3 * n, "pos"), _ptr(vol, torch.float32, n, "vol"),
+                                            _ptr(pos, torch.float32, d * n, "pos"), _ptr(vol, torch.float32, n, "vol"),
                                             _ptr(g), _ptr(res)))
         return res, g
 
