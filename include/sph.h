@@ -316,6 +316,22 @@ int sph_mlp_train_step(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step,
                        float* adam_v, int32_t batch, const uint16_t* feat, const float* target, float* loss,
                        float* grad);
 
+/* sph_mlp_train_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels, arguments and results (bit for bit), with
+ * the training pass's per-workgroup partial records kept in a fixed
+ * workspace of the library (32.2 MB per GPU, held until the process ends;
+ * room for 256 workgroup records) instead of context scratch.  It calls no
+ * allocating routine.  Returns SPH_ERR_CAPACITY if the batch would need more
+ * workgroup records than the workspace holds (a device with more than 256
+ * compute units and batches of more than 256 x 64 samples) and
+ * SPH_ERR_STATE if the workspace could not be located on the context's
+ * device.  Every call on a GPU shares that GPU's workspace: calls that
+ * overlap on one GPU (other streams, other threads) race. */
+int sph_mlp_train_step_noalloc(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step, float* params,
+                               float* adam_m, float* adam_v, int32_t batch, const uint16_t* feat, const float* target,
+                               float* loss, float* grad);
+
 /* One epoch of training steps on rows of a resident training set of nrows
  * rows: step b (b = 0 .. nbatch-1, AdamW step number step0 + b) takes the
  * batch rows[b * batch .. (b + 1) * batch) (int64 indices into feat

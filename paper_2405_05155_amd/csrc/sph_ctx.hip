@@ -92,6 +92,7 @@ int sph_ctx_create(sph_ctx** out, int dim, void* hip_stream) {
         delete c;
         return SPH_ERR_HIP;
     }
+    sph_mlp_noalloc_setup(c->device);
     *out = c;
     return SPH_OK;
 }

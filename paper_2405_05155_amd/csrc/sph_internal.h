@@ -224,6 +224,10 @@ int sph_tiles_prepare(sph_ctx* c, int rec_bytes, int row_bytes, int lds_budget);
 
 int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
 
+// Take the device address of sph_mlp_train_step_noalloc's fixed workspace on
+// `device` (the current device), once per device.
+void sph_mlp_noalloc_setup(int device);
+
 #define SPH_HIP(ctx, expr)                                                                     \
     do {                                                                                       \
         hipError_t _e = (expr);                                                                \

@@ -14,6 +14,8 @@
 // fused with the AdamW update.
 #include "sph_internal.h"
 
+#include <mutex>
+
 namespace {
 
 constexpr int NIN = 100, NH = 128, NOUT = 3;
@@ -893,6 +895,82 @@ void train_launch(sph_ctx* c, const TrainScratch& ts, const sph_adamw_params& ap
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ fixed workspace
+// sph_mlp_train_step_noalloc keeps the training pass's per-workgroup partial
+// records in this file-scope array instead of context scratch: room for
+// NOALLOC_WG workgroups (PR_LEN floats each, 32.2 MB in all) and their FP64
+// loss partials.  Each GPU holds its own copy for the life of the process;
+// host code reaches it only through the address taken once per device by
+// sph_mlp_noalloc_setup (the array's name is a host-side stand-in).
+namespace {
+constexpr int NOALLOC_WG = 256;
+constexpr size_t NOALLOC_PART = ((size_t)NOALLOC_WG * PR_LEN * sizeof(float) + 255) & ~(size_t)255;
+constexpr size_t NOALLOC_BYTES = NOALLOC_PART + (size_t)NOALLOC_WG * sizeof(double);
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_noalloc_err[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+// Take the device address of the fixed workspace on the current device (once
+// per device; later calls return at once).  Called by sph_ctx_create with the
+// context's device current.  A failure is recorded for that device and
+// reported by sph_mlp_train_step_noalloc; contexts work without it.
+void sph_mlp_noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) g_noalloc_ptr[device] = ptr;
+    else g_noalloc_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+}
+
+extern "C" {
+
+int sph_mlp_train_step_noalloc(sph_ctx* c, const sph_adamw_params* ap, int64_t step, float* params, float* adam_m,
+                               float* adam_v, int32_t batch, const uint16_t* feat, const float* target, float* loss,
+                               float* grad) {
+    if (!c) return SPH_ERR_ARG;
+    if (!ap || !params || batch <= 0 || !feat || !target)
+        return sph_fail(c, SPH_ERR_ARG, "sph_mlp_train_step_noalloc: bad arguments");
+    const bool update = ap->lr != 0.0;
+    if (update && (!adam_m || !adam_v || step < 1))
+        return sph_fail(c, SPH_ERR_ARG, "sph_mlp_train_step_noalloc: moments and step >= 1 needed for an update");
+    void* ws = nullptr;
+    hipError_t werr = hipSuccess;
+    if (c->device >= 0 && c->device < NOALLOC_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        ws = g_noalloc_ptr[c->device];
+        werr = g_noalloc_err[c->device];
+    }
+    if (!ws)
+        return sph_fail(c, SPH_ERR_STATE, "sph_mlp_train_step_noalloc: fixed workspace unavailable on device %d (%s)",
+                        c->device, werr == hipSuccess ? "not set up" : hipGetErrorString(werr));
+    if (c->num_cu <= 0) {
+        int n = 0;
+        SPH_HIP(c, hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->num_cu = n > 0 ? n : 1;
+    }
+    // the same workgroup count as sph_mlp_train_step, hence the same sums
+    const int nblk = (batch + TB - 1) / TB;
+    TrainScratch ts;
+    ts.nwg = nblk < c->num_cu ? nblk : c->num_cu;
+    if (ts.nwg > NOALLOC_WG)
+        return sph_fail(c, SPH_ERR_CAPACITY,
+                        "sph_mlp_train_step_noalloc: %d workgroup records exceed the fixed workspace of %d", ts.nwg,
+                        NOALLOC_WG);
+    ts.part = static_cast<float*>(ws);
+    ts.lpart = reinterpret_cast<double*>(static_cast<char*>(ws) + NOALLOC_PART);
+    train_launch(c, ts, *ap, step, params, adam_m, adam_v, batch, feat, batch, nullptr, target, loss, grad);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -86,6 +86,7 @@ _SIGS += [
     ("sph_mlp_features", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
     ("sph_mlp_forward", C.c_int, [_vp, _vp, _i32, _vp, _vp]),
     ("sph_mlp_train_step", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    ("sph_mlp_train_step_noalloc", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     ("sph_mlp_train_epoch", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp]),
     ("sph_mlp_apply", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
 ]
@@ -375,6 +376,20 @@ class Context:
                                              _ptr(target, torch.float32, B * 3, "target"), _ptr(loss), _ptr(grad)))
         return loss, grad
 
+    def mlp_train_step_noalloc(self, adam, step, params, m, v, feat, target, loss=None, grad=None):
+        """sph_mlp_train_step_noalloc: the caller passes every buffer (loss:
+        device FP32 [1], grad: device FP32 [MLP_NPARAMS], both optional);
+        neither this method nor the library allocates."""
+        B = feat.shape[0]
+        self._check(lib().sph_mlp_train_step_noalloc(self._h, C.byref(adam), int(step),
+                                                     _ptr(params, torch.float32, MLP_NPARAMS, "params"),
+                                                     _ptr(m, torch.float32, MLP_NPARAMS, "m"),
+                                                     _ptr(v, torch.float32, MLP_NPARAMS, "v"), B,
+                                                     _ptr(feat, torch.int16, B * MLP_FEAT_STRIDE, "feat"),
+                                                     _ptr(target, torch.float32, B * 3, "target"),
+                                                     _ptr(loss, torch.float32, 1, "loss"),
+                                                     _ptr(grad, torch.float32, MLP_NPARAMS, "grad")))
+
     def mlp_train_epoch(self, adam, step0, params, m, v, rows, feat, target, batch, want_losses=True):
         """Steps step0 .. step0 + nbatch - 1 over the batches rows[b*batch:(b+1)*batch]
         (int64 row indices into feat/target, nbatch = len(rows) // batch)."""
@@ -470,6 +485,10 @@ def sph_mlp_forward(ctx: Context, params, feat):
 
 def sph_mlp_train_step(ctx: Context, adam, step, params, m, v, feat, target, want_loss=True, want_grad=False):
     return ctx.mlp_train_step(adam, step, params, m, v, feat, target, want_loss, want_grad)
+
+
+def sph_mlp_train_step_noalloc(ctx: Context, adam, step, params, m, v, feat, target, loss=None, grad=None):
+    return ctx.mlp_train_step_noalloc(adam, step, params, m, v, feat, target, loss, grad)
 
 
 def sph_mlp_train_epoch(ctx: Context, adam, step0, params, m, v, rows, feat, target, batch, want_losses=True):
