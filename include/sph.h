@@ -344,6 +344,12 @@ int sph_mlp_train_epoch(sph_ctx* ctx, const sph_adamw_params* adam, int64_t step
                         float* adam_v, int32_t batch, int32_t nbatch, int64_t nrows, const int64_t* rows,
                         const uint16_t* feat, const float* target, float* losses);
 
+/* Training targets of the warm start from two configurations of the same
+ * particles: target FP32 [n][3] = (to - from) / h (from, to FP32 [3][n]),
+ * the displacement in units of h that the network's output y stands for
+ * (the move is r += h y). */
+int sph_mlp_targets(sph_ctx* ctx, int32_t n, double h, const float* from, const float* to, float* target);
+
 /* Warm-start move: features of the current positions, y, then r += h y for
  * every particle and the same projection onto the sphere as the relaxation.
  * pos FP32 [3][n] in place. */

@@ -146,3 +146,10 @@ def features(pos, h, center, radius, rows=None, periodic_len=None):
         out[k, 96] = (rr - radius) / h
         out[k, 97:100] = e / rr if rr > 0 else 0.0
     return out
+
+
+def targets(pos_from, pos_to, h):
+    """Training targets of the warm start: (r_to - r_from) / h per particle,
+    [n][3] from positions [3][n] (FP64)."""
+    d = np.asarray(pos_to, dtype=np.float64) - np.asarray(pos_from, dtype=np.float64)
+    return (d / h).T.copy()

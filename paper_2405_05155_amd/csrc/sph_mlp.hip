@@ -840,6 +840,16 @@ __global__ void k_apply_disp(int32_t n, float h, float cx, float cy, float cz, f
     pos[2 * nn + i] = z;
 }
 
+// target (row-major [n][3]) = (to - from) / h, positions SoA [3][n]
+__global__ void k_targets(int32_t n, float hinv, const float* __restrict__ from, const float* __restrict__ to,
+                          float* __restrict__ target) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t nn = n;
+#pragma unroll
+    for (int a = 0; a < NOUT; ++a) target[(int64_t)i * NOUT + a] = (to[a * nn + i] - from[a * nn + i]) * hinv;
+}
+
 // ------------------------------------------------------------------ host helpers
 
 int forward_grid(sph_ctx* c, int32_t n) {
@@ -1035,6 +1045,17 @@ int sph_mlp_train_epoch(sph_ctx* c, const sph_adamw_params* ap, int64_t step0, f
     for (int32_t b = 0; b < nbatch; ++b)
         train_launch(c, ts, *ap, step0 + b, params, adam_m, adam_v, batch, feat, nrows, rows + (int64_t)b * batch,
                      target, losses ? losses + b : nullptr, nullptr);
+    SPH_LAUNCH_CHECK(c);
+    return SPH_OK;
+}
+
+int sph_mlp_targets(sph_ctx* c, int32_t n, double h, const float* from, const float* to, float* target) {
+    if (!c) return SPH_ERR_ARG;
+    if (n < 0 || !(h > 0.0) || (n > 0 && (!from || !to || !target)))
+        return sph_fail(c, SPH_ERR_ARG, "sph_mlp_targets: bad arguments");
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_targets, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, (float)(1.0 / h), from, to,
+                       target);
     SPH_LAUNCH_CHECK(c);
     return SPH_OK;
 }

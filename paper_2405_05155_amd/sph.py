@@ -86,6 +86,7 @@ _SIGS += [
     ("sph_mlp_features", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
     ("sph_mlp_forward", C.c_int, [_vp, _vp, _i32, _vp, _vp]),
     ("sph_mlp_train_step", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
+    ("sph_mlp_targets", C.c_int, [_vp, _i32, C.c_double, _vp, _vp, _vp]),
     ("sph_mlp_train_step_noalloc", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp]),
     ("sph_mlp_train_epoch", C.c_int, [_vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _i64, _vp, _vp, _vp, _vp]),
     ("sph_mlp_apply", C.c_int, [_vp, C.POINTER(sph_domain), C.POINTER(sph_relax_params), _i32, _vp, _vp]),
@@ -376,6 +377,14 @@ class Context:
                                              _ptr(target, torch.float32, B * 3, "target"), _ptr(loss), _ptr(grad)))
         return loss, grad
 
+    def mlp_targets(self, pos_from, pos_to, h):
+        """(pos_to - pos_from) / h as [n][3] (positions [3][n])."""
+        n = pos_from.shape[-1] if pos_from.numel() else 0
+        out = torch.empty((n, 3), dtype=torch.float32, device=self._dev())
+        self._check(lib().sph_mlp_targets(self._h, n, float(h), _ptr(pos_from, torch.float32, 3 * n, "from"),
+                                          _ptr(pos_to, torch.float32, 3 * n, "to"), _ptr(out)))
+        return out
+
     def mlp_train_step_noalloc(self, adam, step, params, m, v, feat, target, loss=None, grad=None):
         """sph_mlp_train_step_noalloc: the caller passes every buffer (loss:
         device FP32 [1], grad: device FP32 [MLP_NPARAMS], both optional);
@@ -485,6 +494,10 @@ def sph_mlp_forward(ctx: Context, params, feat):
 
 def sph_mlp_train_step(ctx: Context, adam, step, params, m, v, feat, target, want_loss=True, want_grad=False):
     return ctx.mlp_train_step(adam, step, params, m, v, feat, target, want_loss, want_grad)
+
+
+def sph_mlp_targets(ctx: Context, pos_from, pos_to, h):
+    return ctx.mlp_targets(pos_from, pos_to, h)
 
 
 def sph_mlp_train_step_noalloc(ctx: Context, adam, step, params, m, v, feat, target, loss=None, grad=None):

@@ -122,7 +122,7 @@ def training_set(ctx: S.Context, w: Workload, snaps: dict, final_pos, horizon=No
         p = snaps[k]
         nxt = final_pos if horizon is None else snaps[k + horizon]
         feats.append(ctx.mlp_features(dom, prm, p))
-        targs.append(((nxt - p) / w.h).t().contiguous())
+        targs.append(ctx.mlp_targets(p, nxt, w.h))
     return torch.cat(feats), torch.cat(targs)
 
 

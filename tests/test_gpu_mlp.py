@@ -105,6 +105,19 @@ def test_forward_matches_oracle(S):
     assert ok, frac
 
 
+def test_targets_match_oracle(S):
+    """Training targets (r_to - r_from)/h of two configurations, [n][3],
+    within two FP32 ulps of the oracle's (the GPU multiplies by 1/h)."""
+    w, dom, prm = _sphere(S)
+    rng = np.random.default_rng(4)
+    to = (w.pos + 0.05 * w.h * rng.standard_normal(w.pos.shape)).astype(np.float32)
+    ctx = S.Context(3)
+    t = host(ctx.mlp_targets(dev(w.pos), dev(to), w.h))
+    ref = M.targets(w.pos, to, w.h)
+    assert t.shape == ref.shape
+    assert np.all(np.abs(t - ref) <= 2.5 * np.finfo(np.float32).eps * np.abs(ref) + 1e-12)
+
+
 def test_gradient_matches_oracle(S):
     rng = np.random.default_rng(3)
     B = 4096
