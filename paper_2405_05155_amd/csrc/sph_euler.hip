@@ -562,6 +562,15 @@ __device__ __forceinline__ void gather3(const float4* __restrict__ R, int32_t j,
     r.q3 = ld32(R, b + 3u);
 }
 
+// j, made to depend on the pair sum just updated (an empty asm statement
+// emits no instruction): the next record's loads then stay after the pair
+// that frees its registers instead of being hoisted above it (which would
+// need a register set per record in flight).
+__device__ __forceinline__ int32_t after(int32_t j, const Kahan& k) {
+    asm volatile("" : "+v"(j) : "v"(k.s));
+    return j;
+}
+
 struct Own3 {
     float x[3], B[6], v[3];
     float p2;     // 2 p_i
@@ -645,10 +654,10 @@ __device__ __forceinline__ void row3(const EulerArgs& ea, const Own3& o, const f
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
             pair3<WRAP>(ea, o, A, sr, sm);
-            if (q + 2 < M) gather3(R, jb[q + 2], A);
+            if (q + 2 < M) gather3(R, after(jb[q + 2], sr), A);
             __builtin_amdgcn_sched_barrier(0);
             pair3<WRAP>(ea, o, B, sr, sm);
-            if (q + 3 < M) gather3(R, jb[q + 3], B);
+            if (q + 3 < M) gather3(R, after(jb[q + 3], sr), B);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -1379,9 +1388,22 @@ void launch3_l(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     else launch3_m<STAGE, L, 6>(c, ea, io);
 }
 
+// Lanes per particle of the 3-D records kernel: 4 from 16 row entries on
+// (measured on the 200^3 Taylor-Green rows, ms per launch for 1, 2, 4, 8
+// lanes: 32 entries 1.59, 1.37, 1.34, 1.83; 80 entries 3.81, 3.22, 3.03,
+// 3.30), 2 from 6, else 1; tuning override SPH_EULER_LANES.
+int lanes3(const sph_ctx* c) {
+    if (const char* e = getenv("SPH_EULER_LANES")) {
+        const int v = atoi(e);
+        if (v == 1 || v == 2 || v == 4 || v == 8) return v;
+    }
+    const double avg = c->n > 0 ? (double)c->nnz / c->n : 0.0;
+    return avg >= 16.0 ? 4 : (avg >= 6.0 ? 2 : 1);
+}
+
 template <int STAGE>
 void launch3(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
-    const int L = lanes_per_particle(c);
+    const int L = lanes3(c);
     if (L == 1) launch3_l<STAGE, 1>(c, ea, io);
     else if (L == 2) launch3_l<STAGE, 2>(c, ea, io);
     else if (L == 4) launch3_l<STAGE, 4>(c, ea, io);
