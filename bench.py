@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "4279a21bd6669683ce80e88dd5ca149af599fc07b5ad81a7a72e408228c8c276": {"2d": 39157539, "3d": 2246174273},
+    "e510378235a66fbe537a75b6fcb0eb5aa3b062f4d59f790ea499f3c14bf0d41e": {"2d": 39153254, "3d": 2351940608},
 }
 
 
@@ -50,7 +50,9 @@ TRAFFIC = {
 # SQ_INSTS_VALU), keyed like TRAFFIC.  The issue fraction is insts x 4 cycles
 # (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles) over
 # 1,024 SIMDs x 2.4 GHz x the live launch time.
-VALU = {}
+VALU = {
+    "e510378235a66fbe537a75b6fcb0eb5aa3b062f4d59f790ea499f3c14bf0d41e": {"3d": 457299834},
+}
 VALU_SIMDS = 1024
 VALU_CLOCK_HZ = 2.4e9
 
