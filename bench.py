@@ -323,9 +323,11 @@ def compressible_section(nside=512):
 
 
 def error_analysis_section():
-    """Sec. 2.3.3 on the lattice (Fig. 2, upper panel) through the GPU's
-    gradient: L2 error of df/dx, f = exp(-x^2/0.1), at dp = D/10, D/20, D/40
-    with and without the correction, and the observed orders."""
+    """Sec. 2.3.3 through the GPU's gradient: on the lattice (Fig. 2, upper
+    panel) the L2 error of df/dx, f = exp(-x^2/0.1), at dp = D/10, D/20, D/40
+    with and without the correction and the observed orders; then the same
+    on the circle relaxed on the GPU with the LG and with the Wendland
+    kernel (the two lower panels) and Table 1's relaxed rows."""
     import math
 
     import numpy as np
@@ -353,19 +355,19 @@ def error_analysis_section():
                 errs.append(float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
             out[f"{tag} {'with' if corrected else 'without'} B"] = {
                 "l2": errs, "orders": [math.log2(errs[i] / errs[i + 1]) for i in range(2)]}
-    out["lg_relaxed_sphere"] = relaxed_sphere_errors()
-    out["wendland_relaxed_sphere"] = relaxed_sphere_errors(kernel="Wendland")
+    out["lg_relaxed_circle"] = relaxed_circle_errors()
+    out["wendland_relaxed_circle"] = relaxed_circle_errors(kernel="Wendland")
     return out
 
 
-def relaxed_sphere_errors(nsides=(16, 32, 64), kernel="LG", iters=400):
-    """Fig. 2's relaxed panels on the 3-D sphere: the seed-2 fill at
-    dx = 1/nside relaxed on the GPU (LG: to R < 1e-4; Wendland: `iters`
-    iterations, the budget in which LG gets there), then the GPU's gradient
-    of f = exp(-((x - c)/R)^2/0.1) with and without the correction: L2 error
-    of df/dx and the observed orders.  At the coarsest dx also Table 1's
-    row: the kernel-sum error (f = 1, no correction) over the particles
-    whose support lies inside the sphere."""
+def relaxed_circle_errors(ndivs=(10, 20, 40), kernel="LG", iters=400):
+    """Fig. 2's relaxed panels and Table 1's relaxed rows on the paper's 2-D
+    circle (D = 2, dp = D/10, D/20, D/40): the seed-2 fill relaxed on the GPU
+    (LG: to R < 1e-4, the residue checked every 10 iterations; Wendland:
+    `iters` iterations), then the GPU's gradient of f = exp(-x^2/0.1) with
+    and without the correction over every particle (L2 error of df/dx and
+    the observed orders), and at D/10 the kernel-sum error (f = 1, no
+    correction) over the particles whose support lies inside the circle."""
     import math
 
     import numpy as np
@@ -373,32 +375,36 @@ def relaxed_sphere_errors(nsides=(16, 32, 64), kernel="LG", iters=400):
 
     from paper_2405_05155_amd import inputs as I
     from paper_2405_05155_amd import sph as S
-    from paper_2405_05155_amd import warmstart as WS
-    errs, residues, table1 = {}, [], {}
-    for nside in nsides:
-        w = I.sphere_fill(dx=1.0 / nside, seed=2)
-        rctx = S.Context(3)
+    errs, residues, table1, its = {}, [], {}, []
+    for nd in ndivs:
+        w = I.circle_fill(dx=2.0 / nd, seed=2)
+        f0 = w.fields
+        dom = S.Domain(dim=2, h=w.h, kappa=2.0, lo=w.lo, hi=w.hi, periodic=(0, 0), kernel=S.LAGUERRE_GAUSS)
+        prm = S.relax_params(f0["center"], f0["radius"], p0=f0["p0"], rho=f0["rho"],
+                             kernel=S.LAGUERRE_GAUSS if kernel == "LG" else S.WENDLAND)
+        rctx = S.Context(2)
         vol = torch.as_tensor(w.vol, device="cuda")
-        if kernel == "LG":
-            run, pos, _ = WS.relax_plain(rctx, w)
-            residues.append(run.residue)
-        else:
-            dom, prm = WS.setup(w, kernel=S.WENDLAND)
-            pos = torch.as_tensor(w.pos, device="cuda").clone()
-            u = torch.zeros_like(pos)
-            res = torch.zeros(1, dtype=torch.float64, device="cuda")
-            rctx.relax_step(dom, prm, pos, u, vol, iters, res)
+        pos = torch.as_tensor(w.pos, device="cuda").clone()
+        u = torch.zeros_like(pos)
+        res = torch.zeros(1, dtype=torch.float64, device="cuda")
+        done = 0
+        while done < (3000 if kernel == "LG" else iters):
             r, _ = rctx.relax_residue(dom, prm, pos, vol, want_g=False)
-            residues.append(float(r.item()))
+            if kernel == "LG" and float(r.item()) < 1e-4:
+                break
+            rctx.relax_step(dom, prm, pos, u, vol, 10, res)
+            done += 10
+        r, _ = rctx.relax_residue(dom, prm, pos, vol, want_g=False)
+        residues.append(float(r.item()))
+        its.append(done)
         rctx.close()
         p = pos.cpu().numpy()
-        f, ex = I.sphere_gradient_fields(p, w.fields["center"], w.fields["radius"])
-        c = np.asarray(w.fields["center"], dtype=np.float64)[:, None]
-        inner = np.sqrt(((p.astype(np.float64) - c) ** 2).sum(0)) < w.fields["radius"] - 2.0 * w.h
+        f, ex = I.circle_gradient_fields(p)
+        inner = np.sqrt((p.astype(np.float64) ** 2).sum(0)) < f0["radius"] - 2.0 * w.h
         for kappa, tag in ((2.0, "SW"), (1.6, "TW")):
-            ctx = S.Context(3)
-            ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, periodic=(0, 0, 0)), pos)
-            if nside == nsides[0]:
+            ctx = S.Context(2)
+            ctx.build_cells(S.Domain(dim=2, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=(0, 0)), pos)
+            if nd == ndivs[0]:
                 ks = ctx.kernel_sum(vol).double().cpu().numpy()[inner]
                 table1[tag] = math.sqrt(float(np.mean((ks - 1.0) ** 2)))   # Eq. (10), phi = 1
                 table1["interior_particles"] = int(inner.sum())
@@ -406,17 +412,17 @@ def relaxed_sphere_errors(nsides=(16, 32, 64), kernel="LG", iters=400):
                 if corrected:
                     ctx.correction_B(vol)
                 else:
-                    ctx.set_correction(vol, torch.eye(3, device="cuda").repeat(w.n, 1, 1).contiguous())
+                    ctx.set_correction(vol, torch.eye(2, device="cuda").repeat(w.n, 1, 1).contiguous())
                 g = ctx.gradient(torch.as_tensor(f.astype(np.float32), device="cuda"))[0].double().cpu().numpy()
                 errs.setdefault(f"{tag} {'with' if corrected else 'without'} B", []).append(
                     float(np.linalg.norm(g - ex) / np.linalg.norm(ex)))
             ctx.close()
-    out = {"dx": [f"1/{k}" for k in nsides], "radius": 0.3, "relaxation": kernel,
-           "iterations": "to R < 1e-4" if kernel == "LG" else iters, "final_residue": residues}
+    out = {"dp": [f"D/{k}" for k in ndivs], "diameter": 2.0, "relaxation": kernel, "iterations": its,
+           "final_residue": residues}
     for k, v in errs.items():
         out[k] = {"l2": v, "orders": [math.log2(v[i] / v[i + 1]) for i in range(len(v) - 1)]}
     printed = {"LG": [0.037, 0.031], "Wendland": [0.034, 0.028]}[kernel]
-    out["table1_kernel_sum"] = dict(table1, dx=f"1/{nsides[0]}", printed_sw_tw=printed)
+    out["table1_kernel_sum"] = dict(table1, dp=f"D/{ndivs[0]}", printed_sw_tw=printed)
     return out
 
 
@@ -860,6 +866,7 @@ def main():
     ap.add_argument("--plate", type=float, default=0.0, help="profile the TLSPH plate line only, at this cut-off")
     ap.add_argument("--shear", action="store_true", help="the double shear layer section only")
     ap.add_argument("--compressible", action="store_true", help="the compressible (HLLC) section only")
+    ap.add_argument("--error-analysis", action="store_true", help="the error-analysis section only")
     ap.add_argument("--relax-iters", type=int, default=0, help="profile N plain relaxation iterations only")
     ap.add_argument("--train-steps", type=int, default=0, help="profile N MLP training steps only")
     ap.add_argument("--cpu-only-json", action="store_true", help=argparse.SUPPRESS)
@@ -878,7 +885,7 @@ def main():
         return
     one_core = None
     default_run = not (args.kappa or args.relax_iters or args.kappa3d or args.train_steps or args.setup
-                       or args.plate or args.shear or args.compressible)
+                       or args.plate or args.shear or args.compressible or args.error_analysis)
     if default_run and not args.no_cpu_baseline and args.cpu_one_core_budget > 0:
         log("oracle on one core (2-D workload)")
         one_core = run_cpu_one_core(1.6, args.cpu_one_core_budget)
@@ -915,6 +922,9 @@ def main():
         return
     if args.compressible:
         print(json.dumps(compressible_section()), flush=True)
+        return
+    if args.error_analysis:
+        print(json.dumps(error_analysis_section()), flush=True)
         return
     if args.train_steps:
         print(json.dumps(run_train(args.train_steps)), flush=True)
@@ -1006,7 +1016,7 @@ def main():
         log("compressible rows")
         out["compressible"] = compressible_section()
         log("error analysis")
-        out["error_analysis_lattice"] = error_analysis_section()
+        out["error_analysis"] = error_analysis_section()
     if not args.no_relax:
         log("relaxation: training and plain / warm-started runs")
         out["relax"] = run_relax(args.relax_epochs, args.relax_nside)
