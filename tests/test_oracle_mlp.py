@@ -123,3 +123,21 @@ def test_features_on_lattice_are_the_first_four_shells():
     e = pos[:, i] - 0.5
     assert abs(f[96] - (np.linalg.norm(e) - 0.3) / h) < 1e-12
     assert np.allclose(f[97:], e / np.linalg.norm(e))
+
+
+def test_targets_of_a_rigid_rotation_and_a_shell_move():
+    """Targets (r_to - r_from)/h, [n][3]: a rotation by 90 degrees about z
+    sends (x, y, z) to (-y, x, z), so the target of particle i is
+    (-y - x, x - y, 0)/h; a pure shift by one lattice spacing along y gives
+    dx/h in the second column only."""
+    pos, dx = I.lattice(6, 3)
+    h = 1.3 * dx
+    rot = np.stack([-pos[1], pos[0], pos[2]])
+    t = M.targets(pos, rot, h)
+    assert t.shape == (pos.shape[1], 3)
+    for i in (0, 17, pos.shape[1] - 1):
+        x, y, _ = (float(v) for v in pos[:, i])
+        assert np.allclose(t[i], [(-y - x) / h, (x - y) / h, 0.0], rtol=0, atol=1e-12)
+    shift = pos.astype(np.float64) + np.array([[0.0], [dx], [0.0]])
+    t = M.targets(pos, shift, h)
+    assert np.allclose(t[:, 1], 1.0 / 1.3) and np.all(t[:, [0, 2]] == 0.0)
