@@ -86,6 +86,22 @@ int sph_set_stream(sph_ctx* ctx, void* hip_stream);
  * runs.  Results agree to rounding.  Returns SPH_ERR_ARG for another mode. */
 enum { SPH_TILING_OFF = 0, SPH_TILING_ON = 1 };
 int sph_set_tiling(sph_ctx* ctx, int mode);
+/* Which pair-loop variant the context's last sph_euler_rhs, sph_euler_step,
+ * sph_hllc_rhs or sph_hllc_step call ran (a diagnostic; every variant gives
+ * results within the parity bars, the last two bit-identical to each other):
+ *  SPH_PATH_NONE     no such call yet, or it had nothing to do;
+ *  SPH_PATH_GENERIC  lane groups per particle gathering separate geometry
+ *                    and state arrays (2-D, the compressible rows, CSR rows
+ *                    or configurations beyond the 3-D records' limits);
+ *  SPH_PATH_TILED    the LDS cell tiles of SPH_TILING_ON;
+ *  SPH_PATH_RECORDS  3-D: one 64-byte record (geometry, trace of B, 2p and
+ *                    velocity) gathered per neighbour;
+ *  SPH_PATH_WINDOWS  3-D: as SPH_PATH_RECORDS, the neighbour records read
+ *                    from a window of the workgroup's neighbourhood staged in
+ *                    LDS (fixed-stride rows whose windows fit).
+ * Returns -1 for a NULL context. */
+enum { SPH_PATH_NONE = 0, SPH_PATH_GENERIC = 1, SPH_PATH_TILED = 2, SPH_PATH_RECORDS = 3, SPH_PATH_WINDOWS = 4 };
+int sph_euler_path(const sph_ctx* ctx);
 
 /* ---------------------------------------------------------------- neighbours
  * sph_build_cells: bind a particle configuration.  Bins the n positions

@@ -108,7 +108,8 @@ void sph_ctx_destroy(sph_ctx* c) {
                       &c->col_s,       &c->scan_tmp,     &c->counter,        &c->geo0,        &c->geo1,
                       &c->geo2,        &c->ua,           &c->ub,             &c->ta,          &c->tb,
                       &c->tc,          &c->tail,         &c->svol,           &c->sfield,      &c->partials,
-                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->rec3};
+                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->rec3,
+                      &c->win3.len, &c->win3.off, &c->win3.list, &c->win3.col};
     for (DevBuf* b : bufs) b->release();
     (void)hipSetDevice(prev);
     delete c;
@@ -129,6 +130,8 @@ int sph_set_tiling(sph_ctx* c, int mode) {
     c->tiling = mode;
     return SPH_OK;
 }
+
+int sph_euler_path(const sph_ctx* c) { return c ? c->euler_path : -1; }
 
 }  // extern "C"
 

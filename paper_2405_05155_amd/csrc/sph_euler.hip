@@ -754,6 +754,259 @@ __global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const i
     Rout[4 * (int64_t)i + 3] = state_quad3(ea, un);
 }
 
+// ------------------------------------------------------------------ record windows
+// Neighbour windows of the 3-D records kernel over fixed-stride rows.  The
+// slots of one workgroup, block b = [b P, b P + P), reference a few hundred
+// distinct neighbours (on the 200^3 lattice at 1.6h about 5.8 per own
+// particle for P = 64).  The window of block b lists its own slots first,
+// in order, then the distinct other slots its rows reference, ascending; the
+// rows are rewritten as 16-bit positions in that list.  A workgroup copies
+// its window's records into LDS once and its pairs then read them there
+// instead of gathering each neighbour through the vector cache.
+constexpr int WIN_MAXE = 8192;  // P * S entries of a block sorted in LDS
+
+// Sort the entries of block b that are not its own slots into a[0 .. E2)
+// (padding and own slots become INT32_MAX), ascending, and return the number
+// of distinct values; every thread's chunk of the sorted array is
+// a[t c .. t c + c), c = E2 / BLK (the first E2 threads take one element when
+// E2 < BLK).
+__device__ int32_t window_sort(int32_t n, int32_t S, int32_t P, int32_t E2, const int32_t* __restrict__ colE,
+                               int32_t b0, int32_t own, int32_t* a, int32_t* lds_scan, int32_t* first,
+                               int32_t* cnt) {
+    const int32_t E = P * S;
+    for (int32_t t = threadIdx.x; t < E2; t += BLK) {
+        int32_t v = INT32_MAX;
+        if (t < E) {
+            const int32_t e = t / P, pp = t - e * P;
+            if (pp < own) {
+                v = colE[(int64_t)e * n + b0 + pp];
+                if (v >= b0 && v < b0 + own) v = INT32_MAX;
+            }
+        }
+        a[t] = v;
+    }
+    __syncthreads();
+    for (int32_t k = 2; k <= E2; k <<= 1) {
+        for (int32_t j = k >> 1; j > 0; j >>= 1) {
+            for (int32_t t = threadIdx.x; t < E2 / 2; t += BLK) {
+                const int32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const int32_t hi = lo + j;
+                const int32_t x = a[lo], y = a[hi];
+                if ((x > y) == ((lo & k) == 0)) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int32_t c = E2 >= BLK ? E2 / BLK : 1;
+    const int32_t beg = E2 >= BLK ? (int32_t)threadIdx.x * c : ((int32_t)threadIdx.x < E2 ? (int32_t)threadIdx.x : E2);
+    const int32_t end = E2 >= BLK ? beg + c : ((int32_t)threadIdx.x < E2 ? beg + 1 : E2);
+    int32_t m = 0;
+    for (int32_t k = beg; k < end; ++k) m += (a[k] != INT32_MAX && (k == 0 || a[k - 1] != a[k])) ? 1 : 0;
+    // exclusive scan of the per-thread counts over the workgroup
+    lds_scan[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 1; o < BLK; o <<= 1) {
+        const int32_t v = (int32_t)threadIdx.x >= o ? lds_scan[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds_scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    *first = lds_scan[threadIdx.x] - m;
+    *cnt = m;
+    return lds_scan[BLK - 1];
+}
+
+// Pass 1 (list == nullptr): window length of every block into len[b] and the
+// longest into *maxlen.  Pass 2: the windows into list[off[b] ..] and the
+// rows' positions into colw (entry k of slot i at colw[k n + i]).
+__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t P, int32_t E2,
+                                                const int32_t* __restrict__ colE, int32_t* __restrict__ len,
+                                                int32_t* __restrict__ maxlen, const int32_t* __restrict__ off,
+                                                int32_t* __restrict__ list, uint16_t* __restrict__ colw) {
+    __shared__ int32_t a[WIN_MAXE];
+    __shared__ int32_t lds_scan[BLK];
+    const int32_t b = (int32_t)blockIdx.x;
+    const int32_t b0 = b * P;
+    const int32_t own = min(P, n - b0);
+    int32_t first, cnt;
+    const int32_t others = window_sort(n, S, P, E2, colE, b0, own, a, lds_scan, &first, &cnt);
+    if (!list) {
+        if (threadIdx.x == 0) {
+            len[b] = own + others;
+            atomicMax(maxlen, own + others);
+        }
+        return;
+    }
+    // the distinct other slots, compacted to the front of a[] (each thread
+    // holds its chunk in registers across the barrier)
+    constexpr int CMAX = WIN_MAXE / BLK;
+    const int32_t c = E2 >= BLK ? E2 / BLK : 1;
+    const int32_t beg = E2 >= BLK ? (int32_t)threadIdx.x * c : (int32_t)threadIdx.x;
+    int32_t vals[CMAX];
+    bool keep[CMAX];
+#pragma unroll
+    for (int q = 0; q < CMAX; ++q) {
+        const int32_t k = beg + q;
+        keep[q] = q < c && k < E2 && a[k] != INT32_MAX && (k == 0 || a[k - 1] != a[k]);
+        vals[q] = keep[q] ? a[k] : 0;
+    }
+    __syncthreads();
+    int32_t at = first;
+#pragma unroll
+    for (int q = 0; q < CMAX; ++q) {
+        if (keep[q]) a[at] = vals[q];
+        at += keep[q] ? 1 : 0;
+    }
+    (void)cnt;
+    __syncthreads();
+    int32_t* out = list + off[b];
+    for (int32_t t = threadIdx.x; t < own + others; t += BLK) out[t] = t < own ? b0 + t : a[t - own];
+    for (int32_t t = threadIdx.x; t < P * S; t += BLK) {
+        const int32_t e = t / P, pp = t - e * P;
+        if (pp >= own) continue;
+        const int64_t at = (int64_t)e * n + b0 + pp;
+        const int32_t v = colE[at];
+        int32_t pos;
+        if (v >= b0 && v < b0 + own) {
+            pos = v - b0;
+        } else {
+            int32_t lo = 0, hi = others;  // first index with a[index] >= v
+            while (lo < hi) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (a[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            pos = own + lo;
+        }
+        colw[at] = (uint16_t)pos;
+    }
+}
+
+// Record k of the window from the LDS planes (plane q holds quad q of every
+// record: a 16-byte read per quad, consecutive records in consecutive bank
+// groups).
+template <int HC>
+__device__ __forceinline__ void wread(const float4* W, uint32_t k, Rec3& r) {
+    r.q0 = W[k];
+    r.q1 = W[HC + k];
+    r.q2 = W[2 * HC + k];
+    r.q3 = W[3 * HC + k];
+}
+
+// row3 over the window: the lane's entries are 16-bit window positions, the
+// records come from LDS (the pair order, and so every sum, is that of row3).
+template <bool WRAP, int M, int HC>
+__device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const float4* W,
+                                      const uint16_t* __restrict__ colw, uint32_t self, uint32_t e0, uint32_t es,
+                                      int32_t m, int32_t mu, Kahan& sr, Kahan* sm) {
+    for (int32_t base = 0; base < mu; base += M) {
+        uint32_t kb[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int32_t t = base + q < m ? base + q : m - 1;
+            const uint32_t v = ld32(colw, m > 0 ? e0 + (uint32_t)t * es : 0u);
+            kb[q] = base + q < m ? v : self;
+        }
+        Rec3 A, B;
+        wread<HC>(W, kb[0], A);
+        wread<HC>(W, kb[1], B);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < M; q += 2) {
+            pair3<WRAP>(ea, o, A, sr, sm);
+            if (q + 2 < M) wread<HC>(W, (uint32_t)after((int32_t)kb[q + 2], sr), A);
+            __builtin_amdgcn_sched_barrier(0);
+            pair3<WRAP>(ea, o, B, sr, sm);
+            if (q + 3 < M) wread<HC>(W, (uint32_t)after((int32_t)kb[q + 3], sr), B);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+// k_euler3 with the neighbour records read from the workgroup's window in
+// LDS (fixed-stride rows only).  Workgroup blk takes block blk of P = BLK / L
+// slots; its window (at most HC records) is copied from R first.  Results
+// are bit-identical to k_euler3's.
+template <int STAGE, int L, int M, int HC>
+__global__ void __launch_bounds__(BLK) k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
+                                                 int32_t S, const int32_t* __restrict__ woff,
+                                                 const int32_t* __restrict__ wlist, const float4* __restrict__ R,
+                                                 float4* Rout, const float4* U, const float4* U0, float4* Uout,
+                                                 const float4* __restrict__ sorted, float* __restrict__ drho_dt,
+                                                 float* __restrict__ dmom_dt) {
+    __shared__ float4 W[4 * HC];
+    const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
+    for (int32_t t = (int32_t)threadIdx.x; t < 4 * wn; t += BLK) {
+        const int32_t k = t >> 2, q = t & 3;
+        W[q * HC + k] = ld32(R, ((uint32_t)wlist[w0 + k] << 2) + (uint32_t)q);
+    }
+    const int sub = (int)(threadIdx.x % L);
+    const int32_t lp = (int32_t)(threadIdx.x / L);
+    const int32_t ig = blk * (BLK / L) + lp;
+    const bool valid = ig < n;
+    const int32_t i = valid ? ig : n - 1;
+    const uint32_t self = (uint32_t)(i - blk * (BLK / L));
+    const uint32_t e0 = (uint32_t)sub * (uint32_t)n + (uint32_t)i;
+    const uint32_t es = (uint32_t)L * (uint32_t)n;
+    const int32_t m = (S - sub + L - 1) / L;
+    const int32_t mu = (S + L - 1) / L;
+    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
+    if (STAGE != 0 && sub == 0) {
+        ui = U[i];
+        if (STAGE == 2) u0 = U0[i];
+    }
+    __syncthreads();
+    Rec3 me;
+    wread<HC>(W, self, me);
+    Own3 o;
+    o.x[0] = me.q0.x; o.x[1] = me.q0.y; o.x[2] = me.q0.z;
+    o.B[0] = me.q1.x; o.B[1] = me.q1.y; o.B[2] = me.q1.z; o.B[3] = me.q1.w;
+    o.B[4] = me.q2.x; o.B[5] = me.q2.y;
+    o.trB = me.q2.z;
+    o.p2 = me.q3.x;
+    o.v[0] = me.q3.y; o.v[1] = me.q3.z; o.v[2] = me.q3.w;
+    o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);
+    bool near = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (ea.invL[a] != 0.f) {
+            const float off = o.x[a] - ea.lo[a];
+            near = near || off < ea.margin || ea.L[a] - off < ea.margin;
+        }
+    }
+    Kahan sr, sm[3];
+    sr.init();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sm[a].init();
+    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, self, e0, es, m, mu, sr, sm);
+    else row3w<false, M, HC>(ea, o, W, colw, self, e0, es, m, mu, sr, sm);
+    float Rt[4];
+    Rt[0] = ea.fr * group_sum<L>(sr);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Rt[1 + a] = ea.fm * group_sum<L>(sm[a]);
+    if (sub != 0 || !valid) return;
+    if (STAGE == 0) {
+        const int32_t ic = __float_as_int(sorted[i].w);
+        drho_dt[ic] = Rt[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dmom_dt[(int64_t)a * n + ic] = Rt[1 + a];
+        return;
+    }
+    float4 un;
+    if (STAGE == 1) {
+        un = make_float4(ui.x + ea.dt * Rt[0], ui.y + ea.dt * Rt[1], ui.z + ea.dt * Rt[2], ui.w + ea.dt * Rt[3]);
+    } else {
+        un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * Rt[0])), 0.5f * (u0.y + (ui.y + ea.dt * Rt[1])),
+                         0.5f * (u0.z + (ui.z + ea.dt * Rt[2])), 0.5f * (u0.w + (ui.w + ea.dt * Rt[3])));
+    }
+    Uout[i] = un;
+    Rout[4 * (int64_t)i + 3] = state_quad3(ea, un);
+}
+
 // ------------------------------------------------------------------ tiled stage
 // One workgroup per cell tile (the tile set of the bound configuration).
 //  1. The records of the tile's own particles and of its halo are staged in
@@ -1401,9 +1654,111 @@ int lanes3(const sph_ctx* c) {
     return avg >= 16.0 ? 4 : (avg >= 6.0 ? 2 : 1);
 }
 
-template <int STAGE>
-void launch3(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+// Longest window the LDS planes of k_euler3w hold.
+constexpr int WIN_HC_MAX = 1024;
+
+// Build (or reuse) the neighbour windows of blocks of P slots for the
+// fixed-stride rows (k_window, two passes with a scan of the window lengths
+// in between).  Leaves c->win3.state = 1 when the records kernel can read
+// its neighbours from LDS, else -1: rows not fixed-stride, P S entries
+// beyond what one block sorts, a window longer than WIN_HC_MAX, or the
+// tuning override SPH_EULER_WINDOW=0.
+int window_prepare(sph_ctx* c, int P) {
+    auto& w = c->win3;
+    if (w.state != 0 && w.P == P) return SPH_OK;
+    w.state = -1;
+    w.P = P;
+    const char* e = getenv("SPH_EULER_WINDOW");
+    if (e && strcmp(e, "0") == 0) return SPH_OK;
+    const int32_t n = c->n, S = c->ell_S;
+    if (c->ell_state != 1 || n <= 0 || S <= 0 || (int64_t)P * S > WIN_MAXE) return SPH_OK;
+    int32_t E2 = 2;
+    while (E2 < P * S) E2 <<= 1;
+    const int32_t nb = (n + P - 1) / P;
+    SPH_HIP(c, w.len.ensure((size_t)nb * sizeof(int32_t)));
+    SPH_HIP(c, w.off.ensure(((size_t)nb + 1) * sizeof(int32_t)));
+    SPH_HIP(c, c->counter.ensure(64));
+    SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, P, E2, c->colE.as<int32_t>(),
+                       w.len.as<int32_t>(), c->counter.as<int32_t>(), nullptr, nullptr, nullptr);
+    SPH_LAUNCH_CHECK(c);
+    int r = sph_scan_i32_to_i32(c, w.len.as<int32_t>(), w.off.as<int32_t>(), nb);
+    if (r) return r;
+    int32_t host[2] = {0, 0};
+    SPH_HIP(c, hipMemcpyAsync(&host[0], c->counter.p, 4, hipMemcpyDeviceToHost, c->stream));
+    SPH_HIP(c, hipMemcpyAsync(&host[1], w.off.as<int32_t>() + nb, 4, hipMemcpyDeviceToHost, c->stream));
+    SPH_HIP(c, hipStreamSynchronize(c->stream));
+    if (host[0] > WIN_HC_MAX) return SPH_OK;
+    SPH_HIP(c, w.list.ensure((size_t)host[1] * sizeof(int32_t)));
+    SPH_HIP(c, w.col.ensure((size_t)S * n * sizeof(uint16_t)));
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, P, E2, c->colE.as<int32_t>(),
+                       nullptr, nullptr, w.off.as<int32_t>(), w.list.as<int32_t>(), w.col.as<uint16_t>());
+    SPH_LAUNCH_CHECK(c);
+    w.max = host[0];
+    w.state = 1;
+    return SPH_OK;
+}
+
+template <int STAGE, int L, int M, int HC>
+void launch3w_h(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const auto& w = c->win3;
+    hipLaunchKernelGGL((k_euler3w<STAGE, L, M, HC>), dim3(grid_for(c->n, BLK / L)), dim3(BLK), 0, c->stream, c->n,
+                       ea, w.col.as<uint16_t>(), c->ell_S, w.off.as<int32_t>(), w.list.as<int32_t>(), io.R,
+                       io.Rout, io.U, io.U0, io.Uout, c->sorted.as<float4>(), io.dr, io.dm);
+}
+
+// LDS planes for the longest window: 512, 768 or 1024 records (32, 48 or
+// 64 KB per workgroup).
+template <int STAGE, int L, int M>
+void launch3w_m(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const int32_t mx = c->win3.max;
+    if constexpr (L == 4) {
+        if (mx <= 512) {
+            launch3w_h<STAGE, L, M, 512>(c, ea, io);
+            return;
+        }
+    }
+    if (mx <= 768) launch3w_h<STAGE, L, M, 768>(c, ea, io);
+    else launch3w_h<STAGE, L, M, 1024>(c, ea, io);
+}
+
+template <int STAGE, int L>
+void launch3w_l(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const int mu = (c->ell_S + L - 1) / L;
+    const int cand[5] = {16, 12, 10, 8, 6};
+    int best = 16, cost = 1 << 30;
+    for (int M : cand) {
+        const int k = (mu + M - 1) / M * M;
+        if (k < cost) cost = k, best = M;
+    }
+    if (best == 16) launch3w_m<STAGE, L, 16>(c, ea, io);
+    else if (best == 12) launch3w_m<STAGE, L, 12>(c, ea, io);
+    else if (best == 10) launch3w_m<STAGE, L, 10>(c, ea, io);
+    else if (best == 8) launch3w_m<STAGE, L, 8>(c, ea, io);
+    else launch3w_m<STAGE, L, 6>(c, ea, io);
+}
+
+// Whether the stage kernels read the neighbour records from LDS windows
+// (built on first use): fixed-stride rows with two or four lanes per
+// particle (blocks of 128 or 64 slots).
+int prepare_windows(sph_ctx* c, bool* use) {
+    *use = false;
     const int L = lanes3(c);
+    if (c->ell_state != 1 || (L != 2 && L != 4)) return SPH_OK;
+    const int r = window_prepare(c, BLK / L);
+    if (r) return r;
+    *use = c->win3.state == 1;
+    return SPH_OK;
+}
+
+template <int STAGE>
+void launch3(sph_ctx* c, const EulerArgs& ea, const Stage3& io, bool windows) {
+    const int L = lanes3(c);
+    if (windows) {
+        if (L == 2) launch3w_l<STAGE, 2>(c, ea, io);
+        else launch3w_l<STAGE, 4>(c, ea, io);
+        return;
+    }
     if (L == 1) launch3_l<STAGE, 1>(c, ea, io);
     else if (L == 2) launch3_l<STAGE, 2>(c, ea, io);
     else if (L == 4) launch3_l<STAGE, 4>(c, ea, io);
@@ -1482,6 +1837,7 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
                   float* dmom_dt) {
     int r = check(c, p, "sph_euler_rhs");
     if (r) return r;
+    c->euler_path = SPH_PATH_NONE;
     if (c->n == 0) return SPH_OK;
     if (!drho || !mom || !drho_dt || !dmom_dt) return sph_fail(c, SPH_ERR_ARG, "sph_euler_rhs: NULL array");
     SPH_HIP(c, c->ua.ensure((size_t)c->n * sizeof(float4)));
@@ -1491,11 +1847,15 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     if (r) return r;
     EulerArgs ea = make_args(c, p);
     if (!tiled && use_rec3(c)) {
+        bool windows = false;
+        r = prepare_windows(c, &windows);
+        if (r) return r;
         r = pack3(c, ea, drho, mom, c->ua.as<float4>());
         if (r) return r;
         Stage3 io{c->rec3.as<float4>(), nullptr, nullptr, nullptr, nullptr, drho_dt, dmom_dt};
-        launch3<0>(c, ea, io);
+        launch3<0>(c, ea, io, windows);
         SPH_LAUNCH_CHECK(c);
+        c->euler_path = windows ? SPH_PATH_WINDOWS : SPH_PATH_RECORDS;
         return SPH_OK;
     }
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
@@ -1503,12 +1863,14 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt};
     launch<SOL_LINEARISED, 0>(c, ea, io, tiled);
     SPH_LAUNCH_CHECK(c);
+    c->euler_path = tiled ? SPH_PATH_TILED : SPH_PATH_GENERIC;
     return SPH_OK;
 }
 
 int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mom, int32_t nsteps) {
     int r = check(c, p, "sph_euler_step");
     if (r) return r;
+    c->euler_path = SPH_PATH_NONE;
     if (nsteps < 0) return sph_fail(c, SPH_ERR_ARG, "sph_euler_step: nsteps < 0");
     if (!(p->dt > 0.0)) return sph_fail(c, SPH_ERR_ARG, "sph_euler_step: dt must be > 0");
     if (c->n == 0 || nsteps == 0) return SPH_OK;
@@ -1526,6 +1888,9 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     if (r) return r;
     EulerArgs ea = make_args(c, p);
     if (!tiled && use_rec3(c)) {
+        bool windows = false;
+        r = prepare_windows(c, &windows);
+        if (r) return r;
         r = pack3(c, ea, drho, mom, U);
         if (r) return r;
         float4* Ra = c->rec3.as<float4>();
@@ -1534,9 +1899,10 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
         Stage3 s1{Ra, Rb, U, nullptr, Us, nullptr, nullptr};
         Stage3 s2{Rb, Ra, Us, U, U, nullptr, nullptr};
         for (int32_t s = 0; s < nsteps; ++s) {
-            launch3<1>(c, ea, s1);
-            launch3<2>(c, ea, s2);
+            launch3<1>(c, ea, s1, windows);
+            launch3<2>(c, ea, s2, windows);
         }
+        c->euler_path = windows ? SPH_PATH_WINDOWS : SPH_PATH_RECORDS;
     } else {
         r = pack(c, ea.rho_ref, drho, mom, U, P);
         if (r) return r;
@@ -1547,6 +1913,7 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
             launch<SOL_LINEARISED, 1>(c, ea, s1, tiled);
             launch<SOL_LINEARISED, 2>(c, ea, s2, tiled);
         }
+        c->euler_path = tiled ? SPH_PATH_TILED : SPH_PATH_GENERIC;
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)
@@ -1563,6 +1930,7 @@ int sph_hllc_rhs(sph_ctx* c, const sph_hllc_params* p, const float* rho, const f
                  float* drho_dt, float* dmom_dt, float* dE_dt) {
     int r = check_hllc(c, p, "sph_hllc_rhs");
     if (r) return r;
+    c->euler_path = SPH_PATH_NONE;
     if (c->n == 0) return SPH_OK;
     if (!rho || !mom || !E || !drho_dt || !dmom_dt || !dE_dt)
         return sph_fail(c, SPH_ERR_ARG, "sph_hllc_rhs: NULL array");
@@ -1576,12 +1944,14 @@ int sph_hllc_rhs(sph_ctx* c, const sph_hllc_params* p, const float* rho, const f
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt, dE_dt};
     launch<SOL_HLLC, 0>(c, ea, io, false);
     SPH_LAUNCH_CHECK(c);
+    c->euler_path = SPH_PATH_GENERIC;
     return SPH_OK;
 }
 
 int sph_hllc_step(sph_ctx* c, const sph_hllc_params* p, float* rho, float* mom, float* E, int32_t nsteps) {
     int r = check_hllc(c, p, "sph_hllc_step");
     if (r) return r;
+    c->euler_path = SPH_PATH_NONE;
     if (nsteps < 0) return sph_fail(c, SPH_ERR_ARG, "sph_hllc_step: nsteps < 0");
     if (!(p->dt > 0.0)) return sph_fail(c, SPH_ERR_ARG, "sph_hllc_step: dt must be > 0");
     if (c->n == 0 || nsteps == 0) return SPH_OK;
@@ -1607,6 +1977,7 @@ int sph_hllc_step(sph_ctx* c, const sph_hllc_params* p, float* rho, float* mom, 
         launch<SOL_HLLC, 2>(c, ea, s2, false);
     }
     SPH_LAUNCH_CHECK(c);
+    c->euler_path = SPH_PATH_GENERIC;
     hipLaunchKernelGGL(k_unpack_hllc, dim3(grid_for(c->n, BLK)), dim3(BLK), 0, c->stream, c->n,
                        c->sorted.as<float4>(), U, rho, mom, E);
     SPH_LAUNCH_CHECK(c);

@@ -200,6 +200,7 @@ struct sph_ctx {
 
     TileSet tiles;
     int tiling = SPH_TILING_OFF;
+    int euler_path = SPH_PATH_NONE;  // variant the last Eulerian call ran
 
     // fixed-stride neighbour rows over cell-sorted slots (ELLPACK): entry k
     // of slot i at colE[k * n + i] for k < ell_S, rows shorter than ell_S
@@ -208,6 +209,20 @@ struct sph_ctx {
     DevBuf colE;
     int32_t ell_S = 0;
     int ell_state = 0;  // 0: not built, 1: valid, -1: rows too uneven (CSR is used)
+
+    // neighbour windows of the 3-D records kernel over the fixed-stride
+    // rows: per block of P consecutive slots, its own slots then the
+    // distinct other slots its rows reference (ascending), and the rows as
+    // 16-bit positions in that list
+    struct Windows {
+        int state = 0;        // 0: not built, 1: valid, -1: not used for this configuration
+        int P = 0;            // slots per block
+        int32_t max = 0;      // longest window
+        DevBuf len;           // int32 [nblocks]
+        DevBuf off;           // int32 [nblocks + 1]
+        DevBuf list;          // int32 [off[nblocks]]
+        DevBuf col;           // uint16 [ell_S * n]: entry k of slot i at k n + i
+    } win3;
 };
 
 // Build (or reuse) the fixed-stride neighbour rows of the bound

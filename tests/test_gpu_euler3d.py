@@ -142,6 +142,7 @@ def test_euler_heun_3d_step_full_size_sampled(S, kappa):
     ctx.correction_B(dev(w.vol))
     d, m = dev(w.fields["drho"]), dev(w.fields["mom"])
     ctx.euler_step(pg, d, m, 1)
+    assert ctx.euler_path() == S.PATH_WINDOWS  # the stage kernels of the timed run
     dg, mg = host(d)[rows].astype(np.float64), host(m)[:, rows].astype(np.float64)
     ctx.close()
     _check_increment(dg, drho0[rows], rho_n - 1.0, s_dr, dt)
@@ -181,3 +182,57 @@ def test_truncated_kernel_equal_accuracy_taylor_green_3d(S):
         err[kappa] = abs(rate / exact - 1.0)
     assert err[1.6] < 0.25 and err[2.0] < 0.25, err
     assert err[1.6] <= 1.10 * err[2.0], err
+
+
+def _run_paths(S, w, kappa, dt, steps):
+    """Rates, then `steps` Heun steps, of the bound configuration; returns
+    (rates, state after the steps, path of the last call)."""
+    pg, _ = _params(S, w, dt)
+    ctx = S.Context(3)
+    ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=w.periodic), dev(w.pos))
+    ctx.correction_B(dev(w.vol))
+    d, m = dev(w.fields["drho"]), dev(w.fields["mom"])
+    dr, dm = ctx.euler_rhs(pg, d, m)
+    path_rhs = ctx.euler_path()
+    ctx.euler_step(pg, d, m, steps)
+    path = ctx.euler_path()
+    out = [host(dr).copy(), host(dm).copy(), host(d).copy(), host(m).copy()]
+    ctx.close()
+    assert path_rhs == path
+    return out, path
+
+
+@pytest.mark.parametrize("kappa,lanes", [(1.6, "2"), (1.6, "4"), (2.0, "4")])
+def test_euler_3d_windows_bit_identical(S, kappa, lanes, monkeypatch):
+    """The stage kernels that read the neighbour records from LDS windows
+    against the kernels that gather them: the same rates and the same state
+    after 5 Heun steps, bit for bit (same pairs in the same order, same
+    sums), at two and four lanes per particle, on a jittered 30^3
+    Taylor-Green field (27,000 particles: the last block of 64 or 128 slots
+    is ragged, the rows uneven)."""
+    w = I.taylor_green_3d(nside=30, nu=0.01, jitter=0.05, seed=21)
+    monkeypatch.setenv("SPH_EULER_LANES", lanes)
+    monkeypatch.setenv("SPH_EULER_WINDOW", "0")
+    ref, p0 = _run_paths(S, w, kappa, w.meta["dt"], 5)
+    monkeypatch.delenv("SPH_EULER_WINDOW")
+    got, p1 = _run_paths(S, w, kappa, w.meta["dt"], 5)
+    assert p0 == S.PATH_RECORDS and p1 == S.PATH_WINDOWS, (p0, p1)
+    for a, b, name in zip(got, ref, ("drho_dt", "dmom_dt", "drho", "mom")):
+        assert np.array_equal(a, b), (name, int(np.sum(a != b)))
+
+
+def test_euler_3d_window_fallbacks(S, monkeypatch):
+    """Configurations the windows do not serve run the gathering kernels:
+    one lane per particle (short rows), CSR rows, and blocks whose entries
+    exceed what one workgroup sorts (128 slots x the 2h rows of ~90)."""
+    w = I.taylor_green_3d(nside=24, nu=0.01, jitter=0.05, seed=3)
+    monkeypatch.setenv("SPH_EULER_LANES", "2")
+    _, p = _run_paths(S, w, 2.0, w.meta["dt"], 1)
+    assert p == S.PATH_RECORDS
+    monkeypatch.setenv("SPH_EULER_LANES", "1")
+    _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
+    assert p == S.PATH_RECORDS
+    monkeypatch.delenv("SPH_EULER_LANES")
+    monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
+    _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
+    assert p == S.PATH_RECORDS
