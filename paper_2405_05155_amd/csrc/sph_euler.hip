@@ -763,28 +763,98 @@ __global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const i
 // rows are rewritten as 16-bit positions in that list.  A workgroup copies
 // its window's records into LDS once and its pairs then read them there
 // instead of gathering each neighbour through the vector cache.
-constexpr int WIN_MAXE = 8192;  // P * S entries of a block sorted in LDS
+constexpr int WIN_HASH = 4096;  // open-addressing set of a block's distinct neighbours (LDS)
+constexpr int WIN_HC_MAX = 1024;  // longest window the LDS planes of k_euler3w hold
 
-// Sort the entries of block b that are not its own slots into a[0 .. E2)
-// (padding and own slots become INT32_MAX), ascending, and return the number
-// of distinct values; every thread's chunk of the sorted array is
-// a[t c .. t c + c), c = E2 / BLK (the first E2 threads take one element when
-// E2 < BLK).
-__device__ int32_t window_sort(int32_t n, int32_t S, int32_t P, int32_t E2, const int32_t* __restrict__ colE,
-                               int32_t b0, int32_t own, int32_t* a, int32_t* lds_scan, int32_t* first,
-                               int32_t* cnt) {
-    const int32_t E = P * S;
-    for (int32_t t = threadIdx.x; t < E2; t += BLK) {
-        int32_t v = INT32_MAX;
-        if (t < E) {
-            const int32_t e = t / P, pp = t - e * P;
-            if (pp < own) {
-                v = colE[(int64_t)e * n + b0 + pp];
-                if (v >= b0 && v < b0 + own) v = INT32_MAX;
-            }
-        }
-        a[t] = v;
+// Exclusive scan of one value per thread over the workgroup (BLK threads);
+// returns the exclusive prefix and stores the total in *total.
+__device__ int32_t wg_exclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < BLK; o <<= 1) {
+        const int32_t u = (int32_t)threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += u;
+        __syncthreads();
     }
+    const int32_t incl = lds[threadIdx.x];
+    *total = lds[BLK - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// Pass 1 (list == nullptr): window length of every block into len[b] and the
+// longest into *maxlen (a block with more than WIN_HC_MAX distinct
+// neighbours reports WIN_HC_MAX + 1).  Pass 2: the windows into
+// list[off[b] ..] and the rows' positions into colw, entry k of slot i at
+// colw[k n + i] for k < Sp: the rows are padded from S to Sp entries with
+// the slot itself (a zero-weight pair), so that every lane's share is a
+// whole number of chunks.  The distinct other slots are collected in an
+// LDS hash set (linear probing, at most WIN_HASH probes per insertion),
+// then compacted and sorted (bitonic).
+__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp, int32_t P,
+                                                const int32_t* __restrict__ colE, int32_t* __restrict__ len,
+                                                int32_t* __restrict__ maxlen, const int32_t* __restrict__ off,
+                                                int32_t* __restrict__ list, uint16_t* __restrict__ colw) {
+    __shared__ int32_t T[WIN_HASH];
+    __shared__ int32_t a[WIN_HASH];
+    __shared__ int32_t lds_scan[BLK];
+    __shared__ int32_t distinct;
+    const int32_t b = (int32_t)blockIdx.x;
+    const int32_t b0 = b * P;
+    const int32_t own = min(P, n - b0);
+    for (int32_t t = threadIdx.x; t < WIN_HASH; t += BLK) T[t] = -1;
+    if (threadIdx.x == 0) distinct = 0;
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < P * S; t += BLK) {
+        const int32_t e = t / P, pp = t - e * P;
+        if (pp >= own) continue;
+        const int32_t v = colE[(int64_t)e * n + b0 + pp];
+        if (v >= b0 && v < b0 + own) continue;
+        if (*(volatile int32_t*)&distinct > WIN_HC_MAX) continue;  // too long already: stop inserting
+        uint32_t h = ((uint32_t)v * 2654435761u) >> 20;  // 12 bits
+        for (int probe = 0; probe < WIN_HASH; ++probe) {
+            const int32_t old = atomicCAS(&T[h], -1, v);
+            if (old == -1) {
+                atomicAdd(&distinct, 1);
+                break;
+            }
+            if (old == v) break;
+            h = (h + 1) & (WIN_HASH - 1);
+        }
+    }
+    __syncthreads();
+    const int32_t others = distinct;
+    if (others + own > WIN_HC_MAX) {
+        if (!list && threadIdx.x == 0) {
+            len[b] = WIN_HC_MAX + 1;
+            atomicMax(maxlen, WIN_HC_MAX + 1);
+        }
+        return;
+    }
+    if (!list) {
+        if (threadIdx.x == 0) {
+            len[b] = own + others;
+            atomicMax(maxlen, own + others);
+        }
+        return;
+    }
+    // compact the set into a[0 .. others), then sort it
+    constexpr int C = WIN_HASH / BLK;
+    int32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < C; ++q) m += T[threadIdx.x * C + q] != -1 ? 1 : 0;
+    int32_t total;
+    int32_t at = wg_exclusive_scan(m, lds_scan, &total);
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const int32_t v = T[threadIdx.x * C + q];
+        if (v != -1) a[at++] = v;
+    }
+    int32_t E2 = 2;
+    while (E2 < others) E2 <<= 1;
+    __syncthreads();
+    for (int32_t t = others + (int32_t)threadIdx.x; t < E2; t += BLK) a[t] = INT32_MAX;
     __syncthreads();
     for (int32_t k = 2; k <= E2; k <<= 1) {
         for (int32_t j = k >> 1; j > 0; j >>= 1) {
@@ -800,75 +870,13 @@ __device__ int32_t window_sort(int32_t n, int32_t S, int32_t P, int32_t E2, cons
             __syncthreads();
         }
     }
-    const int32_t c = E2 >= BLK ? E2 / BLK : 1;
-    const int32_t beg = E2 >= BLK ? (int32_t)threadIdx.x * c : ((int32_t)threadIdx.x < E2 ? (int32_t)threadIdx.x : E2);
-    const int32_t end = E2 >= BLK ? beg + c : ((int32_t)threadIdx.x < E2 ? beg + 1 : E2);
-    int32_t m = 0;
-    for (int32_t k = beg; k < end; ++k) m += (a[k] != INT32_MAX && (k == 0 || a[k - 1] != a[k])) ? 1 : 0;
-    // exclusive scan of the per-thread counts over the workgroup
-    lds_scan[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 1; o < BLK; o <<= 1) {
-        const int32_t v = (int32_t)threadIdx.x >= o ? lds_scan[threadIdx.x - o] : 0;
-        __syncthreads();
-        lds_scan[threadIdx.x] += v;
-        __syncthreads();
-    }
-    *first = lds_scan[threadIdx.x] - m;
-    *cnt = m;
-    return lds_scan[BLK - 1];
-}
-
-// Pass 1 (list == nullptr): window length of every block into len[b] and the
-// longest into *maxlen.  Pass 2: the windows into list[off[b] ..] and the
-// rows' positions into colw (entry k of slot i at colw[k n + i]).
-__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t P, int32_t E2,
-                                                const int32_t* __restrict__ colE, int32_t* __restrict__ len,
-                                                int32_t* __restrict__ maxlen, const int32_t* __restrict__ off,
-                                                int32_t* __restrict__ list, uint16_t* __restrict__ colw) {
-    __shared__ int32_t a[WIN_MAXE];
-    __shared__ int32_t lds_scan[BLK];
-    const int32_t b = (int32_t)blockIdx.x;
-    const int32_t b0 = b * P;
-    const int32_t own = min(P, n - b0);
-    int32_t first, cnt;
-    const int32_t others = window_sort(n, S, P, E2, colE, b0, own, a, lds_scan, &first, &cnt);
-    if (!list) {
-        if (threadIdx.x == 0) {
-            len[b] = own + others;
-            atomicMax(maxlen, own + others);
-        }
-        return;
-    }
-    // the distinct other slots, compacted to the front of a[] (each thread
-    // holds its chunk in registers across the barrier)
-    constexpr int CMAX = WIN_MAXE / BLK;
-    const int32_t c = E2 >= BLK ? E2 / BLK : 1;
-    const int32_t beg = E2 >= BLK ? (int32_t)threadIdx.x * c : (int32_t)threadIdx.x;
-    int32_t vals[CMAX];
-    bool keep[CMAX];
-#pragma unroll
-    for (int q = 0; q < CMAX; ++q) {
-        const int32_t k = beg + q;
-        keep[q] = q < c && k < E2 && a[k] != INT32_MAX && (k == 0 || a[k - 1] != a[k]);
-        vals[q] = keep[q] ? a[k] : 0;
-    }
-    __syncthreads();
-    int32_t at = first;
-#pragma unroll
-    for (int q = 0; q < CMAX; ++q) {
-        if (keep[q]) a[at] = vals[q];
-        at += keep[q] ? 1 : 0;
-    }
-    (void)cnt;
-    __syncthreads();
     int32_t* out = list + off[b];
     for (int32_t t = threadIdx.x; t < own + others; t += BLK) out[t] = t < own ? b0 + t : a[t - own];
-    for (int32_t t = threadIdx.x; t < P * S; t += BLK) {
+    for (int32_t t = threadIdx.x; t < P * Sp; t += BLK) {
         const int32_t e = t / P, pp = t - e * P;
         if (pp >= own) continue;
-        const int64_t at = (int64_t)e * n + b0 + pp;
-        const int32_t v = colE[at];
+        const int64_t at2 = (int64_t)e * n + b0 + pp;
+        const int32_t v = e < S ? colE[at2] : b0 + pp;
         int32_t pos;
         if (v >= b0 && v < b0 + own) {
             pos = v - b0;
@@ -881,7 +889,7 @@ __global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t P,
             }
             pos = own + lo;
         }
-        colw[at] = (uint16_t)pos;
+        colw[at2] = (uint16_t)pos;
     }
 }
 
@@ -898,18 +906,16 @@ __device__ __forceinline__ void wread(const float4* W, uint32_t k, Rec3& r) {
 
 // row3 over the window: the lane's entries are 16-bit window positions, the
 // records come from LDS (the pair order, and so every sum, is that of row3).
+// The rows are padded to a whole number of chunks per lane (mu a multiple
+// of M), so the entry addresses need no clamping.
 template <bool WRAP, int M, int HC>
 __device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const float4* W,
-                                      const uint16_t* __restrict__ colw, uint32_t self, uint32_t e0, uint32_t es,
-                                      int32_t m, int32_t mu, Kahan& sr, Kahan* sm) {
+                                      const uint16_t* __restrict__ colw, uint32_t e0, uint32_t es, int32_t mu,
+                                      Kahan& sr, Kahan* sm) {
     for (int32_t base = 0; base < mu; base += M) {
         uint32_t kb[M];
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const int32_t t = base + q < m ? base + q : m - 1;
-            const uint32_t v = ld32(colw, m > 0 ? e0 + (uint32_t)t * es : 0u);
-            kb[q] = base + q < m ? v : self;
-        }
+        for (int q = 0; q < M; ++q) kb[q] = ld32(colw, e0 + (uint32_t)(base + q) * es);
         Rec3 A, B;
         wread<HC>(W, kb[0], A);
         wread<HC>(W, kb[1], B);
@@ -927,12 +933,13 @@ __device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const 
 }
 
 // k_euler3 with the neighbour records read from the workgroup's window in
-// LDS (fixed-stride rows only).  Workgroup blk takes block blk of P = BLK / L
-// slots; its window (at most HC records) is copied from R first.  Results
-// are bit-identical to k_euler3's.
-template <int STAGE, int L, int M, int HC>
-__global__ void __launch_bounds__(BLK) k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
-                                                 int32_t S, const int32_t* __restrict__ woff,
+// LDS (fixed-stride rows only).  Workgroup blk of NT threads takes block blk
+// of P = NT / L slots; its window (at most HC records) is copied from R
+// first.  Rows of Sp entries (Sp / L a multiple of M).  Results are
+// bit-identical to k_euler3's.
+template <int STAGE, int L, int M, int HC, int NT>
+__global__ void __launch_bounds__(NT) k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
+                                                int32_t Sp, const int32_t* __restrict__ woff,
                                                  const int32_t* __restrict__ wlist, const float4* __restrict__ R,
                                                  float4* Rout, const float4* U, const float4* U0, float4* Uout,
                                                  const float4* __restrict__ sorted, float* __restrict__ drho_dt,
@@ -940,20 +947,19 @@ __global__ void __launch_bounds__(BLK) k_euler3w(int32_t n, EulerArgs ea, const 
     __shared__ float4 W[4 * HC];
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
-    for (int32_t t = (int32_t)threadIdx.x; t < 4 * wn; t += BLK) {
+    for (int32_t t = (int32_t)threadIdx.x; t < 4 * wn; t += NT) {
         const int32_t k = t >> 2, q = t & 3;
         W[q * HC + k] = ld32(R, ((uint32_t)wlist[w0 + k] << 2) + (uint32_t)q);
     }
     const int sub = (int)(threadIdx.x % L);
     const int32_t lp = (int32_t)(threadIdx.x / L);
-    const int32_t ig = blk * (BLK / L) + lp;
+    const int32_t ig = blk * (NT / L) + lp;
     const bool valid = ig < n;
     const int32_t i = valid ? ig : n - 1;
-    const uint32_t self = (uint32_t)(i - blk * (BLK / L));
+    const uint32_t self = (uint32_t)(i - blk * (NT / L));
     const uint32_t e0 = (uint32_t)sub * (uint32_t)n + (uint32_t)i;
     const uint32_t es = (uint32_t)L * (uint32_t)n;
-    const int32_t m = (S - sub + L - 1) / L;
-    const int32_t mu = (S + L - 1) / L;
+    const int32_t mu = Sp / L;
     float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
     if (STAGE != 0 && sub == 0) {
         ui = U[i];
@@ -982,8 +988,8 @@ __global__ void __launch_bounds__(BLK) k_euler3w(int32_t n, EulerArgs ea, const 
     sr.init();
 #pragma unroll
     for (int a = 0; a < 3; ++a) sm[a].init();
-    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, self, e0, es, m, mu, sr, sm);
-    else row3w<false, M, HC>(ea, o, W, colw, self, e0, es, m, mu, sr, sm);
+    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, e0, es, mu, sr, sm);
+    else row3w<false, M, HC>(ea, o, W, colw, e0, es, mu, sr, sm);
     float Rt[4];
     Rt[0] = ea.fr * group_sum<L>(sr);
 #pragma unroll
@@ -1654,33 +1660,49 @@ int lanes3(const sph_ctx* c) {
     return avg >= 16.0 ? 4 : (avg >= 6.0 ? 2 : 1);
 }
 
-// Longest window the LDS planes of k_euler3w hold.
-constexpr int WIN_HC_MAX = 1024;
 
-// Build (or reuse) the neighbour windows of blocks of P slots for the
-// fixed-stride rows (k_window, two passes with a scan of the window lengths
-// in between).  Leaves c->win3.state = 1 when the records kernel can read
-// its neighbours from LDS, else -1: rows not fixed-stride, P S entries
-// beyond what one block sorts, a window longer than WIN_HC_MAX, or the
-// tuning override SPH_EULER_WINDOW=0.
-int window_prepare(sph_ctx* c, int P) {
+// Pairs per chunk of the window kernels: the M in {6, 8, 10, 12} whose
+// chunks cover mu entries with the fewest padding pairs (the larger on a
+// tie).
+int window_chunk(int mu) {
+    const int cand[4] = {12, 10, 8, 6};
+    int best = 12, cost = 1 << 30;
+    for (int M : cand) {
+        const int k = (mu + M - 1) / M * M;
+        if (k < cost) cost = k, best = M;
+    }
+    return best;
+}
+
+// Build (or reuse) the neighbour windows for workgroups of NT threads with L
+// lanes per particle (blocks of P = NT / L slots) over the fixed-stride rows
+// (k_window, two passes with a scan of the window lengths in between).
+// Leaves c->win3.state = 1 when the records kernel can read its neighbours
+// from LDS, else -1: rows not fixed-stride, a window longer than
+// WIN_HC_MAX, or the tuning override SPH_EULER_WINDOW=0.
+int window_prepare(sph_ctx* c, int L, int NT) {
     auto& w = c->win3;
-    if (w.state != 0 && w.P == P) return SPH_OK;
+    const int P = NT / L;
+    if (w.state != 0 && w.P == P && w.L == L) return SPH_OK;
     w.state = -1;
     w.P = P;
+    w.L = L;
     const char* e = getenv("SPH_EULER_WINDOW");
     if (e && strcmp(e, "0") == 0) return SPH_OK;
     const int32_t n = c->n, S = c->ell_S;
-    if (c->ell_state != 1 || n <= 0 || S <= 0 || (int64_t)P * S > WIN_MAXE) return SPH_OK;
-    int32_t E2 = 2;
-    while (E2 < P * S) E2 <<= 1;
+    if (c->ell_state != 1 || n <= 0 || S <= 0) return SPH_OK;
+    const int mu = (S + L - 1) / L;
+    const int M = window_chunk(mu);
+    const int32_t Sp = (mu + M - 1) / M * M * L;
+    if ((double)Sp * n >= 1073741824.0) return SPH_OK;  // 32-bit entry offsets
     const int32_t nb = (n + P - 1) / P;
     SPH_HIP(c, w.len.ensure((size_t)nb * sizeof(int32_t)));
     SPH_HIP(c, w.off.ensure(((size_t)nb + 1) * sizeof(int32_t)));
     SPH_HIP(c, c->counter.ensure(64));
     SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, P, E2, c->colE.as<int32_t>(),
-                       w.len.as<int32_t>(), c->counter.as<int32_t>(), nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P,
+                       c->colE.as<int32_t>(), w.len.as<int32_t>(), c->counter.as<int32_t>(), nullptr, nullptr,
+                       nullptr);
     SPH_LAUNCH_CHECK(c);
     int r = sph_scan_i32_to_i32(c, w.len.as<int32_t>(), w.off.as<int32_t>(), nb);
     if (r) return r;
@@ -1690,62 +1712,69 @@ int window_prepare(sph_ctx* c, int P) {
     SPH_HIP(c, hipStreamSynchronize(c->stream));
     if (host[0] > WIN_HC_MAX) return SPH_OK;
     SPH_HIP(c, w.list.ensure((size_t)host[1] * sizeof(int32_t)));
-    SPH_HIP(c, w.col.ensure((size_t)S * n * sizeof(uint16_t)));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, P, E2, c->colE.as<int32_t>(),
-                       nullptr, nullptr, w.off.as<int32_t>(), w.list.as<int32_t>(), w.col.as<uint16_t>());
+    SPH_HIP(c, w.col.ensure((size_t)Sp * n * sizeof(uint16_t)));
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P,
+                       c->colE.as<int32_t>(), nullptr, nullptr, w.off.as<int32_t>(), w.list.as<int32_t>(),
+                       w.col.as<uint16_t>());
     SPH_LAUNCH_CHECK(c);
     w.max = host[0];
+    w.M = M;
+    w.Sp = Sp;
     w.state = 1;
     return SPH_OK;
 }
 
-template <int STAGE, int L, int M, int HC>
+template <int STAGE, int L, int M, int HC, int NT>
 void launch3w_h(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     const auto& w = c->win3;
-    hipLaunchKernelGGL((k_euler3w<STAGE, L, M, HC>), dim3(grid_for(c->n, BLK / L)), dim3(BLK), 0, c->stream, c->n,
-                       ea, w.col.as<uint16_t>(), c->ell_S, w.off.as<int32_t>(), w.list.as<int32_t>(), io.R,
+    hipLaunchKernelGGL((k_euler3w<STAGE, L, M, HC, NT>), dim3(grid_for(c->n, NT / L)), dim3(NT), 0, c->stream,
+                       c->n, ea, w.col.as<uint16_t>(), w.Sp, w.off.as<int32_t>(), w.list.as<int32_t>(), io.R,
                        io.Rout, io.U, io.U0, io.Uout, c->sorted.as<float4>(), io.dr, io.dm);
 }
 
 // LDS planes for the longest window: 512, 768 or 1024 records (32, 48 or
 // 64 KB per workgroup).
-template <int STAGE, int L, int M>
+template <int STAGE, int M, int NT>
 void launch3w_m(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     const int32_t mx = c->win3.max;
-    if constexpr (L == 4) {
+    if constexpr (NT == 256) {
         if (mx <= 512) {
-            launch3w_h<STAGE, L, M, 512>(c, ea, io);
+            launch3w_h<STAGE, 4, M, 512, NT>(c, ea, io);
             return;
         }
     }
-    if (mx <= 768) launch3w_h<STAGE, L, M, 768>(c, ea, io);
-    else launch3w_h<STAGE, L, M, 1024>(c, ea, io);
+    if (mx <= 768) launch3w_h<STAGE, 4, M, 768, NT>(c, ea, io);
+    else launch3w_h<STAGE, 4, M, 1024, NT>(c, ea, io);
 }
 
-template <int STAGE, int L>
-void launch3w_l(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
-    const int mu = (c->ell_S + L - 1) / L;
-    const int cand[5] = {16, 12, 10, 8, 6};
-    int best = 16, cost = 1 << 30;
-    for (int M : cand) {
-        const int k = (mu + M - 1) / M * M;
-        if (k < cost) cost = k, best = M;
+template <int STAGE, int NT>
+void launch3w_t(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
+    const int M = c->win3.M;
+    if (M == 12) launch3w_m<STAGE, 12, NT>(c, ea, io);
+    else if (M == 10) launch3w_m<STAGE, 10, NT>(c, ea, io);
+    else if (M == 8) launch3w_m<STAGE, 8, NT>(c, ea, io);
+    else launch3w_m<STAGE, 6, NT>(c, ea, io);
+}
+
+// Workgroup size of the window kernels (four lanes per particle): 512
+// threads, blocks of 128 slots (measured on the 200^3 Taylor-Green rows, ms
+// per launch for 256 / 512 threads: 1.20 / 1.13 at 1.6h, 2.25 / 1.76 at 2h;
+// blocks of 256 slots need windows beyond 1024 records); tuning override
+// SPH_EULER_WINDOW_THREADS = 256 or 512.
+int window_threads() {
+    if (const char* e = getenv("SPH_EULER_WINDOW_THREADS")) {
+        const int v = atoi(e);
+        if (v == 256 || v == 512) return v;
     }
-    if (best == 16) launch3w_m<STAGE, L, 16>(c, ea, io);
-    else if (best == 12) launch3w_m<STAGE, L, 12>(c, ea, io);
-    else if (best == 10) launch3w_m<STAGE, L, 10>(c, ea, io);
-    else if (best == 8) launch3w_m<STAGE, L, 8>(c, ea, io);
-    else launch3w_m<STAGE, L, 6>(c, ea, io);
+    return 512;
 }
 
 // Whether the stage kernels read the neighbour records from LDS windows
-// (built on first use): fixed-stride rows with two or four lanes per
-// particle (blocks of 128 or 64 slots).
+// (built on first use): fixed-stride rows with four lanes per particle.
 int prepare_windows(sph_ctx* c, bool* use) {
     *use = false;
-    const int L = lanes3(c);
-    if (c->ell_state != 1 || (L != 2 && L != 4)) return SPH_OK;
-    const int r = window_prepare(c, BLK / L);
+    if (c->ell_state != 1 || lanes3(c) != 4) return SPH_OK;
+    const int r = window_prepare(c, 4, window_threads());
     if (r) return r;
     *use = c->win3.state == 1;
     return SPH_OK;
@@ -1755,8 +1784,8 @@ template <int STAGE>
 void launch3(sph_ctx* c, const EulerArgs& ea, const Stage3& io, bool windows) {
     const int L = lanes3(c);
     if (windows) {
-        if (L == 2) launch3w_l<STAGE, 2>(c, ea, io);
-        else launch3w_l<STAGE, 4>(c, ea, io);
+        if (c->win3.P == 64) launch3w_t<STAGE, 256>(c, ea, io);
+        else launch3w_t<STAGE, 512>(c, ea, io);
         return;
     }
     if (L == 1) launch3_l<STAGE, 1>(c, ea, io);

@@ -217,11 +217,14 @@ struct sph_ctx {
     struct Windows {
         int state = 0;        // 0: not built, 1: valid, -1: not used for this configuration
         int P = 0;            // slots per block
+        int L = 0;            // lanes per particle
+        int M = 0;            // pairs per chunk
+        int32_t Sp = 0;       // row entries, padded with the slot itself to a whole number of chunks per lane
         int32_t max = 0;      // longest window
         DevBuf len;           // int32 [nblocks]
         DevBuf off;           // int32 [nblocks + 1]
         DevBuf list;          // int32 [off[nblocks]]
-        DevBuf col;           // uint16 [ell_S * n]: entry k of slot i at k n + i
+        DevBuf col;           // uint16 [Sp * n]: entry k of slot i at k n + i
     } win3;
 };
 

@@ -15,6 +15,7 @@ where the exact entry vanishes (the off-diagonal entries on a lattice), so
 each component's error follows the scale of all of them (m_z starts at zero
 on the Taylor-Green field and its own scale is the smallest).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -202,16 +203,16 @@ def _run_paths(S, w, kappa, dt, steps):
     return out, path
 
 
-@pytest.mark.parametrize("kappa,lanes", [(1.6, "2"), (1.6, "4"), (2.0, "4")])
-def test_euler_3d_windows_bit_identical(S, kappa, lanes, monkeypatch):
+@pytest.mark.parametrize("kappa,threads", [(1.6, "256"), (1.6, "512"), (2.0, "256"), (2.0, "512")])
+def test_euler_3d_windows_bit_identical(S, kappa, threads, monkeypatch):
     """The stage kernels that read the neighbour records from LDS windows
     against the kernels that gather them: the same rates and the same state
     after 5 Heun steps, bit for bit (same pairs in the same order, same
-    sums), at two and four lanes per particle, on a jittered 30^3
-    Taylor-Green field (27,000 particles: the last block of 64 or 128 slots
-    is ragged, the rows uneven)."""
+    sums), for workgroups of 256 and 512 threads (blocks of 64 and 128
+    slots), on a jittered 30^3 Taylor-Green field (27,000 particles: the
+    last block is ragged, the rows uneven)."""
     w = I.taylor_green_3d(nside=30, nu=0.01, jitter=0.05, seed=21)
-    monkeypatch.setenv("SPH_EULER_LANES", lanes)
+    monkeypatch.setenv("SPH_EULER_WINDOW_THREADS", threads)
     monkeypatch.setenv("SPH_EULER_WINDOW", "0")
     ref, p0 = _run_paths(S, w, kappa, w.meta["dt"], 5)
     monkeypatch.delenv("SPH_EULER_WINDOW")
@@ -223,16 +224,20 @@ def test_euler_3d_windows_bit_identical(S, kappa, lanes, monkeypatch):
 
 def test_euler_3d_window_fallbacks(S, monkeypatch):
     """Configurations the windows do not serve run the gathering kernels:
-    one lane per particle (short rows), CSR rows, and blocks whose entries
-    exceed what one workgroup sorts (128 slots x the 2h rows of ~90)."""
+    one or two lanes per particle (short rows), CSR rows, and blocks whose
+    window would exceed 1024 records (h = 2 dx: rows of ~270 entries,
+    windows of ~1,300 records for 64 slots)."""
     w = I.taylor_green_3d(nside=24, nu=0.01, jitter=0.05, seed=3)
-    monkeypatch.setenv("SPH_EULER_LANES", "2")
-    _, p = _run_paths(S, w, 2.0, w.meta["dt"], 1)
-    assert p == S.PATH_RECORDS
-    monkeypatch.setenv("SPH_EULER_LANES", "1")
-    _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
-    assert p == S.PATH_RECORDS
+    for lanes in ("1", "2"):
+        monkeypatch.setenv("SPH_EULER_LANES", lanes)
+        _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
+        assert p == S.PATH_RECORDS, lanes
     monkeypatch.delenv("SPH_EULER_LANES")
+    wide = dataclasses.replace(w, h=2.0 / 24)
+    monkeypatch.setenv("SPH_EULER_WINDOW_THREADS", "256")
+    _, p = _run_paths(S, wide, 2.0, w.meta["dt"], 1)
+    assert p == S.PATH_RECORDS
+    monkeypatch.delenv("SPH_EULER_WINDOW_THREADS")
     monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
     _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
     assert p == S.PATH_RECORDS
