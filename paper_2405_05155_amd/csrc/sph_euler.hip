@@ -932,26 +932,63 @@ __device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const 
     }
 }
 
+// TwoSum merge of a compensated partial (hi, lo) with another (ohi, olo);
+// the error term of TwoSum is exact, so the result does not depend on which
+// operand is first.
+__device__ __forceinline__ void merge_pair(float& hi, float& lo, float ohi, float olo) {
+    const float s = hi + ohi;
+    const float bp = s - hi;
+    const float e = (hi - (s - bp)) + (ohi - bp);
+    lo = (lo + olo) + e;
+    hi = s;
+}
+
+// The four compensated sums k[0..3] of the four lanes of a group, reduced
+// and distributed: the lane with sub = b0 + 2 b1 returns the total of sum
+// 2 b0 + b1.  The lanes merge the same pairs as group_sum<4> (first lanes x
+// and x ^ 1, then x and x ^ 2), each lane carrying half the sums at the
+// first level and one at the second, so every total has the bits of
+// group_sum<4>'s.
+__device__ __forceinline__ float group_sum4_spread(const Kahan* k, int sub) {
+    const bool b0 = (sub & 1) != 0, b1 = (sub & 2) != 0;
+    float kh0 = b0 ? k[2].s : k[0].s, kl0 = b0 ? -k[2].c : -k[0].c;
+    float kh1 = b0 ? k[3].s : k[1].s, kl1 = b0 ? -k[3].c : -k[1].c;
+    const float sh0 = b0 ? k[0].s : k[2].s, sl0 = b0 ? -k[0].c : -k[2].c;
+    const float sh1 = b0 ? k[1].s : k[3].s, sl1 = b0 ? -k[1].c : -k[3].c;
+    merge_pair(kh0, kl0, __shfl_xor(sh0, 1, 64), __shfl_xor(sl0, 1, 64));
+    merge_pair(kh1, kl1, __shfl_xor(sh1, 1, 64), __shfl_xor(sl1, 1, 64));
+    float kh = b1 ? kh1 : kh0, kl = b1 ? kl1 : kl0;
+    const float sh = b1 ? kh0 : kh1, sl = b1 ? kl0 : kl1;
+    merge_pair(kh, kl, __shfl_xor(sh, 2, 64), __shfl_xor(sl, 2, 64));
+    return kh + kl;
+}
+
 // k_euler3 with the neighbour records read from the workgroup's window in
-// LDS (fixed-stride rows only).  Workgroup blk of NT threads takes block blk
-// of P = NT / L slots; its window (at most HC records) is copied from R
-// first.  Rows of Sp entries (Sp / L a multiple of M).  Results are
-// bit-identical to k_euler3's.
-template <int STAGE, int L, int M, int HC, int NT>
+// LDS (fixed-stride rows only, four lanes per particle).  Workgroup blk of NT
+// threads takes block blk of P = NT / 4 slots; its window (at most HC
+// records) is copied from R first.  Rows of Sp entries (Sp / 4 a multiple of
+// M).  The group's four sums end on its four lanes (group_sum4_spread) and
+// each lane finishes one component: lane sub takes component
+// 2 (sub & 1) + (sub >> 1) of (drho, m).  Results are bit-identical to
+// k_euler3's.
+template <int STAGE, int M, int HC, int NT>
 __global__ void __launch_bounds__(NT) k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
                                                 int32_t Sp, const int32_t* __restrict__ woff,
-                                                 const int32_t* __restrict__ wlist, const float4* __restrict__ R,
-                                                 float4* Rout, const float4* U, const float4* U0, float4* Uout,
-                                                 const float4* __restrict__ sorted, float* __restrict__ drho_dt,
-                                                 float* __restrict__ dmom_dt) {
+                                                const int32_t* __restrict__ wlist, const float4* __restrict__ R,
+                                                float4* Rout, const float4* U, const float4* U0, float4* Uout,
+                                                const float4* __restrict__ sorted, float* __restrict__ drho_dt,
+                                                float* __restrict__ dmom_dt) {
+    constexpr int L = 4;
     __shared__ float4 W[4 * HC];
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
-    for (int32_t t = (int32_t)threadIdx.x; t < 4 * wn; t += NT) {
-        const int32_t k = t >> 2, q = t & 3;
-        W[q * HC + k] = ld32(R, ((uint32_t)wlist[w0 + k] << 2) + (uint32_t)q);
+    {
+        const uint32_t q = threadIdx.x & 3u;
+        for (int32_t k = (int32_t)(threadIdx.x >> 2); k < wn; k += NT / 4)
+            W[q * HC + k] = ld32(R, ((uint32_t)wlist[w0 + k] << 2) + q);
     }
     const int sub = (int)(threadIdx.x % L);
+    const int comp = 2 * (sub & 1) + (sub >> 1);
     const int32_t lp = (int32_t)(threadIdx.x / L);
     const int32_t ig = blk * (NT / L) + lp;
     const bool valid = ig < n;
@@ -960,10 +997,10 @@ __global__ void __launch_bounds__(NT) k_euler3w(int32_t n, EulerArgs ea, const u
     const uint32_t e0 = (uint32_t)sub * (uint32_t)n + (uint32_t)i;
     const uint32_t es = (uint32_t)L * (uint32_t)n;
     const int32_t mu = Sp / L;
-    float4 ui = make_float4(0.f, 0.f, 0.f, 0.f), u0 = ui;
-    if (STAGE != 0 && sub == 0) {
-        ui = U[i];
-        if (STAGE == 2) u0 = U0[i];
+    float uc = 0.f, u0c = 0.f;
+    if (STAGE != 0) {
+        uc = reinterpret_cast<const float*>(U)[4 * (int64_t)i + comp];
+        if (STAGE == 2) u0c = reinterpret_cast<const float*>(U0)[4 * (int64_t)i + comp];
     }
     __syncthreads();
     Rec3 me;
@@ -984,33 +1021,28 @@ __global__ void __launch_bounds__(NT) k_euler3w(int32_t n, EulerArgs ea, const u
             near = near || off < ea.margin || ea.L[a] - off < ea.margin;
         }
     }
-    Kahan sr, sm[3];
-    sr.init();
+    Kahan ks[4];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) sm[a].init();
-    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, e0, es, mu, sr, sm);
-    else row3w<false, M, HC>(ea, o, W, colw, e0, es, mu, sr, sm);
-    float Rt[4];
-    Rt[0] = ea.fr * group_sum<L>(sr);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Rt[1 + a] = ea.fm * group_sum<L>(sm[a]);
-    if (sub != 0 || !valid) return;
+    for (int a = 0; a < 4; ++a) ks[a].init();
+    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, e0, es, mu, ks[0], ks + 1);
+    else row3w<false, M, HC>(ea, o, W, colw, e0, es, mu, ks[0], ks + 1);
+    const float Rc = (comp == 0 ? ea.fr : ea.fm) * group_sum4_spread(ks, sub);
     if (STAGE == 0) {
+        if (!valid) return;
         const int32_t ic = __float_as_int(sorted[i].w);
-        drho_dt[ic] = Rt[0];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) dmom_dt[(int64_t)a * n + ic] = Rt[1 + a];
+        if (comp == 0) drho_dt[ic] = Rc;
+        else dmom_dt[(int64_t)(comp - 1) * n + ic] = Rc;
         return;
     }
-    float4 un;
-    if (STAGE == 1) {
-        un = make_float4(ui.x + ea.dt * Rt[0], ui.y + ea.dt * Rt[1], ui.z + ea.dt * Rt[2], ui.w + ea.dt * Rt[3]);
-    } else {
-        un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * Rt[0])), 0.5f * (u0.y + (ui.y + ea.dt * Rt[1])),
-                         0.5f * (u0.z + (ui.z + ea.dt * Rt[2])), 0.5f * (u0.w + (ui.w + ea.dt * Rt[3])));
-    }
-    Uout[i] = un;
-    Rout[4 * (int64_t)i + 3] = state_quad3(ea, un);
+    float unc;
+    if (STAGE == 1) unc = uc + ea.dt * Rc;
+    else unc = 0.5f * (u0c + (uc + ea.dt * Rc));
+    // the density deviation sits on the group's first lane (component 0)
+    const float dr = __shfl(unc, (int)(threadIdx.x & 63u) & ~3, 64);
+    if (!valid) return;
+    reinterpret_cast<float*>(Uout)[4 * (int64_t)i + comp] = unc;
+    const float q3c = comp == 0 ? fmaf(ea.c2x2, unc, ea.c2x2poff) : unc * fast_rcp(ea.rho_ref + dr);
+    reinterpret_cast<float*>(Rout)[16 * (int64_t)i + 12 + comp] = q3c;
 }
 
 // ------------------------------------------------------------------ tiled stage
@@ -1724,10 +1756,10 @@ int window_prepare(sph_ctx* c, int L, int NT) {
     return SPH_OK;
 }
 
-template <int STAGE, int L, int M, int HC, int NT>
+template <int STAGE, int M, int HC, int NT>
 void launch3w_h(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     const auto& w = c->win3;
-    hipLaunchKernelGGL((k_euler3w<STAGE, L, M, HC, NT>), dim3(grid_for(c->n, NT / L)), dim3(NT), 0, c->stream,
+    hipLaunchKernelGGL((k_euler3w<STAGE, M, HC, NT>), dim3(grid_for(c->n, NT / 4)), dim3(NT), 0, c->stream,
                        c->n, ea, w.col.as<uint16_t>(), w.Sp, w.off.as<int32_t>(), w.list.as<int32_t>(), io.R,
                        io.Rout, io.U, io.U0, io.Uout, c->sorted.as<float4>(), io.dr, io.dm);
 }
@@ -1739,12 +1771,12 @@ void launch3w_m(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     const int32_t mx = c->win3.max;
     if constexpr (NT == 256) {
         if (mx <= 512) {
-            launch3w_h<STAGE, 4, M, 512, NT>(c, ea, io);
+            launch3w_h<STAGE, M, 512, NT>(c, ea, io);
             return;
         }
     }
-    if (mx <= 768) launch3w_h<STAGE, 4, M, 768, NT>(c, ea, io);
-    else launch3w_h<STAGE, 4, M, 1024, NT>(c, ea, io);
+    if (mx <= 768) launch3w_h<STAGE, M, 768, NT>(c, ea, io);
+    else launch3w_h<STAGE, M, 1024, NT>(c, ea, io);
 }
 
 template <int STAGE, int NT>
