@@ -971,8 +971,16 @@ __device__ __forceinline__ float group_sum4_spread(const Kahan* k, int sub) {
 // each lane finishes one component: lane sub takes component
 // 2 (sub & 1) + (sub >> 1) of (drho, m).  Results are bit-identical to
 // k_euler3's.
+// Waves per SIMD when as many window workgroups are resident as a CU's
+// 160 KB of LDS holds; the register budget is capped to match (with 512
+// threads and 768-record windows: three workgroups, six waves per SIMD, at
+// most 80 VGPRs).
+template <int HC, int NT>
+constexpr int window_waves_per_simd() { return 163840 / (64 * HC) * (NT / 64) / 4; }
+
 template <int STAGE, int M, int HC, int NT>
-__global__ void __launch_bounds__(NT) k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(window_waves_per_simd<HC, NT>())))
+k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
                                                 int32_t Sp, const int32_t* __restrict__ woff,
                                                 const int32_t* __restrict__ wlist, const float4* __restrict__ R,
                                                 float4* Rout, const float4* U, const float4* U0, float4* Uout,
