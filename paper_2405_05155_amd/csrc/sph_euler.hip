@@ -786,13 +786,15 @@ __device__ int32_t wg_exclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
 // Pass 1 (list == nullptr): window length of every block into len[b] and the
 // longest into *maxlen (a block with more than WIN_HC_MAX distinct
 // neighbours reports WIN_HC_MAX + 1).  Pass 2: the windows into
-// list[off[b] ..] and the rows' positions into colw, entry k of slot i at
-// colw[k n + i] for k < Sp: the rows are padded from S to Sp entries with
-// the slot itself (a zero-weight pair), so that every lane's share is a
-// whole number of chunks.  The distinct other slots are collected in an
+// list[off[b] ..] and the rows into colw as 16 times the window position
+// (the record's byte offset in an LDS plane).  Rows are padded from S to Sp
+// entries with the slot itself (a zero-weight pair), so that each of the L
+// lanes of a slot takes a whole number of chunks of M entries; entry
+// k = s + L (c M + t) of slot i (lane s, chunk c, t < M) sits at
+// colw[((c n + i) L + s) M + t], so a lane loads a chunk at once.  The distinct other slots are collected in an
 // LDS hash set (linear probing, at most WIN_HASH probes per insertion),
 // then compacted and sorted (bitonic).
-__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp, int32_t P,
+__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp, int32_t P, int32_t L, int32_t M,
                                                 const int32_t* __restrict__ colE, int32_t* __restrict__ len,
                                                 int32_t* __restrict__ maxlen, const int32_t* __restrict__ off,
                                                 int32_t* __restrict__ list, uint16_t* __restrict__ colw) {
@@ -875,8 +877,9 @@ __global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp
     for (int32_t t = threadIdx.x; t < P * Sp; t += BLK) {
         const int32_t e = t / P, pp = t - e * P;
         if (pp >= own) continue;
-        const int64_t at2 = (int64_t)e * n + b0 + pp;
-        const int32_t v = e < S ? colE[at2] : b0 + pp;
+        const int32_t v = e < S ? colE[(int64_t)e * n + b0 + pp] : b0 + pp;
+        const int32_t ls = e % L, lj = e / L;
+        const int64_t at2 = (((int64_t)(lj / M) * n + b0 + pp) * L + ls) * M + lj % M;
         int32_t pos;
         if (v >= b0 && v < b0 + own) {
             pos = v - b0;
@@ -889,7 +892,7 @@ __global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp
             }
             pos = own + lo;
         }
-        colw[at2] = (uint16_t)pos;
+        colw[at2] = (uint16_t)(pos << 4);
     }
 }
 
@@ -904,29 +907,60 @@ __device__ __forceinline__ void wread(const float4* W, uint32_t k, Rec3& r) {
     r.q3 = W[3 * HC + k];
 }
 
-// row3 over the window: the lane's entries are 16-bit window positions, the
-// records come from LDS (the pair order, and so every sum, is that of row3).
-// The rows are padded to a whole number of chunks per lane (mu a multiple
-// of M), so the entry addresses need no clamping.
+// The same from the byte offset 16 k of the record in its plane.
+template <int HC>
+__device__ __forceinline__ void wread_b(const float4* W, uint32_t b, Rec3& r) {
+    const char* w = reinterpret_cast<const char*>(W) + b;
+    r.q0 = *reinterpret_cast<const float4*>(w);
+    r.q1 = *reinterpret_cast<const float4*>(w + 16 * HC);
+    r.q2 = *reinterpret_cast<const float4*>(w + 32 * HC);
+    r.q3 = *reinterpret_cast<const float4*>(w + 48 * HC);
+}
+
+// A lane's M entries of one chunk (M / 2 words of two 16-bit entries each,
+// starting at word `at`), in as few loads as their alignment allows.
+template <int M>
+__device__ __forceinline__ void load_chunk(const uint16_t* __restrict__ colw, uint32_t at, uint32_t (&w)[M / 2]) {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(colw);
+    if constexpr (M == 8) {
+        const uint4 v = ld32(reinterpret_cast<const uint4*>(p), at >> 2);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (M == 12) {
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            const uint2 v = ld32(reinterpret_cast<const uint2*>(p), (at >> 1) + (uint32_t)h);
+            w[2 * h] = v.x;
+            w[2 * h + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < M / 2; ++h) w[h] = ld32(p, at + (uint32_t)h);
+    }
+}
+
+// row3 over the window: the lane's entries are the byte offsets (16 times
+// the window position) of its neighbours' records, the records come from
+// LDS (the pair order, and so every sum, is that of row3).  The lane's
+// entries of chunk c sit together (M 16-bit values from word at0 + c cs),
+// and the rows are padded to a whole number of chunks per lane.
 template <bool WRAP, int M, int HC>
 __device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const float4* W,
-                                      const uint16_t* __restrict__ colw, uint32_t e0, uint32_t es, int32_t mu,
+                                      const uint16_t* __restrict__ colw, uint32_t at0, uint32_t cs, int32_t nchunk,
                                       Kahan& sr, Kahan* sm) {
-    for (int32_t base = 0; base < mu; base += M) {
-        uint32_t kb[M];
-#pragma unroll
-        for (int q = 0; q < M; ++q) kb[q] = ld32(colw, e0 + (uint32_t)(base + q) * es);
+    for (int32_t c = 0; c < nchunk; ++c) {
+        uint32_t w[M / 2];
+        load_chunk<M>(colw, at0 + (uint32_t)c * cs, w);
         Rec3 A, B;
-        wread<HC>(W, kb[0], A);
-        wread<HC>(W, kb[1], B);
+        wread_b<HC>(W, w[0] & 0xffffu, A);
+        wread_b<HC>(W, w[0] >> 16, B);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
             pair3<WRAP>(ea, o, A, sr, sm);
-            if (q + 2 < M) wread<HC>(W, (uint32_t)after((int32_t)kb[q + 2], sr), A);
+            if (q + 2 < M) wread_b<HC>(W, (uint32_t)after((int32_t)(w[q / 2 + 1] & 0xffffu), sr), A);
             __builtin_amdgcn_sched_barrier(0);
             pair3<WRAP>(ea, o, B, sr, sm);
-            if (q + 3 < M) wread<HC>(W, (uint32_t)after((int32_t)kb[q + 3], sr), B);
+            if (q + 3 < M) wread_b<HC>(W, (uint32_t)after((int32_t)(w[q / 2 + 1] >> 16), sr), B);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -1002,9 +1036,10 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     const bool valid = ig < n;
     const int32_t i = valid ? ig : n - 1;
     const uint32_t self = (uint32_t)(i - blk * (NT / L));
-    const uint32_t e0 = (uint32_t)sub * (uint32_t)n + (uint32_t)i;
-    const uint32_t es = (uint32_t)L * (uint32_t)n;
-    const int32_t mu = Sp / L;
+    // chunk c of the lane's entries: words ((c n + i) L + sub) M / 2 ..
+    const uint32_t at0 = ((uint32_t)i * L + (uint32_t)sub) * (uint32_t)(M / 2);
+    const uint32_t cs = (uint32_t)n * L * (uint32_t)(M / 2);
+    const int32_t nchunk = Sp / (L * M);
     float uc = 0.f, u0c = 0.f;
     if (STAGE != 0) {
         uc = reinterpret_cast<const float*>(U)[4 * (int64_t)i + comp];
@@ -1032,8 +1067,8 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     Kahan ks[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) ks[a].init();
-    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, e0, es, mu, ks[0], ks + 1);
-    else row3w<false, M, HC>(ea, o, W, colw, e0, es, mu, ks[0], ks + 1);
+    if (__any(near)) row3w<true, M, HC>(ea, o, W, colw, at0, cs, nchunk, ks[0], ks + 1);
+    else row3w<false, M, HC>(ea, o, W, colw, at0, cs, nchunk, ks[0], ks + 1);
     const float Rc = (comp == 0 ? ea.fr : ea.fm) * group_sum4_spread(ks, sub);
     if (STAGE == 0) {
         if (!valid) return;
@@ -1740,7 +1775,7 @@ int window_prepare(sph_ctx* c, int L, int NT) {
     SPH_HIP(c, w.off.ensure(((size_t)nb + 1) * sizeof(int32_t)));
     SPH_HIP(c, c->counter.ensure(64));
     SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P,
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P, L, M,
                        c->colE.as<int32_t>(), w.len.as<int32_t>(), c->counter.as<int32_t>(), nullptr, nullptr,
                        nullptr);
     SPH_LAUNCH_CHECK(c);
@@ -1753,7 +1788,7 @@ int window_prepare(sph_ctx* c, int L, int NT) {
     if (host[0] > WIN_HC_MAX) return SPH_OK;
     SPH_HIP(c, w.list.ensure((size_t)host[1] * sizeof(int32_t)));
     SPH_HIP(c, w.col.ensure((size_t)Sp * n * sizeof(uint16_t)));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P,
+    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P, L, M,
                        c->colE.as<int32_t>(), nullptr, nullptr, w.off.as<int32_t>(), w.list.as<int32_t>(),
                        w.col.as<uint16_t>());
     SPH_LAUNCH_CHECK(c);

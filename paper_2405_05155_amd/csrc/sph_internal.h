@@ -224,7 +224,7 @@ struct sph_ctx {
         DevBuf len;           // int32 [nblocks]
         DevBuf off;           // int32 [nblocks + 1]
         DevBuf list;          // int32 [off[nblocks]]
-        DevBuf col;           // uint16 [Sp * n]: entry k of slot i at k n + i
+        DevBuf col;           // uint16 [Sp * n]: 16 x window position; entry s + L (c M + t) of slot i at ((c n + i) L + s) M + t
     } win3;
 };
 
