@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the stage kernel measured with rocprofv3
 # (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors read off a plain 256 MiB copy),
 # keyed by the SHA-256 of the code of the stage kernel's sources (comments and
-# blank lines dropped) it was measured on: a changed kernel reports null until
+# blank lines dropped; the stage kernels, the shared header and the window
+# builder) it was measured on: a changed kernel reports null until
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
@@ -98,7 +99,8 @@ def source_sha(*rels: str) -> str:
     return h.hexdigest()
 
 
-STAGE_SOURCES = ("paper_2405_05155_amd/csrc/sph_euler.hip", "paper_2405_05155_amd/csrc/sph_internal.h")
+STAGE_SOURCES = ("paper_2405_05155_amd/csrc/sph_euler.hip", "paper_2405_05155_amd/csrc/sph_internal.h",
+                 "paper_2405_05155_amd/csrc/sph_windows.hip")
 
 
 def stage_bytes_3d(n: int, nnz: int) -> float:

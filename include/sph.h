@@ -76,31 +76,20 @@ void sph_ctx_destroy(sph_ctx* ctx);
 const char* sph_last_error(const sph_ctx* ctx);
 /* Re-bind the context to another stream of the same device. */
 int sph_set_stream(sph_ctx* ctx, void* hip_stream);
-/* Execution strategy of the pair loops over a fixed configuration (the
- * Eulerian stage).  SPH_TILING_OFF (the default): lane groups per particle
- * gather their neighbours through the caches.  SPH_TILING_ON: workgroups
- * stage cell tiles (a Morton-aligned block of cells and its one-cell ring)
- * in LDS and evaluate each unique pair once, wherever the configuration
- * admits tiles (Morton cell keys, periodic axes long enough for a tile and
- * its ring, a tile within the LDS budget); elsewhere the per-particle path
- * runs.  Results agree to rounding.  Returns SPH_ERR_ARG for another mode. */
-enum { SPH_TILING_OFF = 0, SPH_TILING_ON = 1 };
-int sph_set_tiling(sph_ctx* ctx, int mode);
 /* Which pair-loop variant the context's last sph_euler_rhs, sph_euler_step,
  * sph_hllc_rhs or sph_hllc_step call ran (a diagnostic; every variant gives
  * results within the parity bars, the last two bit-identical to each other):
  *  SPH_PATH_NONE     no such call yet, or it had nothing to do;
  *  SPH_PATH_GENERIC  lane groups per particle gathering separate geometry
- *                    and state arrays (2-D, the compressible rows, CSR rows
- *                    or configurations beyond the 3-D records' limits);
- *  SPH_PATH_TILED    the LDS cell tiles of SPH_TILING_ON;
+ *                    and state arrays (2-D, the compressible rows, or
+ *                    configurations beyond the 3-D records' limits);
  *  SPH_PATH_RECORDS  3-D: one 64-byte record (geometry, trace of B, 2p and
  *                    velocity) gathered per neighbour;
  *  SPH_PATH_WINDOWS  3-D: as SPH_PATH_RECORDS, the neighbour records read
  *                    from a window of the workgroup's neighbourhood staged in
  *                    LDS (fixed-stride rows whose windows fit).
  * Returns -1 for a NULL context. */
-enum { SPH_PATH_NONE = 0, SPH_PATH_GENERIC = 1, SPH_PATH_TILED = 2, SPH_PATH_RECORDS = 3, SPH_PATH_WINDOWS = 4 };
+enum { SPH_PATH_NONE = 0, SPH_PATH_GENERIC = 1, SPH_PATH_RECORDS = 2, SPH_PATH_WINDOWS = 3 };
 int sph_euler_path(const sph_ctx* ctx);
 
 /* ---------------------------------------------------------------- neighbours
@@ -195,8 +184,7 @@ int sph_euler_step(sph_ctx* ctx, const sph_euler_params* prm, float* drho, float
  * else the star state of Eq. (22) on the side of u*'s sign (with the normal
  * velocity u_K where the printed formulas show |v_K|), velocity u* n plus the
  * mean tangential velocity.  Wendland kernel, 2-D contexts only
- * (SPH_ERR_ARG otherwise); the per-particle kernel runs whatever the tiling
- * mode.  State: rho FP32 [n] (the density itself), mom = rho v FP32 [2][n],
+ * (SPH_ERR_ARG otherwise).  State: rho FP32 [n] (the density itself), mom = rho v FP32 [2][n],
  * E FP32 [n] (total energy per unit volume). */
 typedef struct {
     double gamma;    /* ratio of specific heats, > 1 */

@@ -108,8 +108,9 @@ void sph_ctx_destroy(sph_ctx* c) {
                       &c->col_s,       &c->scan_tmp,     &c->counter,        &c->geo0,        &c->geo1,
                       &c->geo2,        &c->ua,           &c->ub,             &c->ta,          &c->tb,
                       &c->tc,          &c->tail,         &c->svol,           &c->sfield,      &c->partials,
-                      &c->relax_scalars, &c->tiles.info, &c->tiles.hdr, &c->tiles.task_ptr, &c->tiles.halo, &c->tiles.tasks, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->rec3,
-                      &c->win3.len, &c->win3.off, &c->win3.list, &c->win3.col};
+                      &c->relax_scalars, &c->colE, &c->fa, &c->fb, &c->fc, &c->pa, &c->sorted_tmp, &c->rec3,
+                      &c->win3.len, &c->win3.off, &c->win3.list, &c->win3.col,
+                      &c->wtl.len,  &c->wtl.off,  &c->wtl.list,  &c->wtl.col};
     for (DevBuf* b : bufs) b->release();
     (void)hipSetDevice(prev);
     delete c;
@@ -120,14 +121,6 @@ const char* sph_last_error(const sph_ctx* c) { return c ? c->err : "null context
 int sph_set_stream(sph_ctx* c, void* s) {
     if (!c) return SPH_ERR_ARG;
     c->stream = (hipStream_t)s;
-    return SPH_OK;
-}
-
-int sph_set_tiling(sph_ctx* c, int mode) {
-    if (!c) return SPH_ERR_ARG;
-    if (mode != SPH_TILING_OFF && mode != SPH_TILING_ON)
-        return sph_fail(c, SPH_ERR_ARG, "sph_set_tiling: unknown mode %d", mode);
-    c->tiling = mode;
     return SPH_OK;
 }
 

@@ -755,146 +755,10 @@ __global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const i
 }
 
 // ------------------------------------------------------------------ record windows
-// Neighbour windows of the 3-D records kernel over fixed-stride rows.  The
-// slots of one workgroup, block b = [b P, b P + P), reference a few hundred
-// distinct neighbours (on the 200^3 lattice at 1.6h about 5.8 per own
-// particle for P = 64).  The window of block b lists its own slots first,
-// in order, then the distinct other slots its rows reference, ascending; the
-// rows are rewritten as 16-bit positions in that list.  A workgroup copies
-// its window's records into LDS once and its pairs then read them there
-// instead of gathering each neighbour through the vector cache.
-constexpr int WIN_HASH = 4096;  // open-addressing set of a block's distinct neighbours (LDS)
-constexpr int WIN_HC_MAX = 1024;  // longest window the LDS planes of k_euler3w hold
-
-// Exclusive scan of one value per thread over the workgroup (BLK threads);
-// returns the exclusive prefix and stores the total in *total.
-__device__ int32_t wg_exclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
-    lds[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < BLK; o <<= 1) {
-        const int32_t u = (int32_t)threadIdx.x >= o ? lds[threadIdx.x - o] : 0;
-        __syncthreads();
-        lds[threadIdx.x] += u;
-        __syncthreads();
-    }
-    const int32_t incl = lds[threadIdx.x];
-    *total = lds[BLK - 1];
-    __syncthreads();
-    return incl - v;
-}
-
-// Pass 1 (list == nullptr): window length of every block into len[b] and the
-// longest into *maxlen (a block with more than WIN_HC_MAX distinct
-// neighbours reports WIN_HC_MAX + 1).  Pass 2: the windows into
-// list[off[b] ..] and the rows into colw as 16 times the window position
-// (the record's byte offset in an LDS plane).  Rows are padded from S to Sp
-// entries with the slot itself (a zero-weight pair), so that each of the L
-// lanes of a slot takes a whole number of chunks of M entries; entry
-// k = s + L (c M + t) of slot i (lane s, chunk c, t < M) sits at
-// colw[((c n + i) L + s) M + t], so a lane loads a chunk at once.  The distinct other slots are collected in an
-// LDS hash set (linear probing, at most WIN_HASH probes per insertion),
-// then compacted and sorted (bitonic).
-__global__ void __launch_bounds__(BLK) k_window(int32_t n, int32_t S, int32_t Sp, int32_t P, int32_t L, int32_t M,
-                                                const int32_t* __restrict__ colE, int32_t* __restrict__ len,
-                                                int32_t* __restrict__ maxlen, const int32_t* __restrict__ off,
-                                                int32_t* __restrict__ list, uint16_t* __restrict__ colw) {
-    __shared__ int32_t T[WIN_HASH];
-    __shared__ int32_t a[WIN_HASH];
-    __shared__ int32_t lds_scan[BLK];
-    __shared__ int32_t distinct;
-    const int32_t b = (int32_t)blockIdx.x;
-    const int32_t b0 = b * P;
-    const int32_t own = min(P, n - b0);
-    for (int32_t t = threadIdx.x; t < WIN_HASH; t += BLK) T[t] = -1;
-    if (threadIdx.x == 0) distinct = 0;
-    __syncthreads();
-    for (int32_t t = threadIdx.x; t < P * S; t += BLK) {
-        const int32_t e = t / P, pp = t - e * P;
-        if (pp >= own) continue;
-        const int32_t v = colE[(int64_t)e * n + b0 + pp];
-        if (v >= b0 && v < b0 + own) continue;
-        if (*(volatile int32_t*)&distinct > WIN_HC_MAX) continue;  // too long already: stop inserting
-        uint32_t h = ((uint32_t)v * 2654435761u) >> 20;  // 12 bits
-        for (int probe = 0; probe < WIN_HASH; ++probe) {
-            const int32_t old = atomicCAS(&T[h], -1, v);
-            if (old == -1) {
-                atomicAdd(&distinct, 1);
-                break;
-            }
-            if (old == v) break;
-            h = (h + 1) & (WIN_HASH - 1);
-        }
-    }
-    __syncthreads();
-    const int32_t others = distinct;
-    if (others + own > WIN_HC_MAX) {
-        if (!list && threadIdx.x == 0) {
-            len[b] = WIN_HC_MAX + 1;
-            atomicMax(maxlen, WIN_HC_MAX + 1);
-        }
-        return;
-    }
-    if (!list) {
-        if (threadIdx.x == 0) {
-            len[b] = own + others;
-            atomicMax(maxlen, own + others);
-        }
-        return;
-    }
-    // compact the set into a[0 .. others), then sort it
-    constexpr int C = WIN_HASH / BLK;
-    int32_t m = 0;
-#pragma unroll
-    for (int q = 0; q < C; ++q) m += T[threadIdx.x * C + q] != -1 ? 1 : 0;
-    int32_t total;
-    int32_t at = wg_exclusive_scan(m, lds_scan, &total);
-#pragma unroll
-    for (int q = 0; q < C; ++q) {
-        const int32_t v = T[threadIdx.x * C + q];
-        if (v != -1) a[at++] = v;
-    }
-    int32_t E2 = 2;
-    while (E2 < others) E2 <<= 1;
-    __syncthreads();
-    for (int32_t t = others + (int32_t)threadIdx.x; t < E2; t += BLK) a[t] = INT32_MAX;
-    __syncthreads();
-    for (int32_t k = 2; k <= E2; k <<= 1) {
-        for (int32_t j = k >> 1; j > 0; j >>= 1) {
-            for (int32_t t = threadIdx.x; t < E2 / 2; t += BLK) {
-                const int32_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const int32_t hi = lo + j;
-                const int32_t x = a[lo], y = a[hi];
-                if ((x > y) == ((lo & k) == 0)) {
-                    a[lo] = y;
-                    a[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    int32_t* out = list + off[b];
-    for (int32_t t = threadIdx.x; t < own + others; t += BLK) out[t] = t < own ? b0 + t : a[t - own];
-    for (int32_t t = threadIdx.x; t < P * Sp; t += BLK) {
-        const int32_t e = t / P, pp = t - e * P;
-        if (pp >= own) continue;
-        const int32_t v = e < S ? colE[(int64_t)e * n + b0 + pp] : b0 + pp;
-        const int32_t ls = e % L, lj = e / L;
-        const int64_t at2 = (((int64_t)(lj / M) * n + b0 + pp) * L + ls) * M + lj % M;
-        int32_t pos;
-        if (v >= b0 && v < b0 + own) {
-            pos = v - b0;
-        } else {
-            int32_t lo = 0, hi = others;  // first index with a[index] >= v
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (a[mid] < v) lo = mid + 1;
-                else hi = mid;
-            }
-            pos = own + lo;
-        }
-        colw[at2] = (uint16_t)(pos << 4);
-    }
-}
+// The 3-D stage over neighbour windows (built by sph_windows_prepare): a
+// workgroup copies the records of its block's window into LDS once and its
+// pairs then read them there instead of gathering each neighbour through
+// the vector cache.
 
 // Record k of the window from the LDS planes (plane q holds quad q of every
 // record: a 16-byte read per quad, consecutive records in consecutive bank
@@ -1088,336 +952,6 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     reinterpret_cast<float*>(Rout)[16 * (int64_t)i + 12 + comp] = q3c;
 }
 
-// ------------------------------------------------------------------ tiled stage
-// One workgroup per cell tile (the tile set of the bound configuration).
-//  1. The records of the tile's own particles and of its halo are staged in
-//     LDS: position relative to the tile's first particle (minimum image, so
-//     no wrap is needed per pair; exact for quantised coordinates), V, the
-//     upper triangle of B, p, c rho / 2 and the velocity.
-//  2. Each task (unique neighbour pair) evaluates the Riemann flux once.  The
-//     pair terms are antisymmetric: with Q = (-2 rho* v*.g, -2 (rho* v* (v*.g)
-//     + p* g) + 4 mu (dW/dr)/(2r) (v_i - v_j)), g the corrected gradient,
-//     particle i receives V_j Q and particle j receives -V_i Q.  Both go to
-//     the pair's row entries in LDS.
-//  3. Each own particle sums its row entries in row order (compensated) and
-//     applies the stage update.
-constexpr int TBLK = 256;
-
-template <int DIM>
-constexpr int rec_quads() { return DIM == 2 ? 3 : 4; }
-
-template <int DIM>
-__device__ __forceinline__ void stage_record(float4* rec, const EulerArgs& ea, const float4 org, const float4 g0,
-                                             const float4 g1, const float2 g2, const float4 pr) {
-    constexpr int NQ = rec_quads<DIM>();
-    const float x0 = wrap(g0.x - org.x, ea.L[0], ea.invL[0]);
-    const float x1 = wrap(g0.y - org.y, ea.L[1], ea.invL[1]);
-    const float p = ea.c2 * (pr.x + ea.poff);
-    const float chr = ea.hc * (ea.rho_ref + pr.x);
-    if (DIM == 2) {
-        rec[0] = make_float4(x0, x1, g0.z, g0.w);
-        rec[1] = make_float4(g1.x, g1.y, p, chr);
-        rec[2] = make_float4(pr.y, pr.z, 0.f, 0.f);
-    } else {
-        const float x2 = wrap(g0.z - org.z, ea.L[2], ea.invL[2]);
-        rec[0] = make_float4(x0, x1, x2, g0.w);
-        rec[1] = g1;
-        rec[2] = make_float4(g2.x, g2.y, p, chr);
-        rec[3] = make_float4(pr.y, pr.z, pr.w, 0.f);
-    }
-    (void)NQ;
-}
-
-// Geometry of sorted slot s: 2-D (x, y, V, B00) + (B01, B11); 3-D
-// (x, y, z, V) + (B00, B01, B02, B11) + (B12, B22).
-template <int DIM>
-__device__ __forceinline__ void load_geo(int32_t s, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
-                                         const float2* __restrict__ geo2, float4& g0, float4& g1, float2& g2) {
-    g0 = geo0[s];
-    if (DIM == 2) {
-        float2 t = reinterpret_cast<const float2*>(geo1)[s];
-        g1 = make_float4(t.x, t.y, 0.f, 0.f);
-        g2 = make_float2(0.f, 0.f);
-    } else {
-        g1 = geo1[s];
-        g2 = geo2[s];
-    }
-}
-
-// The unique-pair flux of task tk, written to both row entries.
-template <int DIM>
-__device__ __forceinline__ void pair_flux(const EulerArgs& ea, const float4* rec, float4* row, uint2 tk) {
-    constexpr int NQ = rec_quads<DIM>();
-    const int32_t a = (int32_t)(tk.x & 0xffffu), b = (int32_t)(tk.x >> 16);
-    const int32_t ea_row = (int32_t)(tk.y & 0xffffu), eb_row = (int32_t)(tk.y >> 16);
-    const float4* ra = rec + a * NQ;
-    const float4* rb = rec + b * NQ;
-    const float4 a0 = ra[0], a1 = ra[1], a2 = ra[2];
-    const float4 b0 = rb[0], b1 = rb[1], b2 = rb[2];
-    float d[3], Bs[6], va[3], vb[3];
-    float Va, Vb, pa, pb, ca, cb;
-    if (DIM == 2) {
-        d[0] = a0.x - b0.x; d[1] = a0.y - b0.y; d[2] = 0.f;
-        Va = a0.z; Vb = b0.z;
-        Bs[0] = a0.w + b0.w; Bs[1] = a1.x + b1.x; Bs[2] = a1.y + b1.y;
-        Bs[3] = Bs[4] = Bs[5] = 0.f;
-        pa = a1.z; pb = b1.z; ca = a1.w; cb = b1.w;
-        va[0] = a2.x; va[1] = a2.y; va[2] = 0.f;
-        vb[0] = b2.x; vb[1] = b2.y; vb[2] = 0.f;
-    } else {
-        const float4 a3 = ra[3], b3 = rb[3];
-        d[0] = a0.x - b0.x; d[1] = a0.y - b0.y; d[2] = a0.z - b0.z;
-        Va = a0.w; Vb = b0.w;
-        Bs[0] = a1.x + b1.x; Bs[1] = a1.y + b1.y; Bs[2] = a1.z + b1.z;
-        Bs[3] = a1.w + b1.w; Bs[4] = a2.x + b2.x; Bs[5] = a2.y + b2.y;
-        pa = a2.z; pb = b2.z; ca = a2.w; cb = b2.w;
-        va[0] = a3.x; va[1] = a3.y; va[2] = a3.z;
-        vb[0] = b3.x; vb[1] = b3.y; vb[2] = b3.z;
-    }
-    float r2 = 0.f;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) r2 = fmaf(d[c], d[c], r2);
-    const bool live = r2 > 0.f;
-    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
-    const float tq = fmaf(-0.5f * ea.hinv, r2 * rinv, 1.f);  // 1 - q/2
-    const float Fh = live ? ea.cFh * tq * tq * tq : 0.f;      // (dW/dr)/r / 2
-    float gc[DIM];
-    if (DIM == 2) {
-        gc[0] = Fh * fmaf(Bs[0], d[0], Bs[1] * d[1]);
-        gc[1] = Fh * fmaf(Bs[1], d[0], Bs[2] * d[1]);
-    } else {
-        gc[0] = Fh * fmaf(Bs[0], d[0], fmaf(Bs[1], d[1], Bs[2] * d[2]));
-        gc[1] = Fh * fmaf(Bs[1], d[0], fmaf(Bs[3], d[1], Bs[4] * d[2]));
-        gc[2] = Fh * fmaf(Bs[2], d[0], fmaf(Bs[4], d[1], Bs[5] * d[2]));
-    }
-    // Riemann problem along n = -d / r (from a to b), left = a, right = b
-    float dv[DIM], dvd = 0.f;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        dv[c] = va[c] - vb[c];
-        dvd = fmaf(dv[c], d[c], dvd);
-    }
-    const float du_lr = -dvd * rinv;                 // u_l - u_r
-    const float rhobar_c = ca + cb;                  // c (rho_l + rho_r) / 2
-    const float beta = fminf(ea.eta_c * fmaxf(du_lr, 0.f), 1.f);
-    const float hb2 = 0.5f * beta;
-    const float du = hb2 * beta * (pa - pb) * fast_rcp(rhobar_c);  // u* - mean
-    const float pstar = fmaf(0.5f, pa + pb, hb2 * rhobar_c * du_lr);
-    const float rhostar = fmaf(pstar, ea.c2inv, ea.rho0);
-    const float dun = -du * rinv;
-    float vs[DIM], vg = 0.f;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        vs[c] = fmaf(0.5f, va[c] + vb[c], dun * d[c]);
-        vg = fmaf(vs[c], gc[c], vg);
-    }
-    const float rvg = rhostar * vg;
-    const float visc = ea.mu_tr * (DIM == 2 ? Bs[0] + Bs[2] : (Bs[0] + Bs[3]) + Bs[5]) * Fh;
-    float Q[4];
-    Q[0] = -2.f * rvg;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) Q[1 + c] = fmaf(-2.f, fmaf(rvg, vs[c], pstar * gc[c]), visc * dv[c]);
-    if (DIM == 2) {
-        row[ea_row] = make_float4(Vb * Q[0], Vb * Q[1], Vb * Q[2], 0.f);
-        if (eb_row != 0xffff) row[eb_row] = make_float4(-Va * Q[0], -Va * Q[1], -Va * Q[2], 0.f);
-    } else {
-        row[ea_row] = make_float4(Vb * Q[0], Vb * Q[1], Vb * Q[2], Vb * Q[3]);
-        if (eb_row != 0xffff) row[eb_row] = make_float4(-Va * Q[0], -Va * Q[1], -Va * Q[2], -Va * Q[3]);
-    }
-}
-
-// Raw inputs of one staged record (geometry and primitive state).
-template <int DIM>
-struct RawRec {
-    float4 g0, g1, pr;
-    float2 g2;
-};
-
-template <int DIM>
-__device__ __forceinline__ void gather_rec(int32_t s, const float4* __restrict__ geo0,
-                                           const float4* __restrict__ geo1, const float2* __restrict__ geo2,
-                                           const float4* __restrict__ P, RawRec<DIM>& q) {
-    load_geo<DIM>(s, geo0, geo1, geo2, q.g0, q.g1, q.g2);
-    q.pr = P[s];
-}
-
-// Field-by-field copy of a tile header (keeps it in registers).
-__device__ __forceinline__ TileHdr load_hdr(const TileHdr* __restrict__ hdr, int32_t t) {
-    const TileHdr* p = hdr + t;
-    TileHdr h;
-    h.ob = p->ob;
-    h.oc = p->oc;
-    h.hb = p->hb;
-    h.hc = p->hc;
-    h.kb = p->kb;
-    h.tb = p->tb;
-    h.ntask = p->ntask;
-    h.rows = p->rows;
-    h.pad0 = h.pad1 = 0;
-    h.ox = p->ox;
-    h.oy = p->oy;
-    h.oz = p->oz;
-    h.ow = 0.f;
-    return h;
-}
-
-__device__ __forceinline__ int32_t rec_slot(const TileHdr& h, int32_t r, const int32_t* __restrict__ halo) {
-    return r < h.oc ? h.ob + r : halo[h.hb + (r - h.oc)];
-}
-
-// Each workgroup runs `tpw` consecutive tiles as a software pipeline: while
-// tile t is evaluated, the header and record slots of tile t + 1 are loaded
-// (during the pair phase) and its records gathered into registers (during
-// the summation phase), so the staging latency overlaps arithmetic.  RPT
-// records per thread are carried in registers; a tile with more records
-// loads the rest when it is staged.  L2 lanes per own row in the summation
-// phase: lane sub of the group sums entries e0 + sub, e0 + sub + L2, ...
-// (neighbouring lanes read neighbouring entries) and the compensated
-// partials are combined by group_sum_rt.
-template <int DIM, int STAGE, int RPT>
-__global__ void __launch_bounds__(TBLK) k_euler_tile(EulerArgs ea, const TileHdr* __restrict__ hdr, int32_t ntile,
-                                                     int32_t tpw, int32_t L2, const int32_t* __restrict__ halo,
-                                                     const uint2* __restrict__ tasks, const int64_t* __restrict__ rp_s,
-                                                     const float4* __restrict__ geo0, const float4* __restrict__ geo1,
-                                                     const float2* __restrict__ geo2, const float4* U,
-                                                     const float4* __restrict__ P, const float4* U0, float4* Uout,
-                                                     float4* Pout, const float4* __restrict__ sorted,
-                                                     float* __restrict__ drho_dt, float* __restrict__ dmom_dt,
-                                                     int32_t n) {
-    extern __shared__ float4 lds[];
-    constexpr int NQ = rec_quads<DIM>();
-    const int32_t w = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
-    const int32_t t0 = w * tpw;
-    const int32_t t1 = t0 + tpw < ntile ? t0 + tpw : ntile;
-    if (t0 >= t1) return;
-    const int32_t tid = threadIdx.x;
-    const int32_t p0 = tid / L2, sub = tid % L2;
-
-    TileHdr h = load_hdr(hdr, t0);
-    RawRec<DIM> raw[RPT];
-    {
-        const int32_t R = h.oc + h.hc;
-        int32_t sl[RPT];
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int32_t r = tid + j * TBLK;
-            sl[j] = r < R ? rec_slot(h, r, halo) : h.ob;
-        }
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) gather_rec<DIM>(sl[j], geo0, geo1, geo2, P, raw[j]);
-    }
-
-    for (int32_t t = t0; t < t1; ++t) {
-        const int32_t R = h.oc + h.hc;
-        float4* rec = lds;
-        float4* row = lds + (size_t)R * NQ;
-        const float4 org = make_float4(h.ox, h.oy, h.oz, 0.f);
-
-        // this tile's first task and first summation row, loaded before the waits
-        uint2 tk = tid < h.ntask ? tasks[h.tb + tid] : make_uint2(0u, 0u);
-        const bool has_p = p0 < h.oc;
-        const int32_t i0 = h.ob + (has_p ? p0 : 0);
-        const int64_t e0g = rp_s[i0], e1g = rp_s[i0 + 1];
-        float4 ui0 = make_float4(0.f, 0.f, 0.f, 0.f), u00 = ui0;
-        if (STAGE != 0 && sub == 0 && has_p) {
-            ui0 = U[i0];
-            if (STAGE == 2) u00 = U0[i0];
-        }
-
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-            const int32_t r = tid + j * TBLK;
-            if (r < R) stage_record<DIM>(rec + r * NQ, ea, org, raw[j].g0, raw[j].g1, raw[j].g2, raw[j].pr);
-        }
-        for (int32_t r = tid + RPT * TBLK; r < R; r += TBLK) {
-            RawRec<DIM> q;
-            gather_rec<DIM>(rec_slot(h, r, halo), geo0, geo1, geo2, P, q);
-            stage_record<DIM>(rec + r * NQ, ea, org, q.g0, q.g1, q.g2, q.pr);
-        }
-        __syncthreads();
-
-        // next tile: header and record slots (in flight during the pair phase)
-        const bool more = t + 1 < t1;
-        const TileHdr hn = load_hdr(hdr, more ? t + 1 : t);
-        int32_t sn[RPT];
-        {
-            const int32_t Rn = more ? hn.oc + hn.hc : 0;
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) {
-                const int32_t r = tid + j * TBLK;
-                sn[j] = r < Rn ? rec_slot(hn, r, halo) : hn.ob;
-            }
-        }
-
-        // unique pairs; the next task is loaded before the current one is evaluated
-        for (int32_t k = tid; k < h.ntask; k += TBLK) {
-            const uint2 cur = tk;
-            if (k + TBLK < h.ntask) tk = tasks[h.tb + k + TBLK];
-            pair_flux<DIM>(ea, rec, row, cur);
-        }
-        // next tile's records (in flight during the summation phase)
-        if (more) {
-#pragma unroll
-            for (int j = 0; j < RPT; ++j) gather_rec<DIM>(sn[j], geo0, geo1, geo2, P, raw[j]);
-        }
-        __syncthreads();
-
-        for (int32_t p = p0; p < h.oc; p += TBLK / L2) {
-            const int32_t i = h.ob + p;
-            int32_t e0, e1;
-            float4 ui = ui0, u0 = u00;
-            if (p == p0) {
-                e0 = (int32_t)(e0g - h.kb);
-                e1 = (int32_t)(e1g - h.kb);
-            } else {
-                e0 = (int32_t)(rp_s[i] - h.kb);
-                e1 = (int32_t)(rp_s[i + 1] - h.kb);
-                if (STAGE != 0 && sub == 0) {
-                    ui = U[i];
-                    if (STAGE == 2) u0 = U0[i];
-                }
-            }
-            Kahan sr, sm[DIM];
-            sr.init();
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) sm[c].init();
-            for (int32_t e = e0 + sub; e < e1; e += L2) {
-                const float4 v = row[e];
-                sr.add(v.x);
-                sm[0].add(v.y);
-                sm[1].add(v.z);
-                if (DIM == 3) sm[DIM - 1].add(v.w);
-            }
-            float Rr[4];
-            Rr[0] = group_sum_rt(sr, L2);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) Rr[1 + c] = group_sum_rt(sm[c], L2);
-            if (DIM == 2) Rr[3] = 0.f;
-            if (sub != 0) continue;
-            if (STAGE == 0) {
-                const int32_t ic = __float_as_int(sorted[i].w);
-                drho_dt[ic] = Rr[0];
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) dmom_dt[(int64_t)c * n + ic] = Rr[1 + c];
-                continue;
-            }
-            float4 un;
-            if (STAGE == 1) {
-                un = make_float4(ui.x + ea.dt * Rr[0], ui.y + ea.dt * Rr[1], ui.z + ea.dt * Rr[2],
-                                 DIM == 3 ? ui.w + ea.dt * Rr[3] : 0.f);
-            } else {
-                un = make_float4(0.5f * (u0.x + (ui.x + ea.dt * Rr[0])), 0.5f * (u0.y + (ui.y + ea.dt * Rr[1])),
-                                 0.5f * (u0.z + (ui.z + ea.dt * Rr[2])),
-                                 DIM == 3 ? 0.5f * (u0.w + (ui.w + ea.dt * Rr[3])) : 0.f);
-            }
-            Uout[i] = un;
-            Pout[i] = primitive<DIM>(un, ea.rho_ref);
-        }
-        __syncthreads();
-        h = hn;
-    }
-}
-
 EulerArgs make_args(const sph_ctx* c, const sph_euler_params* p) {
     EulerArgs a{};
     a.c = (float)p->c;
@@ -1567,80 +1101,10 @@ int lanes_per_particle(const sph_ctx* c) {
     return L;
 }
 
-// LDS budget of a tile workgroup (bytes); tuning override SPH_TILE_LDS.
-int tile_budget() {
-    const char* e = getenv("SPH_TILE_LDS");
-    int v = e ? atoi(e) : 0;
-    return v >= 4096 && v <= 160 * 1024 ? v : 64 * 1024;
-}
-
-// Whether the stage runs on cell tiles (built on first use for the bound
-// configuration); the per-particle kernel serves configurations that do not
-// admit tiles and contexts with tiling off.
-int prepare_tiles(sph_ctx* c, bool* tiled) {
-    *tiled = false;
-    int r = sph_ell_prepare(c);
-    if (r) return r;
-    if (c->tiling == SPH_TILING_OFF) return SPH_OK;
-    int rec = (c->dim == 2 ? rec_quads<2>() : rec_quads<3>()) * (int)sizeof(float4);
-    r = sph_tiles_prepare(c, rec, (int)sizeof(float4), tile_budget());
-    if (r == 1) return SPH_OK;
-    if (r) return r;
-    *tiled = true;
-    return SPH_OK;
-}
-
-template <int DIM, int STAGE, int RPT>
-void launch_tile_r(sph_ctx* c, const EulerArgs& ea, const StageIO& io, int32_t tpw, int32_t L2) {
-    const TileSet& ts = c->tiles;
-    const size_t lds = (size_t)ts.max_lds;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)k_euler_tile<DIM, STAGE, RPT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    const int32_t nwg = (ts.ntile + tpw - 1) / tpw;
-    hipLaunchKernelGGL((k_euler_tile<DIM, STAGE, RPT>), dim3(nwg), dim3(TBLK), lds, c->stream, ea,
-                       ts.hdr.as<TileHdr>(), ts.ntile, tpw, L2, ts.halo.as<int32_t>(), ts.tasks.as<uint2>(),
-                       c->rp_s.as<int64_t>(), c->geo0.as<float4>(), c->geo1.as<float4>(), c->geo2.as<float2>(), io.U,
-                       io.P, io.U0, io.Uout, io.Pout, c->sorted.as<float4>(), io.dr, io.dm, c->n);
-}
-
-// Launch shape of the tiled stage:
-//  - lanes per own row in the summation phase: as many as keep the tile's
-//    rows within one pass of the workgroup (at most 4);
-//  - tiles per workgroup: enough that every workgroup is resident at once
-//    (256 CUs, workgroups per CU bounded by LDS and by 8 waves per SIMD);
-//  - records per thread carried in registers: enough for the largest tile
-//    (at most 3; the rest is loaded when staged).
-template <int DIM, int STAGE>
-void launch_tile(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
-    const TileSet& ts = c->tiles;
-    int L2 = 1;
-    while (L2 < 4 && (int64_t)ts.max_own * (L2 * 2) <= TBLK) L2 <<= 1;
-    int per_cu = ts.max_lds > 0 ? (160 * 1024) / ts.max_lds : 8;
-    per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
-    int32_t tpw = (int32_t)((ts.ntile + 256LL * per_cu - 1) / (256LL * per_cu));
-    if (const char* e = getenv("SPH_TILE_TPW")) {
-        int v = atoi(e);
-        if (v >= 1 && v <= 4096) tpw = v;
-    }
-    if (tpw < 1) tpw = 1;
-    int rpt = (int)((ts.max_rec + TBLK - 1) / TBLK);
-    if (rpt <= 1) launch_tile_r<DIM, STAGE, 1>(c, ea, io, tpw, L2);
-    else if (rpt == 2) launch_tile_r<DIM, STAGE, 2>(c, ea, io, tpw, L2);
-    else launch_tile_r<DIM, STAGE, 3>(c, ea, io, tpw, L2);
-}
-
 // One stage of the solver SOL (the compressible rows run on the per-particle
 // kernel in 2-D only; the caller has checked).
 template <int SOL, int STAGE>
-void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io, bool tiled) {
-    if constexpr (SOL == SOL_LINEARISED) {
-        if (tiled) {
-            if (c->dim == 2) launch_tile<2, STAGE>(c, ea, io);
-            else launch_tile<3, STAGE>(c, ea, io);
-            return;
-        }
-    }
+void launch(sph_ctx* c, const EulerArgs& ea, const StageIO& io) {
     if (int bl = batch_lanes(c)) {
         bool done;
         if constexpr (SOL == SOL_LINEARISED)
@@ -1736,69 +1200,6 @@ int lanes3(const sph_ctx* c) {
 }
 
 
-// Pairs per chunk of the window kernels: the M in {6, 8, 10, 12} whose
-// chunks cover mu entries with the fewest padding pairs (the larger on a
-// tie).
-int window_chunk(int mu) {
-    const int cand[4] = {12, 10, 8, 6};
-    int best = 12, cost = 1 << 30;
-    for (int M : cand) {
-        const int k = (mu + M - 1) / M * M;
-        if (k < cost) cost = k, best = M;
-    }
-    return best;
-}
-
-// Build (or reuse) the neighbour windows for workgroups of NT threads with L
-// lanes per particle (blocks of P = NT / L slots) over the fixed-stride rows
-// (k_window, two passes with a scan of the window lengths in between).
-// Leaves c->win3.state = 1 when the records kernel can read its neighbours
-// from LDS, else -1: rows not fixed-stride, a window longer than
-// WIN_HC_MAX, or the tuning override SPH_EULER_WINDOW=0.
-int window_prepare(sph_ctx* c, int L, int NT) {
-    auto& w = c->win3;
-    const int P = NT / L;
-    if (w.state != 0 && w.P == P && w.L == L) return SPH_OK;
-    w.state = -1;
-    w.P = P;
-    w.L = L;
-    const char* e = getenv("SPH_EULER_WINDOW");
-    if (e && strcmp(e, "0") == 0) return SPH_OK;
-    const int32_t n = c->n, S = c->ell_S;
-    if (c->ell_state != 1 || n <= 0 || S <= 0) return SPH_OK;
-    const int mu = (S + L - 1) / L;
-    const int M = window_chunk(mu);
-    const int32_t Sp = (mu + M - 1) / M * M * L;
-    if ((double)Sp * n >= 1073741824.0) return SPH_OK;  // 32-bit entry offsets
-    const int32_t nb = (n + P - 1) / P;
-    SPH_HIP(c, w.len.ensure((size_t)nb * sizeof(int32_t)));
-    SPH_HIP(c, w.off.ensure(((size_t)nb + 1) * sizeof(int32_t)));
-    SPH_HIP(c, c->counter.ensure(64));
-    SPH_HIP(c, hipMemsetAsync(c->counter.p, 0, 4, c->stream));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P, L, M,
-                       c->colE.as<int32_t>(), w.len.as<int32_t>(), c->counter.as<int32_t>(), nullptr, nullptr,
-                       nullptr);
-    SPH_LAUNCH_CHECK(c);
-    int r = sph_scan_i32_to_i32(c, w.len.as<int32_t>(), w.off.as<int32_t>(), nb);
-    if (r) return r;
-    int32_t host[2] = {0, 0};
-    SPH_HIP(c, hipMemcpyAsync(&host[0], c->counter.p, 4, hipMemcpyDeviceToHost, c->stream));
-    SPH_HIP(c, hipMemcpyAsync(&host[1], w.off.as<int32_t>() + nb, 4, hipMemcpyDeviceToHost, c->stream));
-    SPH_HIP(c, hipStreamSynchronize(c->stream));
-    if (host[0] > WIN_HC_MAX) return SPH_OK;
-    SPH_HIP(c, w.list.ensure((size_t)host[1] * sizeof(int32_t)));
-    SPH_HIP(c, w.col.ensure((size_t)Sp * n * sizeof(uint16_t)));
-    hipLaunchKernelGGL(k_window, dim3((unsigned)nb), dim3(BLK), 0, c->stream, n, S, Sp, P, L, M,
-                       c->colE.as<int32_t>(), nullptr, nullptr, w.off.as<int32_t>(), w.list.as<int32_t>(),
-                       w.col.as<uint16_t>());
-    SPH_LAUNCH_CHECK(c);
-    w.max = host[0];
-    w.M = M;
-    w.Sp = Sp;
-    w.state = 1;
-    return SPH_OK;
-}
-
 template <int STAGE, int M, int HC, int NT>
 void launch3w_h(sph_ctx* c, const EulerArgs& ea, const Stage3& io) {
     const auto& w = c->win3;
@@ -1849,7 +1250,9 @@ int window_threads() {
 int prepare_windows(sph_ctx* c, bool* use) {
     *use = false;
     if (c->ell_state != 1 || lanes3(c) != 4) return SPH_OK;
-    const int r = window_prepare(c, 4, window_threads());
+    if (const char* e = getenv("SPH_EULER_WINDOW"))
+        if (strcmp(e, "0") == 0) return SPH_OK;
+    const int r = sph_windows_prepare(c, c->win3, 4, window_threads() / 4);
     if (r) return r;
     *use = c->win3.state == 1;
     return SPH_OK;
@@ -1946,11 +1349,10 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     if (!drho || !mom || !drho_dt || !dmom_dt) return sph_fail(c, SPH_ERR_ARG, "sph_euler_rhs: NULL array");
     SPH_HIP(c, c->ua.ensure((size_t)c->n * sizeof(float4)));
     SPH_HIP(c, c->ta.ensure((size_t)c->n * sizeof(float4)));
-    bool tiled = false;
-    r = prepare_tiles(c, &tiled);
+    r = sph_ell_prepare(c);
     if (r) return r;
     EulerArgs ea = make_args(c, p);
-    if (!tiled && use_rec3(c)) {
+    if (use_rec3(c)) {
         bool windows = false;
         r = prepare_windows(c, &windows);
         if (r) return r;
@@ -1965,9 +1367,9 @@ int sph_euler_rhs(sph_ctx* c, const sph_euler_params* p, const float* drho, cons
     r = pack(c, ea.rho_ref, drho, mom, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt};
-    launch<SOL_LINEARISED, 0>(c, ea, io, tiled);
+    launch<SOL_LINEARISED, 0>(c, ea, io);
     SPH_LAUNCH_CHECK(c);
-    c->euler_path = tiled ? SPH_PATH_TILED : SPH_PATH_GENERIC;
+    c->euler_path = SPH_PATH_GENERIC;
     return SPH_OK;
 }
 
@@ -1987,11 +1389,10 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
     float4* Us = c->ub.as<float4>();
     float4* P = c->ta.as<float4>();
     float4* Ps = c->tb.as<float4>();
-    bool tiled = false;
-    r = prepare_tiles(c, &tiled);
+    r = sph_ell_prepare(c);
     if (r) return r;
     EulerArgs ea = make_args(c, p);
-    if (!tiled && use_rec3(c)) {
+    if (use_rec3(c)) {
         bool windows = false;
         r = prepare_windows(c, &windows);
         if (r) return r;
@@ -2014,10 +1415,10 @@ int sph_euler_step(sph_ctx* c, const sph_euler_params* p, float* drho, float* mo
         StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr};
         StageIO s2{Us, Ps, U, U, P, nullptr, nullptr};
         for (int32_t s = 0; s < nsteps; ++s) {
-            launch<SOL_LINEARISED, 1>(c, ea, s1, tiled);
-            launch<SOL_LINEARISED, 2>(c, ea, s2, tiled);
+            launch<SOL_LINEARISED, 1>(c, ea, s1);
+            launch<SOL_LINEARISED, 2>(c, ea, s2);
         }
-        c->euler_path = tiled ? SPH_PATH_TILED : SPH_PATH_GENERIC;
+        c->euler_path = SPH_PATH_GENERIC;
     }
     SPH_LAUNCH_CHECK(c);
     if (c->dim == 2)
@@ -2046,7 +1447,7 @@ int sph_hllc_rhs(sph_ctx* c, const sph_hllc_params* p, const float* rho, const f
     r = pack_hllc(c, ea.gm1, rho, mom, E, c->ua.as<float4>(), c->ta.as<float4>());
     if (r) return r;
     StageIO io{c->ua.as<float4>(), c->ta.as<float4>(), nullptr, nullptr, nullptr, drho_dt, dmom_dt, dE_dt};
-    launch<SOL_HLLC, 0>(c, ea, io, false);
+    launch<SOL_HLLC, 0>(c, ea, io);
     SPH_LAUNCH_CHECK(c);
     c->euler_path = SPH_PATH_GENERIC;
     return SPH_OK;
@@ -2077,8 +1478,8 @@ int sph_hllc_step(sph_ctx* c, const sph_hllc_params* p, float* rho, float* mom, 
     StageIO s1{U, P, nullptr, Us, Ps, nullptr, nullptr, nullptr};
     StageIO s2{Us, Ps, U, U, P, nullptr, nullptr, nullptr};
     for (int32_t s = 0; s < nsteps; ++s) {
-        launch<SOL_HLLC, 1>(c, ea, s1, false);
-        launch<SOL_HLLC, 2>(c, ea, s2, false);
+        launch<SOL_HLLC, 1>(c, ea, s1);
+        launch<SOL_HLLC, 2>(c, ea, s2);
     }
     SPH_LAUNCH_CHECK(c);
     c->euler_path = SPH_PATH_GENERIC;

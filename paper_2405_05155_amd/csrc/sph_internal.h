@@ -102,44 +102,27 @@ __device__ __forceinline__ int32_t xcd_block(int32_t b, int32_t nb) {
     return x * per + (x < rem ? x : rem) + k;
 }
 
-// Cell tiles for the LDS-staged pair loops over a fixed configuration.  A
-// tile is an aligned block of 2^bits consecutive Morton cell keys, i.e. a
-// box of cells; its own particles are one contiguous range of sorted slots
-// and its halo is every particle of the one-cell ring around the box,
-// ascending by slot.  Record q of a tile is own particle q for q < own
-// count, else halo entry q - own count.  A task is one unique neighbour pair
-// of the tile's own rows: (own p, record q, row entry of (p, q), row entry
-// of (q, p) or 0xffff when q is a halo record); pairs of two own particles
-// appear once, with p < q.  Row entries are numbered from the first row
-// entry of the tile (the sorted CSR).
-// Everything a tile's workgroup needs before its first gather (one 64-byte
-// record): own slots [ob, ob + oc), halo entries [hb, hb + hc), first row
-// entry kb and row-entry count, first task tb and task count, and the
-// position of the first own particle (the origin of relative positions).
-struct TileHdr {
-    int32_t ob, oc, hb, hc;
-    int64_t kb, tb;
-    int32_t ntask, rows, pad0, pad1;
-    float ox, oy, oz, ow;  // origin (x, y, z), 0
-};
-static_assert(sizeof(TileHdr) == 64, "TileHdr is one 64-byte record");
+// Longest window the pair kernels' LDS planes hold.
+constexpr int WIN_HC_MAX = 1024;
 
-struct TileSet {
-    bool valid = false;
-    bool failed = false;     // no tile size fitted (for the request below)
-    int bits = 0;
-    int rec_bytes = 0, row_bytes = 0;  // LDS bytes per record / per row entry
-    int budget = 0;                    // LDS budget of the last request
-    int32_t ntile = 0;
-    int32_t max_lds = 0;     // max LDS bytes of a tile
-    int64_t ntask = 0;
-    DevBuf info;       // int4 [ntile]: own begin (slot), own count, halo begin, halo count
-    DevBuf hdr;        // TileHdr [ntile]
-    int32_t max_own = 0;  // max own particles of a tile
-    int32_t max_rec = 0;  // max own + halo records of a tile
-    DevBuf task_ptr;   // int64 [n + 1]: first task of each sorted slot's row
-    DevBuf halo;       // int32 [sum of halo counts]
-    DevBuf tasks;      // uint2 [ntask]: (p | q << 16, row entry of p | row entry of q << 16)
+// Neighbour windows of blocks of P consecutive cell-sorted slots over the
+// fixed-stride rows: per block its own slots, in order, then the distinct
+// other slots its rows reference, ascending (`list`, offsets `off`), and the
+// rows as 16-bit LDS byte offsets (16 x window position), padded with the
+// slot itself to whole chunks of M entries for each of the L lanes of a slot:
+// entry s + L (c M + t) of slot i (lane s, chunk c, t < M) at
+// col[((c n + i) L + s) M + t].
+struct NeighbourWindows {
+    int state = 0;        // 0: not built, 1: valid, -1: not used for this configuration
+    int P = 0;            // slots per block
+    int L = 0;            // lanes per slot
+    int M = 0;            // entries per chunk
+    int32_t Sp = 0;       // row entries after padding
+    int32_t max = 0;      // longest window
+    DevBuf len;           // int32 [nblocks]
+    DevBuf off;           // int32 [nblocks + 1]
+    DevBuf list;          // int32 [off[nblocks]]
+    DevBuf col;           // uint16 [Sp n]
 };
 
 struct sph_ctx {
@@ -198,8 +181,6 @@ struct sph_ctx {
 
     int num_cu = 0;     // compute units of the device (filled on first use)
 
-    TileSet tiles;
-    int tiling = SPH_TILING_OFF;
     int euler_path = SPH_PATH_NONE;  // variant the last Eulerian call ran
 
     // fixed-stride neighbour rows over cell-sorted slots (ELLPACK): entry k
@@ -210,37 +191,25 @@ struct sph_ctx {
     int32_t ell_S = 0;
     int ell_state = 0;  // 0: not built, 1: valid, -1: rows too uneven (CSR is used)
 
-    // neighbour windows of the 3-D records kernel over the fixed-stride
-    // rows: per block of P consecutive slots, its own slots then the
-    // distinct other slots its rows reference (ascending), and the rows as
-    // 16-bit positions in that list
-    struct Windows {
-        int state = 0;        // 0: not built, 1: valid, -1: not used for this configuration
-        int P = 0;            // slots per block
-        int L = 0;            // lanes per particle
-        int M = 0;            // pairs per chunk
-        int32_t Sp = 0;       // row entries, padded with the slot itself to a whole number of chunks per lane
-        int32_t max = 0;      // longest window
-        DevBuf len;           // int32 [nblocks]
-        DevBuf off;           // int32 [nblocks + 1]
-        DevBuf list;          // int32 [off[nblocks]]
-        DevBuf col;           // uint16 [Sp * n]: 16 x window position; entry s + L (c M + t) of slot i at ((c n + i) L + s) M + t
-    } win3;
+    // neighbour windows over the fixed-stride rows (sph_windows_prepare):
+    // the 3-D Eulerian stage's and the total-Lagrangian kernels'
+    NeighbourWindows win3, wtl;
 };
 
 // Build (or reuse) the fixed-stride neighbour rows of the bound
 // configuration.  Sets c->ell_state; returns an error code only on failure.
 int sph_ell_prepare(sph_ctx* c);
 
-// Build (or reuse) the cell tiles of the bound configuration for a pair
-// loop whose tile needs rec_bytes of LDS per record and row_bytes per own
-// row entry, within lds_budget bytes per workgroup.  Returns SPH_OK with
-// c->tiles valid, 1 when the configuration does not admit tiles (linear
-// cell keys, a periodic axis too short for the tile and its ring, or no
-// tile size fits the budget), or an error code.
-int sph_tiles_prepare(sph_ctx* c, int rec_bytes, int row_bytes, int lds_budget);
 
 int sph_fail(sph_ctx* c, int code, const char* fmt, ...);
+
+// Build (or reuse) the windows w of blocks of P slots with L lanes per slot
+// over the bound configuration's fixed-stride rows (two passes of one
+// workgroup per block: an LDS hash set of the distinct neighbours, then
+// their sorted list and the rewritten rows).  Sets w.state to 1, or to -1
+// when the rows are not fixed-stride or a window would exceed WIN_HC_MAX
+// records; returns an error code only on failure.
+int sph_windows_prepare(sph_ctx* c, NeighbourWindows& w, int L, int P);
 
 // Take the device address of sph_mlp_train_step_noalloc's fixed workspace on
 // `device` (the current device), once per device.

@@ -316,10 +316,9 @@ int sph_bin_cells_grid(sph_ctx* c, const sph_domain* dom, int32_t n, const float
     c->bound = false;
     c->geo_valid = false;
     ++c->geo_gen;
-    c->tiles.valid = false;
-    c->tiles.failed = false;
     c->ell_state = 0;
     c->win3.state = 0;
+    c->wtl.state = 0;
     c->export_valid = false;
     if (!dom) return sph_fail(c, SPH_ERR_ARG, "sph_build_cells: dom is NULL");
     if (dom->dim != c->dim)

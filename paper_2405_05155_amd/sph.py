@@ -20,8 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 
 SPH_OK, SPH_ERR_ARG, SPH_ERR_CAPACITY, SPH_ERR_HIP, SPH_ERR_STATE = 0, -1, -2, -3, -5
 WENDLAND, LAGUERRE_GAUSS = 0, 1
-TILING_OFF, TILING_ON = 0, 1
-PATH_NONE, PATH_GENERIC, PATH_TILED, PATH_RECORDS, PATH_WINDOWS = 0, 1, 2, 3, 4
+PATH_NONE, PATH_GENERIC, PATH_RECORDS, PATH_WINDOWS = 0, 1, 2, 3
 
 
 class SphError(RuntimeError):
@@ -63,7 +62,6 @@ _SIGS = [
     ("sph_ctx_destroy", None, [_vp]),
     ("sph_last_error", C.c_char_p, [_vp]),
     ("sph_set_stream", C.c_int, [_vp, _vp]),
-    ("sph_set_tiling", C.c_int, [_vp, C.c_int]),
     ("sph_euler_path", C.c_int, [_vp]),
     ("sph_build_cells", C.c_int, [_vp, C.POINTER(sph_domain), _i32, _vp]),
     ("sph_neighbors", C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(C.c_int64)]),
@@ -234,13 +232,8 @@ class Context:
     def _dev(self):
         return torch.device("cuda", torch.cuda.current_device())
 
-    def set_tiling(self, mode: int):
-        """TILING_OFF: per-particle pair loops (default); TILING_ON: LDS cell tiles where admitted."""
-        self._check(lib().sph_set_tiling(self._h, int(mode)))
-
     def euler_path(self) -> int:
-        """Pair-loop variant of the last Eulerian call (PATH_NONE, PATH_GENERIC, PATH_TILED, PATH_RECORDS,
-        PATH_WINDOWS)."""
+        """Pair-loop variant of the last Eulerian call (PATH_NONE, PATH_GENERIC, PATH_RECORDS, PATH_WINDOWS)."""
         return int(lib().sph_euler_path(self._h))
 
     # ------------------------------------------------------------ neighbours
@@ -431,10 +424,6 @@ class Context:
 
 # Module-level functions named as the C calls (same argument order, with the
 # Context in place of the sph_ctx pointer).
-def sph_set_tiling(ctx: Context, mode):
-    return ctx.set_tiling(mode)
-
-
 def sph_euler_path(ctx: Context):
     return ctx.euler_path()
 

@@ -45,8 +45,6 @@ def test_empty_configuration_every_call(S, dim):
     dr, dm = ctx.euler_rhs(prm, vol, vec)
     assert dr.numel() == 0 and dm.numel() == 0
     ctx.euler_step(prm, vol, vec, 3)
-    ctx.set_tiling(S.TILING_ON)
-    ctx.euler_step(prm, vol, vec, 3)
     if dim == 2:
         hp = S.hllc_params(1.4, 1.0, 1e-4)
         dr, dm, de = ctx.hllc_rhs(hp, vol, vec, vol)

@@ -58,21 +58,17 @@ def _random_states(n, seed):
     return rho.astype(np.float32), (rho * v).astype(np.float32), E.astype(np.float32)
 
 
-@pytest.mark.parametrize("rows", ["auto", "batch2", "batch4", "batch8", "ell", "csr", "tiling_on"])
+@pytest.mark.parametrize("rows", ["auto", "batch2", "batch4", "batch8", "ell", "csr"])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 def test_hllc_rhs_matches_oracle(S, kappa, rows, monkeypatch):
-    """tiling_on: the context's tiling mode set, which the compressible rows
-    ignore (they run the per-particle kernel)."""
     env = {"auto": {}, "batch2": {"SPH_EULER_BATCH_LANES": "2"}, "batch4": {"SPH_EULER_BATCH_LANES": "4"},
            "batch8": {"SPH_EULER_BATCH_LANES": "8"}, "ell": {"SPH_EULER_BATCH_LANES": "0"},
-           "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_PAIR_ROWS": "csr"}, "tiling_on": {}}[rows]
+           "csr": {"SPH_EULER_BATCH_LANES": "0", "SPH_PAIR_ROWS": "csr"}}[rows]
     for k, v in env.items():
         monkeypatch.setenv(k, v)
     w = I.periodic_square_case(64, 2, 1.3, 0.05, 3, "jittered")
     rho, mom, E = _random_states(w.n, 7)
     ctx = _ctx(S, w, kappa)
-    if rows == "tiling_on":
-        ctx.set_tiling(1)
     prm = S.hllc_params(GAMMA, 1.0)
     dr, dm, de = ctx.hllc_rhs(prm, dev(rho), dev(mom), dev(E))
     box, rp, col, B = _oracle_geometry(w, kappa)

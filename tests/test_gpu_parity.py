@@ -238,12 +238,10 @@ def _euler_prm(S, w, dt=0.0):
 @pytest.mark.parametrize("seed", [0, 1])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
 @pytest.mark.parametrize("mu", [0.0, 0.01])
-@pytest.mark.parametrize("tiling", [0, 1])
-def test_euler_rhs_single_step(S, seed, kappa, mu, tiling):
+def test_euler_rhs_single_step(S, seed, kappa, mu):
     w = I.single_step_2d(seed=seed)
     w.fields["mu"] = mu
     ctx = gpu_ctx(S, w, kappa)
-    ctx.set_tiling(tiling)
     ctx.correction_B(dev(w.vol))
     pg, po = _euler_prm(S, w)
     dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
@@ -255,11 +253,9 @@ def test_euler_rhs_single_step(S, seed, kappa, mu, tiling):
 
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-@pytest.mark.parametrize("tiling", [0, 1])
-def test_euler_heun_steps_taylor_green(S, kappa, tiling):
+def test_euler_heun_steps_taylor_green(S, kappa):
     w = I.taylor_green_2d(nside=64, nu=0.01)
     ctx = gpu_ctx(S, w, kappa)
-    ctx.set_tiling(tiling)
     ctx.correction_B(dev(w.vol))
     dt = w.meta["dt"]
     pg, po = _euler_prm(S, w, dt)
@@ -485,14 +481,13 @@ def test_euler_3d_lanes_and_chunks(S, kappa, lanes, monkeypatch):
 
 @pytest.mark.parametrize("case", ["mixed3d", "tiny2d"])
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
-@pytest.mark.parametrize("tiling", [0, 1])
-def test_euler_rhs_tile_geometries(S, case, kappa, tiling):
-    """Tile edge cases against the oracle: a 3-D box with an open axis
-    (rings clipped at the free surfaces, ragged tiles) and a periodic box
-    too small for tiles (the per-particle kernel runs under either mode)."""
+def test_euler_rhs_box_geometries(S, case, kappa):
+    """Box edge cases against the oracle: a 3-D box with an open axis
+    (neighbourhoods clipped at the free surfaces; windows of uneven length)
+    and a small periodic 2-D box (16^2 particles, six cells per axis at
+    2h)."""
     w = _mixed_box_3d() if case == "mixed3d" else I.taylor_green_2d(nside=16)
     ctx = gpu_ctx(S, w, kappa)
-    ctx.set_tiling(tiling)
     ctx.correction_B(dev(w.vol))
     pg, po = _euler_prm(S, w)
     dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
