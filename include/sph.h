@@ -91,6 +91,14 @@ int sph_set_stream(sph_ctx* ctx, void* hip_stream);
  * Returns -1 for a NULL context. */
 enum { SPH_PATH_NONE = 0, SPH_PATH_GENERIC = 1, SPH_PATH_RECORDS = 2, SPH_PATH_WINDOWS = 3 };
 int sph_euler_path(const sph_ctx* ctx);
+/* Which variant of the stress-divergence loop (Eq. 31) the context's last
+ * sph_tlsph_rhs or sph_tlsph_step call ran: SPH_PATH_GENERIC (neighbour
+ * records gathered through the caches) or SPH_PATH_WINDOWS (read from an LDS
+ * window of the workgroup's neighbourhood; fixed-stride rows with four lanes
+ * per particle whose windows fit).  Results agree to rounding (the sums take
+ * the same pairs in the same order, plus zero-separation padding pairs).
+ * SPH_PATH_NONE before such a call.  Returns -1 for a NULL context. */
+int sph_tlsph_path(const sph_ctx* ctx);
 
 /* ---------------------------------------------------------------- neighbours
  * sph_build_cells: bind a particle configuration.  Bins the n positions

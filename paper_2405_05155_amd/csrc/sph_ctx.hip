@@ -126,6 +126,8 @@ int sph_set_stream(sph_ctx* c, void* s) {
 
 int sph_euler_path(const sph_ctx* c) { return c ? c->euler_path : -1; }
 
+int sph_tlsph_path(const sph_ctx* c) { return c ? c->tlsph_path : -1; }
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ scans

@@ -781,27 +781,6 @@ __device__ __forceinline__ void wread_b(const float4* W, uint32_t b, Rec3& r) {
     r.q3 = *reinterpret_cast<const float4*>(w + 48 * HC);
 }
 
-// A lane's M entries of one chunk (M / 2 words of two 16-bit entries each,
-// starting at word `at`), in as few loads as their alignment allows.
-template <int M>
-__device__ __forceinline__ void load_chunk(const uint16_t* __restrict__ colw, uint32_t at, uint32_t (&w)[M / 2]) {
-    const uint32_t* p = reinterpret_cast<const uint32_t*>(colw);
-    if constexpr (M == 8) {
-        const uint4 v = ld32(reinterpret_cast<const uint4*>(p), at >> 2);
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-    } else if constexpr (M == 12) {
-#pragma unroll
-        for (int h = 0; h < 3; ++h) {
-            const uint2 v = ld32(reinterpret_cast<const uint2*>(p), (at >> 1) + (uint32_t)h);
-            w[2 * h] = v.x;
-            w[2 * h + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int h = 0; h < M / 2; ++h) w[h] = ld32(p, at + (uint32_t)h);
-    }
-}
-
 // row3 over the window: the lane's entries are the byte offsets (16 times
 // the window position) of its neighbours' records, the records come from
 // LDS (the pair order, and so every sum, is that of row3).  The lane's

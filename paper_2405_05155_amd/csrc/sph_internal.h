@@ -182,6 +182,7 @@ struct sph_ctx {
     int num_cu = 0;     // compute units of the device (filled on first use)
 
     int euler_path = SPH_PATH_NONE;  // variant the last Eulerian call ran
+    int tlsph_path = SPH_PATH_NONE;  // variant of kernel B in the last total-Lagrangian call
 
     // fixed-stride neighbour rows over cell-sorted slots (ELLPACK): entry k
     // of slot i at colE[k * n + i] for k < ell_S, rows shorter than ell_S
@@ -367,6 +368,27 @@ BoxArgs make_box_args(const sph_domain& d, double rc, int div = 1, bool linear =
 int64_t cell_slots(const BoxArgs& b);  // size of the cell-key space
 
 // ------------------------------------------------------------------ pair-loop helpers
+
+// A lane's M entries of one chunk (M / 2 words of two 16-bit entries each,
+// starting at word `at`), in as few loads as their alignment allows.
+template <int M>
+__device__ __forceinline__ void load_chunk(const uint16_t* __restrict__ colw, uint32_t at, uint32_t (&w)[M / 2]) {
+    const uint32_t* p = reinterpret_cast<const uint32_t*>(colw);
+    if constexpr (M == 8) {
+        const uint4 v = ld32(reinterpret_cast<const uint4*>(p), at >> 2);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (M == 12) {
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+            const uint2 v = ld32(reinterpret_cast<const uint2*>(p), (at >> 1) + (uint32_t)h);
+            w[2 * h] = v.x;
+            w[2 * h + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < M / 2; ++h) w[h] = ld32(p, at + (uint32_t)h);
+    }
+}
 
 // Periodic geometry for the pair loops: wrap d - L rint(d / L) on periodic
 // axes (invL = 0 elsewhere), needed only by waves holding a particle within

@@ -15,6 +15,7 @@
 #include "sph_internal.h"
 
 #include <cstdlib>
+#include <cstring>
 
 namespace {
 
@@ -300,6 +301,112 @@ __global__ void __launch_bounds__(BLK) k_tl_b(int32_t n, TlArgs t, Wrap w, const
     }
 }
 
+// Kernel B over neighbour windows (fixed-stride rows, four lanes per
+// particle): workgroup blk of NT threads takes block blk of P = NT / 4 slots
+// and first copies the records of its window (X_j and V_j, A_j) into LDS
+// planes; the pairs read them there through 16-bit byte offsets, a lane's
+// chunk of M entries in one load.  The rows are padded with the slot itself
+// (zero separation: the pair adds nothing).  Same arithmetic as k_tl_b.
+template <int HC, int NT>
+constexpr int tl_window_waves() {  // waves per SIMD the LDS allows, at most 6 (80 VGPRs)
+    constexpr int w = 163840 / (52 * HC) * (NT / 64) / 4;
+    return w < 6 ? w : 6;
+}
+
+__device__ __forceinline__ void tl_wread(const char* W, uint32_t b, int HC4, ARec& r) {
+    r.g = *reinterpret_cast<const float4*>(W + b);
+    r.a0 = *reinterpret_cast<const float4*>(W + HC4 + b);
+    r.a1 = *reinterpret_cast<const float4*>(W + 2 * HC4 + b);
+    r.a2 = *reinterpret_cast<const float*>(W + 3 * HC4 + (b >> 2));
+}
+
+// b, made to depend on the pair sum just updated (an empty asm statement
+// emits no instruction), so the next record's LDS reads stay after the pair
+// that frees its registers.
+__device__ __forceinline__ uint32_t tl_after(uint32_t b, const Kahan& k) {
+    asm volatile("" : "+v"(b) : "v"(k.s));
+    return b;
+}
+
+// The lane's chunks of window entries of one row (records from LDS, two in
+// flight), in the order k_tl_b takes them.
+template <bool WRAP, int M>
+__device__ __forceinline__ void tl_row_w(const TlArgs& t, const Wrap& w, const char* W, int HC4,
+                                         const uint16_t* __restrict__ colw, uint32_t at0, uint32_t cs, int32_t nchunk,
+                                         const float4& gi, const float* Ai, Kahan* s) {
+    for (int32_t c = 0; c < nchunk; ++c) {
+        uint32_t e[M / 2];
+        load_chunk<M>(colw, at0 + (uint32_t)c * cs, e);
+        ARec A, B;
+        tl_wread(W, e[0] & 0xffffu, HC4, A);
+        tl_wread(W, e[0] >> 16, HC4, B);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < M; q += 2) {
+            acc_b<WRAP>(t, w, gi, Ai, A, s);
+            if (q + 2 < M) tl_wread(W, tl_after(e[q / 2 + 1] & 0xffffu, s[0]), HC4, A);
+            __builtin_amdgcn_sched_barrier(0);
+            acc_b<WRAP>(t, w, gi, Ai, B, s);
+            if (q + 3 < M) tl_wread(W, tl_after(e[q / 2 + 1] >> 16, s[0]), HC4, B);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int MODE, int M, int HC, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tl_window_waves<HC, NT>())))
+k_tl_bw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t Sp,
+        const int32_t* __restrict__ woff, const int32_t* __restrict__ wlist, const float4* __restrict__ geo0,
+        const float4* __restrict__ A0, const float4* __restrict__ A1, const float* __restrict__ A2,
+        const float4* __restrict__ sorted, float4* __restrict__ VH, float4* __restrict__ ACC,
+        float* __restrict__ acc) {
+    constexpr int L = 4;
+    constexpr int HC4 = 16 * HC;  // bytes of a float4 plane
+    __shared__ __attribute__((aligned(16))) char W[3 * HC4 + 4 * HC];
+    const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
+    for (int32_t k = (int32_t)threadIdx.x; k < wn; k += NT) {
+        const uint32_t j = (uint32_t)wlist[w0 + k];
+        *reinterpret_cast<float4*>(W + 16 * k) = ld32(geo0, j);
+        *reinterpret_cast<float4*>(W + HC4 + 16 * k) = ld32(A0, j);
+        *reinterpret_cast<float4*>(W + 2 * HC4 + 16 * k) = ld32(A1, j);
+        *reinterpret_cast<float*>(W + 3 * HC4 + 4 * k) = ld32(A2, j);
+    }
+    const int sub = (int)(threadIdx.x % L);
+    const int32_t ig = blk * (NT / L) + (int32_t)(threadIdx.x / L);
+    const bool valid = ig < n;
+    const int32_t i = valid ? ig : n - 1;
+    const uint32_t self = 16u * (uint32_t)(i - blk * (NT / L));
+    const uint32_t at0 = ((uint32_t)i * L + (uint32_t)sub) * (uint32_t)(M / 2);
+    const uint32_t cs = (uint32_t)n * L * (uint32_t)(M / 2);
+    const int32_t nchunk = Sp / (L * M);
+    const float4 vh = VH[i];
+    __syncthreads();
+    ARec own;
+    tl_wread(W, self, HC4, own);
+    const float4 gi = own.g;
+    const float Ai[9] = {own.a0.x, own.a0.y, own.a0.z, own.a0.w, own.a1.x, own.a1.y, own.a1.z, own.a1.w, own.a2};
+    const bool wrap = wave_needs_wrap(w, gi);
+    Kahan s[3];
+    s[0].init(); s[1].init(); s[2].init();
+    if (wrap) tl_row_w<true, M>(t, w, W, HC4, colw, at0, cs, nchunk, gi, Ai, s);
+    else tl_row_w<false, M>(t, w, W, HC4, colw, at0, cs, nchunk, gi, Ai, s);
+    const float fa = t.cF * t.inv_rho0;
+    float a[3] = {group_sum<L>(s[0]) * fa, group_sum<L>(s[1]) * fa, group_sum<L>(s[2]) * fa};
+    if (sub != 0 || !valid) return;
+    const bool fixed = vh.w != 0.f;
+    if (fixed) a[0] = a[1] = a[2] = 0.f;
+    if (MODE == 0) {
+        const int32_t ic = __float_as_int(sorted[i].w);
+        acc[ic] = a[0];
+        acc[(int64_t)n + ic] = a[1];
+        acc[2 * (int64_t)n + ic] = a[2];
+    } else {
+        ACC[i] = make_float4(a[0], a[1], a[2], 0.f);
+        if (!fixed) VH[i] = make_float4(vh.x + t.dt * a[0], vh.y + t.dt * a[1], vh.z + t.dt * a[2], 0.f);
+    }
+}
+
 // F (caller [n][9]) and positions (caller SoA, optional) into sorted order, and back.
 __global__ void k_tl_pack(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ F,
                           const float* __restrict__ pos, float4* __restrict__ F0, float4* __restrict__ F1,
@@ -392,20 +499,6 @@ int check(sph_ctx* c, const sph_tlsph_params* p, const char* who) {
     return SPH_OK;
 }
 
-int ensure_scratch(sph_ctx* c) {
-    size_t n = (size_t)(c->n > 0 ? c->n : 1);
-    SPH_HIP(c, c->ua.ensure(n * sizeof(float4)));   // VH
-    SPH_HIP(c, c->ub.ensure(n * sizeof(float4)));   // ACC
-    SPH_HIP(c, c->ta.ensure(n * sizeof(float4)));   // A0
-    SPH_HIP(c, c->tb.ensure(n * sizeof(float4)));   // A1
-    SPH_HIP(c, c->tc.ensure(n * sizeof(float)));    // A2
-    SPH_HIP(c, c->fa.ensure(n * sizeof(float4)));   // F0
-    SPH_HIP(c, c->fb.ensure(n * sizeof(float4)));   // F1
-    SPH_HIP(c, c->fc.ensure(n * sizeof(float)));    // F2
-    SPH_HIP(c, c->pa.ensure(n * sizeof(float4)));   // current positions
-    return sph_ell_prepare(c);
-}
-
 // Lanes per particle of the total-Lagrangian pair loops: the most (up to
 // 4) that leave each lane at least three row entries (measured on the
 // cantilever plate, rows of 26 and 56 entries).  Tuning override
@@ -419,6 +512,30 @@ int tl_lanes(const sph_ctx* c) {
     int L = 1;
     while (L < 4 && avg / (2 * L) >= 3.0) L <<= 1;
     return L;
+}
+
+int ensure_scratch(sph_ctx* c) {
+    size_t n = (size_t)(c->n > 0 ? c->n : 1);
+    SPH_HIP(c, c->ua.ensure(n * sizeof(float4)));   // VH
+    SPH_HIP(c, c->ub.ensure(n * sizeof(float4)));   // ACC
+    SPH_HIP(c, c->ta.ensure(n * sizeof(float4)));   // A0
+    SPH_HIP(c, c->tb.ensure(n * sizeof(float4)));   // A1
+    SPH_HIP(c, c->tc.ensure(n * sizeof(float)));    // A2
+    SPH_HIP(c, c->fa.ensure(n * sizeof(float4)));   // F0
+    SPH_HIP(c, c->fb.ensure(n * sizeof(float4)));   // F1
+    SPH_HIP(c, c->fc.ensure(n * sizeof(float)));    // F2
+    SPH_HIP(c, c->pa.ensure(n * sizeof(float4)));   // current positions
+    int r = sph_ell_prepare(c);
+    if (r) return r;
+    // kernel B reads its neighbour records from LDS windows (four lanes per
+    // particle, blocks of 128 slots); tuning override SPH_TLSPH_WINDOW=0
+    const char* e = getenv("SPH_TLSPH_WINDOW");
+    if (tl_lanes(c) != 4 || (e && strcmp(e, "0") == 0)) {
+        c->wtl.state = -1;
+        c->wtl.P = 0;
+        return SPH_OK;
+    }
+    return sph_windows_prepare(c, c->wtl, 4, 128);
 }
 
 template <int MODE>
@@ -444,9 +561,37 @@ void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
     }
 }
 
+template <int MODE, int M, int HC>
+void launch_bw_h(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
+    const NeighbourWindows& wd = c->wtl;
+    constexpr int NT = 512;
+    hipLaunchKernelGGL((k_tl_bw<MODE, M, HC, NT>), dim3(grid_for(c->n, NT / 4)), dim3(NT), 0, c->stream, c->n, t, w,
+                       wd.col.as<uint16_t>(), wd.Sp, wd.off.as<int32_t>(), wd.list.as<int32_t>(), c->geo0.as<float4>(),
+                       c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>(), c->sorted.as<float4>(),
+                       c->ua.as<float4>(), c->ub.as<float4>(), acc);
+}
+
+template <int MODE, int M>
+void launch_bw_m(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
+    const int32_t mx = c->wtl.max;
+    if (mx <= 512) launch_bw_h<MODE, M, 512>(c, t, w, acc);
+    else if (mx <= 768) launch_bw_h<MODE, M, 768>(c, t, w, acc);
+    else launch_bw_h<MODE, M, 1024>(c, t, w, acc);
+}
+
 template <int MODE>
 void launch_b(sph_ctx* c, const TlArgs& t, const Wrap& w, float* acc) {
     const int LN = tl_lanes(c);
+    c->tlsph_path = SPH_PATH_GENERIC;
+    if (LN == 4 && c->wtl.state == 1) {
+        c->tlsph_path = SPH_PATH_WINDOWS;
+        const int M = c->wtl.M;
+        if (M == 12) launch_bw_m<MODE, 12>(c, t, w, acc);
+        else if (M == 10) launch_bw_m<MODE, 10>(c, t, w, acc);
+        else if (M == 8) launch_bw_m<MODE, 8>(c, t, w, acc);
+        else launch_bw_m<MODE, 6>(c, t, w, acc);
+        return;
+    }
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
     const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {

@@ -63,6 +63,7 @@ _SIGS = [
     ("sph_last_error", C.c_char_p, [_vp]),
     ("sph_set_stream", C.c_int, [_vp, _vp]),
     ("sph_euler_path", C.c_int, [_vp]),
+    ("sph_tlsph_path", C.c_int, [_vp]),
     ("sph_build_cells", C.c_int, [_vp, C.POINTER(sph_domain), _i32, _vp]),
     ("sph_neighbors", C.c_int, [_vp, _vp, _vp, _i64, C.POINTER(C.c_int64)]),
     ("sph_kernel_sum", C.c_int, [_vp, _vp, _vp]),
@@ -235,6 +236,10 @@ class Context:
     def euler_path(self) -> int:
         """Pair-loop variant of the last Eulerian call (PATH_NONE, PATH_GENERIC, PATH_RECORDS, PATH_WINDOWS)."""
         return int(lib().sph_euler_path(self._h))
+
+    def tlsph_path(self) -> int:
+        """Variant of the stress-divergence loop in the last total-Lagrangian call (PATH_GENERIC, PATH_WINDOWS)."""
+        return int(lib().sph_tlsph_path(self._h))
 
     # ------------------------------------------------------------ neighbours
     def build_cells(self, domain: Domain, pos: torch.Tensor):
@@ -426,6 +431,10 @@ class Context:
 # Context in place of the sph_ctx pointer).
 def sph_euler_path(ctx: Context):
     return ctx.euler_path()
+
+
+def sph_tlsph_path(ctx: Context):
+    return ctx.tlsph_path()
 
 
 def sph_build_cells(ctx: Context, domain: Domain, pos):

@@ -650,6 +650,32 @@ def test_tlsph_rhs(S, kappa, model, rows, monkeypatch):
 
 
 @pytest.mark.parametrize("kappa", [2.0, 1.6])
+@pytest.mark.parametrize("model", [0, 1])
+def test_tlsph_windows_match_gathers(S, kappa, model, monkeypatch):
+    """The stress divergence read from LDS windows against the kernel that
+    gathers the neighbour records: the same pairs in the same order, plus
+    zero-separation padding pairs (which can move the compensated sums by
+    an ulp), so the accelerations agree to a few FP32 ulps of their
+    absolute-sum scale; the deformation rates (kernel A, shared) are
+    identical.  The path taken is the one asked for."""
+    w = _plate()
+    rng = np.random.default_rng(4)
+    F = (np.eye(3)[None] + 0.01 * rng.normal(size=(w.n, 3, 3))).astype(np.float32)
+    out = {}
+    for win in ("0", "1"):
+        monkeypatch.setenv("SPH_TLSPH_WINDOW", win)
+        ctx, box, rp, col, Bo, pg, po = _tl_setup(S, w, kappa, model)
+        dF, acc = ctx.tlsph_rhs(pg, dev(w.fields["vel"]), dev(F), dev(w.fields["fixed"], torch.int32))
+        out[win] = (host(dF).copy(), host(acc).copy(), ctx.tlsph_path())
+        ctx.close()
+    assert out["0"][2] == S.PATH_GENERIC and out["1"][2] == S.PATH_WINDOWS
+    assert np.array_equal(out["0"][0], out["1"][0])
+    _, r_acc, s_acc = O.tlsph_rhs(box, w.pos, w.h, rp, col, w.vol, Bo, po, w.fields["vel"], F, w.fields["fixed"])
+    eps = float(np.finfo(np.float32).eps)
+    assert np.all(np.abs(out["1"][1] - out["0"][1]) <= 8 * eps * s_acc)
+
+
+@pytest.mark.parametrize("kappa", [2.0, 1.6])
 @pytest.mark.parametrize("rows", ["ell", "csr"])
 def test_tlsph_steps(S, kappa, rows, monkeypatch):
     if rows == "csr":
