@@ -144,6 +144,53 @@ __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const floa
         for (int c = 0; c < 3; ++c) accum(L[r * 3 + c], dv[r], dw[c]);
 }
 
+// The per-particle end of kernel A (on the group's first lane): dF/dt = L B0,
+// then (MODE 0) dF/dt at the caller index or (MODE 1) F += dt dF/dt and the
+// position drift on non-fixed rows; A_i = P(F_i) B0_i for kernel B.
+template <int MODE>
+__device__ __forceinline__ void tl_a_tail(const TlArgs& t, int32_t i, const float* Ld, const float4& vi, bool fixed,
+                                          const float4& f0, const float4& f1, float f2,
+                                          const float4* __restrict__ geo1, const float2* __restrict__ geo2,
+                                          const float4* __restrict__ sorted, float4* __restrict__ F0,
+                                          float4* __restrict__ F1, float* __restrict__ F2, float4* __restrict__ posS,
+                                          float* __restrict__ dFdt, float4* __restrict__ A0, float4* __restrict__ A1,
+                                          float* __restrict__ A2) {
+    float Fd[9];
+    float B[9];
+    load_B3(i, geo1, geo2, B);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fd[r * 3 + c] = Ld[r * 3 + 0] * B[c] + Ld[r * 3 + 1] * B[3 + c] + Ld[r * 3 + 2] * B[6 + c];
+    float H[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2};
+    if (MODE == 0) {
+        const int32_t ic = __float_as_int(sorted[i].w);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dFdt[(int64_t)ic * 9 + q] = Fd[q];
+    } else if (!fixed) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) H[q] += t.dt * Fd[q];
+        F0[i] = make_float4(H[0], H[1], H[2], H[3]);
+        F1[i] = make_float4(H[4], H[5], H[6], H[7]);
+        F2[i] = H[8];
+        const float4 x = posS[i];
+        posS[i] = make_float4(x.x + t.dt * vi.x, x.y + t.dt * vi.y, x.z + t.dt * vi.z, 0.f);
+    }
+    H[0] -= 1.f;
+    H[4] -= 1.f;
+    H[8] -= 1.f;
+    float P[9];
+    pk1_from_H(H, t, P);
+    float Ai[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ai[r * 3 + c] = P[r * 3 + 0] * B[c] + P[r * 3 + 1] * B[3 + c] + P[r * 3 + 2] * B[6 + c];
+    A0[i] = make_float4(Ai[0], Ai[1], Ai[2], Ai[3]);
+    A1[i] = make_float4(Ai[4], Ai[5], Ai[6], Ai[7]);
+    A2[i] = Ai[8];
+}
+
 // Kernel A (Eq. 32 and the stress of Eq. 30 / neo-Hookean).  One thread per
 // sorted slot; the neighbour records (X_j, V_j and v_j) are gathered one
 // entry ahead of the pair being evaluated.  F lives in cell-sorted order
@@ -186,43 +233,11 @@ __global__ void __launch_bounds__(BLK) k_tl_a(int32_t n, TlArgs t, Wrap w, const
         gj = gn;
         vj = vn;
     }
-    float Ld[9], Fd[9];
+    float Ld[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) Ld[q] = t.cF * group_sum<LN>(L[q]);
     if (sub != 0) return;
-    float B[9];
-    load_B3(i, geo1, geo2, B);
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Fd[r * 3 + c] = Ld[r * 3 + 0] * B[c] + Ld[r * 3 + 1] * B[3 + c] + Ld[r * 3 + 2] * B[6 + c];
-    float H[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f2};
-    if (MODE == 0) {
-        const int32_t ic = __float_as_int(sorted[i].w);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) dFdt[(int64_t)ic * 9 + q] = Fd[q];
-    } else if (!fixed) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) H[q] += t.dt * Fd[q];
-        F0[i] = make_float4(H[0], H[1], H[2], H[3]);
-        F1[i] = make_float4(H[4], H[5], H[6], H[7]);
-        F2[i] = H[8];
-        const float4 x = posS[i];
-        posS[i] = make_float4(x.x + t.dt * vi.x, x.y + t.dt * vi.y, x.z + t.dt * vi.z, 0.f);
-    }
-    H[0] -= 1.f;
-    H[4] -= 1.f;
-    H[8] -= 1.f;
-    float P[9];
-    pk1_from_H(H, t, P);
-    float Ai[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Ai[r * 3 + c] = P[r * 3 + 0] * B[c] + P[r * 3 + 1] * B[3 + c] + P[r * 3 + 2] * B[6 + c];
-    A0[i] = make_float4(Ai[0], Ai[1], Ai[2], Ai[3]);
-    A1[i] = make_float4(Ai[4], Ai[5], Ai[6], Ai[7]);
-    A2[i] = Ai[8];
+    tl_a_tail<MODE>(t, i, Ld, vi, fixed, f0, f1, f2, geo1, geo2, sorted, F0, F1, F2, posS, dFdt, A0, A1, A2);
 }
 
 struct ARec {
@@ -407,6 +422,91 @@ k_tl_bw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t 
     }
 }
 
+// Kernel A over the same neighbour windows: the window's reference records
+// (X_j, V_j) and half-step velocities (v_j, fixed flag) copied into two LDS
+// planes, the pairs read there; the per-particle end as in k_tl_a.
+template <int HC, int NT>
+constexpr int tl_window_waves_a() {  // waves per SIMD the LDS allows, at most 6 (80 VGPRs)
+    constexpr int w = 163840 / (32 * HC) * (NT / 64) / 4;
+    return w < 6 ? w : 6;
+}
+
+template <bool WRAP, int M>
+__device__ __forceinline__ void tl_row_aw(const TlArgs& t, const Wrap& w, const char* W, int HC4,
+                                          const uint16_t* __restrict__ colw, uint32_t at0, uint32_t cs,
+                                          int32_t nchunk, const float4& gi, const float4& vi, Kahan* L) {
+    for (int32_t c = 0; c < nchunk; ++c) {
+        uint32_t e[M / 2];
+        load_chunk<M>(colw, at0 + (uint32_t)c * cs, e);
+        float4 ga = *reinterpret_cast<const float4*>(W + (e[0] & 0xffffu));
+        float4 va = *reinterpret_cast<const float4*>(W + HC4 + (e[0] & 0xffffu));
+        float4 gb = *reinterpret_cast<const float4*>(W + (e[0] >> 16));
+        float4 vb = *reinterpret_cast<const float4*>(W + HC4 + (e[0] >> 16));
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < M; q += 2) {
+            acc_a<WRAP>(t, w, gi, vi, ga, va, L);
+            if (q + 2 < M) {
+                const uint32_t b = tl_after(e[q / 2 + 1] & 0xffffu, L[0]);
+                ga = *reinterpret_cast<const float4*>(W + b);
+                va = *reinterpret_cast<const float4*>(W + HC4 + b);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            acc_a<WRAP>(t, w, gi, vi, gb, vb, L);
+            if (q + 3 < M) {
+                const uint32_t b = tl_after(e[q / 2 + 1] >> 16, L[0]);
+                gb = *reinterpret_cast<const float4*>(W + b);
+                vb = *reinterpret_cast<const float4*>(W + HC4 + b);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <int MODE, int M, int HC, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(tl_window_waves_a<HC, NT>())))
+k_tl_aw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t Sp, const int32_t* __restrict__ woff,
+        const int32_t* __restrict__ wlist, const float4* __restrict__ geo0, const float4* __restrict__ geo1,
+        const float2* __restrict__ geo2, const float4* __restrict__ sorted, const float4* __restrict__ VH,
+        float4* __restrict__ F0, float4* __restrict__ F1, float* __restrict__ F2, float4* __restrict__ posS,
+        float* __restrict__ dFdt, float4* __restrict__ A0, float4* __restrict__ A1, float* __restrict__ A2) {
+    constexpr int L = 4;
+    constexpr int HC4 = 16 * HC;
+    __shared__ __attribute__((aligned(16))) char W[2 * HC4];
+    const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
+    const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
+    for (int32_t k = (int32_t)threadIdx.x; k < wn; k += NT) {
+        const uint32_t j = (uint32_t)wlist[w0 + k];
+        *reinterpret_cast<float4*>(W + 16 * k) = ld32(geo0, j);
+        *reinterpret_cast<float4*>(W + HC4 + 16 * k) = ld32(VH, j);
+    }
+    const int sub = (int)(threadIdx.x % L);
+    const int32_t ig = blk * (NT / L) + (int32_t)(threadIdx.x / L);
+    const bool valid = ig < n;
+    const int32_t i = valid ? ig : n - 1;
+    const uint32_t self = 16u * (uint32_t)(i - blk * (NT / L));
+    const uint32_t at0 = ((uint32_t)i * L + (uint32_t)sub) * (uint32_t)(M / 2);
+    const uint32_t cs = (uint32_t)n * L * (uint32_t)(M / 2);
+    const int32_t nchunk = Sp / (L * M);
+    const float4 f0 = F0[i], f1 = F1[i];
+    const float f2 = F2[i];
+    __syncthreads();
+    const float4 gi = *reinterpret_cast<const float4*>(W + self);
+    const float4 vi = *reinterpret_cast<const float4*>(W + HC4 + self);
+    const bool fixed = vi.w != 0.f;
+    const bool wrap = wave_needs_wrap(w, gi);
+    Kahan Ls[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Ls[k].init();
+    if (wrap) tl_row_aw<true, M>(t, w, W, HC4, colw, at0, cs, nchunk, gi, vi, Ls);
+    else tl_row_aw<false, M>(t, w, W, HC4, colw, at0, cs, nchunk, gi, vi, Ls);
+    float Ld[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Ld[q] = t.cF * group_sum<L>(Ls[q]);
+    if (sub != 0 || !valid) return;
+    tl_a_tail<MODE>(t, i, Ld, vi, fixed, f0, f1, f2, geo1, geo2, sorted, F0, F1, F2, posS, dFdt, A0, A1, A2);
+}
+
 // F (caller [n][9]) and positions (caller SoA, optional) into sorted order, and back.
 __global__ void k_tl_pack(int32_t n, const float4* __restrict__ sorted, const float* __restrict__ F,
                           const float* __restrict__ pos, float4* __restrict__ F0, float4* __restrict__ F1,
@@ -538,9 +638,36 @@ int ensure_scratch(sph_ctx* c) {
     return sph_windows_prepare(c, c->wtl, 4, 128);
 }
 
+template <int MODE, int M, int HC>
+void launch_aw_h(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
+    const NeighbourWindows& wd = c->wtl;
+    constexpr int NT = 512;
+    hipLaunchKernelGGL((k_tl_aw<MODE, M, HC, NT>), dim3(grid_for(c->n, NT / 4)), dim3(NT), 0, c->stream, c->n, t, w,
+                       wd.col.as<uint16_t>(), wd.Sp, wd.off.as<int32_t>(), wd.list.as<int32_t>(), c->geo0.as<float4>(),
+                       c->geo1.as<float4>(), c->geo2.as<float2>(), c->sorted.as<float4>(), c->ua.as<float4>(),
+                       c->fa.as<float4>(), c->fb.as<float4>(), c->fc.as<float>(), c->pa.as<float4>(), dFdt,
+                       c->ta.as<float4>(), c->tb.as<float4>(), c->tc.as<float>());
+}
+
+template <int MODE, int M>
+void launch_aw_m(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
+    const int32_t mx = c->wtl.max;
+    if (mx <= 512) launch_aw_h<MODE, M, 512>(c, t, w, dFdt);
+    else if (mx <= 768) launch_aw_h<MODE, M, 768>(c, t, w, dFdt);
+    else launch_aw_h<MODE, M, 1024>(c, t, w, dFdt);
+}
+
 template <int MODE>
 void launch_a(sph_ctx* c, const TlArgs& t, const Wrap& w, float* dFdt) {
     const int LN = tl_lanes(c);
+    if (LN == 4 && c->wtl.state == 1) {
+        const int M = c->wtl.M;
+        if (M == 12) launch_aw_m<MODE, 12>(c, t, w, dFdt);
+        else if (M == 10) launch_aw_m<MODE, 10>(c, t, w, dFdt);
+        else if (M == 8) launch_aw_m<MODE, 8>(c, t, w, dFdt);
+        else launch_aw_m<MODE, 6>(c, t, w, dFdt);
+        return;
+    }
     dim3 g(grid_for((int64_t)c->n * LN, BLK)), bl(BLK);
     const bool ell = c->ell_state == 1;
     auto go = [&](auto kern) {
