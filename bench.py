@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "7a0f43d3450d4a616ed0faae9cbffb7275426d64a9756e142f4a6fa30da109f7": {"2d": 39153356, "3d": 1980248064},
+    "34834c6080f256ab92b1342a68ddbaac171c48f1461dd504afb77da4995dde60": {"2d": 39152332, "3d": 1980390400},
 }
 
 
@@ -52,7 +52,7 @@ TRAFFIC = {
 # (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles) over
 # 1,024 SIMDs x 2.4 GHz x the live launch time.
 VALU = {
-    "7a0f43d3450d4a616ed0faae9cbffb7275426d64a9756e142f4a6fa30da109f7": {"3d": 433551000},
+    "34834c6080f256ab92b1342a68ddbaac171c48f1461dd504afb77da4995dde60": {"3d": 433551000},
 }
 VALU_SIMDS = 1024
 VALU_CLOCK_HZ = 2.4e9
