@@ -239,3 +239,26 @@ def test_euler_3d_window_fallbacks(S, monkeypatch):
     monkeypatch.setenv("SPH_PAIR_ROWS", "csr")
     _, p = _run_paths(S, w, 1.6, w.meta["dt"], 1)
     assert p == S.PATH_RECORDS
+
+
+def test_euler_3d_windows_rebuilt_with_the_configuration(S):
+    """One context bound to a new configuration (another cut-off, then
+    another field size) rebuilds its windows: each call's rates equal a
+    fresh context's bit for bit."""
+    cases = [(I.taylor_green_3d(nside=24, nu=0.01, jitter=0.05, seed=5), 1.6),
+             (I.taylor_green_3d(nside=24, nu=0.01, jitter=0.05, seed=5), 2.0),
+             (I.taylor_green_3d(nside=28, nu=0.01, jitter=0.05, seed=6), 1.6)]
+    shared = S.Context(3)
+    for w, kappa in cases:
+        pg, _ = _params(S, w, w.meta["dt"])
+        got = []
+        for ctx in (shared, S.Context(3)):
+            ctx.build_cells(S.Domain(dim=3, h=w.h, kappa=kappa, lo=w.lo, hi=w.hi, periodic=w.periodic), dev(w.pos))
+            ctx.correction_B(dev(w.vol))
+            dr, dm = ctx.euler_rhs(pg, dev(w.fields["drho"]), dev(w.fields["mom"]))
+            assert ctx.euler_path() == S.PATH_WINDOWS
+            got.append((host(dr).copy(), host(dm).copy()))
+            if ctx is not shared:
+                ctx.close()
+        assert np.array_equal(got[0][0], got[1][0]) and np.array_equal(got[0][1], got[1][1]), (w.n, kappa)
+    shared.close()
