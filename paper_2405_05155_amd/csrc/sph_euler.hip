@@ -515,10 +515,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
 // ------------------------------------------------------------------ 3-D stage on packed records
 // In 3-D the per-particle stage gathers each neighbour from one 64-byte
 // record (one cache-line half) in cell-sorted order:
-//   q0 = (x, y, z, V), q1 = (B00, B01, B02, B11), q2 = (B12, B22, tr B, 0),
+//   q0 = (x, y, z, V), q1 = (B00, B01, B02, B11), q2 = (B12, B22, k tr B, 0),
 //   q3 = (2 p, v_x, v_y, v_z),  2 p = 2 c^2 (drho + rho_ref - rho0),
-// so that a pair needs no per-partner arithmetic for the pressure or the
-// trace of B.  Two record sets carry the stage input and output; geometry
+// with k = -4 mu / d the viscous prefactor of the call, so that a pair
+// needs no per-partner arithmetic for the pressure or the trace of B.  Two record sets carry the stage input and output; geometry
 // is written into both when the state is packed, and a stage writes only
 // the q3 quad of its output (with the conserved record U).
 
@@ -543,7 +543,7 @@ __global__ void k_pack3(int32_t n, EulerArgs ea, const float4* __restrict__ sort
     U[s] = u;
     const float4 g0 = geo0[s], g1 = geo1[s];
     const float2 g2 = geo2[s];
-    const float4 q2 = make_float4(g2.x, g2.y, (g1.x + g1.w) + g2.y, 0.f);
+    const float4 q2 = make_float4(g2.x, g2.y, ea.kmu * ((g1.x + g1.w) + g2.y), 0.f);
     const float4 q3 = state_quad3(ea, u);
     const int64_t b = 4 * (int64_t)s;
     Ra[b] = g0; Ra[b + 1] = g1; Ra[b + 2] = q2; Ra[b + 3] = q3;
@@ -567,22 +567,30 @@ __device__ __forceinline__ void gather3(const float4* __restrict__ R, int32_t j,
 // that frees its registers instead of being hoisted above it (which would
 // need a register set per record in flight).
 __device__ __forceinline__ int32_t after(int32_t j, const Kahan& k) {
-    asm volatile("" : "+v"(j) : "v"(k.s));
+    asm volatile("" : "+v"(j) : "v"(k.s), "v"(k.c));
     return j;
+}
+
+// v, required in registers at this point (an empty asm statement that reads
+// it: the loads that produce it are complete here).
+__device__ __forceinline__ void held(const float4& v) {
+    asm volatile("" : : "v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
 }
 
 struct Own3 {
     float x[3], B[6], v[3];
     float p2;     // 2 p_i
     float crho;   // c rho_i + c rho0 (so that c (rho_i + rho_j) = crho + 2 p_j / (2 c))
-    float trB;
+    float ktrB;   // k tr B_i, k = -4 mu / d
 };
 
 // One pair (i, j) of Eq. (19) in 3-D with the corrected gradient (Eq. 28)
 // and the limited linearised Riemann solution (Eqs. 26-27): the terms of
-// accumulate_pair, with 2 p_j and tr B_j read from the partner's record
-// and c (rho_i + rho_j) = (c rho_i + c rho0) + 2 p_j / (2 c).
-template <bool WRAP>
+// accumulate_pair, with 2 p_j and k tr B_j read from the partner's record
+// and c (rho_i + rho_j) = (c rho_i + c rho0) + 2 p_j / (2 c).  The row's
+// pairs come two at a time: the first of two opens the compensated
+// additions (OPEN), the second closes them.
+template <bool WRAP, bool OPEN>
 __device__ __forceinline__ void pair3(const EulerArgs& ea, const Own3& o, const Rec3& nb, Kahan& sr, Kahan* sm) {
     float d[3], dv[3];
     d[0] = o.x[0] - nb.q0.x;
@@ -620,11 +628,21 @@ __device__ __forceinline__ void pair3(const EulerArgs& ea, const Own3& o, const 
     const float vs2 = fmaf(-dn, d[2], o.v[2] + nb.q3.w);
     const float vg2 = fmaf(vs0, G0, fmaf(vs1, G1, vs2 * G2));
     const float rh = rhostar * vg2;
-    accum(sr, w, rh);
-    const float kv = ea.kmu * (o.trB + nb.q2.z);
-    accum(sm[0], w, fmaf(rh, vs0, fmaf(p4, G0, kv * dv[0])));
-    accum(sm[1], w, fmaf(rh, vs1, fmaf(p4, G1, kv * dv[1])));
-    accum(sm[2], w, fmaf(rh, vs2, fmaf(p4, G2, kv * dv[2])));
+    const float kv = o.ktrB + nb.q2.z;
+    const float xm0 = fmaf(rh, vs0, fmaf(p4, G0, kv * dv[0]));
+    const float xm1 = fmaf(rh, vs1, fmaf(p4, G1, kv * dv[1]));
+    const float xm2 = fmaf(rh, vs2, fmaf(p4, G2, kv * dv[2]));
+    if (OPEN) {
+        sr.open(w, rh);
+        sm[0].open(w, xm0);
+        sm[1].open(w, xm1);
+        sm[2].open(w, xm2);
+    } else {
+        sr.close(w, rh);
+        sm[0].close(w, xm0);
+        sm[1].close(w, xm1);
+        sm[2].close(w, xm2);
+    }
 }
 
 // The lane's entries t = 0 .. m-1 of row i (entry t at e0 + t es), taken in
@@ -634,7 +652,8 @@ __device__ __forceinline__ void pair3(const EulerArgs& ea, const Own3& o, const 
 // loaded first (no gather then waits behind an index load issued after
 // it), then its records are gathered two ahead of the pair being evaluated,
 // into two register sets refilled in turn (no register copies); scheduling
-// barriers keep each gather where it is issued.
+// barriers keep each gather where it is issued.  M is even: the pairs enter
+// the compensated sums two at a time.
 template <bool WRAP, int M>
 __device__ __forceinline__ void row3(const EulerArgs& ea, const Own3& o, const float4* __restrict__ R,
                                      const int32_t* __restrict__ col, int32_t i, uint32_t e0, uint32_t es, int32_t m,
@@ -653,10 +672,10 @@ __device__ __forceinline__ void row3(const EulerArgs& ea, const Own3& o, const f
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
-            pair3<WRAP>(ea, o, A, sr, sm);
+            pair3<WRAP, true>(ea, o, A, sr, sm);
             if (q + 2 < M) gather3(R, after(jb[q + 2], sr), A);
             __builtin_amdgcn_sched_barrier(0);
-            pair3<WRAP>(ea, o, B, sr, sm);
+            pair3<WRAP, false>(ea, o, B, sr, sm);
             if (q + 3 < M) gather3(R, after(jb[q + 3], sr), B);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -712,7 +731,7 @@ __global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const i
     o.x[0] = self.q0.x; o.x[1] = self.q0.y; o.x[2] = self.q0.z;
     o.B[0] = self.q1.x; o.B[1] = self.q1.y; o.B[2] = self.q1.z; o.B[3] = self.q1.w;
     o.B[4] = self.q2.x; o.B[5] = self.q2.y;
-    o.trB = self.q2.z;
+    o.ktrB = self.q2.z;
     o.p2 = self.q3.x;
     o.v[0] = self.q3.y; o.v[1] = self.q3.z; o.v[2] = self.q3.w;
     o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);
@@ -799,10 +818,10 @@ __device__ __forceinline__ void row3w(const EulerArgs& ea, const Own3& o, const 
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
-            pair3<WRAP>(ea, o, A, sr, sm);
+            pair3<WRAP, true>(ea, o, A, sr, sm);
             if (q + 2 < M) wread_b<HC>(W, (uint32_t)after((int32_t)(w[q / 2 + 1] & 0xffffu), sr), A);
             __builtin_amdgcn_sched_barrier(0);
-            pair3<WRAP>(ea, o, B, sr, sm);
+            pair3<WRAP, false>(ea, o, B, sr, sm);
             if (q + 3 < M) wread_b<HC>(W, (uint32_t)after((int32_t)(w[q / 2 + 1] >> 16), sr), B);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -868,9 +887,38 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
     {
-        const uint32_t q = threadIdx.x & 3u;
-        for (int32_t k = (int32_t)(threadIdx.x >> 2); k < wn; k += NT / 4)
-            W[q * HC + k] = ld32(R, ((uint32_t)wlist[w0 + k] << 2) + q);
+        // a thread per record, at most KC records each: the slot indices
+        // are loaded first, then the records, then written to LDS, so the
+        // copy waits on two memory latencies, not 2 KC.  Threads past the
+        // window's end load its last record again (every window holds the
+        // block's own slots, so it is never empty) and write nothing.
+        constexpr int KC = (HC + NT - 1) / NT;
+        uint32_t b[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) b[r] = (uint32_t)min((int32_t)threadIdx.x + r * NT, wn - 1);
+#pragma unroll
+        for (int r = 0; r < KC; ++r) b[r] = (uint32_t)wlist[w0 + (int32_t)b[r]] << 2;
+        float4 a[KC][4];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[r][q] = ld32(R, b[r] + (uint32_t)q);
+        }
+        // (the records are taken here, so that no load is moved into the
+        // guarded writes below, behind the first of them)
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) held(a[r][q]);
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            const int32_t k = (int32_t)threadIdx.x + r * NT;
+            if (k < wn) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) W[q * HC + k] = a[r][q];
+            }
+        }
     }
     const int sub = (int)(threadIdx.x % L);
     const int comp = 2 * (sub & 1) + (sub >> 1);
@@ -895,7 +943,7 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     o.x[0] = me.q0.x; o.x[1] = me.q0.y; o.x[2] = me.q0.z;
     o.B[0] = me.q1.x; o.B[1] = me.q1.y; o.B[2] = me.q1.z; o.B[3] = me.q1.w;
     o.B[4] = me.q2.x; o.B[5] = me.q2.y;
-    o.trB = me.q2.z;
+    o.ktrB = me.q2.z;
     o.p2 = me.q3.x;
     o.v[0] = me.q3.y; o.v[1] = me.q3.z; o.v[2] = me.q3.w;
     o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);

@@ -254,6 +254,17 @@ struct Kahan {
         c = (t - s) - y;
         s = t;
     }
+    // Terms taken two at a time (w1 x1 + w2 x2, one compensated addition
+    // per two terms): open folds the first into the carried correction (c
+    // then holds y = w1 x1 - c, rounded once, until the matching close),
+    // close adds the second to y and y to the sum.
+    __device__ __forceinline__ void open(float w, float x) { c = fmaf(w, x, -c); }
+    __device__ __forceinline__ void close(float w, float x) {
+        float y = fmaf(w, x, c);
+        float t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
     __device__ __forceinline__ float value() const { return s - c; }
     __device__ __forceinline__ double value64() const { return (double)s - (double)c; }
 };

@@ -343,6 +343,14 @@ __device__ __forceinline__ uint32_t tl_after(uint32_t b, const Kahan& k) {
     return b;
 }
 
+// v, required in registers at this point (an empty asm statement that reads
+// it: the loads that produce it are complete here, and none of them is moved
+// into a guarded block after it).
+__device__ __forceinline__ void tl_held(const float4& v) {
+    asm volatile("" : : "v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+__device__ __forceinline__ void tl_held(float v) { asm volatile("" : : "v"(v)); }
+
 // The lane's chunks of window entries of one row (records from LDS, two in
 // flight), in the order k_tl_b takes them.
 template <bool WRAP, int M>
@@ -380,12 +388,42 @@ k_tl_bw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t 
     __shared__ __attribute__((aligned(16))) char W[3 * HC4 + 4 * HC];
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
-    for (int32_t k = (int32_t)threadIdx.x; k < wn; k += NT) {
-        const uint32_t j = (uint32_t)wlist[w0 + k];
-        *reinterpret_cast<float4*>(W + 16 * k) = ld32(geo0, j);
-        *reinterpret_cast<float4*>(W + HC4 + 16 * k) = ld32(A0, j);
-        *reinterpret_cast<float4*>(W + 2 * HC4 + 16 * k) = ld32(A1, j);
-        *reinterpret_cast<float*>(W + 3 * HC4 + 4 * k) = ld32(A2, j);
+    {
+        // a thread per record, at most KC records each: the slot indices
+        // are loaded first, then the records, then written to LDS, so the
+        // copy waits on two memory latencies, not 2 KC.  Threads past the
+        // window's end load its last record again (every window holds the
+        // block's own slots, so it is never empty) and write nothing.
+        constexpr int KC = (HC + NT - 1) / NT;
+        uint32_t j[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) j[r] = (uint32_t)wlist[w0 + min((int32_t)threadIdx.x + r * NT, wn - 1)];
+        float4 g[KC], a0[KC], a1[KC];
+        float a2[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            g[r] = ld32(geo0, j[r]);
+            a0[r] = ld32(A0, j[r]);
+            a1[r] = ld32(A1, j[r]);
+            a2[r] = ld32(A2, j[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            tl_held(g[r]);
+            tl_held(a0[r]);
+            tl_held(a1[r]);
+            tl_held(a2[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            const int32_t k = (int32_t)threadIdx.x + r * NT;
+            if (k < wn) {
+                *reinterpret_cast<float4*>(W + 16 * k) = g[r];
+                *reinterpret_cast<float4*>(W + HC4 + 16 * k) = a0[r];
+                *reinterpret_cast<float4*>(W + 2 * HC4 + 16 * k) = a1[r];
+                *reinterpret_cast<float*>(W + 3 * HC4 + 4 * k) = a2[r];
+            }
+        }
     }
     const int sub = (int)(threadIdx.x % L);
     const int32_t ig = blk * (NT / L) + (int32_t)(threadIdx.x / L);
@@ -475,10 +513,32 @@ k_tl_aw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t 
     __shared__ __attribute__((aligned(16))) char W[2 * HC4];
     const int32_t blk = xcd_block((int32_t)blockIdx.x, (int32_t)gridDim.x);
     const int32_t w0 = woff[blk], wn = woff[blk + 1] - w0;
-    for (int32_t k = (int32_t)threadIdx.x; k < wn; k += NT) {
-        const uint32_t j = (uint32_t)wlist[w0 + k];
-        *reinterpret_cast<float4*>(W + 16 * k) = ld32(geo0, j);
-        *reinterpret_cast<float4*>(W + HC4 + 16 * k) = ld32(VH, j);
+    {
+        // the window copy in three phases (slot indices, records, LDS
+        // writes), as in k_tl_bw
+        constexpr int KC = (HC + NT - 1) / NT;
+        uint32_t j[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) j[r] = (uint32_t)wlist[w0 + min((int32_t)threadIdx.x + r * NT, wn - 1)];
+        float4 g[KC], v[KC];
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            g[r] = ld32(geo0, j[r]);
+            v[r] = ld32(VH, j[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            tl_held(g[r]);
+            tl_held(v[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < KC; ++r) {
+            const int32_t k = (int32_t)threadIdx.x + r * NT;
+            if (k < wn) {
+                *reinterpret_cast<float4*>(W + 16 * k) = g[r];
+                *reinterpret_cast<float4*>(W + HC4 + 16 * k) = v[r];
+            }
+        }
     }
     const int sub = (int)(threadIdx.x % L);
     const int32_t ig = blk * (NT / L) + (int32_t)(threadIdx.x / L);
