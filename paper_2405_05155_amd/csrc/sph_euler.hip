@@ -851,11 +851,11 @@ __device__ __forceinline__ float group_sum4_spread(const Kahan* k, int sub) {
     float kh1 = b0 ? k[3].s : k[1].s, kl1 = b0 ? -k[3].c : -k[1].c;
     const float sh0 = b0 ? k[0].s : k[2].s, sl0 = b0 ? -k[0].c : -k[2].c;
     const float sh1 = b0 ? k[1].s : k[3].s, sl1 = b0 ? -k[1].c : -k[3].c;
-    merge_pair(kh0, kl0, __shfl_xor(sh0, 1, 64), __shfl_xor(sl0, 1, 64));
-    merge_pair(kh1, kl1, __shfl_xor(sh1, 1, 64), __shfl_xor(sl1, 1, 64));
+    merge_pair(kh0, kl0, lane_xor(sh0, 1), lane_xor(sl0, 1));
+    merge_pair(kh1, kl1, lane_xor(sh1, 1), lane_xor(sl1, 1));
     float kh = b1 ? kh1 : kh0, kl = b1 ? kl1 : kl0;
     const float sh = b1 ? kh0 : kh1, sl = b1 ? kl0 : kl1;
-    merge_pair(kh, kl, __shfl_xor(sh, 2, 64), __shfl_xor(sl, 2, 64));
+    merge_pair(kh, kl, lane_xor(sh, 2), lane_xor(sl, 2));
     return kh + kl;
 }
 
@@ -972,7 +972,7 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     if (STAGE == 1) unc = uc + ea.dt * Rc;
     else unc = 0.5f * (u0c + (uc + ea.dt * Rc));
     // the density deviation sits on the group's first lane (component 0)
-    const float dr = __shfl(unc, (int)(threadIdx.x & 63u) & ~3, 64);
+    const float dr = quad_first(unc);
     if (!valid) return;
     reinterpret_cast<float*>(Uout)[4 * (int64_t)i + comp] = unc;
     const float q3c = comp == 0 ? fmaf(ea.c2x2, unc, ea.c2x2poff) : unc * fast_rcp(ea.rho_ref + dr);

@@ -272,6 +272,20 @@ struct Kahan {
 // w x into a lane's compensated partial sum of one row.
 __device__ __forceinline__ void accum(Kahan& k, float w, float x) { k.add(w * x); }
 
+// v of lane (lane ^ m) of the wave: for m = 1 and 2 (partners within an
+// aligned group of four lanes) a DPP quad permutation, which moves the value
+// inside the vector ALU; otherwise through the LDS crossbar (ds_bpermute).
+__device__ __forceinline__ float lane_xor(float v, int m) {
+    if (m == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+    if (m == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+    return __shfl_xor(v, m, 64);
+}
+
+// v of the first lane of the lane's aligned group of four (DPP broadcast).
+__device__ __forceinline__ float quad_first(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x00, 0xF, 0xF, false));
+}
+
 // Combine the compensated partial sums held by the L lanes of an aligned
 // lane group (xor butterfly; every lane ends with the same value).  Each
 // partial is the pair (hi, lo) = (s, -c); partners merge with TwoSum so the
@@ -281,8 +295,8 @@ __device__ __forceinline__ float group_sum(const Kahan& k) {
     float hi = k.s, lo = -k.c;
 #pragma unroll
     for (int m = 1; m < L; m <<= 1) {
-        float ohi = __shfl_xor(hi, m, 64);
-        float olo = __shfl_xor(lo, m, 64);
+        float ohi = lane_xor(hi, m);
+        float olo = lane_xor(lo, m);
         float s = hi + ohi;
         float bp = s - hi;
         float e = (hi - (s - bp)) + (ohi - bp);
@@ -299,8 +313,8 @@ __device__ __forceinline__ double group_sum64(const Kahan& k) {
     float hi = k.s, lo = -k.c;
 #pragma unroll
     for (int m = 1; m < L; m <<= 1) {
-        float ohi = __shfl_xor(hi, m, 64);
-        float olo = __shfl_xor(lo, m, 64);
+        float ohi = lane_xor(hi, m);
+        float olo = lane_xor(lo, m);
         float s = hi + ohi;
         float bp = s - hi;
         float e = (hi - (s - bp)) + (ohi - bp);
@@ -316,8 +330,8 @@ __device__ __forceinline__ float group_sum_rt(const Kahan& k, int L) {
 #pragma unroll
     for (int m = 1; m < 8; m <<= 1) {
         if (m >= L) break;
-        float ohi = __shfl_xor(hi, m, 64);
-        float olo = __shfl_xor(lo, m, 64);
+        float ohi = lane_xor(hi, m);
+        float olo = lane_xor(lo, m);
         float s = hi + ohi;
         float bp = s - hi;
         float e = (hi - (s - bp)) + (ohi - bp);
