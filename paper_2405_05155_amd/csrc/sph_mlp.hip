@@ -134,40 +134,86 @@ struct FwdLds {
     float b1[NH], b2[NH], b3[4];
 };
 
-// weights -> LDS fragments (all threads of the workgroup)
+// weights -> LDS fragments (all WNT threads of the workgroup).  Each of a
+// thread's fragments has a fixed slot; the thread loads a batch of them
+// (unconditionally: padding columns read an in-range element and are zeroed
+// after) before it packs and stores any, so the batch's global loads are in
+// flight together rather than one round trip apiece.
+constexpr int WNT = 256;
+constexpr int W1_PER = HT * KS1 * 64 / WNT, W2_PER = HT * HT * 64 / WNT, W3_PER = HT * 64 / WNT;
+static_assert(W1_PER * WNT == HT * KS1 * 64 && W2_PER * WNT == HT * HT * 64 && W3_PER * WNT == HT * 64, "whole trips");
 template <bool TRAIN, class LDS>
 __device__ void load_weights(LDS& L, const float* __restrict__ p) {
     const int tid = threadIdx.x;
-    for (int i = tid; i < HT * KS1 * 64; i += blockDim.x) {
-        int t = i / (KS1 * 64), ks = (i / 64) % KS1, ln = i % 64;
-        int row = 16 * t + (ln & 15), k0 = 16 * ks + 4 * (ln >> 4);
-        float4 v = k0 < NIN ? *reinterpret_cast<const float4*>(p + OFF_W1 + row * NIN + k0) : float4{0.f, 0.f, 0.f, 0.f};
-        L.w1f[t][ks][ln] = pack4(v.x, v.y, v.z, v.w);
-    }
-    for (int i = tid; i < HT * HT * 64; i += blockDim.x) {
-        int t = i / (HT * 64), ks = (i / 64) % HT, ln = i % 64;
-        int g = ln >> 4, c = ln & 15;
-        float4 v = *reinterpret_cast<const float4*>(p + OFF_W2 + (16 * t + c) * NH + 16 * ks + 4 * g);
-        L.w2f[t][ks][ln] = pack4(v.x, v.y, v.z, v.w);
-        if constexpr (TRAIN) {
-            const float* q = p + OFF_W2 + (16 * ks + 4 * g) * NH + 16 * t + c;
-            L.w2t[t][ks][ln] = pack4(q[0], q[NH], q[2 * NH], q[3 * NH]);
+    {
+        float4 v[W1_PER];
+#pragma unroll
+        for (int k = 0; k < W1_PER; ++k) {
+            const int i = tid + k * WNT;
+            const int t = i / (KS1 * 64), ks = (i / 64) % KS1, ln = i % 64;
+            const int row = 16 * t + (ln & 15), k0 = 16 * ks + 4 * (ln >> 4);
+            v[k] = *reinterpret_cast<const float4*>(p + OFF_W1 + row * NIN + min(k0, NIN - 4));
+        }
+#pragma unroll
+        for (int k = 0; k < W1_PER; ++k) {
+            const int i = tid + k * WNT;
+            const int t = i / (KS1 * 64), ks = (i / 64) % KS1, ln = i % 64;
+            const bool pad = 16 * ks + 4 * (ln >> 4) >= NIN;
+            L.w1f[t][ks][ln] = pad ? bf16x4{0, 0, 0, 0} : pack4(v[k].x, v[k].y, v[k].z, v[k].w);
         }
     }
-    for (int i = tid; i < HT * 64; i += blockDim.x) {
-        int ks = i / 64, ln = i % 64, c = ln & 15;
-        float4 v = c < NOUT ? *reinterpret_cast<const float4*>(p + OFF_W3 + c * NH + 16 * ks + 4 * (ln >> 4))
-                            : float4{0.f, 0.f, 0.f, 0.f};
-        L.w3f[ks][ln] = pack4(v.x, v.y, v.z, v.w);
+    constexpr int W2_BATCH = 8;
+    static_assert(W2_PER % W2_BATCH == 0, "whole batches");
+#pragma unroll
+    for (int k0 = 0; k0 < W2_PER; k0 += W2_BATCH) {
+        float4 v[W2_BATCH], u[W2_BATCH];
+#pragma unroll
+        for (int k = 0; k < W2_BATCH; ++k) {
+            const int i = tid + (k0 + k) * WNT;
+            const int t = i / (HT * 64), ks = (i / 64) % HT, ln = i % 64;
+            const int g = ln >> 4, c = ln & 15;
+            v[k] = *reinterpret_cast<const float4*>(p + OFF_W2 + (16 * t + c) * NH + 16 * ks + 4 * g);
+            if constexpr (TRAIN) {
+                const float* q = p + OFF_W2 + (16 * ks + 4 * g) * NH + 16 * t + c;
+                u[k] = float4{q[0], q[NH], q[2 * NH], q[3 * NH]};
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < W2_BATCH; ++k) {
+            const int i = tid + (k0 + k) * WNT;
+            const int t = i / (HT * 64), ks = (i / 64) % HT, ln = i % 64;
+            L.w2f[t][ks][ln] = pack4(v[k].x, v[k].y, v[k].z, v[k].w);
+            if constexpr (TRAIN) L.w2t[t][ks][ln] = pack4(u[k].x, u[k].y, u[k].z, u[k].w);
+        }
     }
-    for (int i = tid; i < NH; i += blockDim.x) {
-        L.b1[i] = p[OFF_B1 + i];
-        L.b2[i] = p[OFF_B2 + i];
+    {
+        float4 v[W3_PER];
+#pragma unroll
+        for (int k = 0; k < W3_PER; ++k) {
+            const int i = tid + k * WNT;
+            const int ks = i / 64, ln = i % 64, c = ln & 15;
+            v[k] = *reinterpret_cast<const float4*>(p + OFF_W3 + min(c, NOUT - 1) * NH + 16 * ks + 4 * (ln >> 4));
+        }
+#pragma unroll
+        for (int k = 0; k < W3_PER; ++k) {
+            const int i = tid + k * WNT;
+            const int ks = i / 64, ln = i % 64;
+            L.w3f[ks][ln] = (ln & 15) >= NOUT ? bf16x4{0, 0, 0, 0} : pack4(v[k].x, v[k].y, v[k].z, v[k].w);
+        }
+    }
+    static_assert(NH <= WNT, "one bias entry per thread");
+    if (tid < NH) {
+        L.b1[tid] = p[OFF_B1 + tid];
+        L.b2[tid] = p[OFF_B2 + tid];
     }
     if (tid < 4) L.b3[tid] = tid < NOUT ? p[OFF_B3 + tid] : 0.f;
     if constexpr (TRAIN) {
-        for (int i = tid; i < NOUT * NH; i += blockDim.x) L.w3v[i / NH][i % NH] = bf2f(f2bf(p[OFF_W3 + i]));
-        for (int i = tid; i < 16 * SROW; i += blockDim.x) L.dyt[i / SROW][i % SROW] = 0;
+#pragma unroll
+        for (int k = 0; k < (NOUT * NH + WNT - 1) / WNT; ++k) {
+            const int i = tid + k * WNT;
+            if (i < NOUT * NH) L.w3v[i / NH][i % NH] = bf2f(f2bf(p[OFF_W3 + i]));
+        }
+        for (int i = tid; i < 16 * SROW; i += WNT) L.dyt[i / SROW][i % SROW] = 0;
     }
 }
 
