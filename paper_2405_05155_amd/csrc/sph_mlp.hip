@@ -126,6 +126,33 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// z[t] = sum over ks of A[t][ks] b[ks] (t = 0 .. HT - 1), two tiles at a
+// time: both tiles' weight fragments are read from LDS before their MFMAs,
+// which alternate between the two accumulators, so neither an LDS read nor
+// a dependent MFMA is waited on back to back (each tile keeps its order of
+// accumulation over ks).
+template <int KS>
+__device__ __forceinline__ void tile_layer(const bf16x4 (&A)[HT][KS][64], int wl, const bf16x4* b, f32x4* z) {
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < HT; t += 2) {
+        bf16x4 a0[KS], a1[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            a0[ks] = A[t][ks][wl];
+            a1[ks] = A[t + 1][ks][wl];
+        }
+        f32x4 z0 = zero4, z1 = zero4;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            z0 = mfma16(a0[ks], b[ks], z0);
+            z1 = mfma16(a1[ks], b[ks], z1);
+        }
+        z[t] = z0;
+        z[t + 1] = z1;
+    }
+}
+
 // forward-only LDS: the layer fragments and biases
 struct FwdLds {
     bf16x4 w1f[HT][KS1][64];
@@ -241,24 +268,14 @@ __global__ void __launch_bounds__(256) k_forward_fused(int n, const float* __res
         for (int ks = 0; ks < KS1; ++ks)
             xb[ks] = valid ? *reinterpret_cast<const bf16x4*>(xr + 16 * ks) : bf16x4{0, 0, 0, 0};
         f32x4 z[HT];
-#pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            z[t] = zero4;
-#pragma unroll
-            for (int ks = 0; ks < KS1; ++ks) z[t] = mfma16(L.w1f[t][ks][wl], xb[ks], z[t]);
-        }
+        tile_layer<KS1>(L.w1f, wl, xb, z);
         bf16x4 h[HT];
 #pragma unroll
         for (int t = 0; t < HT; ++t) {
             float4 bb = *reinterpret_cast<const float4*>(&L.b1[16 * t + 4 * g + oz]);
             h[t] = pack4(gelu(z[t][0] + bb.x), gelu(z[t][1] + bb.y), gelu(z[t][2] + bb.z), gelu(z[t][3] + bb.w));
         }
-#pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            z[t] = zero4;
-#pragma unroll
-            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2f[t][ks][wl], h[ks], z[t]);
-        }
+        tile_layer<HT>(L.w2f, wl, h, z);
 #pragma unroll
         for (int t = 0; t < HT; ++t) {
             float4 bb = *reinterpret_cast<const float4*>(&L.b2[16 * t + 4 * g + oz]);
@@ -368,12 +385,7 @@ __global__ void __launch_bounds__(256) k_train_fused(int B, const float* __restr
         }
         // layer 1
         f32x4 z[HT];
-#pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            z[t] = zero4;
-#pragma unroll
-            for (int ks = 0; ks < KS1; ++ks) z[t] = mfma16(L.w1f[t][ks][wl], xb[ks], z[t]);
-        }
+        tile_layer<KS1>(L.w1f, wl, xb, z);
 #pragma unroll
         for (int ks = 0; ks < KS1; ++ks)
 #pragma unroll
@@ -393,12 +405,7 @@ __global__ void __launch_bounds__(256) k_train_fused(int B, const float* __restr
             for (int e = 0; e < 4; ++e) L.h1t[16 * t + 4 * g + e][col] = (uint16_t)h1[t][e];
         }
         // layer 2
-#pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            z[t] = zero4;
-#pragma unroll
-            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2f[t][ks][wl], h1[ks], z[t]);
-        }
+        tile_layer<HT>(L.w2f, wl, h1, z);
         bf16x4 h2[HT];
         float gp2[HT][4];
 #pragma unroll
@@ -474,12 +481,7 @@ __global__ void __launch_bounds__(256) k_train_fused(int B, const float* __restr
 #pragma unroll
             for (int e = 0; e < 4; ++e) L.s2t[16 * t + 4 * g + e][col] = (uint16_t)dz2b[t][e];
         // dZ1 = (bf16(dZ2) bf16(W2)) * GELU'(Z1)
-#pragma unroll
-        for (int t = 0; t < HT; ++t) {
-            z[t] = zero4;
-#pragma unroll
-            for (int ks = 0; ks < HT; ++ks) z[t] = mfma16(L.w2t[t][ks][wl], dz2b[ks], z[t]);
-        }
+        tile_layer<HT>(L.w2t, wl, dz2b, z);
         bf16x4 dz1b[HT];
 #pragma unroll
         for (int t = 0; t < HT; ++t) {
