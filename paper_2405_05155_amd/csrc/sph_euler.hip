@@ -515,10 +515,10 @@ __global__ void __launch_bounds__(BLK) k_euler(int32_t n, EulerArgs ea, const in
 // ------------------------------------------------------------------ 3-D stage on packed records
 // In 3-D the per-particle stage gathers each neighbour from one 64-byte
 // record (one cache-line half) in cell-sorted order:
-//   q0 = (x, y, z, V), q1 = (B00, B01, B02, B11), q2 = (B12, B22, k tr B, 0),
+//   q0 = (x, y, z, V), q1 = (B00, B01, B02, B11), q2 = (B12, B22, 0, 0),
 //   q3 = (2 p, v_x, v_y, v_z),  2 p = 2 c^2 (drho + rho_ref - rho0),
-// with k = -4 mu / d the viscous prefactor of the call, so that a pair
-// needs no per-partner arithmetic for the pressure or the trace of B.  Two record sets carry the stage input and output; geometry
+// so that a pair needs no per-partner arithmetic for the pressure (and
+// reads 56 bytes of the record).  Two record sets carry the stage input and output; geometry
 // is written into both when the state is packed, and a stage writes only
 // the q3 quad of its output (with the conserved record U).
 
@@ -543,7 +543,7 @@ __global__ void k_pack3(int32_t n, EulerArgs ea, const float4* __restrict__ sort
     U[s] = u;
     const float4 g0 = geo0[s], g1 = geo1[s];
     const float2 g2 = geo2[s];
-    const float4 q2 = make_float4(g2.x, g2.y, ea.kmu * ((g1.x + g1.w) + g2.y), 0.f);
+    const float4 q2 = make_float4(g2.x, g2.y, 0.f, 0.f);
     const float4 q3 = state_quad3(ea, u);
     const int64_t b = 4 * (int64_t)s;
     Ra[b] = g0; Ra[b + 1] = g1; Ra[b + 2] = q2; Ra[b + 3] = q3;
@@ -586,8 +586,9 @@ struct Own3 {
 
 // One pair (i, j) of Eq. (19) in 3-D with the corrected gradient (Eq. 28)
 // and the limited linearised Riemann solution (Eqs. 26-27): the terms of
-// accumulate_pair, with 2 p_j and k tr B_j read from the partner's record
-// and c (rho_i + rho_j) = (c rho_i + c rho0) + 2 p_j / (2 c).  The row's
+// accumulate_pair, with 2 p_j read from the partner's record, tr B_j summed
+// from its B entries and c (rho_i + rho_j) = (c rho_i + c rho0) + 2 p_j /
+// (2 c).  The row's
 // pairs come two at a time: the first of two opens the compensated
 // additions (OPEN), the second closes them.
 template <bool WRAP, bool OPEN>
@@ -628,7 +629,7 @@ __device__ __forceinline__ void pair3(const EulerArgs& ea, const Own3& o, const 
     const float vs2 = fmaf(-dn, d[2], o.v[2] + nb.q3.w);
     const float vg2 = fmaf(vs0, G0, fmaf(vs1, G1, vs2 * G2));
     const float rh = rhostar * vg2;
-    const float kv = o.ktrB + nb.q2.z;
+    const float kv = fmaf(ea.kmu, (nb.q1.x + nb.q1.w) + nb.q2.y, o.ktrB);
     const float xm0 = fmaf(rh, vs0, fmaf(p4, G0, kv * dv[0]));
     const float xm1 = fmaf(rh, vs1, fmaf(p4, G1, kv * dv[1]));
     const float xm2 = fmaf(rh, vs2, fmaf(p4, G2, kv * dv[2]));
@@ -731,7 +732,7 @@ __global__ void __launch_bounds__(BLK) k_euler3(int32_t n, EulerArgs ea, const i
     o.x[0] = self.q0.x; o.x[1] = self.q0.y; o.x[2] = self.q0.z;
     o.B[0] = self.q1.x; o.B[1] = self.q1.y; o.B[2] = self.q1.z; o.B[3] = self.q1.w;
     o.B[4] = self.q2.x; o.B[5] = self.q2.y;
-    o.ktrB = self.q2.z;
+    o.ktrB = ea.kmu * ((self.q1.x + self.q1.w) + self.q2.y);
     o.p2 = self.q3.x;
     o.v[0] = self.q3.y; o.v[1] = self.q3.z; o.v[2] = self.q3.w;
     o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);
@@ -943,7 +944,7 @@ k_euler3w(int32_t n, EulerArgs ea, const uint16_t* __restrict__ colw,
     o.x[0] = me.q0.x; o.x[1] = me.q0.y; o.x[2] = me.q0.z;
     o.B[0] = me.q1.x; o.B[1] = me.q1.y; o.B[2] = me.q1.z; o.B[3] = me.q1.w;
     o.B[4] = me.q2.x; o.B[5] = me.q2.y;
-    o.ktrB = me.q2.z;
+    o.ktrB = ea.kmu * ((me.q1.x + me.q1.w) + me.q2.y);
     o.p2 = me.q3.x;
     o.v[0] = me.q3.y; o.v[1] = me.q3.z; o.v[2] = me.q3.w;
     o.crho = fmaf(o.p2, ea.inv2c, ea.crho0x2);
