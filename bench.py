@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # it is measured again.  {sha: {"2d": bytes, "3d": bytes}}
 # (profiles/euler_heun_stage_taylor_green_2d_512.md and _3d_200.md)
 TRAFFIC = {
-    "df30941b6eccf16ee726afc994e4fedfde4f4e0e1462edf8e5b77e1fcb9ac062": {"2d": 39154605, "3d": 1992793621},
+    "9099615b348286075caa4b1f498fe7bc3e8d5954c9db140060b5023f3dbdce51": {"2d": 39154605, "3d": 1992793621},
 }
 
 
@@ -52,7 +52,7 @@ TRAFFIC = {
 # (a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles) over
 # 1,024 SIMDs x 2.4 GHz x the live launch time.
 VALU = {
-    "df30941b6eccf16ee726afc994e4fedfde4f4e0e1462edf8e5b77e1fcb9ac062": {"3d": 400299834},
+    "9099615b348286075caa4b1f498fe7bc3e8d5954c9db140060b5023f3dbdce51": {"3d": 400299834},
 }
 VALU_SIMDS = 1024
 VALU_CLOCK_HZ = 2.4e9

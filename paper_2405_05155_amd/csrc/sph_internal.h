@@ -266,7 +266,6 @@ struct Kahan {
         s = t;
     }
     __device__ __forceinline__ float value() const { return s - c; }
-    __device__ __forceinline__ double value64() const { return (double)s - (double)c; }
 };
 
 // w x into a lane's compensated partial sum of one row.
@@ -322,23 +321,6 @@ __device__ __forceinline__ double group_sum64(const Kahan& k) {
         hi = s;
     }
     return (double)hi + (double)lo;
-}
-
-// group_sum for a run-time group size L in {1, 2, 4, 8}.
-__device__ __forceinline__ float group_sum_rt(const Kahan& k, int L) {
-    float hi = k.s, lo = -k.c;
-#pragma unroll
-    for (int m = 1; m < 8; m <<= 1) {
-        if (m >= L) break;
-        float ohi = lane_xor(hi, m);
-        float olo = lane_xor(lo, m);
-        float s = hi + ohi;
-        float bp = s - hi;
-        float e = (hi - (s - bp)) + (ohi - bp);
-        lo = (lo + olo) + e;
-        hi = s;
-    }
-    return hi + lo;
 }
 
 __device__ __forceinline__ float min_image(float d, float L, float halfL, int periodic) {
