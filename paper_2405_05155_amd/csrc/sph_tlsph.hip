@@ -130,10 +130,19 @@ __device__ __forceinline__ float pair_weight(const TlArgs& t, const Wrap& w, con
     return (gj.w * tq) * (tq * tq);
 }
 
+// w x into a compensated row sum: step 0 a compensated addition of its own,
+// 1 the first and 2 the second of two terms added together (Kahan open and
+// close).
+__device__ __forceinline__ void accum_step(Kahan& k, float w, float x, int step) {
+    if (step == 1) k.open(w, x);
+    else if (step == 2) k.close(w, x);
+    else accum(k, w, x);
+}
+
 // (v_j - v_i) (x) (X_i - X_j) V_j (1 - q/2)^3 into the nine compensated row sums.
 template <bool WRAP>
 __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const float4& gi, const float4& vi,
-                                      const float4& gj, const float4& vj, Kahan* L) {
+                                      const float4& gj, const float4& vj, Kahan* L, int step = 0) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, gj, d);
     const float dv[3] = {vj.x - vi.x, vj.y - vi.y, vj.z - vi.z};
@@ -141,7 +150,7 @@ __device__ __forceinline__ void acc_a(const TlArgs& t, const Wrap& w, const floa
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) accum(L[r * 3 + c], dv[r], dw[c]);
+        for (int c = 0; c < 3; ++c) accum_step(L[r * 3 + c], dv[r], dw[c], step);
 }
 
 // The per-particle end of kernel A (on the group's first lane): dF/dt = L B0,
@@ -257,12 +266,12 @@ __device__ __forceinline__ void gather_a(int32_t j, const float4* __restrict__ g
 // V_j (1 - q/2)^3 (A_i + A_j)(X_i - X_j) into the three compensated row sums.
 template <bool WRAP>
 __device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const float4& gi, const float* Ai,
-                                      const ARec& b, Kahan* s) {
+                                      const ARec& b, Kahan* s, int step = 0) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, b.g, d);
-    accum(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])));
-    accum(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])));
-    accum(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])));
+    accum_step(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])), step);
+    accum_step(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])), step);
+    accum_step(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])), step);
 }
 
 // Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
@@ -339,7 +348,7 @@ __device__ __forceinline__ void tl_wread(const char* W, uint32_t b, int HC4, ARe
 // emits no instruction), so the next record's LDS reads stay after the pair
 // that frees its registers.
 __device__ __forceinline__ uint32_t tl_after(uint32_t b, const Kahan& k) {
-    asm volatile("" : "+v"(b) : "v"(k.s));
+    asm volatile("" : "+v"(b) : "v"(k.s), "v"(k.c));
     return b;
 }
 
@@ -352,7 +361,8 @@ __device__ __forceinline__ void tl_held(const float4& v) {
 __device__ __forceinline__ void tl_held(float v) { asm volatile("" : : "v"(v)); }
 
 // The lane's chunks of window entries of one row (records from LDS, two in
-// flight), in the order k_tl_b takes them.
+// flight), in the order k_tl_b takes them; the pairs enter the compensated
+// sums two at a time (M is even).
 template <bool WRAP, int M>
 __device__ __forceinline__ void tl_row_w(const TlArgs& t, const Wrap& w, const char* W, int HC4,
                                          const uint16_t* __restrict__ colw, uint32_t at0, uint32_t cs, int32_t nchunk,
@@ -366,10 +376,10 @@ __device__ __forceinline__ void tl_row_w(const TlArgs& t, const Wrap& w, const c
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
-            acc_b<WRAP>(t, w, gi, Ai, A, s);
+            acc_b<WRAP>(t, w, gi, Ai, A, s, 1);
             if (q + 2 < M) tl_wread(W, tl_after(e[q / 2 + 1] & 0xffffu, s[0]), HC4, A);
             __builtin_amdgcn_sched_barrier(0);
-            acc_b<WRAP>(t, w, gi, Ai, B, s);
+            acc_b<WRAP>(t, w, gi, Ai, B, s, 2);
             if (q + 3 < M) tl_wread(W, tl_after(e[q / 2 + 1] >> 16, s[0]), HC4, B);
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -462,7 +472,8 @@ k_tl_bw(int32_t n, TlArgs t, Wrap w, const uint16_t* __restrict__ colw, int32_t 
 
 // Kernel A over the same neighbour windows: the window's reference records
 // (X_j, V_j) and half-step velocities (v_j, fixed flag) copied into two LDS
-// planes, the pairs read there; the per-particle end as in k_tl_a.
+// planes, the pairs read there and enter the nine compensated sums two at a
+// time; the per-particle end as in k_tl_a.
 template <int HC, int NT>
 constexpr int tl_window_waves_a() {  // waves per SIMD the LDS allows, at most 6 (80 VGPRs)
     constexpr int w = 163840 / (32 * HC) * (NT / 64) / 4;
@@ -483,14 +494,14 @@ __device__ __forceinline__ void tl_row_aw(const TlArgs& t, const Wrap& w, const 
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
-            acc_a<WRAP>(t, w, gi, vi, ga, va, L);
+            acc_a<WRAP>(t, w, gi, vi, ga, va, L, 1);
             if (q + 2 < M) {
                 const uint32_t b = tl_after(e[q / 2 + 1] & 0xffffu, L[0]);
                 ga = *reinterpret_cast<const float4*>(W + b);
                 va = *reinterpret_cast<const float4*>(W + HC4 + b);
             }
             __builtin_amdgcn_sched_barrier(0);
-            acc_a<WRAP>(t, w, gi, vi, gb, vb, L);
+            acc_a<WRAP>(t, w, gi, vi, gb, vb, L, 2);
             if (q + 3 < M) {
                 const uint32_t b = tl_after(e[q / 2 + 1] >> 16, L[0]);
                 gb = *reinterpret_cast<const float4*>(W + b);
