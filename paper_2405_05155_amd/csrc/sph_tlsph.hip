@@ -266,12 +266,12 @@ __device__ __forceinline__ void gather_a(int32_t j, const float4* __restrict__ g
 // V_j (1 - q/2)^3 (A_i + A_j)(X_i - X_j) into the three compensated row sums.
 template <bool WRAP>
 __device__ __forceinline__ void acc_b(const TlArgs& t, const Wrap& w, const float4& gi, const float* Ai,
-                                      const ARec& b, Kahan* s, int step = 0) {
+                                      const ARec& b, Kahan* s) {
     float d[3];
     const float wt = pair_weight<WRAP>(t, w, gi, b.g, d);
-    accum_step(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])), step);
-    accum_step(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])), step);
-    accum_step(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])), step);
+    accum(s[0], wt, fmaf(Ai[0] + b.a0.x, d[0], fmaf(Ai[1] + b.a0.y, d[1], (Ai[2] + b.a0.z) * d[2])));
+    accum(s[1], wt, fmaf(Ai[3] + b.a0.w, d[0], fmaf(Ai[4] + b.a1.x, d[1], (Ai[5] + b.a1.y) * d[2])));
+    accum(s[2], wt, fmaf(Ai[6] + b.a1.z, d[0], fmaf(Ai[7] + b.a1.w, d[1], (Ai[8] + b.a2) * d[2])));
 }
 
 // Kernel B (Eq. 31), records gathered one entry ahead.  MODE 0: acc (caller
@@ -361,8 +361,9 @@ __device__ __forceinline__ void tl_held(const float4& v) {
 __device__ __forceinline__ void tl_held(float v) { asm volatile("" : : "v"(v)); }
 
 // The lane's chunks of window entries of one row (records from LDS, two in
-// flight), in the order k_tl_b takes them; the pairs enter the compensated
-// sums two at a time (M is even).
+// flight), in the order k_tl_b takes them.  (Its three sums take each pair
+// on its own: two at a time made this kernel slower, 92.6 against 83.9 us
+// per launch on the 1.6M plate.)
 template <bool WRAP, int M>
 __device__ __forceinline__ void tl_row_w(const TlArgs& t, const Wrap& w, const char* W, int HC4,
                                          const uint16_t* __restrict__ colw, uint32_t at0, uint32_t cs, int32_t nchunk,
@@ -376,10 +377,10 @@ __device__ __forceinline__ void tl_row_w(const TlArgs& t, const Wrap& w, const c
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < M; q += 2) {
-            acc_b<WRAP>(t, w, gi, Ai, A, s, 1);
+            acc_b<WRAP>(t, w, gi, Ai, A, s);
             if (q + 2 < M) tl_wread(W, tl_after(e[q / 2 + 1] & 0xffffu, s[0]), HC4, A);
             __builtin_amdgcn_sched_barrier(0);
-            acc_b<WRAP>(t, w, gi, Ai, B, s, 2);
+            acc_b<WRAP>(t, w, gi, Ai, B, s);
             if (q + 3 < M) tl_wread(W, tl_after(e[q / 2 + 1] >> 16, s[0]), HC4, B);
             __builtin_amdgcn_sched_barrier(0);
         }
