@@ -15,8 +15,8 @@ tensor's RMS):
   6e-4, on dW1 at batch 4,096); at the training batch of 65,536, where the
   flips average out over many samples, every element within 1e-4 (measured
   worst 6e-5).
-The survey's reading asks 99.9% within 1e-4; the flip rate above bounds the
-forward pass at about 99.7%."""
+A bar of 99.9% within 1e-4 for the forward pass is out of reach: the flip
+rate above bounds it at about 99.7%."""
 import numpy as np
 import pytest
 
